@@ -1,0 +1,424 @@
+"""Pins for the CPU oracle against facts the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: published
+known-answer vectors, closed forms, brute force on tiny inputs, invariants
+stated in the paper, and numbers the paper prints.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import az, dense, evaluate, grids, lstsq, periodic, philox, rbf, spectra
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- Philox
+
+def test_philox_known_answers():
+    kat = _golden("philox_kat.json")
+    for case in kat["cases"]:
+        ctr = np.array([[int(v, 16) for v in case["ctr"]]], dtype=np.uint32)
+        key = tuple(int(v, 16) for v in case["key"])
+        out = philox.philox4x32(ctr, key, rounds=kat["rounds"])[0]
+        assert [int(v) for v in out] == [int(v, 16) for v in case["out"]]
+
+
+def _philox_scalar(ctr, key):
+    """Independent scalar Philox4x32-10 with Python integers."""
+    c0, c1, c2, c3 = ctr
+    k0, k1 = key
+    for rnd in range(10):
+        if rnd:
+            k0, k1 = (k0 + 0x9E3779B9) & 0xFFFFFFFF, (k1 + 0xBB67AE85) & 0xFFFFFFFF
+        p0 = 0xD2511F53 * c0
+        p1 = 0xCD9E8D57 * c2
+        c0, c1, c2, c3 = ((p1 >> 32) ^ c1 ^ k0, p1 & 0xFFFFFFFF,
+                          (p0 >> 32) ^ c3 ^ k1, p0 & 0xFFFFFFFF)
+    return c0, c1, c2, c3
+
+
+def test_gaussian_sketch_matches_scalar_definition():
+    N, k, seed = 10, 3, (7 << 32) | 12345
+    Om = philox.gaussian_sketch(N, k, seed)
+    for j in range(N):
+        for c in range(k):
+            a = _philox_scalar((j // 4, c, 0, 0), (seed & 0xFFFFFFFF, seed >> 32))
+            u = [(v + 0.5) / 2.0 ** 32 for v in a]
+            pair = (j % 4) // 2
+            r = math.sqrt(-2.0 * math.log(u[2 * pair]))
+            t = 2.0 * math.pi * u[2 * pair + 1]
+            want = r * (math.cos(t) if j % 2 == 0 else math.sin(t))
+            assert abs(Om[j, c] - want) <= 1e-15 * max(1.0, abs(want))
+
+
+def test_gaussian_sketch_statistics():
+    Om = philox.gaussian_sketch(4096, 16, 42)
+    z = Om.ravel()
+    assert abs(z.mean()) < 0.02 and abs(z.var() - 1.0) < 0.03
+    # Kolmogorov-Smirnov distance to the normal CDF
+    zs = np.sort(z)
+    cdf = 0.5 * (1.0 + np.vectorize(math.erf)(zs / math.sqrt(2.0)))
+    ks = np.max(np.abs(cdf - np.arange(1, zs.size + 1) / zs.size))
+    assert ks < 1.63 / math.sqrt(zs.size)     # 1% critical value
+    # columns are not copies of each other
+    C = np.corrcoef(Om.T)
+    assert np.max(np.abs(C - np.eye(16))) < 0.08
+
+
+# ---------------------------------------------------------------- kernel
+
+def test_phi_values_and_second_derivative():
+    eps = 3.7
+    assert rbf.phi(0.0, eps) == 1.0
+    assert abs(rbf.phi(1.0 / eps, eps) - math.exp(-1.0)) < 1e-16
+    # phi'' against a 4th-order central difference of phi
+    r = np.linspace(-0.9, 0.9, 37)
+    d = 1e-3
+    fd = (-rbf.phi(r + 2 * d, eps) + 16 * rbf.phi(r + d, eps) - 30 * rbf.phi(r, eps)
+          + 16 * rbf.phi(r - d, eps) - rbf.phi(r - 2 * d, eps)) / (12 * d * d)
+    assert np.max(np.abs(fd - rbf.phi2(r, eps))) < 1e-6 * eps ** 2
+
+
+def test_periodization_brute_force_and_period():
+    T, eps = 1.0, 0.9        # wide kernel: many images matter
+    x = np.linspace(-2 * T, 2 * T, 41)
+    brute = sum(np.exp(-(eps * (x - 2 * m * T)) ** 2) for m in range(-60, 61))
+    assert np.max(np.abs(rbf.phi_per(x, eps, T) - brute)) < 1e-15 * brute.max()
+    y = np.linspace(-T, 0, 9)
+    assert np.max(np.abs(rbf.phi_per(y + 2 * T, eps, T) - rbf.phi_per(y, eps, T))) < 1e-14
+    brute2 = sum(rbf.phi2(x - 2 * m * T, eps) for m in range(-60, 61))
+    assert np.max(np.abs(rbf.phi2_per(x, eps, T) - brute2)) < 1e-14
+
+
+def test_shape_parameter_rule():
+    # eps h = pi / sqrt(2 log(1 + tau0^-2)): 0.3273 at tau0=1e-10, 0.4629 at 1e-5
+    for tau0, eh in [(1e-10, 0.32731), (1e-5, 0.46289)]:
+        for n, T in [(64, 1.0), (100, 1.4)]:
+            eps = rbf.shape_parameter(tau0, n, T)
+            assert abs(eps * 2 * T / n - eh) < 1e-4
+
+
+# ---------------------------------------------------------------- grids
+
+def test_grids_and_collocation_count():
+    p = W.config_c1(256)
+    c = grids.centres(p.n, p.T)
+    xt = grids.fine_grid(p.n, p.s, p.T)
+    assert np.array_equal(xt[::p.s], c)                # centres lie on the fine grid
+    assert abs(c[1] - c[0] - 2 / 256) < 1e-16 and abs(xt[-1] - (1 - 1 / 256)) < 1e-16
+    idx, x = grids.collocation_1d(p.n, p.s, p.T, p.domain)
+    assert idx.size == 257 and idx[0] == 128 and idx[-1] == 384   # closed interval
+    assert x.min() == -0.5 and x.max() == 0.5
+    p2 = W.config_c3(128)
+    idx2, pts = grids.collocation(p2)
+    assert idx2.size == 32937
+    assert np.all(pts[:, 0] ** 2 + pts[:, 1] ** 2 <= 0.64)
+
+
+# ---------------------------------------------------------------- dense A
+
+def test_dense_1d_entries_brute_force():
+    p = W.config_c1a(16)
+    A, idx, pts, _ = dense.system_matrix(p)
+    c = -1.0 + np.arange(16) * (2.0 / 16)
+    for i in [0, 3, A.shape[0] - 1]:
+        for j in [0, 7, 15]:
+            want = sum(math.exp(-(p.eps * (pts[i, 0] - c[j] - 2 * m)) ** 2)
+                       for m in range(-20, 21))
+            assert abs(A[i, j] - want) < 1e-15
+
+
+def test_dense_2d_rows_are_radial_gaussians():
+    """Section 5: the radial Gaussian of the distance is the product of the
+    univariate Gaussians, so a 2D row equals exp(-eps^2 |x - c|^2) summed over
+    periodic images."""
+    p = W.config_c3a(8)
+    A, idx, pts, _ = dense.system_matrix(p)
+    c = -1.0 + np.arange(8) * 0.25
+    for i in [0, A.shape[0] // 2, A.shape[0] - 1]:
+        for jx, jy in [(0, 0), (3, 5), (7, 2)]:
+            want = 0.0
+            for mx in range(-8, 9):
+                for my in range(-8, 9):
+                    dx = pts[i, 0] - c[jx] - 2 * mx
+                    dy = pts[i, 1] - c[jy] - 2 * my
+                    want += math.exp(-p.eps ** 2 * (dx * dx + dy * dy))
+            assert abs(A[i, jx * 8 + jy] - want) < 1e-15
+
+
+def test_bvp_rows_are_scaled_negative_laplacian():
+    """Interior BVP rows equal -(Lap + k2) phi_j / (4 eps^2) (section 6.2),
+    checked with a finite-difference Laplacian of the radial Gaussian."""
+    p = W.config_c4(8)
+    p.k2 = 3.0
+    eps = p.eps
+    c = -1.0 + np.arange(8) * 0.25
+    pts = np.array([[0.1, -0.2], [0.33, 0.4], [-0.5, 0.05]])
+    rows = dense.interior_rows(p, pts)
+    d = 1e-3
+
+    def g(x, y, jx, jy):
+        return sum(math.exp(-eps ** 2 * ((x - c[jx] - 2 * mx) ** 2 + (y - c[jy] - 2 * my) ** 2))
+                   for mx in range(-4, 5) for my in range(-4, 5))
+    for i, (x, y) in enumerate(pts):
+        for jx, jy in [(3, 4), (4, 2), (1, 1)]:
+            lap = (g(x + d, y, jx, jy) + g(x - d, y, jx, jy) + g(x, y + d, jx, jy)
+                   + g(x, y - d, jx, jy) - 4 * g(x, y, jx, jy)) / (d * d)
+            want = -(lap + p.k2 * g(x, y, jx, jy)) / (4 * eps * eps)
+            assert abs(rows[i, jx * 8 + jy] - want) < 2e-5
+
+
+def test_periodic_matrix_is_block_column_circulant():
+    p = W.config_c1a(16)
+    Ac = periodic.periodic_matrix(p)
+    perm = periodic.pi_perm(p.n, p.s)
+    PA = Ac[perm]
+    for r in range(p.s):
+        blk = PA[r * p.n:(r + 1) * p.n]
+        assert np.max(np.abs(np.roll(np.roll(blk, 1, 0), 1, 1) - blk)) < 1e-15
+
+
+# ---------------------------------------------------------------- lstsq
+
+def test_tsvd_solve_against_construction():
+    rng = np.random.default_rng(0)
+    U, _ = np.linalg.qr(rng.standard_normal((40, 12)))
+    V, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+    S = np.array([1.0, 0.5, 0.2, 1e-2, 1e-4, 1e-6, 1e-14, 2e-15, 1e-15, 5e-16, 1e-16, 1e-17])
+    A = (U * S) @ V.T
+    b = rng.standard_normal(40)
+    x, r = lstsq.tsvd_solve(A, b, tau=1e-12)
+    assert r == 6
+    want = V[:, :6] @ ((U[:, :6].T @ b) / S[:6])
+    # perturbation bound: relative error about u / sigma_min = 1e-10
+    assert np.max(np.abs(x - want)) < 1e-8 * np.max(np.abs(want))
+    # full-rank consistent system: exact solution
+    B = rng.standard_normal((30, 10))
+    xt = rng.standard_normal(10)
+    x2, r2 = lstsq.tsvd_solve(B, B @ xt)
+    assert r2 == 10 and np.max(np.abs(x2 - xt)) < 1e-13
+
+
+# ---------------------------------------------------------------- periodic solver
+
+@pytest.mark.parametrize("s", [1, 2, 3])
+def test_B_is_block_column_diagonal_with_closed_form_diagonals(s):
+    p = W.Problem("t", 1, 16, s, 1.0, 0.5, W.box(1.0), [])
+    B = periodic.block_diagonal_form(p)
+    d = periodic.diagonals(B, p.N)
+    off = B.copy()
+    for i in range(s):
+        off[i * p.N:(i + 1) * p.N] -= np.diag(d[i])
+    scale = np.abs(d).max()
+    assert np.max(np.abs(off)) < 1e-14 * scale
+    for r in range(s):
+        cf = spectra.diag_closed_form(p.n, s, p.T, p.eps, r)
+        assert np.max(np.abs(cf - d[r])) < 1e-14 * scale
+
+
+def test_second_derivative_diagonals_closed_form():
+    p = W.Problem("t", 1, 16, 2, 1.0, 0.5, W.box(1.0), [], op=W.HELMHOLTZ)
+    # A^c of the operator rows -(phi'' + 0)/(2 eps^2): diagonals are -d2/(2 eps^2)
+    B = periodic.block_diagonal_form(p)
+    d = periodic.diagonals(B, p.N)
+    for r in range(2):
+        cf = -spectra.diag_closed_form(p.n, 2, p.T, p.eps, r, deriv=2) / (2 * p.eps ** 2)
+        assert np.max(np.abs(cf - d[r])) < 1e-13 * np.abs(d).max()
+
+
+def test_lemma43_minimum_at_nyquist():
+    for n in [32, 64, 256]:
+        eps = rbf.shape_parameter(1e-10, n, 1.0)
+        d1 = spectra.diag_closed_form(n, 1, 1.0, eps, 0).real
+        assert np.argmin(d1) == n // 2
+        # O(tau0): the minimum is within two orders of magnitude of tau0
+        assert 1e-12 < d1.min() < 1e-8
+
+
+def test_zstar_exact_for_periodic_problem():
+    """Section 4.1: Z* solves the periodic problem exactly, Z* A^c = I."""
+    for s in [1, 2, 3]:
+        p = W.Problem("t", 1, 16, s, 1.0, 0.5, W.box(1.0), [])
+        idx = np.arange(p.n * s)
+        Z, imag = periodic.zstar(p, idx, tauZ=0.0)
+        Ac = periodic.periodic_matrix(p)
+        assert imag < 1e-13 * np.abs(Z).max()
+        assert np.max(np.abs(Z @ Ac - np.eye(p.N))) < 1e-10
+
+
+def test_zstar_literal_equals_pinv_and_normal_form():
+    p = W.config_c1a(16)
+    idx, _ = grids.collocation_1d(p.n, p.s, p.T, p.domain)
+    Z, _ = periodic.zstar(p, idx, tauZ=0.0)
+    Ac = periodic.periodic_matrix(p)
+    E = np.zeros((Ac.shape[0], idx.size))
+    E[idx, np.arange(idx.size)] = 1.0
+    Zp = np.linalg.pinv(Ac, rcond=1e-15) @ E          # SVD-based pseudo-inverse
+    assert np.max(np.abs(Z - Zp)) < 1e-9 * np.max(np.abs(Zp))
+    Zn = periodic.zstar_normal(p, idx, tauZ=0.0)
+    assert np.max(np.abs(Z - Zn)) < 1e-9 * np.max(np.abs(Zn))
+
+
+def test_zstar_2d_literal_kron_equals_normal_form():
+    p = W.config_c3a(8)
+    idx, _ = grids.collocation(p)
+    Z, imag = periodic.zstar(p, idx, tauZ=1e-12)
+    Zn = periodic.zstar_normal(p, idx, tauZ=1e-12)
+    assert imag < 1e-8 * np.abs(Z).max()
+    assert np.max(np.abs(Z - Zn)) < 1e-10 * np.abs(Zn).max()
+    pb = W.config_c4(8)
+    idxb, _ = grids.collocation(pb)
+    Zb, _ = periodic.zstar(pb, idxb, tauZ=1e-12, nb=pb.nb)
+    Zbn = periodic.zstar_normal(pb, idxb, tauZ=1e-12, nb=pb.nb)
+    assert np.max(np.abs(Zb - Zbn)) < 1e-10 * np.abs(Zbn).max()
+    assert np.all(Zb[:, idxb.size:] == 0.0)            # zero columns for boundary rows
+
+
+def test_lemma44_norm_of_I_minus_AZ():
+    for prob in [W.config_c1(64), W.config_c1a(64), W.config_c3a(10)]:
+        A, idx, pts, bpts = dense.system_matrix(prob)
+        Z = periodic.zstar_normal(prob, idx)
+        nrm = np.linalg.norm(np.eye(A.shape[0]) - A @ Z, 2)
+        assert nrm <= 2.0 + 1e-9
+        assert abs(nrm - 1.0) < 1e-6        # an orthogonal projector in fact
+
+
+# ---------------------------------------------------------------- AZ
+
+def _c1_system(n, eh):
+    p = W.config_c1a(n) if eh == 0.5 else W.config_c1(n)
+    A, idx, pts, bpts = dense.system_matrix(p)
+    b = dense.rhs(p, pts, bpts)[:, 0]
+    Z = periodic.zstar_normal(p, idx)
+    _, D = periodic.symbol_weights(p)
+    return p, A, b, Z, math.sqrt(D.max())
+
+
+def test_az_residual_identity_lemma41():
+    """Algorithm 1: b - A x = (I - A Z*)(b - A x1) for any x1."""
+    p, A, b, Z, nA = _c1_system(64, 0.5)
+    res = az.az_solve(A, Z, b, Omega=philox.gaussian_sketch(p.N, 32, 1), normA=nA)
+    lhs = b - A @ res["x"]
+    rhs = b - A @ res["x1"] - A @ (Z @ (b - A @ res["x1"]))
+    assert np.max(np.abs(lhs - rhs)) < 1e-12
+
+
+def test_az_matches_oracle_saturated_regime():
+    p, A, b, Z, nA = _c1_system(256, 1.0)
+    xo, _ = lstsq.tsvd_solve(A, b, 1e-12)
+    res = az.az_solve(A, Z, b, Omega=philox.gaussian_sketch(p.N, 32, 42), normA=nA)
+    ro, ra = evaluate.relres(A, xo, b), evaluate.relres(A, res["x"], b)
+    assert abs(ra - ro) < 0.01 * ro
+
+
+def test_az_with_refinement_matches_oracle():
+    p, A, b, Z, nA = _c1_system(256, 0.5)
+    xo, _ = lstsq.tsvd_solve(A, b, 1e-12)
+    res = az.az_solve(A, Z, b, Omega=philox.gaussian_sketch(p.N, 32, 42), normA=nA, refine=1)
+    tp = W.test_points(p)
+    f = p.rhs[0](tp[:, 0])
+    eo = np.abs(evaluate.eval_dense(p, xo, tp) - f).max()
+    ea = np.abs(evaluate.eval_dense(p, res["x"], tp) - f).max()
+    ro, ra = evaluate.relres(A, xo, b), evaluate.relres(A, res["x"], b)
+    assert ra <= 10 * ro and ra <= 1e-10
+    assert ea <= 10 * eo
+
+
+def test_rank_of_perturbation_flat_in_n_1d():
+    """Theorem 4.6 / Fig. 3.2: the rank of A - A Z* A does not grow with N."""
+    ranks = []
+    for n in [128, 256, 512]:
+        p, A, b, Z, nA = _c1_system(n, 0.5)
+        ranks.append(lstsq.numerical_rank(A - A @ Z @ A, 1e-10))
+    assert max(ranks) - min(ranks) <= 2 and max(ranks) < 32
+
+
+def test_rank_of_perturbation_grows_in_2d():
+    """Section 5.3.2 and Fig. 5.2: the rank grows like sqrt(N) = n in 2D, i.e.
+    by a near-constant amount per added grid line, while rank/N falls."""
+    ranks, Ns = [], []
+    for n in [16, 24, 32]:
+        p = W.config_c3a(n)
+        A, idx, pts, _ = dense.system_matrix(p)
+        Z = periodic.zstar_normal(p, idx)
+        ranks.append(lstsq.numerical_rank(A - A @ Z @ A, 1e-10))
+        Ns.append(p.N)
+    inc = np.diff(ranks)
+    assert abs(inc[1] - inc[0]) < 0.25 * inc[0]
+    assert ranks[0] / Ns[0] > ranks[1] / Ns[1] > ranks[2] / Ns[2]
+
+
+# ---------------------------------------------------------------- printed values
+
+def test_paper_E1_periodic_1d():
+    g = _golden("paper_values.json")["E1_periodic_1d"]
+    norms = []
+    for n in g["n"]:
+        eps = rbf.shape_parameter(g["tau0"], n, g["T"])
+        k = math.floor(n / 5)
+
+        def f(x, k=k):
+            return np.sin(k * np.pi * x)
+        p = W.Problem("E1", 1, n, g["s"], g["T"], eps * 2 * g["T"] / n, W.box(g["T"]), [f])
+        A, idx, pts, bpts = dense.system_matrix(p)
+        x, _ = lstsq.tsvd_solve(A, dense.rhs(p, pts, bpts)[:, 0])
+        tp = W.test_points(p)
+        assert np.abs(evaluate.eval_dense(p, x, tp) - f(tp[:, 0])).max() < g["max_error_below"]
+        norms.append(np.linalg.norm(x) / math.sqrt(n))
+    fac = g["coef_norm_tolerance_factor"]
+    assert g["coef_norm_about"] / fac < norms[-1] < g["coef_norm_about"] * fac
+
+
+def test_paper_E4_periodic_2d():
+    g = _golden("paper_values.json")["E4_periodic_2d"]
+    dom = W.Domain("box2", 2, lambda x, y: np.ones(np.shape(x), bool))
+    for n in g["n"]:
+        eps = rbf.shape_parameter(g["tau0"], n, g["T"])
+        k = math.floor(n / 10)
+
+        def f(x, y, k=k):
+            return np.sin(k * np.pi * (x + y))
+        p = W.Problem("E4", 2, n, g["s"], g["T"], eps * 2 * g["T"] / n, dom, [f])
+        A, idx, pts, bpts = dense.system_matrix(p)
+        x, _ = lstsq.tsvd_solve(A, dense.rhs(p, pts, bpts)[:, 0])
+        tp = W.test_points(p, m2d=61)
+        assert np.abs(evaluate.eval_dense(p, x, tp) - f(tp[:, 0], tp[:, 1])).max() < g["max_error_below"]
+        assert np.linalg.norm(x) / n < g["coef_norm_below"]
+
+
+def test_paper_E7_helmholtz_ode():
+    g = _golden("paper_values.json")["E7_helmholtz_ode"]
+    for n in g["n"]:
+        T = g["T"]
+        eps = rbf.shape_parameter(g["tau0"], n, T)
+        kk = n / 5.0
+
+        def u(x, kk=kk):
+            return np.sin(kk * x)
+        p = W.Problem("E7", 1, n, g["s"], T, eps * 2 * T / n, W.interval(-1.0, 1.0),
+                      [lambda x: 0 * x], op=W.HELMHOLTZ, k2=kk * kk, bnd=[u], nb=2, exact=[u])
+        A, idx, pts, bpts = dense.system_matrix(p)
+        x, _ = lstsq.tsvd_solve(A, dense.rhs(p, pts, bpts)[:, 0])
+        tp = W.test_points(p)
+        assert np.abs(evaluate.eval_dense(p, x, tp) - u(tp[:, 0])).max() < g["max_error_below"]
+
+
+# ---------------------------------------------------------------- local evaluator
+
+def test_local_evaluator_matches_dense():
+    for prob in [W.config_c1a(64), W.config_c3a(48), W.config_c4(48)]:
+        A, idx, pts, bpts = dense.system_matrix(prob)
+        x = np.random.default_rng(3).standard_normal((prob.N, 2))
+        M = idx.size
+        got = evaluate.apply_local(prob, x, pts)
+        assert np.max(np.abs(got - A[:M] @ x)) < 1e-13 * np.abs(A[:M] @ x).max()

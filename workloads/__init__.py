@@ -1,0 +1,310 @@
+"""Seeded synthetic workloads for the AZ RBF solver.
+
+This module describes *problems*, not the method: domains (membership
+predicates and boundary curves), right-hand-side functions, boundary-point
+placement, test-point sets and the served request stream.  It holds none of
+the solver's arithmetic (no grids, kernels, spectra or linear algebra) and is
+the only code shared by the CPU oracle and the GPU path.
+
+Every problem follows the paper's setting: Gaussian RBF centres on a regular
+grid over the bounding box [-T, T) (section 2.2, eq. set_centers), collocation
+points taken from an s-times finer grid inside the domain (eq. set_X,
+eq. set_X_2d), and for boundary value problems weakly imposed Dirichlet data at
+points on the boundary (section 6.2).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional
+
+import numpy as np
+
+__all__ = [
+    "Domain", "interval", "disk", "star", "box",
+    "Problem", "trig_sum_1d", "trig_sum_2d",
+    "config_c1", "config_c1a", "config_c2", "config_c3", "config_c3a",
+    "config_c4", "family_1d", "served_stream", "test_points",
+]
+
+
+# --------------------------------------------------------------------------
+# Domains
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class Domain:
+    """A domain inside the bounding box.
+
+    ``contains`` maps coordinate arrays to a boolean mask.  Membership is
+    inclusive (points on the boundary belong to the domain).  For 2D domains
+    that are star-shaped about the origin, ``radius`` gives the boundary as
+    r(theta) and ``dradius`` its derivative; they define boundary points.
+    """
+    name: str
+    dim: int
+    contains: Callable[..., np.ndarray]
+    bounds: Optional[tuple] = None
+    radius: Optional[Callable[[np.ndarray], np.ndarray]] = None
+    dradius: Optional[Callable[[np.ndarray], np.ndarray]] = None
+    area: Optional[float] = None
+
+
+def interval(a: float, b: float) -> Domain:
+    return Domain(f"interval[{a},{b}]", 1,
+                  lambda x: (x >= a) & (x <= b), bounds=(a, b), area=b - a)
+
+
+def box(T: float = 1.0) -> Domain:
+    """The whole periodic box (the periodic problem of section 3.1)."""
+    return Domain("box", 1, lambda x: np.ones(np.shape(x), dtype=bool),
+                  bounds=(-T, T), area=2 * T)
+
+
+def disk(R: float) -> Domain:
+    return Domain(f"disk(R={R})", 2,
+                  lambda x, y: x * x + y * y <= R * R,
+                  radius=lambda t: np.full(np.shape(t), R, dtype=np.float64),
+                  dradius=lambda t: np.zeros(np.shape(t), dtype=np.float64),
+                  area=math.pi * R * R)
+
+
+def star(R: float, amp: float = 0.1, petals: int = 5) -> Domain:
+    """Star domain r(theta) = R + amp*cos(petals*theta)."""
+    def contains(x, y):
+        return np.sqrt(x * x + y * y) <= R + amp * np.cos(petals * np.arctan2(y, x))
+    return Domain(f"star(R={R},a={amp},p={petals})", 2, contains,
+                  radius=lambda t: R + amp * np.cos(petals * t),
+                  dradius=lambda t: -amp * petals * np.sin(petals * t),
+                  area=math.pi * (R * R + 0.5 * amp * amp))
+
+
+def boundary_length(dom: Domain, nquad: int = 1 << 16) -> float:
+    """Perimeter of a star-shaped boundary by the periodic trapezoid rule."""
+    t = 2 * math.pi * np.arange(nquad) / nquad
+    r, dr = dom.radius(t), dom.dradius(t)
+    return float(np.mean(np.sqrt(r * r + dr * dr)) * 2 * math.pi)
+
+
+def boundary_points(dom: Domain, count: int) -> np.ndarray:
+    """``count`` points theta_j = 2*pi*j/count on the boundary curve, (count, 2)."""
+    t = 2 * math.pi * np.arange(count) / count
+    r = dom.radius(t)
+    return np.stack([r * np.cos(t), r * np.sin(t)], axis=1)
+
+
+# --------------------------------------------------------------------------
+# Right-hand sides
+# --------------------------------------------------------------------------
+
+def trig_sum_1d(seed: int, terms: int = 32, wmax: float = 40.0):
+    """Random trigonometric sum  sum_t a_t cos(w_t x + p_t).
+
+    a ~ N(0,1), w ~ U[0, wmax], p ~ U[0, 2pi), drawn from numpy's PCG64 with
+    ``seed``.  Returns a callable f(x).
+    """
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(terms)
+    w = rng.uniform(0.0, wmax, terms)
+    p = rng.uniform(0.0, 2 * math.pi, terms)
+
+    def f(x):
+        x = np.asarray(x, dtype=np.float64)
+        return np.cos(np.multiply.outer(x, w) + p) @ a
+    return f
+
+
+def trig_sum_2d(seed: int, terms: int = 32, wmax: float = 40.0):
+    """2D random trigonometric sum with wave vectors rho*(cos alpha, sin alpha)."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal(terms)
+    rho = rng.uniform(0.0, wmax, terms)
+    alpha = rng.uniform(0.0, 2 * math.pi, terms)
+    p = rng.uniform(0.0, 2 * math.pi, terms)
+    wx, wy = rho * np.cos(alpha), rho * np.sin(alpha)
+
+    def f(x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        return np.cos(np.multiply.outer(x, wx) + np.multiply.outer(y, wy) + p) @ a
+    return f
+
+
+# --------------------------------------------------------------------------
+# Problems
+# --------------------------------------------------------------------------
+
+APPROX, POISSON, HELMHOLTZ = 0, 1, 2
+
+
+@dataclasses.dataclass
+class Problem:
+    """One least-squares RBF problem on the box [-T, T)^dim.
+
+    n      centres per axis (N = n^dim unknowns)
+    s      oversampling factor per axis (L = s*n grid points per axis)
+    T      half-width of the periodic box
+    eh     shape parameter times centre spacing, eps*h (eps = eh / h)
+    op     APPROX: rows phi_j(x_i).  POISSON/HELMHOLTZ: interior rows of
+           -(Laplacian + k2) phi_j, boundary rows phi_j at boundary points.
+    rhs    list of callables f(x) or f(x, y) giving interior data
+    bnd    for BVPs, callables g giving Dirichlet data (same length as rhs)
+    nb     number of boundary points (BVPs), placed by ``boundary_points``
+    """
+    name: str
+    dim: int
+    n: int
+    s: int
+    T: float
+    eh: float
+    domain: Domain
+    rhs: list
+    op: int = APPROX
+    k2: float = 0.0
+    bnd: Optional[list] = None
+    nb: int = 0
+    bweight: float = 1.0
+    exact: Optional[list] = None      # exact solutions u (BVPs) for error checks
+    k: int = 0                        # sketch width (0: solver's estimate)
+    p: int = 10                       # sketch oversampling
+    seed: int = 42                    # sketch seed
+
+    @property
+    def h(self) -> float:
+        return 2 * self.T / self.n
+
+    @property
+    def eps(self) -> float:
+        return self.eh / self.h
+
+    @property
+    def N(self) -> int:
+        return self.n ** self.dim
+
+    def bpoints(self) -> np.ndarray:
+        if self.nb == 0:
+            return np.zeros((0, self.dim))
+        if self.dim == 1:
+            return np.array([[-1.0], [1.0]])[: self.nb]
+        return boundary_points(self.domain, self.nb)
+
+
+def _f_c1(x):
+    return np.exp(x) * np.sin(7 * x) + x * x
+
+
+def config_c1(n: int = 256) -> Problem:
+    """1D plain AZ, eps = 1/h, Omega = [-0.5, 0.5], f = e^x sin 7x + x^2."""
+    return Problem("C1", 1, n, 2, 1.0, 1.0, interval(-0.5, 0.5), [_f_c1], k=32)
+
+
+def config_c1a(n: int = 256) -> Problem:
+    """C1 at eps*h = 0.5, the regime where FP64 AZ reaches residual 1e-10."""
+    return Problem("C1a", 1, n, 2, 1.0, 0.5, interval(-0.5, 0.5), [_f_c1], k=32)
+
+
+def family_1d(n: int, nrhs: int, eh: float = 0.5, seed0: int = 1000,
+              name: str = "C2") -> Problem:
+    """1D batched family: random trig sums on [-0.5, 0.5], box [-1, 1)."""
+    return Problem(name, 1, n, 2, 1.0, eh, interval(-0.5, 0.5),
+                   [trig_sum_1d(seed0 + i) for i in range(nrhs)], k=32)
+
+
+def config_c2(n: int = 65536, nrhs: int = 64) -> Problem:
+    return family_1d(n, nrhs)
+
+
+def _f_c3(x, y):
+    return np.cos(3 * x + 2 * y) * np.exp(-x * x)
+
+
+def config_c3(n: int = 128, eh: float = 1.0) -> Problem:
+    """2D approximation on the disk of radius 0.8, f = cos(3x+2y) exp(-x^2)."""
+    return Problem("C3" if eh == 1.0 else "C3a", 2, n, 2, 1.0, eh, disk(0.8),
+                   [_f_c3], p=10)
+
+
+def config_c3a(n: int = 128) -> Problem:
+    return config_c3(n, 0.5)
+
+
+def _u_c4(x, y):
+    return np.sin(2 * x) * np.cos(3 * y)
+
+
+def _f_c4(x, y):
+    return 13.0 * np.sin(2 * x) * np.cos(3 * y)
+
+
+def config_c4(n: int = 256, eh: float = 0.5, R: float = 0.7) -> Problem:
+    """2D Poisson -Lap u = f on the star 0.7 + 0.1 cos 5 theta, weak Dirichlet.
+
+    Boundary points: round(4 * length / h), equispaced in theta.
+    """
+    dom = star(R)
+    h = 2.0 / n
+    nb = int(round(4 * boundary_length(dom) / h))
+    return Problem("C4", 2, n, 2, 1.0, eh, dom, [_f_c4], op=POISSON, k2=0.0,
+                   bnd=[_u_c4], nb=nb, exact=[_u_c4], p=10)
+
+
+# --------------------------------------------------------------------------
+# Test points
+# --------------------------------------------------------------------------
+
+def test_points(prob: Problem, m1d: int = 4096, m2d: int = 1024) -> np.ndarray:
+    """Fine test set: 1D linspace over the interval, 2D a cell-centred
+    m2d x m2d lattice on [-1, 1]^2 intersected with the domain."""
+    if prob.dim == 1:
+        lo, hi = prob.domain.bounds
+        if prob.domain.name == "box":
+            return np.linspace(lo, hi, m1d, endpoint=False)[:, None]
+        return np.linspace(lo, hi, m1d)[:, None]
+    t = -prob.T + (np.arange(m2d) + 0.5) * (2.0 * prob.T / m2d)
+    X, Y = np.meshgrid(t, t, indexing="ij")
+    keep = prob.domain.contains(X, Y)
+    return np.stack([X[keep], Y[keep]], axis=1)
+
+
+# --------------------------------------------------------------------------
+# Served request stream
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds from stream start
+    problem: Problem
+
+
+def served_stream(count: int = 512, seed: int = 2024, rate: float = 100.0,
+                  frac_1d: float = 0.7, max_rhs: int = 16, eh: float = 0.5,
+                  sides=(64, 128, 256), exps=range(10, 17)) -> list:
+    """Poisson-arrival stream of mixed 1D / 2D approximation requests.
+
+    1D: N = 2^e with e uniform in ``exps``.  2D: side uniform in ``sides``,
+    disk or star with radius uniform in [0.6, 0.85].  Each request carries
+    1..max_rhs random trigonometric right-hand sides.
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    exps = list(exps)
+    for rid in range(count):
+        t += rng.exponential(1.0 / rate)
+        nrhs = int(rng.integers(1, max_rhs + 1))
+        rseed = int(rng.integers(0, 2**31 - 1))
+        if rng.uniform() < frac_1d:
+            n = 2 ** int(rng.choice(exps))
+            prob = Problem(f"req{rid}-1d", 1, n, 2, 1.0, eh, interval(-0.5, 0.5),
+                           [trig_sum_1d(rseed + i) for i in range(nrhs)], k=32,
+                           seed=rseed)
+        else:
+            n = int(rng.choice(list(sides)))
+            R = float(rng.uniform(0.6, 0.85))
+            dom = disk(R) if rng.uniform() < 0.5 else star(R)
+            prob = Problem(f"req{rid}-2d", 2, n, 2, 1.0, eh, dom,
+                           [trig_sum_2d(rseed + i) for i in range(nrhs)],
+                           seed=rseed)
+        out.append(Request(rid, t, prob))
+    return out
