@@ -1,0 +1,189 @@
+/*
+ * azrbf — AZ least-squares solver for periodized Gaussian RBF approximation
+ * and oversampled collocation on MI355X (gfx950), FP64 throughout.
+ *
+ * The method (Zhou & Huybrechs, "Efficient least squares approximation and
+ * collocation methods using radial basis functions"):
+ *   - N Gaussian RBFs phi(r) = exp(-eps^2 r^2) (eq. rbf), periodized with
+ *     period 2T (eq. periodic_rbf), centred on a regular grid of the box
+ *     [-T, T)^dim (eq. set_centers), n centres per axis, N = n^dim;
+ *   - collocation points: the points of an s-times finer grid (eq. set_Xtilde,
+ *     L = s n per axis) that lie in the domain (eq. set_X, eq. set_X_2d);
+ *   - for boundary value problems, interior rows apply -(Laplacian + k2) to
+ *     the basis (divided by 2 eps^2 in 1D, 4 eps^2 in 2D) and boundary rows
+ *     evaluate the basis at boundary points with weight bweight (section 6);
+ *   - the rectangular system A x = b is solved in the least-squares sense by
+ *     the AZ algorithm (Algorithm 1) with Z* = F B^+ P E (section 3.2.2): a
+ *     randomized low-rank solve of (A - A Z* A) x1 = (I - A Z*) b followed by
+ *     x2 = Z* (b - A x1), x = x1 + x2.
+ *
+ * Conventions
+ *   - Every function returns 0 on success or a negative AZRBF_E* code;
+ *     nothing is thrown across this interface.
+ *   - Matrices of vectors are column-major FP64 with a leading dimension:
+ *     element (i, v) of X is X[i + ld * v].  Such pointers are DEVICE
+ *     pointers owned by the caller and must not alias one another.
+ *   - Coefficient vectors have N entries; in 2D entry jx * n + jy belongs to
+ *     the centre (jx, jy) (x slow, y fast; section 5.1).
+ *   - Row vectors have M + Mb entries: the M collocation points in ascending
+ *     fine-grid order (index ix * L + iy in 2D), then the Mb boundary points
+ *     in the order given.
+ *   - Work is queued on the given HIP stream (hipStream_t passed as void*;
+ *     NULL is the default stream) and returns without synchronising, except
+ *     where stated.  A plan owns its device memory.  A plan may be used from
+ *     one stream at a time; calls on different streams must be ordered by the
+ *     caller.  Different plans are independent.
+ */
+#ifndef AZRBF_H
+#define AZRBF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  AZRBF_OK = 0,
+  AZRBF_EINVAL = -1,        /* bad argument: sizes, pointers, empty domain   */
+  AZRBF_EUNSUPPORTED = -2,  /* valid but not implemented (e.g. n not 2^k)    */
+  AZRBF_ENOMEM = -3,        /* device allocation failed                      */
+  AZRBF_EHIP = -4,          /* a HIP runtime call failed                     */
+  AZRBF_ERANK = -5,         /* sketch not rank-revealing at the largest k    */
+  AZRBF_ESTATE = -6         /* call not valid in the plan's current state    */
+};
+
+enum {
+  AZRBF_OP_APPROX = 0,      /* rows phi_j(x_i)                                */
+  AZRBF_OP_BVP = 1          /* rows -(Lap + k2) phi_j(x_i)/(2 dim eps^2) and */
+                            /* weighted Dirichlet rows at boundary points     */
+};
+
+typedef struct azrbf_plan_s* azrbf_plan_t;
+
+/* Problem description (section 2.2 / 5.1 / 6).  All pointers are HOST
+ * pointers, read during azrbf_plan only. */
+typedef struct {
+  int32_t dim;            /* 1 or 2                                          */
+  int32_t n;              /* centres per axis: a power of two, 16 <= n,      */
+                          /* n <= 65536 (1D), n <= 512 (2D)                  */
+  int32_t s;              /* oversampling factor per axis: 1, 2 or 4         */
+  double T;               /* half-width of the periodic box [-T, T)^dim      */
+  double eps;             /* shape parameter; if <= 0 it follows             */
+                          /* eq. constant_shapeparam from tau0               */
+  double tau0;            /* used only when eps <= 0                         */
+  int32_t op;             /* AZRBF_OP_*                                      */
+  double k2;              /* k^2 of -(Lap + k2) for AZRBF_OP_BVP             */
+  const uint8_t* mask;    /* L^dim bytes, nonzero marks a collocation point; */
+                          /* 2D index ix * L + iy                            */
+  int64_t nb;             /* number of boundary points (BVP only)            */
+  const double* bpts;     /* nb x dim coordinates, point i at bpts[i*dim+a]  */
+  double bweight;         /* weight of the boundary rows                     */
+  double tau;             /* step-1 truncation, relative (e.g. 1e-12)        */
+  double tauZ;            /* Z* regularisation: weights whose denominator    */
+                          /* is <= tauZ * max are zero (e.g. 1e-12)          */
+  int32_t k;              /* sketch width; 0 = estimate from n               */
+  int32_t refine;         /* extra AZ passes on the residual (0, 1, ...)     */
+  uint64_t seed;          /* seed of the Gaussian sketch                     */
+} azrbf_problem;
+
+/* Read-only facts about a plan. */
+typedef struct {
+  int64_t N, M, Mb, L;    /* unknowns, collocation rows, boundary rows,     */
+                          /* fine-grid points (L^dim)                        */
+  int32_t k;              /* sketch width                                    */
+  int32_t rank;           /* retained rank after factoring (-1 before)       */
+  double eps;             /* shape parameter in use                          */
+  double normA;           /* ||A^c||_2 of the periodic operator              */
+  double normZ;           /* ||Z*||_2 (largest regularised weight, sqrt)     */
+  int32_t zeroed;         /* number of regularised (zeroed) weights          */
+  int32_t factored;       /* 1 once the low-rank factor is resident          */
+  int64_t device_bytes;   /* device memory currently owned by the plan       */
+} azrbf_info;
+
+/* Step 0 of section 3.2.3: collocation index list, spectra of B (Lemma 4.2:
+ * DFTs of the kernel sampled on the s^dim shifted grids) and the regularised
+ * weights of B^+ (eq. B_pinv; eq. B_pinv_2d; section 6.2 for BVPs).  The
+ * spectra are computed on the device.  On success *out owns the plan.
+ * Errors: EINVAL (bad sizes, empty mask, nb > 0 without op BVP, ...),
+ * EUNSUPPORTED (n not a power of two or out of range, s not in {1,2,4}),
+ * ENOMEM, EHIP. */
+int azrbf_plan(const azrbf_problem* prob, void* stream, azrbf_plan_t* out);
+
+int azrbf_plan_info(azrbf_plan_t plan, azrbf_info* info);
+
+/* Y = alpha * A X + beta * Y for nvec vectors (eq. Ax_is_b, eq. Aa_is_b_2d):
+ * X is N x nvec (ldx >= N), Y is (M + Mb) x nvec (ldy >= M + Mb).  A is
+ * applied as R Pi^T P* B F* (section 3.2.2): FFTs of the coefficients,
+ * multiplication by the spectra of the s^dim shifted grids, inverse FFTs,
+ * restriction to the collocation points; boundary rows by direct summation.
+ * With beta == 0, Y is not read. */
+int azrbf_apply_A(azrbf_plan_t plan, const double* X, int64_t ldx, int64_t nvec,
+                  double alpha, double beta, double* Y, int64_t ldy, void* stream);
+
+/* Z = alpha * Z* R + beta * Z with Z* = F B^+ P E (section 3.2.2); rows
+ * M..M+Mb-1 of R (boundary rows) are ignored: Z* has zero columns there
+ * (section 6.1.2).  R is (M + Mb) x nvec, Z is N x nvec. */
+int azrbf_apply_Zstar(azrbf_plan_t plan, const double* R, int64_t ldr, int64_t nvec,
+                      double alpha, double beta, double* Z, int64_t ldz, void* stream);
+
+/* Step 1 set-up (section 3.2.3, "low-rank solver"): the Gaussian sketch
+ * Omega (N x k), W = (A - A Z* A) Omega, a Householder tall-skinny QR of W,
+ * a one-sided Jacobi SVD of R and truncation at tau * normA * sqrt(k).  The
+ * factor stays resident in the plan.  Synchronises the stream (the retained
+ * rank is read back).  Returns ERANK if all k directions are retained (the
+ * sketch may be too narrow; the factor is still usable). */
+int azrbf_factor(azrbf_plan_t plan, void* stream);
+
+/* Least-squares solve of A X = B for nrhs right-hand sides (Algorithm 1 plus
+ * `refine` refinement passes on the residual).  B is (M + Mb) x nrhs, X is
+ * N x nrhs.  If relres is not NULL it is a device array of nrhs doubles that
+ * receives ||B - A X|| / ||B|| per column.  Factors first if needed (then
+ * the call synchronises). */
+int azrbf_solve(azrbf_plan_t plan, const double* B, int64_t ldb, int64_t nrhs,
+                double* X, int64_t ldx, double* relres, void* stream);
+
+/* Batched form of azrbf_solve over several factored plans on one stream:
+ * the per-problem work is interleaved pass by pass so that small problems
+ * share launches' latency.  Arrays have length nprob. */
+int azrbf_solve_many(int32_t nprob, const azrbf_plan_t* plans,
+                     const double* const* B, const int64_t* ldb, const int64_t* nrhs,
+                     double* const* X, const int64_t* ldx, double* const* relres,
+                     void* stream);
+
+/* Device bytes a plan for prob needs (plan + factor + workspace for up to
+ * max_rhs right-hand sides per call); used for admission by memory. */
+int64_t azrbf_footprint_bytes(const azrbf_problem* prob, int64_t max_rhs);
+
+/* Copies a resident factor matrix to a caller buffer (device pointer):
+ * which = 0: Omega (N x k), 1: Q (M+Mb x k), 2: R (k x k, upper),
+ * 3: singular values of R (k x 1, descending). ld is the leading dimension
+ * of dst. */
+int azrbf_get_factor(azrbf_plan_t plan, int32_t which, double* dst, int64_t ld,
+                     void* stream);
+
+/* The Gaussian sketch definition used by azrbf_factor, for any size:
+ * dst (rows x cols, leading dimension ld) gets entry (j, c) from Philox4x32-10
+ * with counter (j / 4, c, 0, 0) and key (seed mod 2^32, seed / 2^32) and the
+ * Box-Muller transform (rows 4q, 4q+1 from words 0, 1; rows 4q+2, 4q+3 from
+ * words 2, 3; u = (word + 1/2) / 2^32). */
+int azrbf_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* dst, int64_t ld,
+                   void* stream);
+
+/* Per-launch timing for measurement.  While enabled, every kernel launch of
+ * the library (any plan, any stream) is bracketed by HIP events on its
+ * stream and tagged with the bytes it must move at minimum (its algorithmic
+ * reads and writes).  azrbf_profile_report waits for the recorded events,
+ * writes a JSON array of {"name", "calls", "ms", "max_ms", "bytes"} totals
+ * per kernel name into buf (len bytes, NUL-terminated; EINVAL if too small)
+ * and clears the records. */
+int azrbf_profile_enable(int32_t on);
+int azrbf_profile_report(char* buf, int64_t len);
+
+void azrbf_destroy(azrbf_plan_t plan);
+const char* azrbf_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AZRBF_H */

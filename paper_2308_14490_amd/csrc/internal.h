@@ -1,0 +1,136 @@
+// Internal declarations shared by the azrbf translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/azrbf.h"
+
+namespace az {
+
+#define AZ_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return AZRBF_EHIP;           \
+  } while (0)
+
+#define AZ_TRY(call)                                   \
+  do {                                                 \
+    int rc_ = (call);                                  \
+    if (rc_ != AZRBF_OK) return rc_;                   \
+  } while (0)
+
+// Geometry and spectra of the operator as seen by the FFT kernels.
+//
+// Coefficients are an N1 x N2 row-major array (index a*N2 + b):
+//   1D, N > 8192: the four-step split n = b + N2*a (a column index, b row
+//                 element); spectra stored in transposed order k1*N2 + k2
+//                 for frequency k1 + N1*k2;
+//   2D:           a = jx, b = jy, N1 = N2 = n.
+// Phase ph in [0, s^dim) is a shifted grid: 1D r = ph; 2D (rx, ry) =
+// (ph / s, ph % s).  Coefficient (a, b) of phase ph sits at fine-grid point
+//   1D: s*(a*N2 + b) + ph;   2D: (s*a + rx)*L + s*b + ry.
+struct Geo {
+  int dim, s, N1, N2, L;
+  int64_t N;                 // N1*N2
+  int64_t M;                 // collocation rows
+  int64_t i0;                // 1D: fine-grid index of collocation row 0
+  const int32_t* inv;        // 2D: fine-grid point -> collocation row or -1
+  // 1D spectra, [phase][N], frequency layout as above, 1/N folded in:
+  const double2* spA;        // d_r / N
+  const double2* spZ;        // w * conj(d_r) / N
+  // 2D: per-axis factors fac[deriv 0|1][phase][n] (unnormalised DFTs of the
+  // kernel and of its second derivative on the shifted 1D grids), and the
+  // regularised weights w2 = 1/(N D) on the n x n frequency grid.
+  const double2* fac;
+  const double* w2;
+  int op;                    // AZRBF_OP_*
+  double k2, opscale;        // BVP: spectrum = opscale*(d2 d0 + d0 d2 + k2 d0 d0)
+};
+
+struct Plan;
+
+// Per-launch timing (plan.hip).  When enabled, a Prof object brackets one
+// kernel launch with HIP events on its stream and records the algorithmic
+// bytes the launch must move (what it reads and writes at minimum).
+bool prof_enabled();
+int prof_begin(hipStream_t st);
+void prof_end(int slot, const char* name, double bytes, hipStream_t st);
+struct Prof {
+  int slot;
+  const char* name;
+  double bytes;
+  hipStream_t st;
+  Prof(const char* n, double b, hipStream_t s) : slot(-1), name(n), bytes(b), st(s) {
+    if (prof_enabled()) slot = prof_begin(st);
+  }
+  ~Prof() {
+    if (slot >= 0) prof_end(slot, name, bytes, st);
+  }
+};
+
+// ops.hip
+int ops_init_twiddles(int device, const double2** tw);
+int ops_spectra(Plan& P, hipStream_t st);
+int ops_apply_A(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta,
+                double* Y, int64_t ldy, hipStream_t st);
+int ops_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,
+                double* Z, int64_t ldz, hipStream_t st);
+
+// dense.hip
+int dense_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* dst, int64_t ld, hipStream_t st);
+int dense_factor(Plan& P, hipStream_t st);
+int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
+                double* relres, hipStream_t st);
+
+struct Plan {
+  azrbf_problem prob{};
+  int device = 0;
+  int dim = 1, n = 0, s = 1, ph = 1;     // ph = s^dim phases
+  double T = 1, eps = 0, h = 0, hL = 0;
+  int64_t N = 0, Lax = 0, Lg = 0, M = 0, Mb = 0, Mt = 0;
+  bool fused = false;                     // 1D single-kernel path
+  Geo geo{};
+  const double2* tw = nullptr;            // shared twiddle table (per device)
+
+  // device memory owned by the plan
+  std::vector<void*> allocs;
+  int64_t bytes = 0;
+  int32_t* inv = nullptr;
+  double2* spA = nullptr;
+  double2* spZ = nullptr;
+  double2* fac = nullptr;
+  double* w2 = nullptr;
+  double* bpts = nullptr;                 // Mb x dim, device
+  double bweight = 1;
+  double normA = 0, normZ = 0;
+  int zeroed = 0;
+
+  // FFT-engine workspace
+  double2* ws1 = nullptr;
+  double2* ws2 = nullptr;
+  int64_t ws_pairs = 0;
+
+  // factor
+  int k = 0, rank = -1, refine = 0;
+  double tau = 1e-12, tauZ = 1e-12;
+  bool factored = false;
+  double* Om = nullptr;     // N x k, then Omega * P
+  double* Yf = nullptr;     // Mt x k, A Omega, then (A Omega) * P
+  double* Q = nullptr;      // Mt x k
+  double* Rf = nullptr;     // k x k
+  double* sig = nullptr;    // k
+  double* Pm = nullptr;     // k x k = V_r S_r^-1 U_r^T
+  double* dscr = nullptr;   // dense scratch
+  int64_t dscr_bytes = 0;
+
+  // solve workspace
+  double* sw = nullptr;
+  int64_t sw_rhs = 0;
+
+  int alloc(void** p, int64_t bytes);
+  void release();
+};
+
+}  // namespace az

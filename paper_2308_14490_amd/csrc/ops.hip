@@ -1,0 +1,956 @@
+// Structured operators of the AZ method on gfx950: A (collocation matrix)
+// and Z* (regularised periodic inverse), both applied to blocks of real
+// vectors through FFTs, plus the spectra they use (step 0 of section 3.2.3).
+//
+// A = R Pi^T P* B F* and Z* = F B^+ P E (section 3.2.2).  With the shifted
+// grids written out (Pi groups the fine grid into s^dim phases), phase r of
+// A^c x is IDFT(d_r .* DFT(x)) and Z* y = IDFT(w .* sum_r conj(d_r) .* DFT(y_r))
+// with d_r the DFT of the kernel on shifted grid r (Lemma 4.2) and
+// w = 1 / sum_r |d_r|^2 (eq. B_pinv), regularised.  Both maps are complex
+// linear and map real vectors to real vectors, so two real vectors travel
+// as the real and imaginary parts of one complex vector: every transform
+// does useful work on both halves.
+//
+// Paths:
+//   fused  (1D, N <= 8192): one kernel per operator, the whole transform of
+//          a vector pair in one workgroup.
+//   engine (1D, N > 8192, and 2D): three passes over an N1 x N2 array
+//          (column FFT; row FFT + spectral product + row IFFT; column IFFT),
+//          the 1D case being the four-step factorisation with twiddles.
+#include <cmath>
+#include <cstring>
+#include <algorithm>
+#include <mutex>
+#include <string>
+
+#include "fft.h"
+#include "internal.h"
+
+namespace az {
+
+// ------------------------------------------------------------------ twiddles
+
+static const double2* g_tw[64] = {};
+static std::mutex g_tw_mu;
+
+int ops_init_twiddles(int device, const double2** tw) {
+  std::lock_guard<std::mutex> lk(g_tw_mu);
+  if (device < 0 || device >= 64) return AZRBF_EINVAL;
+  if (!g_tw[device]) {
+    std::vector<double2> h(TW_SIZE);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < TW_SIZE; ++i) {
+      const long double a = -2.0L * pi * (long double)i / (long double)TW_SIZE;
+      h[i] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    double2* d = nullptr;
+    if (hipMalloc(&d, sizeof(double2) * TW_SIZE) != hipSuccess) return AZRBF_ENOMEM;
+    if (hipMemcpy(d, h.data(), sizeof(double2) * TW_SIZE, hipMemcpyHostToDevice) != hipSuccess)
+      return AZRBF_EHIP;
+    g_tw[device] = d;
+  }
+  *tw = g_tw[device];
+  return AZRBF_OK;
+}
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int64_t grid_index(const Geo& g, int ph, int64_t a, int64_t b) {
+  if (g.dim == 1) return (int64_t)g.s * (a * g.N2 + b) + ph;
+  const int rx = ph / g.s, ry = ph - rx * g.s;
+  return ((int64_t)g.s * a + rx) * g.L + (int64_t)g.s * b + ry;
+}
+
+__device__ __forceinline__ int64_t row_of(const Geo& g, int64_t gi) {
+  if (g.dim == 1) {
+    const int64_t r = gi - g.i0;
+    return (r >= 0 && r < g.M) ? r : -1;
+  }
+  return g.inv[gi];
+}
+
+// Unnormalised 2D spectrum of phase ph at frequency (ka, kb).
+__device__ __forceinline__ double2 spec2d(const Geo& g, int ph, int ka, int kb) {
+  const int rx = ph / g.s, ry = ph - rx * g.s;
+  const int n = g.N2;
+  const double2 x0 = g.fac[rx * n + ka], y0 = g.fac[ry * n + kb];
+  if (g.op == AZRBF_OP_APPROX) return cmul(x0, y0);
+  const double2* f2 = g.fac + (int64_t)g.s * n;
+  const double2 x2 = f2[rx * n + ka], y2 = f2[ry * n + kb];
+  const double2 d00 = cmul(x0, y0);
+  double2 d = cadd(cadd(cmul(x2, y0), cmul(x0, y2)), cscale(d00, g.k2));
+  return cscale(d, g.opscale);
+}
+
+__device__ __forceinline__ double2 specA(const Geo& g, int ph, int ka, int kb) {
+  if (g.dim == 1) return g.spA[(int64_t)ph * g.N + (int64_t)ka * g.N2 + kb];
+  return cscale(spec2d(g, ph, ka, kb), 1.0 / (double)g.N);
+}
+
+__device__ __forceinline__ double2 specZ(const Geo& g, int ph, int ka, int kb) {
+  if (g.dim == 1) return g.spZ[(int64_t)ph * g.N + (int64_t)ka * g.N2 + kb];
+  return cscale(cconj(spec2d(g, ph, ka, kb)), g.w2[(int64_t)ka * g.N2 + kb]);
+}
+
+__device__ __forceinline__ void store_pair(double* Y, int64_t ldy, int64_t row, int64_t v0, int64_t nvec,
+                                           double2 val, double alpha, double beta) {
+  double* p0 = Y + row + ldy * v0;
+  *p0 = beta == 0.0 ? alpha * val.x : fma(alpha, val.x, beta * *p0);
+  if (v0 + 1 < nvec) {
+    double* p1 = p0 + ldy;
+    *p1 = beta == 0.0 ? alpha * val.y : fma(alpha, val.y, beta * *p1);
+  }
+}
+
+__device__ __forceinline__ double2 load_pair(const double* X, int64_t ldx, int64_t row, int64_t v0,
+                                             int64_t nvec) {
+  if (v0 >= nvec) return make_double2(0.0, 0.0);
+  const double* p0 = X + row + ldx * v0;
+  return make_double2(*p0, v0 + 1 < nvec ? p0[ldx] : 0.0);
+}
+
+template <int N>
+struct Fused {
+  static constexpr int T = N / RADIX;
+  static constexpr int LINES = T >= 256 ? 1 : 256 / T;
+  static constexpr int BLOCK = LINES * T;
+  static constexpr int LDS = LINES * RowLds::stride(N) * (int)sizeof(double2);
+};
+
+// ------------------------------------------------------------------ fused 1D
+
+template <int N>
+__global__ void __launch_bounds__(Fused<N>::BLOCK)
+k_fused_A(Geo g, const double2* __restrict__ tw, const double* __restrict__ X, int64_t ldx,
+          int64_t nvec, double alpha, double beta, double* __restrict__ Y, int64_t ldy) {
+  using F = Fused<N>;
+  extern __shared__ double2 smem[];
+  const RowLds lds{smem, RowLds::stride(N)};
+  const int t = threadIdx.x % F::T, line = threadIdx.x / F::T;
+  const int64_t v0 = 2 * ((int64_t)blockIdx.x * F::LINES + line);
+  double2 a[RADIX];
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) a[m] = load_pair(X, ldx, t + m * F::T, v0, nvec);
+  fft_line<N, false>(a, lds, line, t, tw);
+  for (int r = 0; r < g.s; ++r) {
+    double2 b[RADIX];
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) b[m] = cmul(a[m], g.spA[(int64_t)r * N + t + m * F::T]);
+    fft_line<N, true>(b, lds, line, t, tw);
+    if (v0 < nvec) {
+#pragma unroll
+      for (int m = 0; m < RADIX; ++m) {
+        const int64_t row = (int64_t)g.s * (t + m * F::T) + r - g.i0;
+        if (row >= 0 && row < g.M) store_pair(Y, ldy, row, v0, nvec, b[m], alpha, beta);
+      }
+    }
+  }
+}
+
+template <int N>
+__global__ void __launch_bounds__(Fused<N>::BLOCK)
+k_fused_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R, int64_t ldr,
+          int64_t nvec, double alpha, double beta, double* __restrict__ Z, int64_t ldz) {
+  using F = Fused<N>;
+  extern __shared__ double2 smem[];
+  const RowLds lds{smem, RowLds::stride(N)};
+  const int t = threadIdx.x % F::T, line = threadIdx.x / F::T;
+  const int64_t v0 = 2 * ((int64_t)blockIdx.x * F::LINES + line);
+  double2 acc[RADIX];
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) acc[m] = make_double2(0.0, 0.0);
+  for (int q = 0; q < g.s; ++q) {
+    double2 a[RADIX];
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) {
+      const int64_t row = (int64_t)g.s * (t + m * F::T) + q - g.i0;
+      a[m] = (row >= 0 && row < g.M) ? load_pair(R, ldr, row, v0, nvec) : make_double2(0.0, 0.0);
+    }
+    fft_line<N, false>(a, lds, line, t, tw);
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m)
+      acc[m] = cadd(acc[m], cmul(a[m], g.spZ[(int64_t)q * N + t + m * F::T]));
+  }
+  fft_line<N, true>(acc, lds, line, t, tw);
+  if (v0 < nvec) {
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) store_pair(Z, ldz, t + m * F::T, v0, nvec, acc[m], alpha, beta);
+  }
+}
+
+// Forward FFT of complex lines (spectra set-up), natural order, length N <= 8192.
+template <int N>
+__global__ void __launch_bounds__(Fused<N>::BLOCK)
+k_fused_fwd(const double2* __restrict__ tw, const double2* __restrict__ in, double2* __restrict__ out,
+            int64_t lines) {
+  using F = Fused<N>;
+  extern __shared__ double2 smem[];
+  const RowLds lds{smem, RowLds::stride(N)};
+  const int t = threadIdx.x % F::T, line = threadIdx.x / F::T;
+  const int64_t li = (int64_t)blockIdx.x * F::LINES + line;
+  double2 a[RADIX];
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m)
+    a[m] = li < lines ? in[li * N + t + m * F::T] : make_double2(0.0, 0.0);
+  fft_line<N, false>(a, lds, line, t, tw);
+  if (li < lines) {
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) out[li * N + t + m * F::T] = a[m];
+  }
+}
+
+// ------------------------------------------------------------------ engine
+
+// Column passes: C adjacent columns per block, T = N1/16 threads per column,
+// column index fastest (coalesced runs of C elements).
+template <int N1>
+struct Col {
+  static constexpr int T = N1 / RADIX;
+  static constexpr int CMAX = T >= 256 ? 1 : 256 / T;
+};
+// Row passes: LINES rows per block, T = N2/16 threads per row.
+template <int N2>
+struct Row {
+  static constexpr int T = N2 / RADIX;
+  static constexpr int LMAX = T >= 256 ? 1 : 256 / T;
+};
+
+__device__ __forceinline__ double2 tw_fwd(const double2* tw, int64_t e, int64_t N) {
+  return tw[(e & (N - 1)) * (TW_SIZE / N)];
+}
+
+// P1 of A: column DFT of the coefficient pair array, four-step twiddle.
+template <int N1, bool TWID>
+__global__ void __launch_bounds__(256)
+k_col_fwd_A(Geo g, const double2* __restrict__ tw, const double* __restrict__ X, int64_t ldx,
+            int64_t nvec, int64_t pair0, double2* __restrict__ ws1, int C) {
+  constexpr int T = Col<N1>::T;
+  extern __shared__ double2 smem[];
+  const ColLds lds{smem, C};
+  const int l = threadIdx.x % C, t = threadIdx.x / C;
+  const int64_t b = (int64_t)blockIdx.x * C + l;
+  const int64_t pair = blockIdx.y;
+  const int64_t v0 = 2 * (pair0 + pair);
+  double2 a[RADIX];
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) a[m] = load_pair(X, ldx, (int64_t)(t + m * T) * g.N2 + b, v0, nvec);
+  fft_line<N1, false>(a, lds, l, t, tw);
+  double2* out = ws1 + pair * g.N;
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) {
+    const int64_t k1 = t + m * T;
+    double2 v = a[m];
+    if (TWID) v = cmul(v, tw_fwd(tw, k1 * b, g.N));
+    out[k1 * g.N2 + b] = v;
+  }
+}
+
+// P2 of A: row DFT, product with each phase's spectrum, row IDFT.
+template <int N2, bool TWID>
+__global__ void __launch_bounds__(256)
+k_row_A(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws1,
+        double2* __restrict__ ws2, int LINES) {
+  constexpr int T = Row<N2>::T;
+  extern __shared__ double2 smem[];
+  const RowLds lds{smem, RowLds::stride(N2)};
+  const int t = threadIdx.x % T, l = threadIdx.x / T;
+  const int64_t k1 = (int64_t)blockIdx.x * LINES + l;
+  const int64_t pair = blockIdx.y;
+  const int nph = g.dim == 1 ? g.s : g.s * g.s;
+  double2 a[RADIX];
+  const double2* in = ws1 + pair * g.N + k1 * N2;
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) a[m] = in[t + m * T];
+  fft_line<N2, false>(a, lds, l, t, tw);
+  for (int ph = 0; ph < nph; ++ph) {
+    double2 b[RADIX];
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) b[m] = cmul(a[m], specA(g, ph, (int)k1, t + m * T));
+    fft_line<N2, true>(b, lds, l, t, tw);
+    double2* out = ws2 + (pair * nph + ph) * g.N + k1 * N2;
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) {
+      double2 v = b[m];
+      if (TWID) v = cmulc(v, tw_fwd(tw, k1 * (t + m * T), g.N));
+      out[t + m * T] = v;
+    }
+  }
+}
+
+// P3 of A: column IDFT of every phase, restriction to collocation rows.
+template <int N1>
+__global__ void __launch_bounds__(256)
+k_col_inv_A(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws2, int64_t nvec,
+            int64_t pair0, double alpha, double beta, double* __restrict__ Y, int64_t ldy, int C) {
+  constexpr int T = Col<N1>::T;
+  extern __shared__ double2 smem[];
+  const ColLds lds{smem, C};
+  const int l = threadIdx.x % C, t = threadIdx.x / C;
+  const int64_t b = (int64_t)blockIdx.x * C + l;
+  const int64_t pair = blockIdx.y;
+  const int64_t v0 = 2 * (pair0 + pair);
+  const int nph = g.dim == 1 ? g.s : g.s * g.s;
+  for (int ph = 0; ph < nph; ++ph) {
+    double2 a[RADIX];
+    const double2* in = ws2 + (pair * nph + ph) * g.N;
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) a[m] = in[(int64_t)(t + m * T) * g.N2 + b];
+    fft_line<N1, true>(a, lds, l, t, tw);
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) {
+      const int64_t row = row_of(g, grid_index(g, ph, t + m * T, b));
+      if (row >= 0) store_pair(Y, ldy, row, v0, nvec, a[m], alpha, beta);
+    }
+  }
+}
+
+// P1 of Z*: extension by zero to each phase grid, column DFT, twiddle.
+template <int N1, bool TWID>
+__global__ void __launch_bounds__(256)
+k_col_fwd_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R, int64_t ldr,
+            int64_t nvec, int64_t pair0, double2* __restrict__ ws1, int C) {
+  constexpr int T = Col<N1>::T;
+  extern __shared__ double2 smem[];
+  const ColLds lds{smem, C};
+  const int l = threadIdx.x % C, t = threadIdx.x / C;
+  const int64_t b = (int64_t)blockIdx.x * C + l;
+  const int64_t pair = blockIdx.y;
+  const int64_t v0 = 2 * (pair0 + pair);
+  const int nph = g.dim == 1 ? g.s : g.s * g.s;
+  for (int ph = 0; ph < nph; ++ph) {
+    double2 a[RADIX];
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) {
+      const int64_t row = row_of(g, grid_index(g, ph, t + m * T, b));
+      a[m] = row >= 0 ? load_pair(R, ldr, row, v0, nvec) : make_double2(0.0, 0.0);
+    }
+    fft_line<N1, false>(a, lds, l, t, tw);
+    double2* out = ws1 + (pair * nph + ph) * g.N;
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) {
+      const int64_t k1 = t + m * T;
+      double2 v = a[m];
+      if (TWID) v = cmul(v, tw_fwd(tw, k1 * b, g.N));
+      out[k1 * g.N2 + b] = v;
+    }
+  }
+}
+
+// P2 of Z*: row DFT of each phase, sum of products with w conj(d_r), row IDFT.
+template <int N2, bool TWID>
+__global__ void __launch_bounds__(256)
+k_row_Z(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws1,
+        double2* __restrict__ ws2, int LINES) {
+  constexpr int T = Row<N2>::T;
+  extern __shared__ double2 smem[];
+  const RowLds lds{smem, RowLds::stride(N2)};
+  const int t = threadIdx.x % T, l = threadIdx.x / T;
+  const int64_t k1 = (int64_t)blockIdx.x * LINES + l;
+  const int64_t pair = blockIdx.y;
+  const int nph = g.dim == 1 ? g.s : g.s * g.s;
+  double2 acc[RADIX];
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) acc[m] = make_double2(0.0, 0.0);
+  for (int ph = 0; ph < nph; ++ph) {
+    double2 a[RADIX];
+    const double2* in = ws1 + (pair * nph + ph) * g.N + k1 * N2;
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) a[m] = in[t + m * T];
+    fft_line<N2, false>(a, lds, l, t, tw);
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) acc[m] = cadd(acc[m], cmul(a[m], specZ(g, ph, (int)k1, t + m * T)));
+  }
+  fft_line<N2, true>(acc, lds, l, t, tw);
+  double2* out = ws2 + pair * g.N + k1 * N2;
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) {
+    double2 v = acc[m];
+    if (TWID) v = cmulc(v, tw_fwd(tw, k1 * (t + m * T), g.N));
+    out[t + m * T] = v;
+  }
+}
+
+// P3 of Z*: column IDFT, coefficients out.
+template <int N1>
+__global__ void __launch_bounds__(256)
+k_col_inv_Z(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws2, int64_t nvec,
+            int64_t pair0, double alpha, double beta, double* __restrict__ Z, int64_t ldz, int C) {
+  constexpr int T = Col<N1>::T;
+  extern __shared__ double2 smem[];
+  const ColLds lds{smem, C};
+  const int l = threadIdx.x % C, t = threadIdx.x / C;
+  const int64_t b = (int64_t)blockIdx.x * C + l;
+  const int64_t pair = blockIdx.y;
+  const int64_t v0 = 2 * (pair0 + pair);
+  double2 a[RADIX];
+  const double2* in = ws2 + pair * g.N;
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) a[m] = in[(int64_t)(t + m * T) * g.N2 + b];
+  fft_line<N1, true>(a, lds, l, t, tw);
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) store_pair(Z, ldz, (int64_t)(t + m * T) * g.N2 + b, v0, nvec, a[m], alpha, beta);
+}
+
+// Plain forward FFT of complex N1 x N2 arrays in the engine's layout (spectra set-up):
+// column pass (with twiddle) then row pass; output in transposed frequency order.
+template <int N1, bool TWID>
+__global__ void __launch_bounds__(256)
+k_col_fwd_C(Geo g, const double2* __restrict__ tw, const double2* __restrict__ in,
+            double2* __restrict__ out, int C) {
+  constexpr int T = Col<N1>::T;
+  extern __shared__ double2 smem[];
+  const ColLds lds{smem, C};
+  const int l = threadIdx.x % C, t = threadIdx.x / C;
+  const int64_t b = (int64_t)blockIdx.x * C + l;
+  const int64_t line = blockIdx.y;
+  double2 a[RADIX];
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) a[m] = in[line * g.N + (int64_t)(t + m * T) * g.N2 + b];
+  fft_line<N1, false>(a, lds, l, t, tw);
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) {
+    const int64_t k1 = t + m * T;
+    double2 v = a[m];
+    if (TWID) v = cmul(v, tw_fwd(tw, k1 * b, g.N));
+    out[line * g.N + k1 * g.N2 + b] = v;
+  }
+}
+
+template <int N2>
+__global__ void __launch_bounds__(256)
+k_row_fwd_C(Geo g, const double2* __restrict__ tw, double2* __restrict__ data, int LINES) {
+  constexpr int T = Row<N2>::T;
+  extern __shared__ double2 smem[];
+  const RowLds lds{smem, RowLds::stride(N2)};
+  const int t = threadIdx.x % T, l = threadIdx.x / T;
+  const int64_t k1 = (int64_t)blockIdx.x * LINES + l;
+  double2* p = data + (int64_t)blockIdx.y * g.N + k1 * N2;
+  double2 a[RADIX];
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) a[m] = p[t + m * T];
+  fft_line<N2, false>(a, lds, l, t, tw);
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) p[t + m * T] = a[m];
+}
+
+// ------------------------------------------------------------------ boundary rows
+
+// Y[M + i] = alpha * bweight * sum_j phi_j(x_b) X[j] + beta * Y[M + i]:
+// direct summation over the centres within the Gaussian's numerical support
+// (phi < 1e-20), periodized images included.
+__device__ __forceinline__ double phi_per_dev(double d, double eps, double T, int mimg) {
+  double s = 0.0;
+  for (int m = -mimg; m <= mimg; ++m) {
+    const double x = eps * (d - 2.0 * T * m);
+    s += exp(-x * x);
+  }
+  return s;
+}
+
+__global__ void k_boundary_A(int dim, int n, double T, double h, double eps, int mimg, int W,
+                             const double* __restrict__ bp, int64_t Mb, double bw, const double* __restrict__ X,
+                             int64_t ldx, int64_t nvec, double alpha, double beta, double* __restrict__ Y,
+                             int64_t ldy, int64_t M) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t v = blockIdx.y;
+  if (i >= Mb || v >= nvec) return;
+  const int nw = 2 * W + 2 < n ? 2 * W + 2 : n;
+  double wx[64], wy[64];
+  int jx0, jy0 = 0;
+  {
+    const double x = bp[i * dim];
+    jx0 = (int)floor((x + T) / h) - W;
+    for (int o = 0; o < nw; ++o) {
+      const int j = ((jx0 + o) % n + n) % n;
+      double d = x - (-T + j * h);
+      d -= 2.0 * T * nearbyint(d / (2.0 * T));
+      wx[o] = phi_per_dev(d, eps, T, mimg);
+    }
+  }
+  if (dim == 2) {
+    const double y = bp[i * dim + 1];
+    jy0 = (int)floor((y + T) / h) - W;
+    for (int o = 0; o < nw; ++o) {
+      const int j = ((jy0 + o) % n + n) % n;
+      double d = y - (-T + j * h);
+      d -= 2.0 * T * nearbyint(d / (2.0 * T));
+      wy[o] = phi_per_dev(d, eps, T, mimg);
+    }
+  }
+  const double* x = X + ldx * v;
+  double acc = 0.0;
+  if (dim == 1) {
+    for (int o = 0; o < nw; ++o) acc = fma(wx[o], x[((jx0 + o) % n + n) % n], acc);
+  } else {
+    for (int ox = 0; ox < nw; ++ox) {
+      const int jx = ((jx0 + ox) % n + n) % n;
+      double r = 0.0;
+      for (int oy = 0; oy < nw; ++oy) r = fma(wy[oy], x[(int64_t)jx * n + ((jy0 + oy) % n + n) % n], r);
+      acc = fma(wx[ox], r, acc);
+    }
+  }
+  double* y = Y + M + i + ldy * v;
+  *y = beta == 0.0 ? alpha * bw * acc : fma(alpha * bw, acc, beta * *y);
+}
+
+// ------------------------------------------------------------------ spectra set-up
+
+// Kernel phi (which = 0) or phi'' (which = 1) sampled at m * hL, m = 0..L-1,
+// split into s phases: out[r * n + j] = k[s j + r].
+__global__ void k_sample_phases(double2* out, int n, int s, double hL, double eps, double T, int mimg,
+                                int which) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * s) return;
+  const int r = (int)(i / n), j = (int)(i % n);
+  double x = ((int64_t)s * j + r) * hL;
+  if (x >= T) x -= 2.0 * T;
+  double v = 0.0;
+  const double e2 = eps * eps;
+  for (int m = -mimg; m <= mimg; ++m) {
+    const double d = x - 2.0 * T * m;
+    const double g = exp(-e2 * d * d);
+    v += which == 0 ? g : -2.0 * e2 * g * (1.0 - 2.0 * e2 * d * d);
+  }
+  out[i] = make_double2(v, 0.0);
+}
+
+__device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
+  atomicMax((unsigned long long*)addr, (unsigned long long)__double_as_longlong(v));
+}
+
+// 1D: combine kernel spectra into d_r (BVP: opscale (d2 + k2 d0)), D = sum |d_r|^2.
+__global__ void k_combine_1d(double2* d, const double2* d2, int64_t N, int s, int op, double k2,
+                             double opscale, double* D, double* dmax) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double acc = 0.0;
+  for (int r = 0; r < s; ++r) {
+    double2 v = d[(int64_t)r * N + i];
+    if (op != AZRBF_OP_APPROX) {
+      v = cscale(cadd(d2[(int64_t)r * N + i], cscale(v, k2)), opscale);
+      d[(int64_t)r * N + i] = v;
+    }
+    acc += v.x * v.x + v.y * v.y;
+  }
+  D[i] = acc;
+  atomic_max_nonneg(dmax, acc);
+}
+
+__global__ void k_weights_1d(const double2* d, double2* spA, double2* spZ, const double* D, int64_t N,
+                             int s, double tauZ, const double* dmax, double* wmax, int* zeroed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double Dv = D[i];
+  const bool keep = Dv > tauZ * *dmax;
+  const double w = keep ? 1.0 / Dv : 0.0;
+  if (!keep) atomicAdd(zeroed, 1);
+  else atomic_max_nonneg(wmax, w);
+  const double inv = 1.0 / (double)N;
+  for (int r = 0; r < s; ++r) {
+    const double2 v = d[(int64_t)r * N + i];
+    spA[(int64_t)r * N + i] = cscale(v, inv);
+    spZ[(int64_t)r * N + i] = cscale(cconj(v), w * inv);
+  }
+}
+
+__global__ void k_D_2d(Geo g, double* D, double* dmax) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  const int ka = (int)(i / g.N2), kb = (int)(i % g.N2);
+  double acc = 0.0;
+  for (int ph = 0; ph < g.s * g.s; ++ph) {
+    const double2 v = spec2d(g, ph, ka, kb);
+    acc += v.x * v.x + v.y * v.y;
+  }
+  D[i] = acc;
+  atomic_max_nonneg(dmax, acc);
+}
+
+__global__ void k_weights_2d(double* w2, const double* D, int64_t N, double tauZ, const double* dmax,
+                             double* wmax, int* zeroed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double Dv = D[i];
+  const bool keep = Dv > tauZ * *dmax;
+  const double w = keep ? 1.0 / Dv : 0.0;
+  if (!keep) atomicAdd(zeroed, 1);
+  else atomic_max_nonneg(wmax, w);
+  w2[i] = w / (double)N;
+}
+
+// ------------------------------------------------------------------ dispatch
+
+template <class K>
+static int set_lds(K kern, int bytes) {
+  if (bytes > 64 * 1024) {
+    if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) !=
+        hipSuccess)
+      return AZRBF_EHIP;
+  }
+  return AZRBF_OK;
+}
+
+#define AZ_SWITCH_N(n, F, ...)                                                     \
+  switch (n) {                                                                     \
+    case 16: return F<16>(__VA_ARGS__);                                            \
+    case 32: return F<32>(__VA_ARGS__);                                            \
+    case 64: return F<64>(__VA_ARGS__);                                            \
+    case 128: return F<128>(__VA_ARGS__);                                          \
+    case 256: return F<256>(__VA_ARGS__);                                          \
+    case 512: return F<512>(__VA_ARGS__);                                          \
+    case 1024: return F<1024>(__VA_ARGS__);                                        \
+    case 2048: return F<2048>(__VA_ARGS__);                                        \
+    case 4096: return F<4096>(__VA_ARGS__);                                        \
+    case 8192: return F<8192>(__VA_ARGS__);                                        \
+    default: return AZRBF_EUNSUPPORTED;                                            \
+  }
+
+#define AZ_SWITCH_ENGINE(n, F, ...)                                                \
+  switch (n) {                                                                     \
+    case 16: return F<16>(__VA_ARGS__);                                            \
+    case 32: return F<32>(__VA_ARGS__);                                            \
+    case 64: return F<64>(__VA_ARGS__);                                            \
+    case 128: return F<128>(__VA_ARGS__);                                          \
+    case 256: return F<256>(__VA_ARGS__);                                          \
+    case 512: return F<512>(__VA_ARGS__);                                          \
+    default: return AZRBF_EUNSUPPORTED;                                            \
+  }
+
+template <int N>
+static int launch_fused_A(const Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha,
+                          double beta, double* Y, int64_t ldy, hipStream_t st) {
+  using F = Fused<N>;
+  AZ_TRY(set_lds(k_fused_A<N>, F::LDS));
+  const int64_t npairs = (nvec + 1) / 2;
+  const int64_t blocks = (npairs + F::LINES - 1) / F::LINES;
+  static const std::string name = "fused_A n=" + std::to_string(N);
+  Prof pr(name.c_str(), 8.0 * nvec * (N + P.M * (beta != 0.0 ? 2.0 : 1.0)) + 16.0 * P.s * N, st);
+  k_fused_A<N><<<dim3((unsigned)blocks), dim3(F::BLOCK), F::LDS, st>>>(P.geo, P.tw, X, ldx, nvec, alpha,
+                                                                       beta, Y, ldy);
+  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+}
+
+template <int N>
+static int launch_fused_Z(const Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha,
+                          double beta, double* Z, int64_t ldz, hipStream_t st) {
+  using F = Fused<N>;
+  AZ_TRY(set_lds(k_fused_Z<N>, F::LDS));
+  const int64_t npairs = (nvec + 1) / 2;
+  const int64_t blocks = (npairs + F::LINES - 1) / F::LINES;
+  static const std::string name = "fused_Z n=" + std::to_string(N);
+  Prof pr(name.c_str(), 8.0 * nvec * (P.M + N * (beta != 0.0 ? 2.0 : 1.0)) + 16.0 * P.s * N, st);
+  k_fused_Z<N><<<dim3((unsigned)blocks), dim3(F::BLOCK), F::LDS, st>>>(P.geo, P.tw, R, ldr, nvec, alpha,
+                                                                       beta, Z, ldz);
+  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+}
+
+template <int N>
+static int launch_fused_fwd(const double2* tw, const double2* in, double2* out, int64_t lines,
+                            hipStream_t st) {
+  using F = Fused<N>;
+  AZ_TRY(set_lds(k_fused_fwd<N>, F::LDS));
+  const int64_t blocks = (lines + F::LINES - 1) / F::LINES;
+  k_fused_fwd<N><<<dim3((unsigned)blocks), dim3(F::BLOCK), F::LDS, st>>>(tw, in, out, lines);
+  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+}
+
+static int col_C(int N1, int N2) {
+  const int T = N1 / RADIX;
+  int C = T >= 256 ? 1 : 256 / T;
+  return C > N2 ? N2 : C;
+}
+static int row_L(int N1, int N2) {
+  const int T = N2 / RADIX;
+  int Lr = T >= 256 ? 1 : 256 / T;
+  return Lr > N1 ? N1 : Lr;
+}
+
+// Column-pass launchers (template on the column length N1).
+struct ColArgs {
+  const Plan* P;
+  int mode;                 // 0 fwd A, 1 inv A, 2 fwd Z, 3 inv Z, 4 fwd complex
+  const double* in;
+  int64_t ldi;
+  const double2* cin;
+  double2* cout;
+  int64_t nvec, pair0, npairs;
+  double alpha, beta;
+  double* out;
+  int64_t ldo;
+  hipStream_t st;
+};
+
+template <int N1>
+static int launch_col(const ColArgs& a) {
+  const Plan& P = *a.P;
+  const Geo& g = P.geo;
+  const int C = col_C(g.N1, g.N2);
+  const int block = C * Col<N1>::T;
+  const int lds = C * N1 * (int)sizeof(double2);
+  const dim3 grid((unsigned)(g.N2 / C), (unsigned)a.npairs);
+  const bool tw4 = g.dim == 1;
+  static const char* names[5] = {"col_fwd_A", "col_inv_A", "col_fwd_Z", "col_inv_Z", "col_fwd_C"};
+  static std::string full[5];
+  if (full[a.mode].empty()) full[a.mode] = std::string(names[a.mode]) + " n1=" + std::to_string(N1);
+  const double vc = (double)std::min<int64_t>(a.nvec - 2 * a.pair0, 2 * a.npairs);
+  const double cN = 16.0 * (double)g.N * (double)a.npairs;   // one complex array per pair
+  const double bmul = a.beta != 0.0 ? 2.0 : 1.0;
+  double bytes = 0;
+  switch (a.mode) {
+    case 0: bytes = 8.0 * g.N * vc + cN; break;
+    case 1: bytes = cN * P.ph + 8.0 * g.M * vc * bmul; break;
+    case 2: bytes = 8.0 * g.M * vc + (g.dim == 2 ? 4.0 * (double)P.Lg : 0.0) + cN * P.ph; break;
+    case 3: bytes = cN + 8.0 * g.N * vc * bmul; break;
+    default: bytes = 2.0 * cN; break;
+  }
+  Prof pr(full[a.mode].c_str(), bytes, a.st);
+  switch (a.mode) {
+    case 0:
+      if (tw4) {
+        AZ_TRY(set_lds(k_col_fwd_A<N1, true>, lds));
+        k_col_fwd_A<N1, true><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.ldi, a.nvec, a.pair0, a.cout, C);
+      } else {
+        AZ_TRY(set_lds(k_col_fwd_A<N1, false>, lds));
+        k_col_fwd_A<N1, false><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.ldi, a.nvec, a.pair0, a.cout, C);
+      }
+      break;
+    case 1:
+      AZ_TRY(set_lds(k_col_inv_A<N1>, lds));
+      k_col_inv_A<N1><<<grid, block, lds, a.st>>>(g, P.tw, a.cin, a.nvec, a.pair0, a.alpha, a.beta, a.out,
+                                                  a.ldo, C);
+      break;
+    case 2:
+      if (tw4) {
+        AZ_TRY(set_lds(k_col_fwd_Z<N1, true>, lds));
+        k_col_fwd_Z<N1, true><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.ldi, a.nvec, a.pair0, a.cout, C);
+      } else {
+        AZ_TRY(set_lds(k_col_fwd_Z<N1, false>, lds));
+        k_col_fwd_Z<N1, false><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.ldi, a.nvec, a.pair0, a.cout, C);
+      }
+      break;
+    case 3:
+      AZ_TRY(set_lds(k_col_inv_Z<N1>, lds));
+      k_col_inv_Z<N1><<<grid, block, lds, a.st>>>(g, P.tw, a.cin, a.nvec, a.pair0, a.alpha, a.beta, a.out,
+                                                  a.ldo, C);
+      break;
+    case 4:
+      if (tw4) {
+        AZ_TRY(set_lds(k_col_fwd_C<N1, true>, lds));
+        k_col_fwd_C<N1, true><<<grid, block, lds, a.st>>>(g, P.tw, a.cin, a.cout, C);
+      } else {
+        AZ_TRY(set_lds(k_col_fwd_C<N1, false>, lds));
+        k_col_fwd_C<N1, false><<<grid, block, lds, a.st>>>(g, P.tw, a.cin, a.cout, C);
+      }
+      break;
+  }
+  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+}
+
+struct RowArgs {
+  const Plan* P;
+  int mode;                 // 0 A, 1 Z, 2 fwd complex in place
+  const double2* in;
+  double2* out;
+  int64_t npairs;
+  hipStream_t st;
+};
+
+template <int N2>
+static int launch_row(const RowArgs& a) {
+  const Plan& P = *a.P;
+  const Geo& g = P.geo;
+  const int Lr = row_L(g.N1, g.N2);
+  const int block = Lr * Row<N2>::T;
+  const int lds = Lr * RowLds::stride(N2) * (int)sizeof(double2);
+  const dim3 grid((unsigned)(g.N1 / Lr), (unsigned)a.npairs);
+  const bool tw4 = g.dim == 1;
+  static const char* names[3] = {"row_A", "row_Z", "row_fwd_C"};
+  static std::string full[3];
+  if (full[a.mode].empty()) full[a.mode] = std::string(names[a.mode]) + " n2=" + std::to_string(N2);
+  const double cN = 16.0 * (double)g.N * (double)a.npairs;
+  const double spec = g.dim == 1 ? 16.0 * (double)g.N * P.s : 0.0;
+  const double bytes = a.mode == 2 ? 2.0 * cN : cN * (1.0 + P.ph) + spec;
+  Prof pr(full[a.mode].c_str(), bytes, a.st);
+  switch (a.mode) {
+    case 0:
+      if (tw4) {
+        AZ_TRY(set_lds(k_row_A<N2, true>, lds));
+        k_row_A<N2, true><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.out, Lr);
+      } else {
+        AZ_TRY(set_lds(k_row_A<N2, false>, lds));
+        k_row_A<N2, false><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.out, Lr);
+      }
+      break;
+    case 1:
+      if (tw4) {
+        AZ_TRY(set_lds(k_row_Z<N2, true>, lds));
+        k_row_Z<N2, true><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.out, Lr);
+      } else {
+        AZ_TRY(set_lds(k_row_Z<N2, false>, lds));
+        k_row_Z<N2, false><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.out, Lr);
+      }
+      break;
+    case 2:
+      AZ_TRY(set_lds(k_row_fwd_C<N2>, lds));
+      k_row_fwd_C<N2><<<grid, block, lds, a.st>>>(g, P.tw, a.out, Lr);
+      break;
+  }
+  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+}
+
+static int run_col(const ColArgs& a) { AZ_SWITCH_ENGINE(a.P->geo.N1, launch_col, a) }
+static int run_row(const RowArgs& a) { AZ_SWITCH_ENGINE(a.P->geo.N2, launch_row, a) }
+
+static int ensure_ws(Plan& P, int64_t pairs) {
+  if (pairs <= P.ws_pairs) return AZRBF_OK;
+  const int64_t per = (int64_t)P.ph * P.N * (int64_t)sizeof(double2);
+  void *a = nullptr, *b = nullptr;
+  AZ_TRY(P.alloc(&a, per * pairs));
+  AZ_TRY(P.alloc(&b, per * pairs));
+  P.ws1 = (double2*)a;
+  P.ws2 = (double2*)b;
+  P.ws_pairs = pairs;
+  return AZRBF_OK;
+}
+
+// Pairs per engine chunk: about 64 MiB of each workspace buffer.
+static int64_t engine_chunk(const Plan& P, int64_t npairs) {
+  const int64_t per = (int64_t)P.ph * P.N * (int64_t)sizeof(double2);
+  int64_t c = ((int64_t)64 << 20) / per;
+  if (c < 1) c = 1;
+  if (c > 64) c = 64;
+  return npairs < c ? npairs : c;
+}
+
+static int boundary_rows(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta,
+                         double* Y, int64_t ldy, hipStream_t st) {
+  if (P.Mb == 0) return AZRBF_OK;
+  const int mimg = (int)ceil(6.8 / (2.0 * P.eps * P.T)) + 2;
+  const int W = (int)ceil(6.8 / (P.eps * P.h)) + 1;
+  const int nw = 2 * W + 2 < P.n ? 2 * W + 2 : P.n;   // window length, must fit k_boundary_A's arrays
+  if (nw > 64) return AZRBF_EUNSUPPORTED;
+  const dim3 grid((unsigned)((P.Mb + 127) / 128), (unsigned)nvec);
+  Prof pr("boundary_A", 8.0 * (double)P.Mb * nvec * (beta != 0.0 ? 2.0 : 1.0), st);
+  k_boundary_A<<<grid, 128, 0, st>>>(P.dim, P.n, P.T, P.h, P.eps, mimg, W, P.bpts, P.Mb, P.bweight, X, ldx,
+                                     nvec, alpha, beta, Y, ldy, P.M);
+  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+}
+
+static int fused_A(const Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta,
+                   double* Y, int64_t ldy, hipStream_t st) {
+  AZ_SWITCH_N(P.n, launch_fused_A, P, X, ldx, nvec, alpha, beta, Y, ldy, st)
+}
+
+int ops_apply_A(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta, double* Y,
+                int64_t ldy, hipStream_t st) {
+  if (nvec <= 0) return AZRBF_OK;
+  if (P.fused) {
+    AZ_TRY(fused_A(P, X, ldx, nvec, alpha, beta, Y, ldy, st));
+    return boundary_rows(P, X, ldx, nvec, alpha, beta, Y, ldy, st);
+  }
+  const int64_t npairs = (nvec + 1) / 2;
+  const int64_t chunk = engine_chunk(P, npairs);
+  AZ_TRY(ensure_ws(P, chunk));
+  for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
+    const int64_t np = npairs - p0 < chunk ? npairs - p0 : chunk;
+    ColArgs c1{&P, 0, X, ldx, nullptr, P.ws1, nvec, p0, np, 0, 0, nullptr, 0, st};
+    AZ_TRY(run_col(c1));
+    RowArgs r{&P, 0, P.ws1, P.ws2, np, st};
+    AZ_TRY(run_row(r));
+    ColArgs c3{&P, 1, nullptr, 0, P.ws2, nullptr, nvec, p0, np, alpha, beta, Y, ldy, st};
+    AZ_TRY(run_col(c3));
+  }
+  return boundary_rows(P, X, ldx, nvec, alpha, beta, Y, ldy, st);
+}
+
+// Boundary rows of the result are ignored (Z* has zero columns there).
+int ops_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta, double* Z,
+                int64_t ldz, hipStream_t st) {
+  if (nvec <= 0) return AZRBF_OK;
+  if (P.fused) {
+    AZ_SWITCH_N(P.n, launch_fused_Z, P, R, ldr, nvec, alpha, beta, Z, ldz, st)
+  }
+  const int64_t npairs = (nvec + 1) / 2;
+  const int64_t chunk = engine_chunk(P, npairs);
+  AZ_TRY(ensure_ws(P, chunk));
+  for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
+    const int64_t np = npairs - p0 < chunk ? npairs - p0 : chunk;
+    ColArgs c1{&P, 2, R, ldr, nullptr, P.ws1, nvec, p0, np, 0, 0, nullptr, 0, st};
+    AZ_TRY(run_col(c1));
+    RowArgs r{&P, 1, P.ws1, P.ws2, np, st};
+    AZ_TRY(run_row(r));
+    ColArgs c3{&P, 3, nullptr, 0, P.ws2, nullptr, nvec, p0, np, alpha, beta, Z, ldz, st};
+    AZ_TRY(run_col(c3));
+  }
+  return AZRBF_OK;
+}
+
+// ------------------------------------------------------------------ spectra
+
+static int fft_lines_fwd(Plan& P, const double2* in, double2* out, int n, int64_t lines, bool engine,
+                         hipStream_t st) {
+  if (!engine) { AZ_SWITCH_N(n, launch_fused_fwd, P.tw, in, out, lines, st) }
+  ColArgs c{&P, 4, nullptr, 0, in, out, 0, 0, lines, 0, 0, nullptr, 0, st};
+  AZ_TRY(run_col(c));
+  RowArgs r{&P, 2, nullptr, out, lines, st};
+  return run_row(r);
+}
+
+int ops_spectra(Plan& P, hipStream_t st) {
+  const int n = P.n, s = P.s;
+  const int mimg = (int)ceil(6.8 / (2.0 * P.eps * P.T)) + 2;
+  const bool bvp = P.prob.op != AZRBF_OP_APPROX;
+  const int nk = bvp ? 2 : 1;
+  // samples of phi (and phi'') on the s shifted 1D grids, then their DFTs
+  double2 *samp = nullptr, *fac = nullptr;
+  AZ_TRY(P.alloc((void**)&samp, (int64_t)nk * s * n * sizeof(double2)));
+  AZ_TRY(P.alloc((void**)&fac, (int64_t)nk * s * n * sizeof(double2)));
+  double* red = nullptr;   // [dmax, wmax, zeroed(int)]
+  AZ_TRY(P.alloc((void**)&red, 4 * sizeof(double)));
+  AZ_HIP(hipMemsetAsync(red, 0, 4 * sizeof(double), st));
+  const int64_t ns = (int64_t)n * s;
+  for (int which = 0; which < nk; ++which) {
+    k_sample_phases<<<(unsigned)((ns + 255) / 256), 256, 0, st>>>(samp + which * ns, n, s, P.hL, P.eps, P.T,
+                                                                  mimg, which);
+    AZ_HIP(hipGetLastError());
+  }
+  const bool engine = P.dim == 1 && !P.fused;
+  AZ_TRY(fft_lines_fwd(P, samp, fac, n, (int64_t)nk * s, engine, st));
+  double* D = nullptr;
+  AZ_TRY(P.alloc((void**)&D, P.N * sizeof(double)));
+  int* zeroed = (int*)(red + 2);
+  if (P.dim == 1) {
+    const double opscale = -1.0 / (2.0 * P.eps * P.eps);
+    AZ_TRY(P.alloc((void**)&P.spA, (int64_t)s * P.N * sizeof(double2)));
+    AZ_TRY(P.alloc((void**)&P.spZ, (int64_t)s * P.N * sizeof(double2)));
+    const unsigned nb = (unsigned)((P.N + 255) / 256);
+    k_combine_1d<<<nb, 256, 0, st>>>(fac, bvp ? fac + ns : nullptr, P.N, s, P.prob.op, P.prob.k2, opscale, D,
+                                     red);
+    AZ_HIP(hipGetLastError());
+    k_weights_1d<<<nb, 256, 0, st>>>(fac, P.spA, P.spZ, D, P.N, s, P.tauZ, red, red + 1, zeroed);
+    AZ_HIP(hipGetLastError());
+    P.geo.spA = P.spA;
+    P.geo.spZ = P.spZ;
+  } else {
+    P.fac = fac;
+    P.geo.fac = fac;
+    AZ_TRY(P.alloc((void**)&P.w2, P.N * sizeof(double)));
+    const unsigned nb = (unsigned)((P.N + 255) / 256);
+    k_D_2d<<<nb, 256, 0, st>>>(P.geo, D, red);
+    AZ_HIP(hipGetLastError());
+    k_weights_2d<<<nb, 256, 0, st>>>(P.w2, D, P.N, P.tauZ, red, red + 1, zeroed);
+    AZ_HIP(hipGetLastError());
+    P.geo.w2 = P.w2;
+  }
+  double hred[4];
+  AZ_HIP(hipMemcpyAsync(hred, red, sizeof(hred), hipMemcpyDeviceToHost, st));
+  AZ_HIP(hipStreamSynchronize(st));
+  P.normA = sqrt(hred[0] / (P.dim == 1 ? 1.0 : 1.0));
+  P.normZ = sqrt(hred[1]);
+  int z;
+  std::memcpy(&z, &hred[2], sizeof(int));
+  P.zeroed = z;
+  return AZRBF_OK;
+}
+
+}  // namespace az

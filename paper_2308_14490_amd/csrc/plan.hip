@@ -1,0 +1,404 @@
+// C ABI of the azrbf library: plans, operators, factor and solve.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+struct azrbf_plan_s {
+  az::Plan p;
+};
+
+namespace az {
+
+int Plan::alloc(void** ptr, int64_t nbytes) {
+  *ptr = nullptr;
+  if (nbytes <= 0) nbytes = 8;
+  if (hipMalloc(ptr, (size_t)nbytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return AZRBF_ENOMEM;
+  }
+  allocs.push_back(*ptr);
+  bytes += nbytes;
+  return AZRBF_OK;
+}
+
+void Plan::release() {
+  for (void* q : allocs) (void)hipFree(q);
+  allocs.clear();
+  bytes = 0;
+}
+
+// ------------------------------------------------------------------ per-launch timing
+
+namespace {
+struct ProfRec {
+  std::string name;
+  double bytes;
+  hipEvent_t a, b;
+  bool done;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_prof_pool;
+
+hipEvent_t pool_get() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+bool prof_enabled() { return g_prof_on; }
+
+int prof_begin(hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  ProfRec r{std::string(), 0.0, pool_get(), pool_get(), false};
+  if (!r.a || !r.b) return -1;
+  (void)hipEventRecord(r.a, st);
+  g_prof.push_back(r);
+  return (int)g_prof.size() - 1;
+}
+
+void prof_end(int slot, const char* name, double bytes, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (slot < 0 || slot >= (int)g_prof.size()) return;
+  ProfRec& r = g_prof[slot];
+  r.name = name;
+  r.bytes = bytes;
+  r.done = true;
+  (void)hipEventRecord(r.b, st);
+}
+
+static bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static int default_k(const azrbf_problem& pr) {
+  if (pr.k > 0) return pr.k;
+  return 32;
+}
+
+// Four-step split of a 1D transform of length N > 8192 (or forced): N = N1 * N2.
+static void split_1d(int64_t N, int* N1, int* N2) {
+  int lg = 0;
+  while ((1LL << lg) < N) ++lg;
+  int l2 = (lg + 1) / 2;
+  if (l2 > 9) l2 = 9;
+  if (lg - l2 > 9) l2 = lg - 9;
+  *N2 = 1 << l2;
+  *N1 = (int)(N >> l2);
+}
+
+}  // namespace az
+
+using az::Plan;
+
+extern "C" {
+
+const char* azrbf_strerror(int code) {
+  switch (code) {
+    case AZRBF_OK: return "ok";
+    case AZRBF_EINVAL: return "invalid argument";
+    case AZRBF_EUNSUPPORTED: return "unsupported problem size or option";
+    case AZRBF_ENOMEM: return "device memory allocation failed";
+    case AZRBF_EHIP: return "HIP runtime error";
+    case AZRBF_ERANK: return "sketch not rank-revealing: all sketch directions retained";
+    case AZRBF_ESTATE: return "call not valid in the plan's state";
+    default: return "unknown error";
+  }
+}
+
+int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
+  if (!pr || !out) return AZRBF_EINVAL;
+  *out = nullptr;
+  const azrbf_problem& q = *pr;
+  if (q.dim != 1 && q.dim != 2) return AZRBF_EINVAL;
+  if (!(q.T > 0) || !q.mask || q.n <= 0 || q.s <= 0) return AZRBF_EINVAL;
+  if (q.op != AZRBF_OP_APPROX && q.op != AZRBF_OP_BVP) return AZRBF_EINVAL;
+  if (q.nb < 0 || (q.nb > 0 && (!q.bpts || q.op != AZRBF_OP_BVP))) return AZRBF_EINVAL;
+  if (!(q.tau > 0) || q.tauZ < 0 || q.refine < 0 || q.refine > 8 || q.k < 0) return AZRBF_EINVAL;
+  if (q.eps <= 0 && !(q.tau0 > 0 && q.tau0 < 1)) return AZRBF_EINVAL;
+  if (!az::pow2(q.n) || q.n < 16) return AZRBF_EUNSUPPORTED;
+  if ((q.dim == 1 && q.n > 65536) || (q.dim == 2 && q.n > 512)) return AZRBF_EUNSUPPORTED;
+  if (q.s != 1 && q.s != 2 && q.s != 4) return AZRBF_EUNSUPPORTED;
+
+  azrbf_plan_s* h = new (std::nothrow) azrbf_plan_s();
+  if (!h) return AZRBF_ENOMEM;
+  Plan& P = h->p;
+  hipStream_t st = (hipStream_t)stream;
+  P.prob = q;
+  P.prob.mask = nullptr;
+  P.prob.bpts = nullptr;
+  if (hipGetDevice(&P.device) != hipSuccess) { delete h; return AZRBF_EHIP; }
+  P.dim = q.dim;
+  P.n = q.n;
+  P.s = q.s;
+  P.ph = q.dim == 1 ? q.s : q.s * q.s;
+  P.T = q.T;
+  P.h = 2.0 * q.T / q.n;
+  P.hL = P.h / q.s;
+  if (q.eps > 0) {
+    P.eps = q.eps;
+  } else {   // eq. constant_shapeparam: eps = c N, c = pi / (2 T sqrt(2 log(1 + tau0^-2)))
+    const double c = M_PI / (2.0 * q.T * sqrt(2.0 * log1p(1.0 / (q.tau0 * q.tau0))));
+    P.eps = c * q.n;
+  }
+  P.tau = q.tau;
+  P.tauZ = q.tauZ;
+  P.refine = q.refine;
+  P.bweight = q.bweight;
+  P.N = q.dim == 1 ? (int64_t)q.n : (int64_t)q.n * q.n;
+  P.Lax = (int64_t)q.s * q.n;
+  P.Lg = q.dim == 1 ? P.Lax : P.Lax * P.Lax;
+  P.Mb = q.nb;
+
+  int rc = az::ops_init_twiddles(P.device, &P.tw);
+  if (rc) { delete h; return rc; }
+
+  az::Geo& g = P.geo;
+  g.dim = P.dim;
+  g.s = P.s;
+  g.L = (int)P.Lax;
+  g.N = P.N;
+  g.op = q.op;
+  g.k2 = q.k2;
+  g.opscale = q.dim == 1 ? -1.0 / (2.0 * P.eps * P.eps) : -1.0 / (4.0 * P.eps * P.eps);
+
+  // collocation rows: ascending fine-grid order
+  int64_t M = 0;
+  for (int64_t i = 0; i < P.Lg; ++i) M += q.mask[i] != 0;
+  if (M == 0) { delete h; return AZRBF_EINVAL; }
+  P.M = M;
+  P.Mt = M + P.Mb;
+  g.M = M;
+  if (P.dim == 1) {
+    int64_t i0 = 0;
+    while (!q.mask[i0]) ++i0;
+    for (int64_t i = i0; i < i0 + M; ++i)
+      if (!q.mask[i]) { delete h; return AZRBF_EUNSUPPORTED; }   // 1D domains are intervals
+    g.i0 = i0;
+    const char* force = getenv("AZRBF_ENGINE");
+    P.fused = P.N <= 8192 && !(force && force[0] == '1' && P.N >= 256);
+    if (P.fused) {
+      g.N1 = 1;
+      g.N2 = (int)P.N;
+    } else {
+      az::split_1d(P.N, &g.N1, &g.N2);
+      if (g.N1 < 16 || g.N2 < 16 || g.N1 > 512 || g.N2 > 512) { delete h; return AZRBF_EUNSUPPORTED; }
+    }
+  } else {
+    g.N1 = g.N2 = P.n;
+    std::vector<int32_t> inv(P.Lg);
+    int64_t m = 0;
+    for (int64_t i = 0; i < P.Lg; ++i) inv[i] = q.mask[i] ? (int32_t)m++ : -1;
+    rc = P.alloc((void**)&P.inv, sizeof(int32_t) * P.Lg);
+    if (!rc && hipMemcpyAsync(P.inv, inv.data(), sizeof(int32_t) * P.Lg, hipMemcpyHostToDevice, st) != hipSuccess)
+      rc = AZRBF_EHIP;
+    if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = AZRBF_EHIP;
+    if (rc) { P.release(); delete h; return rc; }
+    g.inv = P.inv;
+  }
+  if (P.Mb > 0) {
+    rc = P.alloc((void**)&P.bpts, sizeof(double) * P.Mb * P.dim);
+    if (!rc && hipMemcpyAsync(P.bpts, q.bpts, sizeof(double) * P.Mb * P.dim, hipMemcpyHostToDevice, st) != hipSuccess)
+      rc = AZRBF_EHIP;
+    if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = AZRBF_EHIP;
+    if (rc) { P.release(); delete h; return rc; }
+  }
+  P.k = az::default_k(q);
+  rc = az::ops_spectra(P, st);
+  if (rc) { P.release(); delete h; return rc; }
+  *out = h;
+  return AZRBF_OK;
+}
+
+int azrbf_plan_info(azrbf_plan_t h, azrbf_info* info) {
+  if (!h || !info) return AZRBF_EINVAL;
+  const Plan& P = h->p;
+  info->N = P.N;
+  info->M = P.M;
+  info->Mb = P.Mb;
+  info->L = P.Lg;
+  info->k = P.k;
+  info->rank = P.factored ? P.rank : -1;
+  info->eps = P.eps;
+  info->normA = P.normA;
+  info->normZ = P.normZ;
+  info->zeroed = P.zeroed;
+  info->factored = P.factored ? 1 : 0;
+  info->device_bytes = P.bytes;
+  return AZRBF_OK;
+}
+
+int azrbf_apply_A(azrbf_plan_t h, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta,
+                  double* Y, int64_t ldy, void* stream) {
+  if (!h || nvec < 0) return AZRBF_EINVAL;
+  Plan& P = h->p;
+  if (nvec == 0) return AZRBF_OK;
+  if (!X || !Y || ldx < P.N || ldy < P.Mt) return AZRBF_EINVAL;
+  return az::ops_apply_A(P, X, ldx, nvec, alpha, beta, Y, ldy, (hipStream_t)stream);
+}
+
+int azrbf_apply_Zstar(azrbf_plan_t h, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,
+                      double* Z, int64_t ldz, void* stream) {
+  if (!h || nvec < 0) return AZRBF_EINVAL;
+  Plan& P = h->p;
+  if (nvec == 0) return AZRBF_OK;
+  if (!R || !Z || ldr < P.Mt || ldz < P.N) return AZRBF_EINVAL;
+  return az::ops_apply_Z(P, R, ldr, nvec, alpha, beta, Z, ldz, (hipStream_t)stream);
+}
+
+int azrbf_factor(azrbf_plan_t h, void* stream) {
+  if (!h) return AZRBF_EINVAL;
+  return az::dense_factor(h->p, (hipStream_t)stream);
+}
+
+int azrbf_solve(azrbf_plan_t h, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
+                double* relres, void* stream) {
+  if (!h || nrhs < 0) return AZRBF_EINVAL;
+  Plan& P = h->p;
+  if (nrhs == 0) return AZRBF_OK;
+  if (!B || !X || ldb < P.Mt || ldx < P.N) return AZRBF_EINVAL;
+  if (!P.factored) {
+    const int rc = az::dense_factor(P, (hipStream_t)stream);
+    if (rc != AZRBF_OK && rc != AZRBF_ERANK) return rc;
+  }
+  return az::dense_solve(P, B, ldb, nrhs, X, ldx, relres, (hipStream_t)stream);
+}
+
+int azrbf_solve_many(int32_t nprob, const azrbf_plan_t* plans, const double* const* B, const int64_t* ldb,
+                     const int64_t* nrhs, double* const* X, const int64_t* ldx, double* const* relres,
+                     void* stream) {
+  if (nprob < 0 || (nprob > 0 && (!plans || !B || !ldb || !nrhs || !X || !ldx))) return AZRBF_EINVAL;
+  for (int32_t i = 0; i < nprob; ++i) {
+    const int rc = azrbf_solve(plans[i], B[i], ldb[i], nrhs[i], X[i], ldx[i], relres ? relres[i] : nullptr,
+                               stream);
+    if (rc) return rc;
+  }
+  return AZRBF_OK;
+}
+
+int64_t azrbf_footprint_bytes(const azrbf_problem* pr, int64_t max_rhs) {
+  if (!pr || pr->n <= 0 || pr->s <= 0 || (pr->dim != 1 && pr->dim != 2)) return -1;
+  const int64_t n = pr->n, s = pr->s;
+  const int64_t N = pr->dim == 1 ? n : n * n;
+  const int64_t Lg = pr->dim == 1 ? s * n : s * s * n * n;
+  const int64_t ph = pr->dim == 1 ? s : s * s;
+  int64_t M = 0;
+  if (pr->mask)
+    for (int64_t i = 0; i < Lg; ++i) M += pr->mask[i] != 0;
+  else
+    M = Lg;
+  const int64_t Mt = M + pr->nb;
+  const int64_t k = pr->k > 0 ? pr->k : 32;
+  int64_t b = 0;
+  b += 2 * ph * N * 16;                                 // spectra (1D) or factors + weights (2D)
+  b += pr->dim == 2 ? Lg * 4 : 0;                       // inverse map
+  int64_t chunk = ((int64_t)64 << 20) / (ph * N * 16);
+  chunk = chunk < 1 ? 1 : (chunk > 64 ? 64 : chunk);
+  const int64_t pairs = (std::max<int64_t>(k, max_rhs) + 1) / 2;
+  if (!(pr->dim == 1 && N <= 8192)) b += 2 * ph * N * 16 * std::min<int64_t>(chunk, pairs);
+  b += 8 * (2 * N * k + 3 * Mt * k + 2 * k * k);        // factor and its scratch
+  b += 8 * (Mt * k / 4 + Mt * k / 4);                   // TSQR tree (upper bound)
+  b += 8 * max_rhs * (N + 3 * Mt + k + ((Mt + 1023) / 1024) * k + 2);
+  return b;
+}
+
+int azrbf_get_factor(azrbf_plan_t h, int32_t which, double* dst, int64_t ld, void* stream) {
+  if (!h || !dst) return AZRBF_EINVAL;
+  Plan& P = h->p;
+  hipStream_t st = (hipStream_t)stream;
+  if (!P.factored) return AZRBF_ESTATE;
+  const int k = P.k;
+  switch (which) {
+    case 0:
+      if (ld < P.N) return AZRBF_EINVAL;
+      return az::dense_gaussian(P.prob.seed, P.N, k, dst, ld, st);
+    case 1:
+      if (ld < P.Mt) return AZRBF_EINVAL;
+      return hipMemcpy2DAsync(dst, 8 * ld, P.Q, 8 * P.Mt, 8 * P.Mt, k, hipMemcpyDeviceToDevice, st) == hipSuccess
+                 ? AZRBF_OK : AZRBF_EHIP;
+    case 2:
+      if (ld < k) return AZRBF_EINVAL;
+      return hipMemcpy2DAsync(dst, 8 * ld, P.Rf, 8 * k, 8 * k, k, hipMemcpyDeviceToDevice, st) == hipSuccess
+                 ? AZRBF_OK : AZRBF_EHIP;
+    case 3:
+      return hipMemcpyAsync(dst, P.sig, 8 * k, hipMemcpyDeviceToDevice, st) == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+    default:
+      return AZRBF_EINVAL;
+  }
+}
+
+int azrbf_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* dst, int64_t ld, void* stream) {
+  if (rows < 0 || cols < 0 || (rows > 0 && cols > 0 && (!dst || ld < rows))) return AZRBF_EINVAL;
+  return az::dense_gaussian(seed, rows, cols, dst, ld, (hipStream_t)stream);
+}
+
+int azrbf_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(az::g_prof_mu);
+  az::g_prof_on = on != 0;
+  return AZRBF_OK;
+}
+
+int azrbf_profile_report(char* buf, int64_t len) {
+  if (!buf || len <= 0) return AZRBF_EINVAL;
+  std::lock_guard<std::mutex> lk(az::g_prof_mu);
+  struct Acc {
+    int64_t calls = 0;
+    double ms = 0, bytes = 0, max_ms = 0;
+  };
+  std::map<std::string, Acc> acc;
+  int rc = AZRBF_OK;
+  for (auto& r : az::g_prof) {
+    if (!r.done) continue;
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      rc = AZRBF_EHIP;
+      continue;
+    }
+    Acc& a = acc[r.name];
+    a.calls += 1;
+    a.ms += ms;
+    a.bytes += r.bytes;
+    if (ms > a.max_ms) a.max_ms = ms;
+  }
+  for (auto& r : az::g_prof) {
+    if (r.a) az::g_prof_pool.push_back(r.a);
+    if (r.b) az::g_prof_pool.push_back(r.b);
+  }
+  az::g_prof.clear();
+  std::string out = "[";
+  bool first = true;
+  char tmp[512];
+  for (auto& kv : acc) {
+    snprintf(tmp, sizeof(tmp), "%s{\"name\": \"%s\", \"calls\": %lld, \"ms\": %.6f, \"max_ms\": %.6f, \"bytes\": %.0f}",
+             first ? "" : ", ", kv.first.c_str(), (long long)kv.second.calls, kv.second.ms, kv.second.max_ms,
+             kv.second.bytes);
+    out += tmp;
+    first = false;
+  }
+  out += "]";
+  if ((int64_t)out.size() + 1 > len) return AZRBF_EINVAL;
+  memcpy(buf, out.c_str(), out.size() + 1);
+  return rc;
+}
+
+void azrbf_destroy(azrbf_plan_t h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  h->p.release();
+  delete h;
+}
+
+}  // extern "C"

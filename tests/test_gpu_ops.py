@@ -1,0 +1,129 @@
+"""GPU parity of the structured operators A and Z* and of the sketch generator
+against the CPU oracle (dense matrices built entry by entry).
+
+Tolerances follow from FFT rounding: a radix-2^q transform of length N has
+relative error about u log2 N (u = 2^-53), so A X agrees to 20 u log2 N of its
+size; Z* divides by the symbol, which amplifies that by at most
+||A^c|| ||Z*||, so Z* R agrees to 20 u log2 N ||A^c|| ||Z*||.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dense, grids, periodic, philox
+
+from gpu_util import announce, engine_path, rel_err, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+
+
+def _az():
+    require_gpu()
+    from paper_2308_14490_amd import azrbf, problems
+    return azrbf, problems
+
+
+def _tol_A(N):
+    return 20 * U * math.log2(N) + 1e-16
+
+
+def _tol_Z(N, plan):
+    inf = plan.info()
+    return 20 * U * math.log2(N) * inf["normA"] * inf["normZ"]
+
+
+def _case(prob, nvec, ld_pad, engine, seed=0):
+    azrbf, problems = _az()
+    announce(prob.name, prob.dim, prob.n, prob.s, "nvec", nvec, "pad", ld_pad, "engine", engine)
+    if engine:
+        with engine_path():
+            p = problems.plan_for(prob)
+    else:
+        p = problems.plan_for(prob)
+    A, idx, pts, bpts = dense.system_matrix(prob)
+    assert p.M == idx.size and p.Mb == bpts.shape[0]
+    assert np.array_equal(p.points(), pts)
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((nvec, prob.N))
+    Xd = to_dev(np.pad(X, ((0, 0), (0, ld_pad))))[:, :prob.N]
+    Y = azrbf.apply_A(p, Xd)
+    want = X @ A.T
+    assert rel_err(Y, want) < _tol_A(prob.N), rel_err(Y, want)
+    # alpha/beta form
+    Y0 = rng.standard_normal((nvec, p.Mt))
+    Yd = to_dev(Y0)
+    azrbf.apply_A(p, Xd, Yd, alpha=-0.5, beta=2.0)
+    assert rel_err(Yd, 2.0 * Y0 - 0.5 * want) < 4 * _tol_A(prob.N)
+    # Z*
+    Zo = periodic.zstar_normal(prob, idx, 1e-12, nb=bpts.shape[0])
+    R = rng.standard_normal((nvec, p.Mt))
+    Z = azrbf.apply_Zstar(p, to_dev(R))
+    wz = R @ Zo.T
+    assert rel_err(Z, wz) < _tol_Z(prob.N, p), (rel_err(Z, wz), _tol_Z(prob.N, p))
+    Z0 = rng.standard_normal((nvec, prob.N))
+    Zd = to_dev(Z0)
+    azrbf.apply_Zstar(p, to_dev(R), Zd, alpha=1.0, beta=1.0)
+    assert rel_err(Zd, Z0 + wz) < 2 * _tol_Z(prob.N, p)
+    p.destroy()
+
+
+@pytest.mark.parametrize("n,s,nvec", [(16, 2, 1), (64, 1, 3), (256, 2, 4), (256, 4, 2), (1024, 2, 5),
+                                      (4096, 2, 2)])
+def test_apply_1d_fused(n, s, nvec):
+    prob = W.config_c1a(n)
+    prob.s = s
+    prob.name = f"1d-fused-s{s}"
+    _case(prob, nvec, ld_pad=3 if nvec > 1 else 0, engine=False)
+
+
+def test_apply_1d_saturated_shape_parameter():
+    _case(W.config_c1(256), 3, 0, engine=False)
+
+
+@pytest.mark.parametrize("n,s,nvec", [(256, 2, 3), (1024, 2, 2), (2048, 1, 1), (4096, 4, 3)])
+def test_apply_1d_four_step(n, s, nvec):
+    prob = W.config_c1a(n)
+    prob.s = s
+    prob.name = f"1d-4step-s{s}"
+    _case(prob, nvec, ld_pad=1, engine=True)
+
+
+@pytest.mark.parametrize("n,nvec", [(16, 1), (32, 3), (64, 2)])
+def test_apply_2d_disk(n, nvec):
+    _case(W.config_c3a(n), nvec, ld_pad=2, engine=False)
+
+
+@pytest.mark.parametrize("n,nvec", [(16, 2), (32, 3)])
+def test_apply_2d_poisson_star(n, nvec):
+    _case(W.config_c4(n), nvec, ld_pad=0, engine=False)
+
+
+def test_apply_1d_bvp_with_boundary_rows():
+    n = 128
+    prob = W.Problem("ode", 1, n, 2, 1.5, 0.5, W.interval(-1.0, 1.0), [lambda x: 0 * x],
+                     op=W.HELMHOLTZ, k2=(n / 5.0) ** 2, bnd=[lambda x: np.sin(n * x / 5)], nb=2)
+    _case(prob, 3, 0, engine=False)
+
+
+def test_gaussian_sketch_matches_oracle():
+    azrbf, _ = _az()
+    for rows, cols, seed in [(10, 3, 42), (1027, 5, (5 << 32) | 77)]:
+        announce("gaussian", rows, cols, seed)
+        got = azrbf.gaussian(seed, rows, cols).cpu().numpy().T
+        want = philox.gaussian_sketch(rows, cols, seed)
+        assert np.max(np.abs(got - want)) < 1e-14 * np.max(np.abs(want))
+
+
+def test_empty_and_zero_vector_calls():
+    azrbf, problems = _az()
+    p = problems.plan_for(W.config_c1a(64))
+    import torch
+    X = torch.zeros((0, p.N), dtype=torch.float64, device="cuda")
+    Y = azrbf.apply_A(p, X)
+    assert Y.shape == (0, p.Mt)
+    Z = azrbf.apply_Zstar(p, torch.zeros((2, p.Mt), dtype=torch.float64, device="cuda"))
+    assert float(Z.abs().max()) == 0.0
+    p.destroy()

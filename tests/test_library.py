@@ -1,0 +1,69 @@
+"""The C-ABI library builds, loads and exports every function the header declares
+(no GPU calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "azrbf.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(azrbf_[a-z_A-Z]+)\s*\(", src)))
+
+
+def _lib_path():
+    from paper_2308_14490_amd import azrbf
+    if not os.path.exists(azrbf.LIB_PATH):
+        from paper_2308_14490_amd import build
+        build.build(verbose=False)
+    return azrbf.LIB_PATH
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ["azrbf_plan", "azrbf_apply_A", "azrbf_apply_Zstar", "azrbf_solve", "azrbf_factor",
+                 "azrbf_destroy", "azrbf_strerror", "azrbf_footprint_bytes", "azrbf_solve_many"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib_path())
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_2308_14490_amd import azrbf
+    assert set(_declared()) == set(azrbf.EXPORTS)
+
+
+def test_strerror_and_footprint_without_gpu():
+    from paper_2308_14490_amd import azrbf
+    lib = azrbf._lib()
+    assert lib.azrbf_strerror(0) == b"ok"
+    assert b"invalid" in lib.azrbf_strerror(-1)
+    pr = azrbf._Problem()
+    pr.dim, pr.n, pr.s, pr.T, pr.k = 1, 65536, 2, 1.0, 32
+    assert lib.azrbf_footprint_bytes(ctypes.byref(pr), 64) > 8 * 65536 * 64
+    pr.n = 0
+    assert lib.azrbf_footprint_bytes(ctypes.byref(pr), 64) == -1
+
+
+def test_plan_rejects_bad_arguments_before_touching_the_gpu():
+    import numpy as np
+    from paper_2308_14490_amd import azrbf
+    lib = azrbf._lib()
+    mask = np.ones(64, dtype=np.uint8)
+    h = ctypes.c_void_p()
+    for field, val, code in [("n", 24, azrbf.EUNSUPPORTED), ("s", 3, azrbf.EUNSUPPORTED),
+                             ("dim", 3, azrbf.EINVAL), ("tau", 0.0, azrbf.EINVAL)]:
+        pr = azrbf._Problem()
+        pr.dim, pr.n, pr.s, pr.T, pr.eps, pr.tau, pr.tauZ = 1, 32, 2, 1.0, 8.0, 1e-12, 1e-12
+        pr.mask = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        setattr(pr, field, val)
+        assert lib.azrbf_plan(ctypes.byref(pr), None, ctypes.byref(h)) == code
