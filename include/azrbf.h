@@ -98,6 +98,7 @@ typedef struct {
   double normZ;           /* ||Z*||_2 (largest regularised weight, sqrt)     */
   int32_t zeroed;         /* number of regularised (zeroed) weights          */
   int32_t factored;       /* 1 once the low-rank factor is resident          */
+  int32_t sweeps;         /* Jacobi sweeps of the last factorisation         */
   int64_t device_bytes;   /* device memory currently owned by the plan       */
 } azrbf_info;
 
@@ -180,7 +181,12 @@ int azrbf_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* dst, int64
 int azrbf_profile_enable(int32_t on);
 int azrbf_profile_report(char* buf, int64_t len);
 
+/* Releases a plan.  Waits for the work queued on the plan's latest stream;
+ * its device blocks return to the library's memory pool for later plans. */
 void azrbf_destroy(azrbf_plan_t plan);
+
+/* Frees the pool's cached device blocks (blocks owned by live plans stay). */
+int azrbf_release_cached_memory(void);
 const char* azrbf_strerror(int code);
 
 #ifdef __cplusplus

@@ -45,7 +45,7 @@ class _Info(ctypes.Structure):
         ("N", ctypes.c_int64), ("M", ctypes.c_int64), ("Mb", ctypes.c_int64), ("L", ctypes.c_int64),
         ("k", ctypes.c_int32), ("rank", ctypes.c_int32), ("eps", ctypes.c_double),
         ("normA", ctypes.c_double), ("normZ", ctypes.c_double), ("zeroed", ctypes.c_int32),
-        ("factored", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+        ("factored", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
     ]
 
 
@@ -70,6 +70,7 @@ EXPORTS = {
     "azrbf_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
     "azrbf_profile_report": (ctypes.c_int, [ctypes.c_char_p, _I64]),
     "azrbf_destroy": (None, [_P]),
+    "azrbf_release_cached_memory": (ctypes.c_int, []),
     "azrbf_strerror": (ctypes.c_char_p, [ctypes.c_int]),
 }
 
@@ -304,6 +305,10 @@ def profile_report():
     buf = ctypes.create_string_buffer(1 << 20)
     _check(_lib().azrbf_profile_report(buf, len(buf)), "azrbf_profile_report")
     return json.loads(buf.value.decode())
+
+
+def release_cached_memory():
+    _check(_lib().azrbf_release_cached_memory(), "azrbf_release_cached_memory")
 
 
 def exported_symbols():

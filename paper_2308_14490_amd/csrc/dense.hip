@@ -15,7 +15,6 @@
 namespace az {
 
 constexpr int KMAX = 64;       // largest sketch width of this path
-constexpr int TSQR_RB = 256;   // rows per TSQR block (= threads per block)
 
 // ------------------------------------------------------------------ Philox4x32-10
 
@@ -68,123 +67,237 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Column sums of v_t * x_c[t] for columns c in [c0, k) over a 256-thread
-// block; result in wv[c].  red holds 4 * KMAX doubles.
-__device__ __forceinline__ void block_dots(const double* x, int ldx, double v, int c0, int k, double* red,
-                                           double* wv) {
-  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  for (int c = c0; c < k; ++c) {
-    const double s = wave_sum(v * x[c * ldx + t]);
-    if (lane == 0) red[w * KMAX + c] = s;
-  }
-  __syncthreads();
-  if (t >= c0 && t < k) wv[t] = (red[t] + red[KMAX + t]) + (red[2 * KMAX + t] + red[3 * KMAX + t]);
-  __syncthreads();
-}
-
 // ------------------------------------------------------------------ TSQR
 
-constexpr int TSQR_LDL = TSQR_RB + 1;
+// Each TSQR block holds RB = TSQR_ELEMS / k rows of the k columns in LDS
+// (column-major, odd leading dimension).  256 threads: for the column
+// dot products thread t takes column t % k and row group t / k (64 rows).
+constexpr int TSQR_ELEMS = 16384;
+constexpr int TSQR_THREADS = 256;
+
+// (k = 64 keeps fewer rows so that the k x k T factor also fits in LDS)
+__host__ __device__ constexpr int tsqr_rows(int k) { return k <= 32 ? TSQR_ELEMS / k : 12288 / k; }
 
 static int tsqr_lds_bytes(int k) {
-  return (int)(sizeof(double) * ((int64_t)TSQR_LDL * k + 4 * KMAX + 2 * KMAX));
+  const int RB = tsqr_rows(k);
+  // a (RB+1) x k, partial sums 256, w, scalars 4, g, T (k x k)
+  return (int)(sizeof(double) * ((int64_t)(RB + 1) * k + TSQR_THREADS + 2 * KMAX + 4 + k * k));
 }
 
 // Householder QR of one RB x k block of A (rows >= m read as zero).
-// Reflector j is H_j = I - tau_j v_j v_j^T with v_j[j] = 1, zero above.
-// Out: R (upper k x k, zeros below) at rows b*k.. of Rout, the reflectors
-// over the block's rows of V, and tau at taus[b*k + j].
-__global__ void __launch_bounds__(TSQR_RB)
+// Reflector j is H_j = I - tau_j v_j v_j^T with v_j[j] = 1 and zeros above.
+// For column j the sums D_c = sum_{r > j} a[r][j] a[r][c] (c >= j) give both
+// sigma^2 = D_j and v_j^T a_c = a[j][c] + D_c / (alpha - beta); the threads
+// of columns c < j meanwhile form v_c^T v_j, from which the triangular
+// factor of the compact WY form H_0 ... H_{k-1} = I - V T V^T is built
+// (T_jj = tau_j, T_ij = -tau_j sum_{l=i}^{j-1} T_il v_l^T v_j).
+// Out: R (upper k x k) at rows b*k.. of Rout, the reflectors over the
+// block's rows of V, T (k x k, column-major) at Tout + b*k*k.
+__global__ void __launch_bounds__(TSQR_THREADS)
 k_tsqr_block(const double* __restrict__ A, int64_t lda, int64_t m, int k, double* __restrict__ Rout,
-             int64_t ldr, double* __restrict__ V, int64_t ldv, double* __restrict__ taus) {
+             int64_t ldr, double* __restrict__ V, int64_t ldv, double* __restrict__ Tout) {
   extern __shared__ double sm[];
-  double* a = sm;                              // RB x k, column-major, ld TSQR_LDL
-  double* red = sm + (int64_t)TSQR_LDL * k;    // 4 * KMAX
-  double* wv = red + 4 * KMAX;                 // KMAX
-  double* scal = wv + KMAX;                    // [beta, tau]
+  const int RB = tsqr_rows(k), LDL = RB + 1;
+  double* a = sm;                                // a[c * LDL + r]
+  double* part = a + (int64_t)LDL * k;           // 256
+  double* wv = part + TSQR_THREADS;              // KMAX
+  double* scal = wv + KMAX;                      // beta, tau, scale
+  double* gv = scal + 4;                         // KMAX: v_c^T v_j for c < j
+  double* Tm = gv + KMAX;                        // k x k, column-major
   const int t = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * TSQR_RB;
-  const int64_t gi = r0 + t;
-  for (int c = 0; c < k; ++c) a[c * TSQR_LDL + t] = gi < m ? A[gi + lda * c] : 0.0;
+  const int64_t r0 = (int64_t)blockIdx.x * RB;
+  for (int c = 0; c < k; ++c)
+    for (int r = t; r < RB; r += TSQR_THREADS) a[c * LDL + r] = r0 + r < m ? A[r0 + r + lda * c] : 0.0;
   __syncthreads();
+  const int G = TSQR_THREADS / k, rows_g = RB / G;
+  const int cc = t % k, gg = t / k;
   for (int j = 0; j < k; ++j) {
-    const double x = t > j ? a[j * TSQR_LDL + t] : 0.0;
-    const double s = wave_sum(x * x);
-    if ((t & 63) == 0) red[t >> 6] = s;
+    {
+      const double* aj = a + j * LDL;
+      const double* ac = a + cc * LDL;
+      const int lo = max(gg * rows_g, j + 1), hi = (gg + 1) * rows_g;
+      // short dependency chains: eight partial sums
+      double d[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      int r = lo;
+      for (; r + 8 <= hi; r += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) d[u] = fma(aj[r + u], ac[r + u], d[u]);
+      }
+      for (; r < hi; ++r) d[0] = fma(aj[r], ac[r], d[0]);
+      part[gg * k + cc] = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]));
+    }
     __syncthreads();
-    if (t == 0) {
-      const double sig2 = (red[0] + red[1]) + (red[2] + red[3]);
-      const double alpha = a[j * TSQR_LDL + j];
-      double beta = alpha, tau = 0.0;
+    if (t < k) {
+      double s0 = 0.0, s1 = 0.0, c0 = 0.0, c1 = 0.0;
+      for (int g = 0; g < G; g += 2) {
+        s0 += part[g * k + j];
+        s1 += part[(g + 1) * k + j];
+        c0 += part[g * k + t];
+        c1 += part[(g + 1) * k + t];
+      }
+      const double sig2 = s0 + s1, dc = c0 + c1;
+      const double alpha = a[j * LDL + j];
+      double beta = alpha, tau = 0.0, scale = 0.0;
       if (sig2 > 0.0) {
         beta = -copysign(sqrt(alpha * alpha + sig2), alpha);
         tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
       }
-      scal[0] = beta;
-      scal[1] = tau;
-      scal[2] = sig2 > 0.0 ? 1.0 / (alpha - beta) : 0.0;
+      if (t == j) {
+        scal[0] = beta;
+        scal[1] = tau;
+        scal[2] = scale;
+      } else if (t > j) {
+        wv[t] = tau * (a[t * LDL + j] + dc * scale);
+      } else {
+        gv[t] = a[t * LDL + j] + dc * scale;   // v_t^T v_j (v_t[j] = a[j][t] stored below t's diagonal)
+      }
     }
     __syncthreads();
-    const double tau = scal[1];
-    const double v = t == j ? 1.0 : (t > j ? x * scal[2] : 0.0);
-    block_dots(a, TSQR_LDL, v, j + 1, k, red, wv);
-    for (int c = j + 1; c < k; ++c) a[c * TSQR_LDL + t] -= tau * wv[c] * v;
-    if (t > j) a[j * TSQR_LDL + t] = v;
-    if (t == j) a[j * TSQR_LDL + j] = scal[0];
-    if (t == 0) taus[(int64_t)blockIdx.x * k + j] = tau;
+    if (t < j) {   // T(0:j, j) = -tau_j T(0:j, 0:j) g
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int l = t;
+      for (; l + 4 <= j; l += 4) {
+        a0 = fma(Tm[l * k + t], gv[l], a0);
+        a1 = fma(Tm[(l + 1) * k + t], gv[l + 1], a1);
+        a2 = fma(Tm[(l + 2) * k + t], gv[l + 2], a2);
+        a3 = fma(Tm[(l + 3) * k + t], gv[l + 3], a3);
+      }
+      for (; l < j; ++l) a0 = fma(Tm[l * k + t], gv[l], a0);
+      Tm[j * k + t] = -scal[1] * ((a0 + a1) + (a2 + a3));
+    } else if (t == j) {
+      Tm[j * k + j] = scal[1];
+    }
+    const double scale = scal[2];
+    for (int r = t; r < RB; r += TSQR_THREADS) {
+      if (r < j) continue;
+      const double v = r == j ? 1.0 : a[j * LDL + r] * scale;
+      int c = j + 1;
+      for (; c + 4 <= k; c += 4) {
+        const double x0 = a[c * LDL + r], x1 = a[(c + 1) * LDL + r];
+        const double x2 = a[(c + 2) * LDL + r], x3 = a[(c + 3) * LDL + r];
+        a[c * LDL + r] = fma(-wv[c], v, x0);
+        a[(c + 1) * LDL + r] = fma(-wv[c + 1], v, x1);
+        a[(c + 2) * LDL + r] = fma(-wv[c + 2], v, x2);
+        a[(c + 3) * LDL + r] = fma(-wv[c + 3], v, x3);
+      }
+      for (; c < k; ++c) a[c * LDL + r] = fma(-wv[c], v, a[c * LDL + r]);
+      a[j * LDL + r] = r == j ? scal[0] : v;
+    }
     __syncthreads();
   }
+  for (int e = t; e < k * k; e += TSQR_THREADS) {
+    const int r = e % k, c = e / k;
+    Tout[(int64_t)blockIdx.x * k * k + e] = r <= c ? Tm[c * k + r] : 0.0;
+  }
   for (int c = 0; c < k; ++c) {
-    if (t < k) Rout[(int64_t)blockIdx.x * k + t + ldr * c] = t <= c ? a[c * TSQR_LDL + t] : 0.0;
-    if (gi < m) V[gi + ldv * c] = t > c ? a[c * TSQR_LDL + t] : (t == c ? 1.0 : 0.0);
+    if (t < k) Rout[(int64_t)blockIdx.x * k + t + ldr * c] = t <= c ? a[c * LDL + t] : 0.0;
+    for (int r = t; r < RB; r += TSQR_THREADS)
+      if (r0 + r < m) V[r0 + r + ldv * c] = r > c ? a[c * LDL + r] : (r == c ? 1.0 : 0.0);
   }
 }
 
-// E_b = H_0 ... H_{k-1} [C_b; 0] for block b: C_b is rows b*k.. of the
-// level above's explicit Q (Cup), or the identity at the top (Cup null).
-__global__ void __launch_bounds__(TSQR_RB)
-k_tsqr_formq(const double* __restrict__ V, int64_t ldv, const double* __restrict__ taus, int64_t m, int k,
+// E_b = H_0 ... H_{k-1} [C_b; 0] = [C_b; 0] - V (T (V_top^T C_b)) for block b
+// (compact WY; V_top = the block's first k reflector rows, unit lower
+// triangular).  C_b is rows b*k.. of the level above's explicit Q (Cup), or
+// the identity at the top (Cup null).  Fully parallel over the block's rows.
+__global__ void __launch_bounds__(TSQR_THREADS)
+k_tsqr_formq(const double* __restrict__ V, int64_t ldv, const double* __restrict__ Tin, int64_t m, int k,
              const double* __restrict__ Cup, int64_t ldc, double* __restrict__ E, int64_t lde) {
-  extern __shared__ double sm[];
-  double* e = sm;
-  double* red = sm + (int64_t)TSQR_LDL * k;
-  double* wv = red + 4 * KMAX;
+  __shared__ double Cb[KMAX * (KMAX + 1)];
+  __shared__ double X[KMAX * (KMAX + 1)];     // V_top, then V_top^T C_b
+  __shared__ double Mm[KMAX * (KMAX + 1)];    // T, then T V_top^T C_b
+  const int ld = KMAX + 1;
+  const int RB = tsqr_rows(k);
   const int t = threadIdx.x;
-  const int64_t gi = (int64_t)blockIdx.x * TSQR_RB + t;
-  for (int c = 0; c < k; ++c) {
-    double val = 0.0;
-    if (t < k) val = Cup ? Cup[(int64_t)blockIdx.x * k + t + ldc * c] : (t == c ? 1.0 : 0.0);
-    e[c * TSQR_LDL + t] = val;
+  const int64_t r0 = (int64_t)blockIdx.x * RB;
+  const double* Tb = Tin + (int64_t)blockIdx.x * k * k;
+  __shared__ double Vt[KMAX * (KMAX + 1)];
+  for (int e = t; e < k * k; e += TSQR_THREADS) {
+    const int r = e % k, c = e / k;
+    Cb[c * ld + r] = Cup ? Cup[(int64_t)blockIdx.x * k + r + ldc * c] : (r == c ? 1.0 : 0.0);
+    Vt[c * ld + r] = r0 + r < m ? V[r0 + r + ldv * c] : 0.0;       // unit lower, zeros above
+    Mm[c * ld + r] = Tb[e];                                         // T, upper triangular
   }
   __syncthreads();
-  for (int j = k - 1; j >= 0; --j) {
-    const double v = (t >= j && gi < m) ? V[gi + ldv * j] : 0.0;
-    const double tau = taus[(int64_t)blockIdx.x * k + j];
-    block_dots(e, TSQR_LDL, v, 0, k, red, wv);
-    for (int c = 0; c < k; ++c) e[c * TSQR_LDL + t] -= tau * wv[c] * v;
-    __syncthreads();
+  // X = V_top^T C_b: X[i][c] = sum_{l >= i} V_top[l][i] C_b[l][c]
+  double xv[KMAX * KMAX / TSQR_THREADS];
+  int ne = 0;
+  for (int e = t; e < k * k; e += TSQR_THREADS, ++ne) {
+    const int i = e % k, c = e / k;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int l = i;
+    for (; l + 4 <= k; l += 4) {
+      a0 = fma(Vt[i * ld + l], Cb[c * ld + l], a0);
+      a1 = fma(Vt[i * ld + l + 1], Cb[c * ld + l + 1], a1);
+      a2 = fma(Vt[i * ld + l + 2], Cb[c * ld + l + 2], a2);
+      a3 = fma(Vt[i * ld + l + 3], Cb[c * ld + l + 3], a3);
+    }
+    for (; l < k; ++l) a0 = fma(Vt[i * ld + l], Cb[c * ld + l], a0);
+    xv[ne] = (a0 + a1) + (a2 + a3);
   }
-  if (gi < m)
-    for (int c = 0; c < k; ++c) E[gi + lde * c] = e[c * TSQR_LDL + t];
+  ne = 0;
+  for (int e = t; e < k * k; e += TSQR_THREADS, ++ne) X[(e / k) * ld + e % k] = xv[ne];
+  __syncthreads();
+  // M = T X (T upper triangular): M[i][c] = sum_{l >= i} T[i][l] X[l][c]
+  ne = 0;
+  for (int e = t; e < k * k; e += TSQR_THREADS, ++ne) {
+    const int i = e % k, c = e / k;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int l = i;
+    for (; l + 4 <= k; l += 4) {
+      a0 = fma(Mm[l * ld + i], X[c * ld + l], a0);
+      a1 = fma(Mm[(l + 1) * ld + i], X[c * ld + l + 1], a1);
+      a2 = fma(Mm[(l + 2) * ld + i], X[c * ld + l + 2], a2);
+      a3 = fma(Mm[(l + 3) * ld + i], X[c * ld + l + 3], a3);
+    }
+    for (; l < k; ++l) a0 = fma(Mm[l * ld + i], X[c * ld + l], a0);
+    xv[ne] = (a0 + a1) + (a2 + a3);
+  }
+  __syncthreads();
+  ne = 0;
+  for (int e = t; e < k * k; e += TSQR_THREADS, ++ne) Mm[(e / k) * ld + e % k] = xv[ne];
+  __syncthreads();
+  for (int r = t; r < RB; r += TSQR_THREADS) {
+    const int64_t gi = r0 + r;
+    if (gi >= m) break;
+    double vr[KMAX];
+#pragma unroll
+    for (int l = 0; l < KMAX; ++l) vr[l] = l < k ? V[gi + ldv * l] : 0.0;
+    for (int c = 0; c < k; ++c) {
+      double a0 = r < k ? Cb[c * ld + r] : 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+      for (int l = 0; l < KMAX; l += 4) {
+        if (l < k) {
+          a0 = fma(-vr[l], Mm[c * ld + l], a0);
+          a1 = fma(-vr[l + 1], Mm[c * ld + l + 1], a1);
+          a2 = fma(-vr[l + 2], Mm[c * ld + l + 2], a2);
+          a3 = fma(-vr[l + 3], Mm[c * ld + l + 3], a3);
+        }
+      }
+      E[gi + lde * c] = (a0 + a1) + (a2 + a3);
+    }
+  }
 }
 
 struct TsqrLevel {
   int64_t m, nb;
   double* A;     // level input; overwritten by the level's reflectors
-  double* tau;   // nb x k
+  double* tau;   // compact-WY T factors, nb x (k x k)
   double* R;     // stacked R factors (nb*k x k): the next level's input
 };
 
 static void tsqr_plan(int64_t m, int k, std::vector<TsqrLevel>& lv, int64_t* scratch_doubles,
                       int64_t* e_doubles) {
   lv.clear();
+  const int RB = tsqr_rows(k);
   int64_t mm = m, tot = 0, emax = 0;
   while (true) {
     TsqrLevel L{};
     L.m = mm;
-    L.nb = (mm + TSQR_RB - 1) / TSQR_RB;
+    L.nb = (mm + RB - 1) / RB;
     lv.push_back(L);
-    tot += L.nb * k + L.nb * k * k;
+    tot += 2 * L.nb * k * k;   // T factors + stacked R
     if (lv.size() > 1) emax = std::max(emax, mm * k);
     if (L.nb == 1) break;
     mm = L.nb * k;
@@ -208,22 +321,25 @@ static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double*
   tsqr_plan(m, k, lv, &sd, &ed);
   double* p = scratch;
   for (size_t l = 0; l < lv.size(); ++l) {
-    lv[l].tau = p;
-    p += lv[l].nb * k;
+    lv[l].tau = p;             // T factors, nb x (k x k)
+    p += lv[l].nb * k * k;
     lv[l].R = p;
     p += lv[l].nb * k * k;
     lv[l].A = l == 0 ? W : lv[l - 1].R;
   }
   double* Ebuf[2] = {p, p + ed};
   const int lds = tsqr_lds_bytes(k);
-  if (lds > 64 * 1024) {
-    AZ_HIP(hipFuncSetAttribute((const void*)k_tsqr_block, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    AZ_HIP(hipFuncSetAttribute((const void*)k_tsqr_formq, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  static bool attr = false;
+  if (!attr) {
+    const int most = std::max(tsqr_lds_bytes(16), std::max(tsqr_lds_bytes(32), tsqr_lds_bytes(64)));
+    AZ_HIP(hipFuncSetAttribute((const void*)k_tsqr_block, hipFuncAttributeMaxDynamicSharedMemorySize, most));
+
+    attr = true;
   }
   for (size_t l = 0; l < lv.size(); ++l) {
     const TsqrLevel& L = lv[l];
     Prof pr(l == 0 ? "tsqr_block" : "tsqr_block (tree)", 16.0 * L.m * k + 8.0 * L.nb * k * (k + 1), st);
-    k_tsqr_block<<<(unsigned)L.nb, TSQR_RB, lds, st>>>(L.A, L.m, L.m, k, L.R, L.nb * k, L.A, L.m, L.tau);
+    k_tsqr_block<<<(unsigned)L.nb, TSQR_THREADS, lds, st>>>(L.A, L.m, L.m, k, L.R, L.nb * k, L.A, L.m, L.tau);
     AZ_HIP(hipGetLastError());
   }
   AZ_HIP(hipMemcpyAsync(R, lv.back().R, sizeof(double) * k * k, hipMemcpyDeviceToDevice, st));
@@ -233,7 +349,7 @@ static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double*
     const TsqrLevel& L = lv[l];
     double* E = l == 0 ? Q : Ebuf[l & 1];
     Prof pr(l == 0 ? "tsqr_formq" : "tsqr_formq (tree)", 16.0 * L.m * k + 8.0 * L.nb * k * (k + 1), st);
-    k_tsqr_formq<<<(unsigned)L.nb, TSQR_RB, lds, st>>>(L.A, L.m, L.tau, L.m, k, up, ldup, E, L.m);
+    k_tsqr_formq<<<(unsigned)L.nb, TSQR_THREADS, 0, st>>>(L.A, L.m, L.tau, L.m, k, up, ldup, E, L.m);
     AZ_HIP(hipGetLastError());
     up = E;
     ldup = L.m;
@@ -243,11 +359,30 @@ static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double*
 
 // ------------------------------------------------------------------ Jacobi SVD
 
-// One-sided Jacobi SVD of the k x k matrix R (k even, <= KMAX) in one block:
-// columns of A = R are orthogonalised by plane rotations from the right,
-// A V = U S.  Pairs follow the round-robin (circle) schedule, k/2 pairs per
-// round handled by groups of G = 512/k threads.  On exit: sig (descending),
-// Pm = sum_{i < rank} v_i u_i^T / sigma_i with rank = #{sigma_i > thr}.
+// 1/x and 1/sqrt(x) from the hardware estimates refined by one Newton step
+// (relative error near the FP64 rounding unit).  They keep the dependency
+// chain of a rotation short; the rotation stays orthogonal because c and s
+// are formed from the same t.
+__device__ __forceinline__ double fast_rcp(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ __forceinline__ double fast_rsq(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
+// One-sided Jacobi SVD of the k x k triangular factor R (k in {16, 32, 64})
+// in one block, applied to A = R^T: its columns (the rows of R) are
+// orthogonalised by plane rotations from the right, R^T V = U S, so
+// R = V S U^T and the truncated pseudo-inverse of R is sum u_i v_i^T / s_i.
+// (The transposed factor converges in about half the sweeps: its columns are
+// far closer to orthogonal than those of R.)  Round-robin (circle) schedule: in round r pair 0 is
+// (r, k-1) and pair i > 0 is ((r+i) mod (k-1), (r-i) mod (k-1)); k/2 pairs
+// per round, G = 512/k threads per pair.  A rotation is skipped when
+// |a_p . a_q| <= tol sqrt(|a_p|^2 |a_q|^2); sweeps stop when none happens.
+// On exit: sig (descending), info = {rank, sweeps} with rank = #{sigma > thr},
+// Pm = sum_{i < rank} u_i v_i^T / sigma_i (the truncated pseudo-inverse of R).
 __global__ void __launch_bounds__(256)
 k_jacobi(const double* __restrict__ R, int k, double thr, double tol, int max_sweeps, double* __restrict__ sig,
          double* __restrict__ Pm, int* __restrict__ info) {
@@ -255,26 +390,23 @@ k_jacobi(const double* __restrict__ R, int k, double thr, double tol, int max_sw
   __shared__ double V[KMAX * (KMAX + 1)];
   __shared__ double sv[KMAX];
   __shared__ int ord[KMAX];
-  __shared__ int pos[KMAX];
-  __shared__ int off_flag;
+  __shared__ int flag;
   const int lda = KMAX + 1;
   const int t = threadIdx.x;
   for (int i = t; i < k * k; i += blockDim.x) {
     const int r = i % k, c = i / k;
-    A[c * lda + r] = R[r + (int64_t)k * c];
+    A[r * lda + c] = R[r + (int64_t)k * c];      // A = R^T
     V[c * lda + r] = r == c ? 1.0 : 0.0;
   }
-  if (t < k) pos[t] = t;
-  __syncthreads();
-  const int G = 512 / k;                 // threads per pair (k/2 pairs * G = 256)
-  const int pair = t / G, gl = t % G;
+  const int G = 512 / k;
+  const int pi = t / G, gl = t % G, km1 = k - 1;
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
-    if (t == 0) off_flag = 0;
+    if (t == 0) flag = 0;
     __syncthreads();
-    for (int round = 0; round < k - 1; ++round) {
-      // circle schedule: positions pos[0..k-1]; pair i = (pos[i], pos[k-1-i])
-      const int p = pos[pair], q = pos[k - 1 - pair];
+    for (int round = 0; round < km1; ++round) {
+      const int p = pi == 0 ? round : (round + pi) % km1;
+      const int q = pi == 0 ? km1 : (round - pi + km1) % km1;
       double al = 0.0, be = 0.0, ga = 0.0;
       for (int r = gl; r < k; r += G) {
         const double x = A[p * lda + r], y = A[q * lda + r];
@@ -287,17 +419,17 @@ k_jacobi(const double* __restrict__ R, int k, double thr, double tol, int max_sw
         be += __shfl_xor(be, o, G);
         ga += __shfl_xor(ga, o, G);
       }
-      double c = 1.0, s = 0.0;
-      bool rot = false;
-      if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-        const double zeta = (be - al) / (2.0 * ga);
-        const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        c = 1.0 / sqrt(1.0 + tt * tt);
-        s = c * tt;
-        rot = true;
-      }
-      if (rot) {
-        if (gl == 0) off_flag = 1;
+      if (ga != 0.0 && ga * ga > tol * tol * (al * be)) {
+        // tan of the rotation angle (Rutishauser): t = sign(z) / (|z| + sqrt(1 + z^2)),
+        // z = (be - al) / (2 ga); c = 1/sqrt(1 + t^2), s = c t.  For |z| > 1e8 the
+        // square would overflow the useful range and t = 1/(2z) to rounding.
+        const double zeta = (be - al) * fast_rcp(2.0 * ga);
+        const double az = fabs(zeta);
+        const double w = 1.0 + zeta * zeta;
+        const double root = az > 1e8 ? az : w * fast_rsq(w);
+        const double tt = copysign(fast_rcp(az + root), zeta);
+        const double c = fast_rsq(fma(tt, tt, 1.0)), s = c * tt;
+        if (gl == 0) flag = 1;
         for (int r = gl; r < k; r += G) {
           const double x = A[p * lda + r], y = A[q * lda + r];
           A[p * lda + r] = c * x - s * y;
@@ -308,50 +440,38 @@ k_jacobi(const double* __restrict__ R, int k, double thr, double tol, int max_sw
         }
       }
       __syncthreads();
-      if (t == 0) {   // rotate positions 1..k-1
-        const int last = pos[k - 1];
-        for (int i = k - 1; i > 1; --i) pos[i] = pos[i - 1];
-        pos[1] = last;
-      }
-      __syncthreads();
     }
-    const int flag = off_flag;
+    const int f = flag;
     __syncthreads();
-    if (!flag) break;
+    if (!f) break;
   }
-  // singular values, order, rank
   if (t < k) {
     double s2 = 0.0;
     for (int r = 0; r < k; ++r) s2 = fma(A[t * lda + r], A[t * lda + r], s2);
     sv[t] = sqrt(s2);
   }
   __syncthreads();
+  if (t < k) {   // position of column t in descending order (ties by index)
+    int pos = 0;
+    for (int j = 0; j < k; ++j) pos += (sv[j] > sv[t]) || (sv[j] == sv[t] && j < t);
+    ord[pos] = t;
+  }
+  __syncthreads();
+  int rank = 0;
+  for (int i = 0; i < k; ++i) rank += sv[i] > thr;
   if (t == 0) {
-    for (int i = 0; i < k; ++i) ord[i] = i;
-    for (int i = 0; i < k; ++i)
-      for (int j = i + 1; j < k; ++j)
-        if (sv[ord[j]] > sv[ord[i]]) {
-          const int tmp = ord[i];
-          ord[i] = ord[j];
-          ord[j] = tmp;
-        }
-    int rank = 0;
-    for (int i = 0; i < k; ++i)
-      if (sv[ord[i]] > thr) ++rank;
     info[0] = rank;
     info[1] = sweep;
   }
-  __syncthreads();
   if (t < k) sig[t] = sv[ord[t]];
-  const int rank = info[0];
-  // Pm[r][c] = sum_i V[r][i] U[c][i] / s_i = sum_i V[r][i] A[c][i] / s_i^2
+  // Pm[r][c] = sum_i U[r][i] V[c][i] / s_i = sum_i A[r][i] V[c][i] / s_i^2
   for (int e = t; e < k * k; e += blockDim.x) {
     const int r = e % k, c = e / k;
     double acc = 0.0;
     for (int ii = 0; ii < rank; ++ii) {
       const int i = ord[ii];
       const double si = sv[i];
-      acc = fma(V[i * lda + r], A[i * lda + c] / (si * si), acc);
+      acc = fma(A[i * lda + r], V[i * lda + c] / (si * si), acc);
     }
     Pm[r + (int64_t)k * c] = acc;
   }
@@ -361,6 +481,7 @@ k_jacobi(const double* __restrict__ R, int k, double thr, double tol, int max_sw
 
 // Out = alpha * A B + beta * Cin; A is m x k (ld lda), B is k x ncol (ld ldb,
 // small), Out/Cin m x ncol.  Each thread owns one row and up to 16 columns.
+// Out may alias Cin (each element is read and written by the same thread).
 __global__ void __launch_bounds__(256)
 k_gemm_nn(const double* __restrict__ A, int64_t lda, int64_t m, int k, const double* __restrict__ B, int64_t ldb,
           int64_t ncol, double alpha, const double* Cin, int64_t ldci, double beta, double* Out, int64_t ldo) {
@@ -392,49 +513,55 @@ k_gemm_nn(const double* __restrict__ A, int64_t lda, int64_t m, int k, const dou
   }
 }
 
-constexpr int TN_ROWS = 1024;   // rows per partial-sum block
+constexpr int TN_ROWS = 256;   // rows per partial-sum block
+constexpr int TN_COLS = 64;    // right-hand sides per block
 
-// part[blk][v][c] = sum over the block's rows of Q[i, c] * C[i, v].
+// part[blk][v][c] = sum over the block's rows of Q[i, c] * C[i, v]
+// (k * TN_COLS outputs per block, up to 16 per thread).
 __global__ void __launch_bounds__(256)
 k_gemm_tn_part(const double* __restrict__ Q, int64_t ldq, int64_t m, int k, const double* __restrict__ C,
                int64_t ldc, int64_t ncol, double* __restrict__ part) {
-  __shared__ double qs[32 * KMAX];
-  __shared__ double cs[32 * 16];
+  __shared__ double qs[32 * (KMAX + 1)];
+  __shared__ double cs[32 * (TN_COLS + 1)];
   const int64_t r0 = (int64_t)blockIdx.x * TN_ROWS;
-  const int64_t v0 = (int64_t)blockIdx.y * 16;
-  const int nv = (int)std::min<int64_t>(16, ncol - v0);
+  const int64_t v0 = (int64_t)blockIdx.y * TN_COLS;
+  const int nv = (int)std::min<int64_t>(TN_COLS, ncol - v0);
   const int t = threadIdx.x;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  // thread owns outputs e = t + 256*u, e -> (c = e % k, v = e / k), k*16 <= 1024
-  for (int64_t rb = r0; rb < std::min<int64_t>(m, r0 + TN_ROWS); rb += 32) {
-    const int nr = (int)std::min<int64_t>(32, m - rb);
+  const int nout = k * nv;
+  double acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+  const int64_t rend = std::min<int64_t>(m, r0 + TN_ROWS);
+  for (int64_t rb = r0; rb < rend; rb += 32) {
+    const int nr = (int)std::min<int64_t>(32, rend - rb);
     for (int e = t; e < 32 * k; e += 256) {
       const int r = e % 32, c = e / 32;
-      qs[r * KMAX + c] = r < nr ? Q[rb + r + ldq * c] : 0.0;
+      qs[r * (KMAX + 1) + c] = r < nr ? Q[rb + r + ldq * c] : 0.0;
     }
-    for (int e = t; e < 32 * 16; e += 256) {
+    for (int e = t; e < 32 * nv; e += 256) {
       const int r = e % 32, v = e / 32;
-      cs[r * 16 + v] = (r < nr && v < nv) ? C[rb + r + ldc * (v0 + v)] : 0.0;
+      cs[r * (TN_COLS + 1) + v] = r < nr ? C[rb + r + ldc * (v0 + v)] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const int e = t + 256 * u;
-      if (e < k * 16) {
+      if (e < nout) {
         const int c = e % k, v = e / k;
         double a = acc[u];
-        for (int r = 0; r < 32; ++r) a = fma(qs[r * KMAX + c], cs[r * 16 + v], a);
+#pragma unroll 8
+        for (int r = 0; r < 32; ++r) a = fma(qs[r * (KMAX + 1) + c], cs[r * (TN_COLS + 1) + v], a);
         acc[u] = a;
       }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < 16; ++u) {
     const int e = t + 256 * u;
-    if (e < k * 16) {
+    if (e < nout) {
       const int c = e % k, v = e / k;
-      if (v < nv) part[((int64_t)blockIdx.x * ncol + v0 + v) * k + c] = acc[u];
+      part[((int64_t)blockIdx.x * ncol + v0 + v) * k + c] = acc[u];
     }
   }
 }
@@ -444,27 +571,52 @@ __global__ void k_reduce_part(const double* __restrict__ part, int64_t nblk, int
                               double* __restrict__ T) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)k * ncol) return;
-  double s = 0.0;
-  for (int64_t b = 0; b < nblk; ++b) s += part[b * ncol * k + e];
-  T[e] = s;
+  // eight independent partial sums keep eight loads in flight
+  const int64_t st = ncol * k;
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t b = 0;
+  for (; b + 8 <= nblk; b += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += part[(b + u) * st + e];
+  }
+  for (; b < nblk; ++b) s[0] += part[b * st + e];
+  T[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
-// Sum of squares of each column (one block per column, fixed-order tree).
+constexpr int NORM_CHUNKS = 32;
+
+// part[col * NORM_CHUNKS + chunk] = sum of squares over the chunk's rows.
 __global__ void __launch_bounds__(256)
-k_colnorm2(const double* __restrict__ X, int64_t ld, int64_t m, double* __restrict__ out) {
+k_colnorm2_part(const double* __restrict__ X, int64_t ld, int64_t m, double* __restrict__ part) {
   __shared__ double red[4];
-  const double* x = X + ld * (int64_t)blockIdx.x;
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < m; i += 256) s = fma(x[i], x[i], s);
-  s = wave_sum(s);
+  const int64_t col = blockIdx.y;
+  const int64_t per = (m + NORM_CHUNKS - 1) / NORM_CHUNKS;
+  const int64_t lo = blockIdx.x * per, hi = std::min<int64_t>(m, lo + per);
+  const double* x = X + ld * col;
+  double s0 = 0.0, s1 = 0.0;
+  int64_t i = lo + threadIdx.x;
+  for (; i + 256 < hi; i += 512) {
+    s0 = fma(x[i], x[i], s0);
+    s1 = fma(x[i + 256], x[i + 256], s1);
+  }
+  if (i < hi) s0 = fma(x[i], x[i], s0);
+  double s = wave_sum(s0 + s1);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) part[col * NORM_CHUNKS + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ void k_ratio_sqrt(const double* num, const double* den, double* out, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = den[i] > 0.0 ? sqrt(num[i] / den[i]) : sqrt(num[i]);
+// out[c] = sqrt(sum num parts / sum den parts), parts summed in order.
+__global__ void k_relres(const double* __restrict__ num, const double* __restrict__ den, double* out,
+                         int64_t n) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < NORM_CHUNKS; ++i) {
+    a += num[c * NORM_CHUNKS + i];
+    b += den[c * NORM_CHUNKS + i];
+  }
+  out[c] = b > 0.0 ? sqrt(a / b) : sqrt(a);
 }
 
 static int gemm_nn(const double* A, int64_t lda, int64_t m, int k, const double* B, int64_t ldb, int64_t ncol,
@@ -484,8 +636,8 @@ static int gemm_tn(const double* Q, int64_t ldq, int64_t m, int k, const double*
   const int64_t nb = tn_blocks(m);
   {
     Prof pr("gemm_tn", 8.0 * m * (k + ncol), st);
-    k_gemm_tn_part<<<dim3((unsigned)nb, (unsigned)((ncol + 15) / 16)), 256, 0, st>>>(Q, ldq, m, k, C, ldc, ncol,
-                                                                                    part);
+    k_gemm_tn_part<<<dim3((unsigned)nb, (unsigned)((ncol + TN_COLS - 1) / TN_COLS)), 256, 0, st>>>(
+        Q, ldq, m, k, C, ldc, ncol, part);
   }
   AZ_HIP(hipGetLastError());
   const int64_t ne = (int64_t)k * ncol;
@@ -493,12 +645,16 @@ static int gemm_tn(const double* Q, int64_t ldq, int64_t m, int k, const double*
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
-static int copy_cols(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t rows, int64_t cols,
-                     hipStream_t st) {
-  if (rows <= 0 || cols <= 0) return AZRBF_OK;
-  AZ_HIP(hipMemcpy2DAsync(dst, sizeof(double) * ldd, src, sizeof(double) * lds, sizeof(double) * rows, cols,
-                          hipMemcpyDeviceToDevice, st));
-  return AZRBF_OK;
+static int relres_norms(const double* R, int64_t ldr, const double* B, int64_t ldb, int64_t m, int64_t ncol,
+                        double* scratch, double* out, hipStream_t st) {
+  const dim3 grid(NORM_CHUNKS, (unsigned)ncol);
+  Prof pr("relres", 16.0 * m * ncol, st);
+  k_colnorm2_part<<<grid, 256, 0, st>>>(R, ldr, m, scratch);
+  AZ_HIP(hipGetLastError());
+  k_colnorm2_part<<<grid, 256, 0, st>>>(B, ldb, m, scratch + NORM_CHUNKS * ncol);
+  AZ_HIP(hipGetLastError());
+  k_relres<<<(unsigned)((ncol + 255) / 256), 256, 0, st>>>(scratch, scratch + NORM_CHUNKS * ncol, out, ncol);
+  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
 // ------------------------------------------------------------------ factor
@@ -510,40 +666,43 @@ int dense_factor(Plan& P, hipStream_t st) {
   const int64_t N = P.N, Mt = P.Mt;
   if (!P.Om) {
     AZ_TRY(P.alloc((void**)&P.Om, sizeof(double) * N * k));
+    AZ_TRY(P.alloc((void**)&P.Om2, sizeof(double) * N * k));
     AZ_TRY(P.alloc((void**)&P.Yf, sizeof(double) * Mt * k));
+    AZ_TRY(P.alloc((void**)&P.Yf2, sizeof(double) * Mt * k));
     AZ_TRY(P.alloc((void**)&P.Q, sizeof(double) * Mt * k));
     AZ_TRY(P.alloc((void**)&P.Rf, sizeof(double) * k * k));
     AZ_TRY(P.alloc((void**)&P.sig, sizeof(double) * k));
     AZ_TRY(P.alloc((void**)&P.Pm, sizeof(double) * k * k));
-    const int64_t sd = N * k + Mt * k + tsqr_scratch_doubles(Mt, k) + 8;
+    const int64_t sd = tsqr_scratch_doubles(Mt, k) + 8;
     AZ_TRY(P.alloc((void**)&P.dscr, sizeof(double) * sd));
     P.dscr_bytes = sizeof(double) * sd;
   }
-  double* Zy = P.dscr;                 // N x k
-  double* W = Zy + N * k;              // Mt x k
-  double* tq = W + Mt * k;             // TSQR scratch
+  double* Zy = P.Om2;                  // N x k scratch, later Omega P
+  double* W = P.Yf2;                   // Mt x k sketch, later (A Omega) P
+  double* tq = P.dscr;                 // TSQR scratch
   int* info = (int*)(tq + tsqr_scratch_doubles(Mt, k));
   AZ_TRY(dense_gaussian(P.prob.seed, N, k, P.Om, N, st));
-  AZ_TRY(ops_apply_A(P, P.Om, N, k, 1.0, 0.0, P.Yf, Mt, st));        // Y = A Omega
-  AZ_TRY(ops_apply_Z(P, P.Yf, Mt, k, 1.0, 0.0, Zy, N, st));          // Z* Y
-  AZ_TRY(copy_cols(P.Yf, Mt, W, Mt, Mt, k, st));
-  AZ_TRY(ops_apply_A(P, Zy, N, k, -1.0, 1.0, W, Mt, st));            // W = Y - A Z* Y
+  AZ_TRY(ops_apply_A(P, P.Om, N, k, 1.0, 0.0, nullptr, 0, P.Yf, Mt, st));     // Y = A Omega
+  AZ_TRY(ops_apply_Z(P, P.Yf, Mt, k, 1.0, 0.0, nullptr, 0, Zy, N, st));       // Z* Y
+  AZ_TRY(ops_apply_A(P, Zy, N, k, -1.0, 1.0, P.Yf, Mt, W, Mt, st));          // W = Y - A Z* Y
+  // TSQR destroys W; the QR is of the sketch, W is then free scratch
   AZ_TRY(tsqr(W, Mt, k, tq, P.Q, P.Rf, st));
   const double thr = P.tau * P.normA * sqrt((double)k);
   {
     Prof pj("jacobi", 8.0 * 3 * k * k, st);
-    k_jacobi<<<1, 256, 0, st>>>(P.Rf, k, thr, 1e-15, 60, P.sig, P.Pm, info);
+    k_jacobi<<<1, 256, 0, st>>>(P.Rf, k, thr, 4.0 * k * 1.1102230246251565e-16, 40, P.sig, P.Pm, info);
   }
   AZ_HIP(hipGetLastError());
-  // Omega <- Omega Pm, Y <- Y Pm (row-wise in place: a thread reads its whole row first)
+  // Omega P and (A Omega) P: the solve needs only these (y = P Q^T c)
   AZ_TRY(gemm_nn(P.Om, N, N, k, P.Pm, k, k, 1.0, nullptr, 0, 0.0, Zy, N, st));
-  AZ_TRY(copy_cols(Zy, N, P.Om, N, N, k, st));
   AZ_TRY(gemm_nn(P.Yf, Mt, Mt, k, P.Pm, k, k, 1.0, nullptr, 0, 0.0, W, Mt, st));
-  AZ_TRY(copy_cols(W, Mt, P.Yf, Mt, Mt, k, st));
+  std::swap(P.Om, P.Om2);
+  std::swap(P.Yf, P.Yf2);
   int hinfo[2];
   AZ_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
   AZ_HIP(hipStreamSynchronize(st));
   P.rank = hinfo[0];
+  P.sweeps = hinfo[1];
   P.factored = true;
   return P.rank >= k ? AZRBF_ERANK : AZRBF_OK;
 }
@@ -554,9 +713,10 @@ int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, 
                 hipStream_t st) {
   const int k = P.k;
   const int64_t N = P.N, Mt = P.Mt;
+  const int64_t nparts = tn_blocks(Mt) * ((nrhs + TN_COLS - 1) / TN_COLS) * TN_COLS;
   if (nrhs > P.sw_rhs) {
-    const int64_t per = N + 3 * Mt + k + tn_blocks(Mt) * k + 2;
-    AZ_TRY(P.alloc((void**)&P.sw, sizeof(double) * per * nrhs));
+    const int64_t per = N + 3 * Mt + k + tn_blocks(Mt) * k + 2 * NORM_CHUNKS;
+    AZ_TRY(P.alloc((void**)&P.sw, sizeof(double) * (per * nrhs + nparts * k)));
     P.sw_rhs = nrhs;
   }
   double* Zr = P.sw;                   // N x nrhs
@@ -564,31 +724,22 @@ int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, 
   double* R1 = C + Mt * nrhs;          // Mt x nrhs
   double* Rc = R1 + Mt * nrhs;         // Mt x nrhs
   double* Tm = Rc + Mt * nrhs;         // k x nrhs
-  double* part = Tm + (int64_t)k * nrhs;
-  double* nrm = part + tn_blocks(Mt) * k * nrhs;   // 2 x nrhs
+  double* nrm = Tm + (int64_t)k * nrhs;            // 2 * NORM_CHUNKS x nrhs
+  double* part = nrm + 2 * NORM_CHUNKS * nrhs;     // TSQR-free GEMM partials
   const double* rin = B;
   int64_t ldr = ldb;
   for (int it = 0; it <= P.refine; ++it) {
-    AZ_TRY(ops_apply_Z(P, rin, ldr, nrhs, 1.0, 0.0, Zr, N, st));              // Z* r
-    AZ_TRY(copy_cols(rin, ldr, C, Mt, Mt, nrhs, st));
-    AZ_TRY(ops_apply_A(P, Zr, N, nrhs, -1.0, 1.0, C, Mt, st));                // c = (I - A Z*) r
-    AZ_TRY(gemm_tn(P.Q, Mt, Mt, k, C, Mt, nrhs, part, Tm, st));               // t = Q^T c
-    AZ_TRY(gemm_nn(P.Om, N, N, k, Tm, k, nrhs, 1.0, X, ldx, it == 0 ? 0.0 : 1.0, X, ldx, st));  // x1
+    AZ_TRY(ops_apply_Z(P, rin, ldr, nrhs, 1.0, 0.0, nullptr, 0, Zr, N, st));        // Z* r
+    AZ_TRY(ops_apply_A(P, Zr, N, nrhs, -1.0, 1.0, rin, ldr, C, Mt, st));           // c = (I - A Z*) r
+    AZ_TRY(gemm_tn(P.Q, Mt, Mt, k, C, Mt, nrhs, part, Tm, st));                     // t = Q^T c
+    AZ_TRY(gemm_nn(P.Om, N, N, k, Tm, k, nrhs, 1.0, X, ldx, it == 0 ? 0.0 : 1.0, X, ldx, st));  // x += x1
     AZ_TRY(gemm_nn(P.Yf, Mt, Mt, k, Tm, k, nrhs, -1.0, rin, ldr, 1.0, R1, Mt, st));            // r - A x1
-    AZ_TRY(ops_apply_Z(P, R1, Mt, nrhs, 1.0, 1.0, X, ldx, st));               // x += Z* (r - A x1)
-    AZ_TRY(copy_cols(B, ldb, Rc, Mt, Mt, nrhs, st));
-    AZ_TRY(ops_apply_A(P, X, ldx, nrhs, -1.0, 1.0, Rc, Mt, st));              // residual b - A x
+    AZ_TRY(ops_apply_Z(P, R1, Mt, nrhs, 1.0, 1.0, nullptr, 0, X, ldx, st));          // x += Z* (r - A x1)
+    AZ_TRY(ops_apply_A(P, X, ldx, nrhs, -1.0, 1.0, B, ldb, Rc, Mt, st));            // residual b - A x
     rin = Rc;
     ldr = Mt;
   }
-  if (relres) {
-    k_colnorm2<<<(unsigned)nrhs, 256, 0, st>>>(Rc, Mt, Mt, nrm);
-    AZ_HIP(hipGetLastError());
-    k_colnorm2<<<(unsigned)nrhs, 256, 0, st>>>(B, ldb, Mt, nrm + nrhs);
-    AZ_HIP(hipGetLastError());
-    k_ratio_sqrt<<<(unsigned)((nrhs + 255) / 256), 256, 0, st>>>(nrm, nrm + nrhs, relres, nrhs);
-    AZ_HIP(hipGetLastError());
-  }
+  if (relres) AZ_TRY(relres_norms(Rc, Mt, B, ldb, Mt, nrhs, nrm, relres, st));
   return AZRBF_OK;
 }
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
 #include <vector>
 
 #include "../../include/azrbf.h"
@@ -70,13 +71,16 @@ struct Prof {
   }
 };
 
+int pool_trim();
+
 // ops.hip
 int ops_init_twiddles(int device, const double2** tw);
 int ops_spectra(Plan& P, hipStream_t st);
+// Y = alpha A X + beta Yin (Yin null: Yin = Y); Z = alpha Z* R + beta Zin likewise.
 int ops_apply_A(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta,
-                double* Y, int64_t ldy, hipStream_t st);
+                const double* Yin, int64_t ldyi, double* Y, int64_t ldy, hipStream_t st);
 int ops_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,
-                double* Z, int64_t ldz, hipStream_t st);
+                const double* Zin, int64_t ldzi, double* Z, int64_t ldz, hipStream_t st);
 
 // dense.hip
 int dense_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* dst, int64_t ld, hipStream_t st);
@@ -94,8 +98,10 @@ struct Plan {
   Geo geo{};
   const double2* tw = nullptr;            // shared twiddle table (per device)
 
-  // device memory owned by the plan
-  std::vector<void*> allocs;
+  hipStream_t last_stream = nullptr;      // stream of the plan's latest work
+
+  // device memory owned by the plan (pointer, pool size class)
+  std::vector<std::pair<void*, int64_t>> allocs;
   int64_t bytes = 0;
   int32_t* inv = nullptr;
   double2* spA = nullptr;
@@ -116,8 +122,11 @@ struct Plan {
   int k = 0, rank = -1, refine = 0;
   double tau = 1e-12, tauZ = 1e-12;
   bool factored = false;
+  int sweeps = 0;            // Jacobi sweeps of the last factor
   double* Om = nullptr;     // N x k, then Omega * P
+  double* Om2 = nullptr;    // N x k scratch
   double* Yf = nullptr;     // Mt x k, A Omega, then (A Omega) * P
+  double* Yf2 = nullptr;    // Mt x k scratch (the sketch W)
   double* Q = nullptr;      // Mt x k
   double* Rf = nullptr;     // k x k
   double* sig = nullptr;    // k

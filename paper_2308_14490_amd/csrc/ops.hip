@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
 
@@ -92,13 +93,16 @@ __device__ __forceinline__ double2 specZ(const Geo& g, int ph, int ka, int kb) {
   return cscale(cconj(spec2d(g, ph, ka, kb)), g.w2[(int64_t)ka * g.N2 + kb]);
 }
 
-__device__ __forceinline__ void store_pair(double* Y, int64_t ldy, int64_t row, int64_t v0, int64_t nvec,
-                                           double2 val, double alpha, double beta) {
+// Y[row, v0..v0+1] = alpha * val + beta * Yin[row, v0..v0+1] (Yin unread if beta == 0;
+// Yin may equal Y).
+__device__ __forceinline__ void store_pair(double* Y, int64_t ldy, const double* Yin, int64_t ldyi, int64_t row,
+                                           int64_t v0, int64_t nvec, double2 val, double alpha, double beta) {
   double* p0 = Y + row + ldy * v0;
-  *p0 = beta == 0.0 ? alpha * val.x : fma(alpha, val.x, beta * *p0);
+  const double* q0 = Yin + row + ldyi * v0;
+  *p0 = beta == 0.0 ? alpha * val.x : fma(alpha, val.x, beta * *q0);
   if (v0 + 1 < nvec) {
     double* p1 = p0 + ldy;
-    *p1 = beta == 0.0 ? alpha * val.y : fma(alpha, val.y, beta * *p1);
+    *p1 = beta == 0.0 ? alpha * val.y : fma(alpha, val.y, beta * q0[ldyi]);
   }
 }
 
@@ -119,10 +123,13 @@ struct Fused {
 
 // ------------------------------------------------------------------ fused 1D
 
-template <int N>
+// The s phase results of a coefficient index are adjacent on the fine grid
+// (rows s*e + r): they are computed into registers first and written
+// together, so each store instruction covers contiguous rows.
+template <int N, int S>
 __global__ void __launch_bounds__(Fused<N>::BLOCK)
 k_fused_A(Geo g, const double2* __restrict__ tw, const double* __restrict__ X, int64_t ldx,
-          int64_t nvec, double alpha, double beta, double* __restrict__ Y, int64_t ldy) {
+          int64_t nvec, double alpha, double beta, const double* Yin, int64_t ldyi, double* Y, int64_t ldy) {
   using F = Fused<N>;
   extern __shared__ double2 smem[];
   const RowLds lds{smem, RowLds::stride(N)};
@@ -132,49 +139,57 @@ k_fused_A(Geo g, const double2* __restrict__ tw, const double* __restrict__ X, i
 #pragma unroll
   for (int m = 0; m < RADIX; ++m) a[m] = load_pair(X, ldx, t + m * F::T, v0, nvec);
   fft_line<N, false>(a, lds, line, t, tw);
-  for (int r = 0; r < g.s; ++r) {
-    double2 b[RADIX];
+  double2 res[S][RADIX];
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) b[m] = cmul(a[m], g.spA[(int64_t)r * N + t + m * F::T]);
-    fft_line<N, true>(b, lds, line, t, tw);
-    if (v0 < nvec) {
+  for (int r = 0; r < S; ++r) {
 #pragma unroll
-      for (int m = 0; m < RADIX; ++m) {
-        const int64_t row = (int64_t)g.s * (t + m * F::T) + r - g.i0;
-        if (row >= 0 && row < g.M) store_pair(Y, ldy, row, v0, nvec, b[m], alpha, beta);
+    for (int m = 0; m < RADIX; ++m) res[r][m] = cmul(a[m], g.spA[(int64_t)r * N + t + m * F::T]);
+    fft_line<N, true>(res[r], lds, line, t, tw);
+  }
+  if (v0 < nvec) {
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) {
+#pragma unroll
+      for (int r = 0; r < S; ++r) {
+        const int64_t row = (int64_t)S * (t + m * F::T) + r - g.i0;
+        if (row >= 0 && row < g.M) store_pair(Y, ldy, Yin, ldyi, row, v0, nvec, res[r][m], alpha, beta);
       }
     }
   }
 }
 
-template <int N>
+template <int N, int S>
 __global__ void __launch_bounds__(Fused<N>::BLOCK)
 k_fused_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R, int64_t ldr,
-          int64_t nvec, double alpha, double beta, double* __restrict__ Z, int64_t ldz) {
+          int64_t nvec, double alpha, double beta, const double* Zin, int64_t ldzi, double* Z, int64_t ldz) {
   using F = Fused<N>;
   extern __shared__ double2 smem[];
   const RowLds lds{smem, RowLds::stride(N)};
   const int t = threadIdx.x % F::T, line = threadIdx.x / F::T;
   const int64_t v0 = 2 * ((int64_t)blockIdx.x * F::LINES + line);
+  double2 in[S][RADIX];
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) {
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const int64_t row = (int64_t)S * (t + m * F::T) + q - g.i0;
+      in[q][m] = (row >= 0 && row < g.M) ? load_pair(R, ldr, row, v0, nvec) : make_double2(0.0, 0.0);
+    }
+  }
   double2 acc[RADIX];
 #pragma unroll
   for (int m = 0; m < RADIX; ++m) acc[m] = make_double2(0.0, 0.0);
-  for (int q = 0; q < g.s; ++q) {
-    double2 a[RADIX];
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) {
-      const int64_t row = (int64_t)g.s * (t + m * F::T) + q - g.i0;
-      a[m] = (row >= 0 && row < g.M) ? load_pair(R, ldr, row, v0, nvec) : make_double2(0.0, 0.0);
-    }
-    fft_line<N, false>(a, lds, line, t, tw);
+  for (int q = 0; q < S; ++q) {
+    fft_line<N, false>(in[q], lds, line, t, tw);
 #pragma unroll
     for (int m = 0; m < RADIX; ++m)
-      acc[m] = cadd(acc[m], cmul(a[m], g.spZ[(int64_t)q * N + t + m * F::T]));
+      acc[m] = cadd(acc[m], cmul(in[q][m], g.spZ[(int64_t)q * N + t + m * F::T]));
   }
   fft_line<N, true>(acc, lds, line, t, tw);
   if (v0 < nvec) {
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) store_pair(Z, ldz, t + m * F::T, v0, nvec, acc[m], alpha, beta);
+    for (int m = 0; m < RADIX; ++m) store_pair(Z, ldz, Zin, ldzi, t + m * F::T, v0, nvec, acc[m], alpha, beta);
   }
 }
 
@@ -278,10 +293,13 @@ k_row_A(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws1,
 }
 
 // P3 of A: column IDFT of every phase, restriction to collocation rows.
-template <int N1>
+// Phases are taken in groups of S whose fine-grid points are adjacent
+// (1D: all s phases; 2D: the s values of ry for one rx) and stored together.
+template <int N1, int S>
 __global__ void __launch_bounds__(256)
 k_col_inv_A(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws2, int64_t nvec,
-            int64_t pair0, double alpha, double beta, double* __restrict__ Y, int64_t ldy, int C) {
+            int64_t pair0, double alpha, double beta, const double* Yin, int64_t ldyi, double* Y, int64_t ldy,
+            int C) {
   constexpr int T = Col<N1>::T;
   extern __shared__ double2 smem[];
   const ColLds lds{smem, C};
@@ -289,23 +307,30 @@ k_col_inv_A(Geo g, const double2* __restrict__ tw, const double2* __restrict__ w
   const int64_t b = (int64_t)blockIdx.x * C + l;
   const int64_t pair = blockIdx.y;
   const int64_t v0 = 2 * (pair0 + pair);
-  const int nph = g.dim == 1 ? g.s : g.s * g.s;
-  for (int ph = 0; ph < nph; ++ph) {
-    double2 a[RADIX];
-    const double2* in = ws2 + (pair * nph + ph) * g.N;
+  const int nph = g.dim == 1 ? S : S * S;
+  for (int gx = 0; gx < nph; gx += S) {
+    double2 res[S][RADIX];
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) a[m] = in[(int64_t)(t + m * T) * g.N2 + b];
-    fft_line<N1, true>(a, lds, l, t, tw);
+    for (int ry = 0; ry < S; ++ry) {
+      const double2* in = ws2 + (pair * nph + gx + ry) * g.N;
+#pragma unroll
+      for (int m = 0; m < RADIX; ++m) res[ry][m] = in[(int64_t)(t + m * T) * g.N2 + b];
+      fft_line<N1, true>(res[ry], lds, l, t, tw);
+    }
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) {
-      const int64_t row = row_of(g, grid_index(g, ph, t + m * T, b));
-      if (row >= 0) store_pair(Y, ldy, row, v0, nvec, a[m], alpha, beta);
+#pragma unroll
+      for (int ry = 0; ry < S; ++ry) {
+        const int64_t row = row_of(g, grid_index(g, gx + ry, t + m * T, b));
+        if (row >= 0) store_pair(Y, ldy, Yin, ldyi, row, v0, nvec, res[ry][m], alpha, beta);
+      }
     }
   }
 }
 
-// P1 of Z*: extension by zero to each phase grid, column DFT, twiddle.
-template <int N1, bool TWID>
+// P1 of Z*: extension by zero to each phase grid (phases adjacent on the
+// fine grid loaded together), column DFT, twiddle.
+template <int N1, bool TWID, int S>
 __global__ void __launch_bounds__(256)
 k_col_fwd_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R, int64_t ldr,
             int64_t nvec, int64_t pair0, double2* __restrict__ ws1, int C) {
@@ -316,22 +341,28 @@ k_col_fwd_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R,
   const int64_t b = (int64_t)blockIdx.x * C + l;
   const int64_t pair = blockIdx.y;
   const int64_t v0 = 2 * (pair0 + pair);
-  const int nph = g.dim == 1 ? g.s : g.s * g.s;
-  for (int ph = 0; ph < nph; ++ph) {
-    double2 a[RADIX];
+  const int nph = g.dim == 1 ? S : S * S;
+  for (int gx = 0; gx < nph; gx += S) {
+    double2 in[S][RADIX];
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) {
-      const int64_t row = row_of(g, grid_index(g, ph, t + m * T, b));
-      a[m] = row >= 0 ? load_pair(R, ldr, row, v0, nvec) : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int ry = 0; ry < S; ++ry) {
+        const int64_t row = row_of(g, grid_index(g, gx + ry, t + m * T, b));
+        in[ry][m] = row >= 0 ? load_pair(R, ldr, row, v0, nvec) : make_double2(0.0, 0.0);
+      }
     }
-    fft_line<N1, false>(a, lds, l, t, tw);
-    double2* out = ws1 + (pair * nph + ph) * g.N;
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) {
-      const int64_t k1 = t + m * T;
-      double2 v = a[m];
-      if (TWID) v = cmul(v, tw_fwd(tw, k1 * b, g.N));
-      out[k1 * g.N2 + b] = v;
+    for (int ry = 0; ry < S; ++ry) {
+      fft_line<N1, false>(in[ry], lds, l, t, tw);
+      double2* out = ws1 + (pair * nph + gx + ry) * g.N;
+#pragma unroll
+      for (int m = 0; m < RADIX; ++m) {
+        const int64_t k1 = t + m * T;
+        double2 v = in[ry][m];
+        if (TWID) v = cmul(v, tw_fwd(tw, k1 * b, g.N));
+        out[k1 * g.N2 + b] = v;
+      }
     }
   }
 }
@@ -374,7 +405,8 @@ k_row_Z(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws1,
 template <int N1>
 __global__ void __launch_bounds__(256)
 k_col_inv_Z(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws2, int64_t nvec,
-            int64_t pair0, double alpha, double beta, double* __restrict__ Z, int64_t ldz, int C) {
+            int64_t pair0, double alpha, double beta, const double* Zin, int64_t ldzi, double* Z, int64_t ldz,
+            int C) {
   constexpr int T = Col<N1>::T;
   extern __shared__ double2 smem[];
   const ColLds lds{smem, C};
@@ -388,7 +420,8 @@ k_col_inv_Z(Geo g, const double2* __restrict__ tw, const double2* __restrict__ w
   for (int m = 0; m < RADIX; ++m) a[m] = in[(int64_t)(t + m * T) * g.N2 + b];
   fft_line<N1, true>(a, lds, l, t, tw);
 #pragma unroll
-  for (int m = 0; m < RADIX; ++m) store_pair(Z, ldz, (int64_t)(t + m * T) * g.N2 + b, v0, nvec, a[m], alpha, beta);
+  for (int m = 0; m < RADIX; ++m)
+    store_pair(Z, ldz, Zin, ldzi, (int64_t)(t + m * T) * g.N2 + b, v0, nvec, a[m], alpha, beta);
 }
 
 // Plain forward FFT of complex N1 x N2 arrays in the engine's layout (spectra set-up):
@@ -449,8 +482,8 @@ __device__ __forceinline__ double phi_per_dev(double d, double eps, double T, in
 
 __global__ void k_boundary_A(int dim, int n, double T, double h, double eps, int mimg, int W,
                              const double* __restrict__ bp, int64_t Mb, double bw, const double* __restrict__ X,
-                             int64_t ldx, int64_t nvec, double alpha, double beta, double* __restrict__ Y,
-                             int64_t ldy, int64_t M) {
+                             int64_t ldx, int64_t nvec, double alpha, double beta, const double* Yin,
+                             int64_t ldyi, double* Y, int64_t ldy, int64_t M) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t v = blockIdx.y;
   if (i >= Mb || v >= nvec) return;
@@ -489,8 +522,7 @@ __global__ void k_boundary_A(int dim, int n, double T, double h, double eps, int
       acc = fma(wx[ox], r, acc);
     }
   }
-  double* y = Y + M + i + ldy * v;
-  *y = beta == 0.0 ? alpha * bw * acc : fma(alpha * bw, acc, beta * *y);
+  Y[M + i + ldy * v] = beta == 0.0 ? alpha * bw * acc : fma(alpha * bw, acc, beta * Yin[M + i + ldyi * v]);
 }
 
 // ------------------------------------------------------------------ spectra set-up
@@ -580,13 +612,19 @@ __global__ void k_weights_2d(double* w2, const double* D, int64_t N, double tauZ
 
 // ------------------------------------------------------------------ dispatch
 
+// Kernels that need more than 64 KiB of LDS get the attribute once (the
+// largest request seen so far is kept per kernel).
 template <class K>
 static int set_lds(K kern, int bytes) {
-  if (bytes > 64 * 1024) {
-    if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) !=
-        hipSuccess)
-      return AZRBF_EHIP;
-  }
+  if (bytes <= 64 * 1024) return AZRBF_OK;
+  static std::mutex mu;
+  static std::map<const void*, int> done;
+  std::lock_guard<std::mutex> lk(mu);
+  int& have = done[(const void*)kern];
+  if (have >= bytes) return AZRBF_OK;
+  if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
+    return AZRBF_EHIP;
+  have = bytes;
   return AZRBF_OK;
 }
 
@@ -616,32 +654,52 @@ static int set_lds(K kern, int bytes) {
     default: return AZRBF_EUNSUPPORTED;                                            \
   }
 
-template <int N>
-static int launch_fused_A(const Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha,
-                          double beta, double* Y, int64_t ldy, hipStream_t st) {
+template <int N, int S>
+static int launch_fused_A_s(const Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha,
+                            double beta, const double* Yin, int64_t ldyi, double* Y, int64_t ldy, hipStream_t st) {
   using F = Fused<N>;
-  AZ_TRY(set_lds(k_fused_A<N>, F::LDS));
+  AZ_TRY(set_lds(k_fused_A<N, S>, F::LDS));
   const int64_t npairs = (nvec + 1) / 2;
   const int64_t blocks = (npairs + F::LINES - 1) / F::LINES;
   static const std::string name = "fused_A n=" + std::to_string(N);
   Prof pr(name.c_str(), 8.0 * nvec * (N + P.M * (beta != 0.0 ? 2.0 : 1.0)) + 16.0 * P.s * N, st);
-  k_fused_A<N><<<dim3((unsigned)blocks), dim3(F::BLOCK), F::LDS, st>>>(P.geo, P.tw, X, ldx, nvec, alpha,
-                                                                       beta, Y, ldy);
+  k_fused_A<N, S><<<dim3((unsigned)blocks), dim3(F::BLOCK), F::LDS, st>>>(P.geo, P.tw, X, ldx, nvec, alpha,
+                                                                          beta, Yin, ldyi, Y, ldy);
+  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+}
+
+template <int N>
+static int launch_fused_A(const Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha,
+                          double beta, const double* Yin, int64_t ldyi, double* Y, int64_t ldy, hipStream_t st) {
+  switch (P.s) {
+    case 1: return launch_fused_A_s<N, 1>(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st);
+    case 2: return launch_fused_A_s<N, 2>(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st);
+    default: return launch_fused_A_s<N, 4>(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st);
+  }
+}
+
+template <int N, int S>
+static int launch_fused_Z_s(const Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha,
+                            double beta, const double* Zin, int64_t ldzi, double* Z, int64_t ldz, hipStream_t st) {
+  using F = Fused<N>;
+  AZ_TRY(set_lds(k_fused_Z<N, S>, F::LDS));
+  const int64_t npairs = (nvec + 1) / 2;
+  const int64_t blocks = (npairs + F::LINES - 1) / F::LINES;
+  static const std::string name = "fused_Z n=" + std::to_string(N);
+  Prof pr(name.c_str(), 8.0 * nvec * (P.M + N * (beta != 0.0 ? 2.0 : 1.0)) + 16.0 * P.s * N, st);
+  k_fused_Z<N, S><<<dim3((unsigned)blocks), dim3(F::BLOCK), F::LDS, st>>>(P.geo, P.tw, R, ldr, nvec, alpha,
+                                                                          beta, Zin, ldzi, Z, ldz);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
 template <int N>
 static int launch_fused_Z(const Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha,
-                          double beta, double* Z, int64_t ldz, hipStream_t st) {
-  using F = Fused<N>;
-  AZ_TRY(set_lds(k_fused_Z<N>, F::LDS));
-  const int64_t npairs = (nvec + 1) / 2;
-  const int64_t blocks = (npairs + F::LINES - 1) / F::LINES;
-  static const std::string name = "fused_Z n=" + std::to_string(N);
-  Prof pr(name.c_str(), 8.0 * nvec * (P.M + N * (beta != 0.0 ? 2.0 : 1.0)) + 16.0 * P.s * N, st);
-  k_fused_Z<N><<<dim3((unsigned)blocks), dim3(F::BLOCK), F::LDS, st>>>(P.geo, P.tw, R, ldr, nvec, alpha,
-                                                                       beta, Z, ldz);
-  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+                          double beta, const double* Zin, int64_t ldzi, double* Z, int64_t ldz, hipStream_t st) {
+  switch (P.s) {
+    case 1: return launch_fused_Z_s<N, 1>(P, R, ldr, nvec, alpha, beta, Zin, ldzi, Z, ldz, st);
+    case 2: return launch_fused_Z_s<N, 2>(P, R, ldr, nvec, alpha, beta, Zin, ldzi, Z, ldz, st);
+    default: return launch_fused_Z_s<N, 4>(P, R, ldr, nvec, alpha, beta, Zin, ldzi, Z, ldz, st);
+  }
 }
 
 template <int N>
@@ -675,6 +733,8 @@ struct ColArgs {
   double2* cout;
   int64_t nvec, pair0, npairs;
   double alpha, beta;
+  const double* oin;
+  int64_t ldoi;
   double* out;
   int64_t ldo;
   hipStream_t st;
@@ -715,23 +775,28 @@ static int launch_col(const ColArgs& a) {
       }
       break;
     case 1:
-      AZ_TRY(set_lds(k_col_inv_A<N1>, lds));
-      k_col_inv_A<N1><<<grid, block, lds, a.st>>>(g, P.tw, a.cin, a.nvec, a.pair0, a.alpha, a.beta, a.out,
-                                                  a.ldo, C);
+#define AZ_COLINV(S)                                                                                    \
+  AZ_TRY(set_lds(k_col_inv_A<N1, S>, lds));                                                             \
+  k_col_inv_A<N1, S><<<grid, block, lds, a.st>>>(g, P.tw, a.cin, a.nvec, a.pair0, a.alpha, a.beta, a.oin, \
+                                                 a.ldoi, a.out, a.ldo, C);
+      if (g.s == 1) { AZ_COLINV(1) } else if (g.s == 2) { AZ_COLINV(2) } else { AZ_COLINV(4) }
+#undef AZ_COLINV
       break;
     case 2:
+#define AZ_COLFZ(TW, S)                                                                                 \
+  AZ_TRY(set_lds(k_col_fwd_Z<N1, TW, S>, lds));                                                         \
+  k_col_fwd_Z<N1, TW, S><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.ldi, a.nvec, a.pair0, a.cout, C);
       if (tw4) {
-        AZ_TRY(set_lds(k_col_fwd_Z<N1, true>, lds));
-        k_col_fwd_Z<N1, true><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.ldi, a.nvec, a.pair0, a.cout, C);
+        if (g.s == 1) { AZ_COLFZ(true, 1) } else if (g.s == 2) { AZ_COLFZ(true, 2) } else { AZ_COLFZ(true, 4) }
       } else {
-        AZ_TRY(set_lds(k_col_fwd_Z<N1, false>, lds));
-        k_col_fwd_Z<N1, false><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.ldi, a.nvec, a.pair0, a.cout, C);
+        if (g.s == 1) { AZ_COLFZ(false, 1) } else if (g.s == 2) { AZ_COLFZ(false, 2) } else { AZ_COLFZ(false, 4) }
       }
+#undef AZ_COLFZ
       break;
     case 3:
       AZ_TRY(set_lds(k_col_inv_Z<N1>, lds));
-      k_col_inv_Z<N1><<<grid, block, lds, a.st>>>(g, P.tw, a.cin, a.nvec, a.pair0, a.alpha, a.beta, a.out,
-                                                  a.ldo, C);
+      k_col_inv_Z<N1><<<grid, block, lds, a.st>>>(g, P.tw, a.cin, a.nvec, a.pair0, a.alpha, a.beta, a.oin,
+                                                  a.ldoi, a.out, a.ldo, C);
       break;
     case 4:
       if (tw4) {
@@ -823,7 +888,7 @@ static int64_t engine_chunk(const Plan& P, int64_t npairs) {
 }
 
 static int boundary_rows(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta,
-                         double* Y, int64_t ldy, hipStream_t st) {
+                         const double* Yin, int64_t ldyi, double* Y, int64_t ldy, hipStream_t st) {
   if (P.Mb == 0) return AZRBF_OK;
   const int mimg = (int)ceil(6.8 / (2.0 * P.eps * P.T)) + 2;
   const int W = (int)ceil(6.8 / (P.eps * P.h)) + 1;
@@ -832,54 +897,65 @@ static int boundary_rows(Plan& P, const double* X, int64_t ldx, int64_t nvec, do
   const dim3 grid((unsigned)((P.Mb + 127) / 128), (unsigned)nvec);
   Prof pr("boundary_A", 8.0 * (double)P.Mb * nvec * (beta != 0.0 ? 2.0 : 1.0), st);
   k_boundary_A<<<grid, 128, 0, st>>>(P.dim, P.n, P.T, P.h, P.eps, mimg, W, P.bpts, P.Mb, P.bweight, X, ldx,
-                                     nvec, alpha, beta, Y, ldy, P.M);
+                                     nvec, alpha, beta, Yin, ldyi, Y, ldy, P.M);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
 static int fused_A(const Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta,
-                   double* Y, int64_t ldy, hipStream_t st) {
-  AZ_SWITCH_N(P.n, launch_fused_A, P, X, ldx, nvec, alpha, beta, Y, ldy, st)
+                   const double* Yin, int64_t ldyi, double* Y, int64_t ldy, hipStream_t st) {
+  AZ_SWITCH_N(P.n, launch_fused_A, P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st)
 }
 
-int ops_apply_A(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta, double* Y,
-                int64_t ldy, hipStream_t st) {
+int ops_apply_A(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta,
+                const double* Yin, int64_t ldyi, double* Y, int64_t ldy, hipStream_t st) {
   if (nvec <= 0) return AZRBF_OK;
+  if (!Yin) {
+    Yin = Y;
+    ldyi = ldy;
+  }
   if (P.fused) {
-    AZ_TRY(fused_A(P, X, ldx, nvec, alpha, beta, Y, ldy, st));
-    return boundary_rows(P, X, ldx, nvec, alpha, beta, Y, ldy, st);
+    AZ_TRY(fused_A(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st));
+    return boundary_rows(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st);
   }
   const int64_t npairs = (nvec + 1) / 2;
   const int64_t chunk = engine_chunk(P, npairs);
   AZ_TRY(ensure_ws(P, chunk));
   for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
     const int64_t np = npairs - p0 < chunk ? npairs - p0 : chunk;
-    ColArgs c1{&P, 0, X, ldx, nullptr, P.ws1, nvec, p0, np, 0, 0, nullptr, 0, st};
+    ColArgs c1{&P, 0, X, ldx, nullptr, P.ws1, nvec, p0, np, 0, 0, nullptr, 0, nullptr, 0, st};
     AZ_TRY(run_col(c1));
     RowArgs r{&P, 0, P.ws1, P.ws2, np, st};
     AZ_TRY(run_row(r));
-    ColArgs c3{&P, 1, nullptr, 0, P.ws2, nullptr, nvec, p0, np, alpha, beta, Y, ldy, st};
+    ColArgs c3{&P, 1, nullptr, 0, P.ws2, nullptr, nvec, p0, np, alpha, beta, Yin, ldyi, Y, ldy, st};
     AZ_TRY(run_col(c3));
   }
-  return boundary_rows(P, X, ldx, nvec, alpha, beta, Y, ldy, st);
+  return boundary_rows(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st);
 }
 
-// Boundary rows of the result are ignored (Z* has zero columns there).
-int ops_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta, double* Z,
-                int64_t ldz, hipStream_t st) {
+static int fused_Z(const Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,
+                   const double* Zin, int64_t ldzi, double* Z, int64_t ldz, hipStream_t st) {
+  AZ_SWITCH_N(P.n, launch_fused_Z, P, R, ldr, nvec, alpha, beta, Zin, ldzi, Z, ldz, st)
+}
+
+// Boundary rows of R are ignored (Z* has zero columns there).
+int ops_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,
+                const double* Zin, int64_t ldzi, double* Z, int64_t ldz, hipStream_t st) {
   if (nvec <= 0) return AZRBF_OK;
-  if (P.fused) {
-    AZ_SWITCH_N(P.n, launch_fused_Z, P, R, ldr, nvec, alpha, beta, Z, ldz, st)
+  if (!Zin) {
+    Zin = Z;
+    ldzi = ldz;
   }
+  if (P.fused) return fused_Z(P, R, ldr, nvec, alpha, beta, Zin, ldzi, Z, ldz, st);
   const int64_t npairs = (nvec + 1) / 2;
   const int64_t chunk = engine_chunk(P, npairs);
   AZ_TRY(ensure_ws(P, chunk));
   for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
     const int64_t np = npairs - p0 < chunk ? npairs - p0 : chunk;
-    ColArgs c1{&P, 2, R, ldr, nullptr, P.ws1, nvec, p0, np, 0, 0, nullptr, 0, st};
+    ColArgs c1{&P, 2, R, ldr, nullptr, P.ws1, nvec, p0, np, 0, 0, nullptr, 0, nullptr, 0, st};
     AZ_TRY(run_col(c1));
     RowArgs r{&P, 1, P.ws1, P.ws2, np, st};
     AZ_TRY(run_row(r));
-    ColArgs c3{&P, 3, nullptr, 0, P.ws2, nullptr, nvec, p0, np, alpha, beta, Z, ldz, st};
+    ColArgs c3{&P, 3, nullptr, 0, P.ws2, nullptr, nvec, p0, np, alpha, beta, Zin, ldzi, Z, ldz, st};
     AZ_TRY(run_col(c3));
   }
   return AZRBF_OK;
@@ -890,7 +966,7 @@ int ops_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alph
 static int fft_lines_fwd(Plan& P, const double2* in, double2* out, int n, int64_t lines, bool engine,
                          hipStream_t st) {
   if (!engine) { AZ_SWITCH_N(n, launch_fused_fwd, P.tw, in, out, lines, st) }
-  ColArgs c{&P, 4, nullptr, 0, in, out, 0, 0, lines, 0, 0, nullptr, 0, st};
+  ColArgs c{&P, 4, nullptr, 0, in, out, 0, 0, lines, 0, 0, nullptr, 0, nullptr, 0, st};
   AZ_TRY(run_col(c));
   RowArgs r{&P, 2, nullptr, out, lines, st};
   return run_row(r);

@@ -16,23 +16,68 @@ struct azrbf_plan_s {
 
 namespace az {
 
+// Device memory pool shared by all plans of the process: freed blocks are
+// kept per device and size class and handed to later plans, so creating and
+// destroying plans of a recurring size does not call hipMalloc / hipFree.
+// Blocks return to the pool only after the owning plan's stream has drained.
+namespace {
+std::mutex g_pool_mu;
+std::multimap<std::pair<int, int64_t>, void*> g_pool;   // (device, bytes) -> block
+int64_t g_pool_bytes = 0;
+constexpr int64_t kPoolCap = (int64_t)16 << 30;
+
+int64_t size_class(int64_t n) {
+  if (n <= 4096) return 4096;
+  int64_t c = 4096;
+  while (c < n) c += c < ((int64_t)1 << 20) ? c : (c >> 2);   // x2 to 1 MiB, then +25%
+  return c;
+}
+}  // namespace
+
 int Plan::alloc(void** ptr, int64_t nbytes) {
   *ptr = nullptr;
-  if (nbytes <= 0) nbytes = 8;
-  if (hipMalloc(ptr, (size_t)nbytes) != hipSuccess) {
-    (void)hipGetLastError();
-    *ptr = nullptr;
-    return AZRBF_ENOMEM;
+  const int64_t cls = size_class(nbytes <= 0 ? 8 : nbytes);
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    auto it = g_pool.find({device, cls});
+    if (it != g_pool.end()) {
+      *ptr = it->second;
+      g_pool.erase(it);
+      g_pool_bytes -= cls;
+    }
   }
-  allocs.push_back(*ptr);
-  bytes += nbytes;
+  if (!*ptr) {
+    if (hipMalloc(ptr, (size_t)cls) != hipSuccess) {
+      (void)hipGetLastError();
+      *ptr = nullptr;
+      return AZRBF_ENOMEM;
+    }
+  }
+  allocs.push_back({*ptr, cls});
+  bytes += cls;
   return AZRBF_OK;
 }
 
 void Plan::release() {
-  for (void* q : allocs) (void)hipFree(q);
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  for (auto& a : allocs) {
+    if (g_pool_bytes + a.second > kPoolCap) {
+      (void)hipFree(a.first);
+      continue;
+    }
+    g_pool.insert({{device, a.second}, a.first});
+    g_pool_bytes += a.second;
+  }
   allocs.clear();
   bytes = 0;
+}
+
+int pool_trim() {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  for (auto& kv : g_pool) (void)hipFree(kv.second);
+  g_pool.clear();
+  g_pool_bytes = 0;
+  return AZRBF_OK;
 }
 
 // ------------------------------------------------------------------ per-launch timing
@@ -137,6 +182,7 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
   if (!h) return AZRBF_ENOMEM;
   Plan& P = h->p;
   hipStream_t st = (hipStream_t)stream;
+  P.last_stream = st;
   P.prob = q;
   P.prob.mask = nullptr;
   P.prob.bpts = nullptr;
@@ -237,6 +283,7 @@ int azrbf_plan_info(azrbf_plan_t h, azrbf_info* info) {
   info->normZ = P.normZ;
   info->zeroed = P.zeroed;
   info->factored = P.factored ? 1 : 0;
+  info->sweeps = P.sweeps;
   info->device_bytes = P.bytes;
   return AZRBF_OK;
 }
@@ -247,7 +294,8 @@ int azrbf_apply_A(azrbf_plan_t h, const double* X, int64_t ldx, int64_t nvec, do
   Plan& P = h->p;
   if (nvec == 0) return AZRBF_OK;
   if (!X || !Y || ldx < P.N || ldy < P.Mt) return AZRBF_EINVAL;
-  return az::ops_apply_A(P, X, ldx, nvec, alpha, beta, Y, ldy, (hipStream_t)stream);
+  P.last_stream = (hipStream_t)stream;
+  return az::ops_apply_A(P, X, ldx, nvec, alpha, beta, nullptr, 0, Y, ldy, (hipStream_t)stream);
 }
 
 int azrbf_apply_Zstar(azrbf_plan_t h, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,
@@ -256,11 +304,13 @@ int azrbf_apply_Zstar(azrbf_plan_t h, const double* R, int64_t ldr, int64_t nvec
   Plan& P = h->p;
   if (nvec == 0) return AZRBF_OK;
   if (!R || !Z || ldr < P.Mt || ldz < P.N) return AZRBF_EINVAL;
-  return az::ops_apply_Z(P, R, ldr, nvec, alpha, beta, Z, ldz, (hipStream_t)stream);
+  P.last_stream = (hipStream_t)stream;
+  return az::ops_apply_Z(P, R, ldr, nvec, alpha, beta, nullptr, 0, Z, ldz, (hipStream_t)stream);
 }
 
 int azrbf_factor(azrbf_plan_t h, void* stream) {
   if (!h) return AZRBF_EINVAL;
+  h->p.last_stream = (hipStream_t)stream;
   return az::dense_factor(h->p, (hipStream_t)stream);
 }
 
@@ -270,6 +320,7 @@ int azrbf_solve(azrbf_plan_t h, const double* B, int64_t ldb, int64_t nrhs, doub
   Plan& P = h->p;
   if (nrhs == 0) return AZRBF_OK;
   if (!B || !X || ldb < P.Mt || ldx < P.N) return AZRBF_EINVAL;
+  P.last_stream = (hipStream_t)stream;
   if (!P.factored) {
     const int rc = az::dense_factor(P, (hipStream_t)stream);
     if (rc != AZRBF_OK && rc != AZRBF_ERANK) return rc;
@@ -320,6 +371,7 @@ int azrbf_get_factor(azrbf_plan_t h, int32_t which, double* dst, int64_t ld, voi
   Plan& P = h->p;
   hipStream_t st = (hipStream_t)stream;
   if (!P.factored) return AZRBF_ESTATE;
+  P.last_stream = st;
   const int k = P.k;
   switch (which) {
     case 0:
@@ -396,9 +448,12 @@ int azrbf_profile_report(char* buf, int64_t len) {
 
 void azrbf_destroy(azrbf_plan_t h) {
   if (!h) return;
-  (void)hipDeviceSynchronize();
+  // the plan's blocks go back to the pool: wait for the work queued on them
+  (void)hipStreamSynchronize(h->p.last_stream);
   h->p.release();
   delete h;
 }
+
+int azrbf_release_cached_memory(void) { return az::pool_trim(); }
 
 }  // extern "C"
