@@ -171,6 +171,17 @@ int azrbf_get_factor(azrbf_plan_t plan, int32_t which, double* dst, int64_t ld,
 int azrbf_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* dst, int64_t ld,
                    void* stream);
 
+/* Utility: C = alpha op(A) op(B) + beta C in FP64 on the matrix cores (the
+ * GEMM of the low-rank stage for wide sketches, section 3.2.3).  op(A) is
+ * m x k, op(B) is k x n, C is m x n; all DEVICE pointers, column-major, with
+ * leading dimensions lda >= rows of A as stored (m, or k if transa), likewise
+ * ldb, and ldc >= m.  transa, transb: 0 = as stored, 1 = transposed.  With
+ * beta == 0, C is not read.  Long reductions that are split over blocks use a
+ * temporary buffer, and then the call synchronises the stream. */
+int azrbf_dgemm(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k, double alpha,
+                const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                int64_t ldc, void* stream);
+
 /* Per-launch timing for measurement.  While enabled, every kernel launch of
  * the library (any plan, any stream) is bracketed by HIP events on its
  * stream and tagged with the bytes it must move at minimum (its algorithmic

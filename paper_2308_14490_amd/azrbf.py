@@ -67,6 +67,8 @@ EXPORTS = {
     "azrbf_footprint_bytes": (ctypes.c_int64, [ctypes.POINTER(_Problem), _I64]),
     "azrbf_get_factor": (ctypes.c_int, [_P, ctypes.c_int32, _P, _I64, _P]),
     "azrbf_gaussian": (ctypes.c_int, [ctypes.c_uint64, _I64, _I64, _P, _I64, _P]),
+    "azrbf_dgemm": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _I64, _I64, _I64, _D, _P, _I64, _P, _I64,
+                                   _D, _P, _I64, _P]),
     "azrbf_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
     "azrbf_profile_report": (ctypes.c_int, [ctypes.c_char_p, _I64]),
     "azrbf_destroy": (None, [_P]),
@@ -225,7 +227,9 @@ def factor(p, stream=None):
     rc = _lib().azrbf_factor(p.handle, _stream(stream))
     if rc not in (OK, ERANK):
         _check(rc, "azrbf_factor")
-    return p.info()["rank"]
+    inf = p.info()
+    p.k = inf["k"]          # the width may have grown
+    return inf["rank"]
 
 
 def solve(p, B, X=None, relres=None, stream=None):
@@ -293,6 +297,34 @@ def gaussian(seed, rows, cols, stream=None):
     out = torch.empty((cols, rows), dtype=torch.float64, device=dev)
     _check(_lib().azrbf_gaussian(int(seed), rows, cols, out.data_ptr(), rows, _stream(stream)), "azrbf_gaussian")
     return out
+
+
+def _colmajor(t, name):
+    """A column-major matrix held as a (cols, rows) tensor: (rows, cols, ld)."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or t.dim() != 2:
+        raise TypeError(f"{name} must be a 2-D float64 CUDA tensor")
+    if t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit row stride")
+    return t.shape[1], t.shape[0], max(t.stride(0), t.shape[1], 1)
+
+
+def dgemm(A, B, C=None, transa=False, transb=False, alpha=1.0, beta=0.0, stream=None):
+    """C = alpha op(A) op(B) + beta C on the matrix cores.  Matrices are
+    column-major, held as (cols, rows) tensors (tensor row j = column j)."""
+    ra, ca, lda = _colmajor(A, "A")
+    rb, cb, ldb = _colmajor(B, "B")
+    m, k = (ca, ra) if transa else (ra, ca)
+    kb, n = (cb, rb) if transb else (rb, cb)
+    if k != kb:
+        raise ValueError(f"inner dimensions differ: {k} vs {kb}")
+    if C is None:
+        C = torch.zeros((n, m), dtype=torch.float64, device=A.device)
+    rc_, cc_, ldc = _colmajor(C, "C")
+    if (rc_, cc_) != (m, n):
+        raise ValueError(f"C must hold a {m} x {n} matrix")
+    _check(_lib().azrbf_dgemm(int(bool(transa)), int(bool(transb)), m, n, k, float(alpha), A.data_ptr(), lda,
+                              B.data_ptr(), ldb, float(beta), C.data_ptr(), ldc, _stream(stream)), "azrbf_dgemm")
+    return C
 
 
 def profile_enable(on=True):

@@ -4,8 +4,8 @@
 // the small triangular factor, and the per-right-hand-side solve of
 // Algorithm 1 with optional refinement passes.
 //
-// Sketch widths k <= 64: every TSQR block holds RB x k values in LDS, the
-// Jacobi SVD of the k x k factor runs in one workgroup.
+// Sketch widths k <= 64: every TSQR block holds RB x k values in registers
+// (tsqr.hip), the Jacobi SVD of the k x k factor runs in one workgroup.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -69,133 +69,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // ------------------------------------------------------------------ TSQR
 
-// Each TSQR block holds RB = TSQR_ELEMS / k rows of the k columns in LDS
-// (column-major, odd leading dimension).  256 threads: for the column
-// dot products thread t takes column t % k and row group t / k (64 rows).
-constexpr int TSQR_ELEMS = 16384;
+// TSQR blocks (the block QR kernel lives in tsqr.hip) hold RB = 16384 / k
+// rows; the Q formation below uses the same row blocking.
 constexpr int TSQR_THREADS = 256;
-
-// (k = 64 keeps fewer rows so that the k x k T factor also fits in LDS)
-__host__ __device__ constexpr int tsqr_rows(int k) { return k <= 32 ? TSQR_ELEMS / k : 12288 / k; }
-
-static int tsqr_lds_bytes(int k) {
-  const int RB = tsqr_rows(k);
-  // a (RB+1) x k, partial sums 256, w, scalars 4, g, T (k x k)
-  return (int)(sizeof(double) * ((int64_t)(RB + 1) * k + TSQR_THREADS + 2 * KMAX + 4 + k * k));
-}
-
-// Householder QR of one RB x k block of A (rows >= m read as zero).
-// Reflector j is H_j = I - tau_j v_j v_j^T with v_j[j] = 1 and zeros above.
-// For column j the sums D_c = sum_{r > j} a[r][j] a[r][c] (c >= j) give both
-// sigma^2 = D_j and v_j^T a_c = a[j][c] + D_c / (alpha - beta); the threads
-// of columns c < j meanwhile form v_c^T v_j, from which the triangular
-// factor of the compact WY form H_0 ... H_{k-1} = I - V T V^T is built
-// (T_jj = tau_j, T_ij = -tau_j sum_{l=i}^{j-1} T_il v_l^T v_j).
-// Out: R (upper k x k) at rows b*k.. of Rout, the reflectors over the
-// block's rows of V, T (k x k, column-major) at Tout + b*k*k.
-__global__ void __launch_bounds__(TSQR_THREADS)
-k_tsqr_block(const double* __restrict__ A, int64_t lda, int64_t m, int k, double* __restrict__ Rout,
-             int64_t ldr, double* __restrict__ V, int64_t ldv, double* __restrict__ Tout) {
-  extern __shared__ double sm[];
-  const int RB = tsqr_rows(k), LDL = RB + 1;
-  double* a = sm;                                // a[c * LDL + r]
-  double* part = a + (int64_t)LDL * k;           // 256
-  double* wv = part + TSQR_THREADS;              // KMAX
-  double* scal = wv + KMAX;                      // beta, tau, scale
-  double* gv = scal + 4;                         // KMAX: v_c^T v_j for c < j
-  double* Tm = gv + KMAX;                        // k x k, column-major
-  const int t = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * RB;
-  for (int c = 0; c < k; ++c)
-    for (int r = t; r < RB; r += TSQR_THREADS) a[c * LDL + r] = r0 + r < m ? A[r0 + r + lda * c] : 0.0;
-  __syncthreads();
-  const int G = TSQR_THREADS / k, rows_g = RB / G;
-  const int cc = t % k, gg = t / k;
-  for (int j = 0; j < k; ++j) {
-    {
-      const double* aj = a + j * LDL;
-      const double* ac = a + cc * LDL;
-      const int lo = max(gg * rows_g, j + 1), hi = (gg + 1) * rows_g;
-      // short dependency chains: eight partial sums
-      double d[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-      int r = lo;
-      for (; r + 8 <= hi; r += 8) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) d[u] = fma(aj[r + u], ac[r + u], d[u]);
-      }
-      for (; r < hi; ++r) d[0] = fma(aj[r], ac[r], d[0]);
-      part[gg * k + cc] = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]));
-    }
-    __syncthreads();
-    if (t < k) {
-      double s0 = 0.0, s1 = 0.0, c0 = 0.0, c1 = 0.0;
-      for (int g = 0; g < G; g += 2) {
-        s0 += part[g * k + j];
-        s1 += part[(g + 1) * k + j];
-        c0 += part[g * k + t];
-        c1 += part[(g + 1) * k + t];
-      }
-      const double sig2 = s0 + s1, dc = c0 + c1;
-      const double alpha = a[j * LDL + j];
-      double beta = alpha, tau = 0.0, scale = 0.0;
-      if (sig2 > 0.0) {
-        beta = -copysign(sqrt(alpha * alpha + sig2), alpha);
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      if (t == j) {
-        scal[0] = beta;
-        scal[1] = tau;
-        scal[2] = scale;
-      } else if (t > j) {
-        wv[t] = tau * (a[t * LDL + j] + dc * scale);
-      } else {
-        gv[t] = a[t * LDL + j] + dc * scale;   // v_t^T v_j (v_t[j] = a[j][t] stored below t's diagonal)
-      }
-    }
-    __syncthreads();
-    if (t < j) {   // T(0:j, j) = -tau_j T(0:j, 0:j) g
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int l = t;
-      for (; l + 4 <= j; l += 4) {
-        a0 = fma(Tm[l * k + t], gv[l], a0);
-        a1 = fma(Tm[(l + 1) * k + t], gv[l + 1], a1);
-        a2 = fma(Tm[(l + 2) * k + t], gv[l + 2], a2);
-        a3 = fma(Tm[(l + 3) * k + t], gv[l + 3], a3);
-      }
-      for (; l < j; ++l) a0 = fma(Tm[l * k + t], gv[l], a0);
-      Tm[j * k + t] = -scal[1] * ((a0 + a1) + (a2 + a3));
-    } else if (t == j) {
-      Tm[j * k + j] = scal[1];
-    }
-    const double scale = scal[2];
-    for (int r = t; r < RB; r += TSQR_THREADS) {
-      if (r < j) continue;
-      const double v = r == j ? 1.0 : a[j * LDL + r] * scale;
-      int c = j + 1;
-      for (; c + 4 <= k; c += 4) {
-        const double x0 = a[c * LDL + r], x1 = a[(c + 1) * LDL + r];
-        const double x2 = a[(c + 2) * LDL + r], x3 = a[(c + 3) * LDL + r];
-        a[c * LDL + r] = fma(-wv[c], v, x0);
-        a[(c + 1) * LDL + r] = fma(-wv[c + 1], v, x1);
-        a[(c + 2) * LDL + r] = fma(-wv[c + 2], v, x2);
-        a[(c + 3) * LDL + r] = fma(-wv[c + 3], v, x3);
-      }
-      for (; c < k; ++c) a[c * LDL + r] = fma(-wv[c], v, a[c * LDL + r]);
-      a[j * LDL + r] = r == j ? scal[0] : v;
-    }
-    __syncthreads();
-  }
-  for (int e = t; e < k * k; e += TSQR_THREADS) {
-    const int r = e % k, c = e / k;
-    Tout[(int64_t)blockIdx.x * k * k + e] = r <= c ? Tm[c * k + r] : 0.0;
-  }
-  for (int c = 0; c < k; ++c) {
-    if (t < k) Rout[(int64_t)blockIdx.x * k + t + ldr * c] = t <= c ? a[c * LDL + t] : 0.0;
-    for (int r = t; r < RB; r += TSQR_THREADS)
-      if (r0 + r < m) V[r0 + r + ldv * c] = r > c ? a[c * LDL + r] : (r == c ? 1.0 : 0.0);
-  }
-}
+__host__ __device__ constexpr int tsqr_rows(int k) { return 16384 / k; }
 
 // E_b = H_0 ... H_{k-1} [C_b; 0] = [C_b; 0] - V (T (V_top^T C_b)) for block b
 // (compact WY; V_top = the block's first k reflector rows, unit lower
@@ -328,19 +205,10 @@ static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double*
     lv[l].A = l == 0 ? W : lv[l - 1].R;
   }
   double* Ebuf[2] = {p, p + ed};
-  const int lds = tsqr_lds_bytes(k);
-  static bool attr = false;
-  if (!attr) {
-    const int most = std::max(tsqr_lds_bytes(16), std::max(tsqr_lds_bytes(32), tsqr_lds_bytes(64)));
-    AZ_HIP(hipFuncSetAttribute((const void*)k_tsqr_block, hipFuncAttributeMaxDynamicSharedMemorySize, most));
-
-    attr = true;
-  }
   for (size_t l = 0; l < lv.size(); ++l) {
     const TsqrLevel& L = lv[l];
     Prof pr(l == 0 ? "tsqr_block" : "tsqr_block (tree)", 16.0 * L.m * k + 8.0 * L.nb * k * (k + 1), st);
-    k_tsqr_block<<<(unsigned)L.nb, TSQR_THREADS, lds, st>>>(L.A, L.m, L.m, k, L.R, L.nb * k, L.A, L.m, L.tau);
-    AZ_HIP(hipGetLastError());
+    AZ_TRY(tsqr_block_qr(L.A, L.m, L.m, k, L.R, L.nb * k, L.A, L.m, L.tau, st));
   }
   AZ_HIP(hipMemcpyAsync(R, lv.back().R, sizeof(double) * k * k, hipMemcpyDeviceToDevice, st));
   const double* up = nullptr;
@@ -355,6 +223,11 @@ static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double*
     ldup = L.m;
   }
   return AZRBF_OK;
+}
+
+int64_t tsqr_scratch(int64_t m, int k) { return tsqr_scratch_doubles(m, k); }
+int tsqr_panel(double* W, int64_t m, int k, double* scratch, double* Q, double* R, hipStream_t st) {
+  return tsqr(W, m, k, scratch, Q, R, st);
 }
 
 // ------------------------------------------------------------------ Jacobi SVD
@@ -584,6 +457,7 @@ __global__ void k_reduce_part(const double* __restrict__ part, int64_t nblk, int
 }
 
 constexpr int NORM_CHUNKS = 32;
+int relres_chunks() { return NORM_CHUNKS; }
 
 // part[col * NORM_CHUNKS + chunk] = sum of squares over the chunk's rows.
 __global__ void __launch_bounds__(256)
@@ -645,7 +519,7 @@ static int gemm_tn(const double* Q, int64_t ldq, int64_t m, int k, const double*
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
-static int relres_norms(const double* R, int64_t ldr, const double* B, int64_t ldb, int64_t m, int64_t ncol,
+int relres_norms(const double* R, int64_t ldr, const double* B, int64_t ldb, int64_t m, int64_t ncol,
                         double* scratch, double* out, hipStream_t st) {
   const dim3 grid(NORM_CHUNKS, (unsigned)ncol);
   Prof pr("relres", 16.0 * m * ncol, st);

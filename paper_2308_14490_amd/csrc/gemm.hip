@@ -1,0 +1,184 @@
+// FP64 matrix-core GEMMs of the low-rank stage (section 3.2.3) for sketch
+// widths in the hundreds to thousands: the projections Q^T X and updates
+// X - Q S of the block Gram-Schmidt QR, the products with the Jacobi
+// rotations and the per-right-hand-side solve.
+//
+// One block computes a 64 x 64 tile of C with four waves (32 x 32 each, four
+// 16 x 16 v_mfma_f64_16x16x4 accumulators).  op(A) and op(B) are staged in
+// LDS in chunks of 16 along the reduction.  The product is formed as
+// (op(A) op(B))^T = op(B)^T op(A)^T so that the accumulator lanes run along
+// the rows of the column-major C and the stores are contiguous.
+//
+// Reductions over very long dimensions (the tall-skinny Q^T X) are split
+// over blocks: each writes a partial tile, and k_sum_splits adds them in a
+// fixed order, so results do not depend on scheduling.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace az {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int GT = 64;   // output tile edge
+constexpr int GK = 16;   // reduction chunk staged in LDS
+constexpr int GP = GT + 2;
+
+template <bool TA>
+__device__ __forceinline__ double load_opA(const double* A, int64_t lda, int64_t i, int64_t kk) {
+  return TA ? A[kk + lda * i] : A[i + lda * kk];
+}
+
+template <bool TB>
+__device__ __forceinline__ double load_opB(const double* B, int64_t ldb, int64_t kk, int64_t j) {
+  return TB ? B[j + ldb * kk] : B[kk + ldb * j];
+}
+
+// Batch entry z / splits, reduction range [sp * kchunk, (sp + 1) * kchunk) of
+// split sp = z % splits.  With splits > 1 the raw tile sums are stored at
+// C + z * sC (ld ldc) and alpha, beta are applied by k_sum_splits.
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256)
+k_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda, int64_t sA,
+       const double* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC,
+       int splits, int64_t kchunk) {
+  __shared__ double As[GK][GP];   // As[kk][i] = op(A)(i0 + i, kb + kk)
+  __shared__ double Bs[GK][GP];   // Bs[kk][j] = op(B)(kb + kk, j0 + j)
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int z = blockIdx.z, bz = z / splits, sp = z % splits;
+  A += (int64_t)bz * sA;
+  B += (int64_t)bz * sB;
+  C += (int64_t)(splits > 1 ? z : bz) * sC;
+  const int64_t i0 = (int64_t)blockIdx.x * GT, j0 = (int64_t)blockIdx.y * GT;
+  const int64_t k0 = (int64_t)sp * kchunk, k1 = std::min(K, k0 + kchunk);
+  const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t kb = k0; kb < k1; kb += GK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      // contiguous global runs: along i for A, along kk for A^T (likewise B)
+      const int ai = TA ? (t >> 4) + 16 * q : (t & 63);
+      const int ak = TA ? (t & 15) : (t >> 6) + 4 * q;
+      const int64_t gi = i0 + ai, gka = kb + ak;
+      As[ak][ai] = (gi < M && gka < k1) ? load_opA<TA>(A, lda, gi, gka) : 0.0;
+      const int bj = TB ? (t & 63) : (t >> 4) + 16 * q;
+      const int bk = TB ? (t >> 6) + 4 * q : (t & 15);
+      const int64_t gj = j0 + bj, gkb = kb + bk;
+      Bs[bk][bj] = (gj < N && gkb < k1) ? load_opB<TB>(B, ldb, gkb, gj) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GK / 4; ++ks) {
+      const int kk = 4 * ks + (l >> 4);
+      double av[2], bv[2];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) av[mi] = As[kk][wi + 16 * mi + (l & 15)];
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) bv[ni] = Bs[kk][wj + 16 * ni + (l & 15)];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[ni], av[mi], acc[mi][ni], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // The accumulator of a 16 x 16 x 4 f64 product holds element (r, c) =
+  // ((l >> 4) + 4 v, l & 15) in lane l, entry v; here r runs along j, c along i:
+  // acc[mi][ni][v] = C(i0 + wi + 16 mi + (l & 15), j0 + wj + 16 ni + (l >> 4) + 4 v)
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi) {
+    const int64_t i = i0 + wi + 16 * mi + (l & 15);
+    if (i >= M) continue;
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t j = j0 + wj + 16 * ni + (l >> 4) + 4 * v;
+        if (j >= N) continue;
+        double* p = C + i + ldc * j;
+        const double s = acc[mi][ni][v];
+        if (splits > 1) *p = s;
+        else *p = beta == 0.0 ? alpha * s : fma(alpha, s, beta * *p);
+      }
+    }
+  }
+}
+
+// C = alpha sum_s P_s + beta C for each batch entry; P_s at P + (b*splits+s)*sP.
+__global__ void k_sum_splits(int64_t M, int64_t N, int splits, const double* __restrict__ P, int64_t ldp,
+                             int64_t sP, double alpha, double beta, double* C, int64_t ldc, int64_t sC) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * N) return;
+  const int64_t b = blockIdx.y, i = e % M, j = e / M;
+  const double* p = P + (int64_t)b * splits * sP + i + ldp * j;
+  double s0 = 0.0, s1 = 0.0;
+  int s = 0;
+  for (; s + 2 <= splits; s += 2) {
+    s0 += p[(int64_t)s * sP];
+    s1 += p[(int64_t)(s + 1) * sP];
+  }
+  if (s < splits) s0 += p[(int64_t)s * sP];
+  double* c = C + (int64_t)b * sC + i + ldc * j;
+  const double v = s0 + s1;
+  *c = beta == 0.0 ? alpha * v : fma(alpha, v, beta * *c);
+}
+
+template <bool TA, bool TB>
+void launch_gemm(dim3 grid, hipStream_t st, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                 int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C,
+                 int64_t ldc, int64_t sC, int splits, int64_t kchunk) {
+  k_gemm<TA, TB><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, splits, kchunk);
+}
+
+}  // namespace
+
+int64_t gemm_split_doubles(int64_t M, int64_t N, int64_t K, int64_t batch) {
+  const int64_t tiles = ((M + GT - 1) / GT) * ((N + GT - 1) / GT) * batch;
+  if (tiles >= 256 || K < 2048) return 0;
+  const int64_t splits = std::min<int64_t>({64, (512 + tiles - 1) / tiles, K / 1024});
+  return splits > 1 ? splits * batch * M * N : 0;
+}
+
+int gemm_mfma(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+              int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc,
+              int64_t sC, int64_t batch, double* part, int64_t part_doubles, hipStream_t st) {
+  if (M <= 0 || N <= 0 || batch <= 0) return AZRBF_OK;
+  if (batch > 65535) return AZRBF_EINVAL;
+  const int64_t tx = (M + GT - 1) / GT, ty = (N + GT - 1) / GT;
+  if (tx > 0x7fffffff || ty > 65535) return AZRBF_EINVAL;
+  int splits = 1;
+  const int64_t need = gemm_split_doubles(M, N, K, batch);
+  if (need > 0 && part && need <= part_doubles) splits = (int)(need / (batch * M * N));
+  int64_t kchunk = K;
+  if (splits > 1) {
+    kchunk = ((K + splits - 1) / splits + GK - 1) / GK * GK;
+    splits = (int)((K + kchunk - 1) / kchunk);
+  }
+  if ((int64_t)splits * batch > 65535) return AZRBF_EINVAL;
+  Prof pr("gemm_mfma", 8.0 * batch * (M * K + K * N + M * N * (beta != 0.0 ? 2.0 : 1.0)), st,
+          2.0 * batch * M * N * K);
+  const dim3 grid((unsigned)tx, (unsigned)ty, (unsigned)(splits * batch));
+  double* Cout = splits > 1 ? part : C;
+  const int64_t ldo = splits > 1 ? M : ldc, so = splits > 1 ? M * N : sC;
+  if (!ta && !tb) launch_gemm<false, false>(grid, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cout, ldo, so, splits, kchunk);
+  else if (ta && !tb) launch_gemm<true, false>(grid, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cout, ldo, so, splits, kchunk);
+  else if (!ta && tb) launch_gemm<false, true>(grid, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cout, ldo, so, splits, kchunk);
+  else launch_gemm<true, true>(grid, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cout, ldo, so, splits, kchunk);
+  AZ_HIP(hipGetLastError());
+  if (splits > 1) {
+    const int64_t e = M * N;
+    k_sum_splits<<<dim3((unsigned)((e + 255) / 256), (unsigned)batch), 256, 0, st>>>(M, N, splits, part, M, M * N,
+                                                                                  alpha, beta, C, ldc, sC);
+    AZ_HIP(hipGetLastError());
+  }
+  return AZRBF_OK;
+}
+
+}  // namespace az

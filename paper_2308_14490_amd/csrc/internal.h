@@ -57,17 +57,17 @@ struct Plan;
 // bytes the launch must move (what it reads and writes at minimum).
 bool prof_enabled();
 int prof_begin(hipStream_t st);
-void prof_end(int slot, const char* name, double bytes, hipStream_t st);
+void prof_end(int slot, const char* name, double bytes, double flops, hipStream_t st);
 struct Prof {
   int slot;
   const char* name;
-  double bytes;
+  double bytes, flops;
   hipStream_t st;
-  Prof(const char* n, double b, hipStream_t s) : slot(-1), name(n), bytes(b), st(s) {
+  Prof(const char* n, double b, hipStream_t s, double f = 0.0) : slot(-1), name(n), bytes(b), flops(f), st(s) {
     if (prof_enabled()) slot = prof_begin(st);
   }
   ~Prof() {
-    if (slot >= 0) prof_end(slot, name, bytes, st);
+    if (slot >= 0) prof_end(slot, name, bytes, flops, st);
   }
 };
 
@@ -82,8 +82,37 @@ int ops_apply_A(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alph
 int ops_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,
                 const double* Zin, int64_t ldzi, double* Z, int64_t ldz, hipStream_t st);
 
+// tsqr.hip: Householder QR of the RB-row blocks of A (m x k, k in {16, 32,
+// 64}, RB = tsqr_block_rows(k)); R factors stacked at rows b*k of R, the
+// reflectors over A's rows into V (may equal A), compact-WY T factors at
+// T + b*k*k.
+int tsqr_block_rows(int k);
+int tsqr_block_qr(const double* A, int64_t lda, int64_t m, int k, double* R, int64_t ldr, double* V,
+                  int64_t ldv, double* T, hipStream_t st);
+
+// gemm.hip: C = alpha op(A) op(B) + beta C on the FP64 matrix cores, batch
+// entries at strides sA, sB, sC.  Long reductions with few output tiles are
+// split over blocks when part holds gemm_split_doubles(...) doubles.
+int64_t gemm_split_doubles(int64_t M, int64_t N, int64_t K, int64_t batch);
+int gemm_mfma(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+              int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc,
+              int64_t sC, int64_t batch, double* part, int64_t part_doubles, hipStream_t st);
+
 // dense.hip
 int dense_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* dst, int64_t ld, hipStream_t st);
+// Householder TSQR of W (m x k, ld m, destroyed): Q (m x k, ld m), R (k x k, ld k)
+int64_t tsqr_scratch(int64_t m, int k);
+int tsqr_panel(double* W, int64_t m, int k, double* scratch, double* Q, double* R, hipStream_t st);
+// relres[c] = ||R(:, c)|| / ||B(:, c)|| over m rows; nrm holds 2 relres_chunks() x ncol
+int relres_chunks();
+int relres_norms(const double* R, int64_t ldr, const double* B, int64_t ldb, int64_t m, int64_t ncol,
+                 double* nrm, double* out, hipStream_t st);
+
+// wide.hip: sketch widths k > 64 (multiples of 64)
+int64_t wide_factor_doubles(int64_t N, int64_t Mt, int k);
+int wide_factor(Plan& P, hipStream_t st);
+int wide_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx, double* relres,
+               hipStream_t st);
 int dense_factor(Plan& P, hipStream_t st);
 int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
                 double* relres, hipStream_t st);
@@ -131,15 +160,19 @@ struct Plan {
   double* Rf = nullptr;     // k x k
   double* sig = nullptr;    // k
   double* Pm = nullptr;     // k x k = V_r S_r^-1 U_r^T
+  double* Gj = nullptr;     // k x k: R^T, rotated by the wide Jacobi (k > 64)
+  double* Vj = nullptr;     // k x k: accumulated Jacobi rotations (k > 64)
   double* dscr = nullptr;   // dense scratch
   int64_t dscr_bytes = 0;
 
   // solve workspace
   double* sw = nullptr;
-  int64_t sw_rhs = 0;
+  int64_t sw_rhs = 0, sw_part = 0;
 
   int alloc(void** p, int64_t bytes);
   void release();
+  void release_one(void* p);   // one block back to the pool
+  void release_factor();       // the factor and solve workspace back to the pool
 };
 
 }  // namespace az

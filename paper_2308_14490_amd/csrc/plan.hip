@@ -1,4 +1,5 @@
 // C ABI of the azrbf library: plans, operators, factor and solve.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -72,6 +73,37 @@ void Plan::release() {
   bytes = 0;
 }
 
+void Plan::release_one(void* ptr) {
+  if (!ptr) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  for (size_t i = 0; i < allocs.size(); ++i) {
+    if (allocs[i].first != ptr) continue;
+    const int64_t cls = allocs[i].second;
+    if (g_pool_bytes + cls > kPoolCap) {
+      (void)hipFree(ptr);
+    } else {
+      g_pool.insert({{device, cls}, ptr});
+      g_pool_bytes += cls;
+    }
+    bytes -= cls;
+    allocs.erase(allocs.begin() + (long)i);
+    return;
+  }
+}
+
+// The stream must have drained the factor's work.
+void Plan::release_factor() {
+  double** bufs[] = {&Om, &Om2, &Yf, &Yf2, &Q, &Rf, &sig, &Pm, &Gj, &Vj, &dscr, &sw};
+  for (double** b : bufs) {
+    release_one(*b);
+    *b = nullptr;
+  }
+  dscr_bytes = 0;
+  sw_rhs = sw_part = 0;
+  factored = false;
+  rank = -1;
+}
+
 int pool_trim() {
   std::lock_guard<std::mutex> lk(g_pool_mu);
   for (auto& kv : g_pool) (void)hipFree(kv.second);
@@ -85,7 +117,7 @@ int pool_trim() {
 namespace {
 struct ProfRec {
   std::string name;
-  double bytes;
+  double bytes, flops;
   hipEvent_t a, b;
   bool done;
 };
@@ -110,28 +142,77 @@ bool prof_enabled() { return g_prof_on; }
 
 int prof_begin(hipStream_t st) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  ProfRec r{std::string(), 0.0, pool_get(), pool_get(), false};
+  ProfRec r{std::string(), 0.0, 0.0, pool_get(), pool_get(), false};
   if (!r.a || !r.b) return -1;
   (void)hipEventRecord(r.a, st);
   g_prof.push_back(r);
   return (int)g_prof.size() - 1;
 }
 
-void prof_end(int slot, const char* name, double bytes, hipStream_t st) {
+void prof_end(int slot, const char* name, double bytes, double flops, hipStream_t st) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
   if (slot < 0 || slot >= (int)g_prof.size()) return;
   ProfRec& r = g_prof[slot];
   r.name = name;
   r.bytes = bytes;
+  r.flops = flops;
   r.done = true;
   (void)hipEventRecord(r.b, st);
 }
 
 static bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
-static int default_k(const azrbf_problem& pr) {
-  if (pr.k > 0) return pr.k;
-  return 32;
+// Largest usable sketch width: a multiple of 64 (16 for tiny problems) not
+// above the number of unknowns or of rows.
+static int k_cap(int64_t N, int64_t Mt) {
+  const int64_t m = std::min(N, Mt);
+  if (m >= 64) return (int)std::min<int64_t>(m / 64 * 64, 1 << 15);
+  return m >= 32 ? 32 : 16;
+}
+
+// Sketch width when the caller leaves it open.  1D: the rank of A - A Z* A
+// stays near 20 whatever N (Theorem 4.6), so 32.  2D: the rank grows with the
+// boundary (section 5.3.2); measured on disks and stars it is about 4 per
+// fine-grid boundary point at s = 2 (8 / s), plus one per boundary row; the
+// estimate takes 9 / s per boundary point and 10 more columns, rounded up to
+// a multiple of 64.  A sketch that turns out too narrow is widened by
+// the factorisation (grow_k).
+static int default_k(const azrbf_problem& q, int64_t Lax, int64_t N, int64_t Mt) {
+  if (q.k > 0) return q.k;
+  if (q.dim == 1) return 32;
+  int64_t perim = 0;
+  for (int64_t ix = 0; ix < Lax; ++ix)
+    for (int64_t iy = 0; iy < Lax; ++iy) {
+      if (!q.mask[ix * Lax + iy]) continue;
+      const bool edge = ix == 0 || iy == 0 || ix == Lax - 1 || iy == Lax - 1 ||
+                        !q.mask[(ix - 1) * Lax + iy] || !q.mask[(ix + 1) * Lax + iy] ||
+                        !q.mask[ix * Lax + iy - 1] || !q.mask[ix * Lax + iy + 1];
+      perim += edge;
+    }
+  const int64_t est = 9 * perim / q.s + q.nb + 10;
+  const int cap = k_cap(N, Mt);
+  if (cap <= 64) return cap;
+  const int64_t k = (est + 63) / 64 * 64;
+  return (int)std::max<int64_t>(64, std::min<int64_t>(k, cap));
+}
+
+// Factor with the plan's sketch width; a sketch that keeps more than k - 10
+// directions is widened by a quarter (up to three times) when the width was
+// not fixed by the caller.
+static int factor_plan(Plan& P, hipStream_t st) {
+  for (int attempt = 0;; ++attempt) {
+    const int rc = P.k > 64 ? wide_factor(P, st) : dense_factor(P, st);
+    if (rc != AZRBF_ERANK || P.prob.k > 0 || attempt >= 3) return rc;
+    const int cap = k_cap(P.N, P.Mt);
+    if (P.k >= cap) return rc;
+    int nk = P.k <= 64 ? 64 : (int)(((int64_t)P.k * 5 / 4 + 63) / 64 * 64);
+    if (P.k < 64 && nk > cap) nk = cap;
+    if (nk > cap) nk = cap;
+    if (nk <= P.k) return rc;
+    if (hipStreamSynchronize(st) != hipSuccess) return AZRBF_EHIP;
+    P.release_factor();
+    P.k = nk;
+  }
 }
 
 // Four-step split of a 1D transform of length N > 8192 (or forced): N = N1 * N2.
@@ -262,7 +343,7 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
     if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = AZRBF_EHIP;
     if (rc) { P.release(); delete h; return rc; }
   }
-  P.k = az::default_k(q);
+  P.k = az::default_k(q, P.Lax, P.N, P.Mt);
   rc = az::ops_spectra(P, st);
   if (rc) { P.release(); delete h; return rc; }
   *out = h;
@@ -311,7 +392,7 @@ int azrbf_apply_Zstar(azrbf_plan_t h, const double* R, int64_t ldr, int64_t nvec
 int azrbf_factor(azrbf_plan_t h, void* stream) {
   if (!h) return AZRBF_EINVAL;
   h->p.last_stream = (hipStream_t)stream;
-  return az::dense_factor(h->p, (hipStream_t)stream);
+  return az::factor_plan(h->p, (hipStream_t)stream);
 }
 
 int azrbf_solve(azrbf_plan_t h, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
@@ -322,9 +403,10 @@ int azrbf_solve(azrbf_plan_t h, const double* B, int64_t ldb, int64_t nrhs, doub
   if (!B || !X || ldb < P.Mt || ldx < P.N) return AZRBF_EINVAL;
   P.last_stream = (hipStream_t)stream;
   if (!P.factored) {
-    const int rc = az::dense_factor(P, (hipStream_t)stream);
+    const int rc = az::factor_plan(P, (hipStream_t)stream);
     if (rc != AZRBF_OK && rc != AZRBF_ERANK) return rc;
   }
+  if (P.k > 64) return az::wide_solve(P, B, ldb, nrhs, X, ldx, relres, (hipStream_t)stream);
   return az::dense_solve(P, B, ldb, nrhs, X, ldx, relres, (hipStream_t)stream);
 }
 
@@ -341,10 +423,11 @@ int azrbf_solve_many(int32_t nprob, const azrbf_plan_t* plans, const double* con
 }
 
 int64_t azrbf_footprint_bytes(const azrbf_problem* pr, int64_t max_rhs) {
-  if (!pr || pr->n <= 0 || pr->s <= 0 || (pr->dim != 1 && pr->dim != 2)) return -1;
+  if (!pr || pr->n <= 0 || pr->s <= 0 || (pr->dim != 1 && pr->dim != 2) || max_rhs < 0) return -1;
   const int64_t n = pr->n, s = pr->s;
   const int64_t N = pr->dim == 1 ? n : n * n;
-  const int64_t Lg = pr->dim == 1 ? s * n : s * s * n * n;
+  const int64_t Lax = s * n;
+  const int64_t Lg = pr->dim == 1 ? Lax : Lax * Lax;
   const int64_t ph = pr->dim == 1 ? s : s * s;
   int64_t M = 0;
   if (pr->mask)
@@ -352,7 +435,7 @@ int64_t azrbf_footprint_bytes(const azrbf_problem* pr, int64_t max_rhs) {
   else
     M = Lg;
   const int64_t Mt = M + pr->nb;
-  const int64_t k = pr->k > 0 ? pr->k : 32;
+  int k = pr->k > 0 ? pr->k : (pr->dim == 1 || !pr->mask ? 32 : az::default_k(*pr, Lax, N, Mt));
   int64_t b = 0;
   b += 2 * ph * N * 16;                                 // spectra (1D) or factors + weights (2D)
   b += pr->dim == 2 ? Lg * 4 : 0;                       // inverse map
@@ -360,9 +443,14 @@ int64_t azrbf_footprint_bytes(const azrbf_problem* pr, int64_t max_rhs) {
   chunk = chunk < 1 ? 1 : (chunk > 64 ? 64 : chunk);
   const int64_t pairs = (std::max<int64_t>(k, max_rhs) + 1) / 2;
   if (!(pr->dim == 1 && N <= 8192)) b += 2 * ph * N * 16 * std::min<int64_t>(chunk, pairs);
-  b += 8 * (2 * N * k + 3 * Mt * k + 2 * k * k);        // factor and its scratch
-  b += 8 * (Mt * k / 4 + Mt * k / 4);                   // TSQR tree (upper bound)
-  b += 8 * max_rhs * (N + 3 * Mt + k + ((Mt + 1023) / 1024) * k + 2);
+  if (k > 64) {
+    b += 8 * az::wide_factor_doubles(N, Mt, k);
+    b += 8 * (max_rhs * (2 * N + 3 * Mt + 2 * k + 64) + az::gemm_split_doubles(k, max_rhs, Mt, 1) + 1);
+  } else {
+    b += 8 * (2 * N * k + 3 * Mt * k + 2 * k * k);        // factor and its scratch
+    b += 8 * (Mt * k / 4 + Mt * k / 4);                   // TSQR tree (upper bound)
+    b += 8 * max_rhs * (N + 3 * Mt + k + ((Mt + 1023) / 1024) * k + 2);
+  }
   return b;
 }
 
@@ -397,6 +485,33 @@ int azrbf_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* dst, int64
   return az::dense_gaussian(seed, rows, cols, dst, ld, (hipStream_t)stream);
 }
 
+int azrbf_dgemm(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k, double alpha,
+                const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                int64_t ldc, void* stream) {
+  if (m < 0 || n < 0 || k < 0) return AZRBF_EINVAL;
+  if (m == 0 || n == 0) return AZRBF_OK;
+  if (!C || ldc < m) return AZRBF_EINVAL;
+  if (k > 0) {
+    if (!A || !B) return AZRBF_EINVAL;
+    if (lda < std::max<int64_t>(1, transa ? k : m) || ldb < std::max<int64_t>(1, transb ? n : k))
+      return AZRBF_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t need = az::gemm_split_doubles(m, n, k, 1);
+  double* part = nullptr;
+  if (need > 0 && hipMalloc((void**)&part, sizeof(double) * need) != hipSuccess) {
+    (void)hipGetLastError();
+    part = nullptr;   // unsplit fallback: same result, fewer blocks
+  }
+  int rc = az::gemm_mfma(transa != 0, transb != 0, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1,
+                         part, part ? need : 0, st);
+  if (part) {
+    if (hipStreamSynchronize(st) != hipSuccess) rc = AZRBF_EHIP;
+    (void)hipFree(part);
+  }
+  return rc;
+}
+
 int azrbf_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(az::g_prof_mu);
   az::g_prof_on = on != 0;
@@ -408,7 +523,7 @@ int azrbf_profile_report(char* buf, int64_t len) {
   std::lock_guard<std::mutex> lk(az::g_prof_mu);
   struct Acc {
     int64_t calls = 0;
-    double ms = 0, bytes = 0, max_ms = 0;
+    double ms = 0, bytes = 0, flops = 0, max_ms = 0;
   };
   std::map<std::string, Acc> acc;
   int rc = AZRBF_OK;
@@ -423,6 +538,7 @@ int azrbf_profile_report(char* buf, int64_t len) {
     a.calls += 1;
     a.ms += ms;
     a.bytes += r.bytes;
+    a.flops += r.flops;
     if (ms > a.max_ms) a.max_ms = ms;
   }
   for (auto& r : az::g_prof) {
@@ -434,9 +550,11 @@ int azrbf_profile_report(char* buf, int64_t len) {
   bool first = true;
   char tmp[512];
   for (auto& kv : acc) {
-    snprintf(tmp, sizeof(tmp), "%s{\"name\": \"%s\", \"calls\": %lld, \"ms\": %.6f, \"max_ms\": %.6f, \"bytes\": %.0f}",
+    snprintf(tmp, sizeof(tmp),
+             "%s{\"name\": \"%s\", \"calls\": %lld, \"ms\": %.6f, \"max_ms\": %.6f, \"bytes\": %.0f, "
+             "\"flops\": %.0f}",
              first ? "" : ", ", kv.first.c_str(), (long long)kv.second.calls, kv.second.ms, kv.second.max_ms,
-             kv.second.bytes);
+             kv.second.bytes, kv.second.flops);
     out += tmp;
     first = false;
   }

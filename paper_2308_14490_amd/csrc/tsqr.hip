@@ -1,0 +1,270 @@
+// Householder QR of tall-skinny row blocks with the block held in registers
+// (the leaf and tree nodes of the TSQR of section 3.2.3's sketch, widths
+// k = 16, 32, 64).
+//
+// Thread t of the 256 owns rows t + 256 i (i < 64/k) of the block with all k
+// columns in VGPRs, so the block is RB = 16384/k rows.  Column j of the
+// Householder sweep needs one block-wide reduction, D_c = sum_{r>j} a_rj a_rc
+// for every c: each lane forms its k partial sums, a butterfly
+// reduce-scatter across the wave (DPP for lane distances below 16, a swizzle
+// for 16, a permute for 32) leaves one column sum per lane, and the four
+// waves meet in LDS.  From D one gets sigma^2 = D_j, v_j^T a_c for c > j (the
+// rank-one update) and v_c^T v_j for c < j (the compact-WY factor T).  The
+// column loop is unrolled so that every register index is static.
+#include <utility>
+
+#include "internal.h"
+
+namespace az {
+
+namespace {
+
+template <int K>
+struct RegQR {
+  static constexpr int RPT = 64 / K;   // rows per thread
+  static constexpr int RB = 256 * RPT; // rows per block
+};
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  // every lane of the permutation is valid, so no old value is needed
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double swz16_d(double x) {
+  // bitmask swizzle: and 0x1f, or 0, xor 0x10 (lane ^ 16 within 32 lanes)
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), 0x401F);
+  return __hiloint2double(hi, lo);
+}
+
+// Stage S exchanges with partner lane lane ^ X_S, X = 15, 7, 2, 1, 16, 32
+// (row mirror, half-row mirror, two quad permutations, swizzle, permute);
+// lanes of a pair differ in bit B_S = 3, 2, 1, 0, 4, 5 and agree in the
+// bits of all earlier stages.
+template <int S>
+__device__ __forceinline__ double xchg(double x) {
+  if constexpr (S == 0) return dpp_d<0x140>(x);
+  else if constexpr (S == 1) return dpp_d<0x141>(x);
+  else if constexpr (S == 2) return dpp_d<0x4E>(x);
+  else if constexpr (S == 3) return dpp_d<0xB1>(x);
+  else if constexpr (S == 4) return swz16_d(x);
+  else return __shfl_xor(x, 32, 64);
+}
+
+constexpr int stage_bit(int s) { return s == 0 ? 3 : s == 1 ? 2 : s == 2 ? 1 : s == 3 ? 0 : s == 4 ? 4 : 5; }
+
+// Halves the N live values: the lane whose bit B_S is set keeps the upper
+// half, its partner the lower half, and each adds what the other sent.
+template <int S, int N>
+__device__ __forceinline__ void rs_stage(double* v, int lane) {
+  const bool up = (lane >> stage_bit(S)) & 1;
+#pragma unroll
+  for (int q = 0; q < N / 2; ++q) {
+    const double send = up ? v[q] : v[q + N / 2];
+    const double keep = up ? v[q + N / 2] : v[q];
+    v[q] = keep + xchg<S>(send);
+  }
+}
+
+template <int S>
+__device__ __forceinline__ void ar_stage(double* v) {
+  v[0] += xchg<S>(v[0]);
+}
+
+// Wave-wide sums of K values per lane; the lane is left with the sum of value
+// rs_col<K>(lane).
+template <int K>
+__device__ __forceinline__ double wave_reduce_scatter(double* v, int lane) {
+  rs_stage<0, K>(v, lane);
+  rs_stage<1, K / 2>(v, lane);
+  rs_stage<2, K / 4>(v, lane);
+  rs_stage<3, K / 8>(v, lane);
+  if constexpr (K >= 32) rs_stage<4, K / 16>(v, lane); else ar_stage<4>(v);
+  if constexpr (K >= 64) rs_stage<5, K / 32>(v, lane); else ar_stage<5>(v);
+  return v[0];
+}
+
+template <int K>
+__device__ __forceinline__ int rs_col(int lane) {
+  int c = ((lane >> 3) & 1) * (K / 2) + ((lane >> 2) & 1) * (K / 4) + ((lane >> 1) & 1) * (K / 8) +
+          (lane & 1) * (K / 16);
+  if constexpr (K >= 32) c += ((lane >> 4) & 1) * (K / 32);
+  if constexpr (K >= 64) c += ((lane >> 5) & 1) * (K / 64);
+  return c;
+}
+
+template <int K>
+__device__ __forceinline__ bool rs_writer(int lane) {
+  if constexpr (K == 16) return lane < 16;
+  else if constexpr (K == 32) return lane < 32;
+  else return true;
+}
+
+template <int K>
+struct QrShared {
+  double (*red)[K];
+  double* rowj;
+  double* wv;
+  double* gv;
+  double* scal;
+  double* Tm;
+};
+
+// Column J of the sweep (J static, so every register index is static).
+template <int K, int J>
+__device__ __forceinline__ void qr_column(double (&a)[RegQR<K>::RPT][K], const QrShared<K>& sh, int t,
+                                          int lane, int wave, int col, bool writer) {
+  constexpr int RPT = RegQR<K>::RPT;
+  double p[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) p[c] = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const double aj = (t + 256 * i > J) ? a[i][J] : 0.0;
+#pragma unroll
+    for (int c = 0; c < K; ++c) p[c] = fma(aj, a[i][c], p[c]);
+  }
+  const double s = wave_reduce_scatter<K>(p, lane);
+  if (writer) sh.red[wave][col] = s;
+  __syncthreads();
+  if (t < K) {
+    const double sig2 = (sh.red[0][J] + sh.red[1][J]) + (sh.red[2][J] + sh.red[3][J]);
+    const double dt = (sh.red[0][t] + sh.red[1][t]) + (sh.red[2][t] + sh.red[3][t]);
+    const double alpha = sh.rowj[J];
+    double beta = alpha, tau = 0.0, scale = 0.0;
+    if (sig2 > 0.0) {
+      beta = -copysign(sqrt(fma(alpha, alpha, sig2)), alpha);
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    if (t == J) {
+      sh.scal[0] = beta;
+      sh.scal[1] = tau;
+      sh.scal[2] = scale;
+    } else if (t > J) {
+      sh.wv[t] = tau * fma(dt, scale, sh.rowj[t]);
+    } else {
+      sh.gv[t] = fma(dt, scale, sh.rowj[t]);   // v_t[J] = a[J][t] sits below t's diagonal
+    }
+  }
+  __syncthreads();
+  const double beta = sh.scal[0], tau = sh.scal[1], scale = sh.scal[2];
+  if (t < J) {   // T(t, J) = -tau_J sum_{l=t}^{J-1} T(t, l) g_l
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int l = t;
+    for (; l + 4 <= J; l += 4) {
+      a0 = fma(sh.Tm[l * K + t], sh.gv[l], a0);
+      a1 = fma(sh.Tm[(l + 1) * K + t], sh.gv[l + 1], a1);
+      a2 = fma(sh.Tm[(l + 2) * K + t], sh.gv[l + 2], a2);
+      a3 = fma(sh.Tm[(l + 3) * K + t], sh.gv[l + 3], a3);
+    }
+    for (; l < J; ++l) a0 = fma(sh.Tm[l * K + t], sh.gv[l], a0);
+    sh.Tm[J * K + t] = -tau * ((a0 + a1) + (a2 + a3));
+  } else if (t == J) {
+    sh.Tm[J * K + J] = tau;
+  }
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int row = t + 256 * i;
+    if (row >= J) {
+      const double v = row == J ? 1.0 : a[i][J] * scale;
+#pragma unroll
+      for (int c = J + 1; c < K; ++c) a[i][c] = fma(-sh.wv[c], v, a[i][c]);
+      a[i][J] = row == J ? beta : v;
+    }
+  }
+  if constexpr (J + 1 < K) {
+    if (t == J + 1) {
+#pragma unroll
+      for (int c = 0; c < K; ++c) sh.rowj[c] = a[0][c];
+    }
+  }
+}
+
+template <int K, int... J>
+__device__ __forceinline__ void qr_columns(double (&a)[RegQR<K>::RPT][K], const QrShared<K>& sh, int t,
+                                           int lane, int wave, int col, bool writer,
+                                           std::integer_sequence<int, J...>) {
+  (qr_column<K, J>(a, sh, t, lane, wave, col, writer), ...);
+}
+
+// One block of RB rows: R (upper k x k) to rows b*k.. of Rout, the
+// reflectors (unit lower trapezoid) over the block's rows of V, and the
+// compact-WY T (k x k, column-major) to Tout + b*k*k, so that
+// H_0 ... H_{k-1} = I - V T V^T.  Rows >= m are read as zero and not
+// written.  A and V may be the same array.
+template <int K>
+__global__ void __launch_bounds__(256)
+k_tsqr_reg(const double* A, int64_t lda, int64_t m, double* __restrict__ Rout, int64_t ldr, double* V,
+           int64_t ldv, double* __restrict__ Tout) {
+  using C = RegQR<K>;
+  __shared__ double red[4][K];    // per-wave column sums
+  __shared__ double rowj[K];      // the pivot row
+  __shared__ double wv[K];        // tau_j v_j^T a_c, c > j
+  __shared__ double gv[K];        // v_c^T v_j, c < j
+  __shared__ double scal[4];      // beta, tau, scale
+  __shared__ double Tm[K * K];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * C::RB;
+  double a[C::RPT][K];
+#pragma unroll
+  for (int i = 0; i < C::RPT; ++i) {
+    const int64_t gr = r0 + t + 256 * i;
+#pragma unroll
+    for (int c = 0; c < K; ++c) a[i][c] = gr < m ? A[gr + lda * c] : 0.0;
+  }
+  if (t == 0) {
+#pragma unroll
+    for (int c = 0; c < K; ++c) rowj[c] = a[0][c];
+  }
+  const int col = rs_col<K>(lane);
+  const bool writer = rs_writer<K>(lane);
+  QrShared<K> sh{red, rowj, wv, gv, scal, Tm};
+  qr_columns<K>(a, sh, t, lane, wave, col, writer, std::make_integer_sequence<int, K>{});
+  __syncthreads();
+  for (int e = t; e < K * K; e += 256) {
+    const int r = e % K, c = e / K;
+    Tout[(int64_t)blockIdx.x * K * K + e] = r <= c ? Tm[c * K + r] : 0.0;
+  }
+  if (t < K) {
+#pragma unroll
+    for (int c = 0; c < K; ++c) Rout[(int64_t)blockIdx.x * K + t + ldr * c] = c >= t ? a[0][c] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < C::RPT; ++i) {
+    const int row = t + 256 * i;
+    const int64_t gr = r0 + row;
+    if (gr < m) {
+#pragma unroll
+      for (int c = 0; c < K; ++c) V[gr + ldv * c] = row > c ? a[i][c] : (row == c ? 1.0 : 0.0);
+    }
+  }
+}
+
+template <int K>
+int launch_reg(const double* A, int64_t lda, int64_t m, double* R, int64_t ldr, double* V, int64_t ldv,
+               double* T, hipStream_t st) {
+  const int64_t nb = (m + RegQR<K>::RB - 1) / RegQR<K>::RB;
+  k_tsqr_reg<K><<<(unsigned)nb, 256, 0, st>>>(A, lda, m, R, ldr, V, ldv, T);
+  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+}
+
+}  // namespace
+
+int tsqr_block_rows(int k) { return 16384 / k; }
+
+int tsqr_block_qr(const double* A, int64_t lda, int64_t m, int k, double* R, int64_t ldr, double* V,
+                  int64_t ldv, double* T, hipStream_t st) {
+  if (m <= 0) return AZRBF_OK;
+  switch (k) {
+    case 16: return launch_reg<16>(A, lda, m, R, ldr, V, ldv, T, st);
+    case 32: return launch_reg<32>(A, lda, m, R, ldr, V, ldv, T, st);
+    case 64: return launch_reg<64>(A, lda, m, R, ldr, V, ldv, T, st);
+    default: return AZRBF_EUNSUPPORTED;
+  }
+}
+
+}  // namespace az

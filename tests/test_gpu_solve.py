@@ -149,3 +149,50 @@ def test_refine_zero_and_two():
     ro = evaluate.relres(A, Xo, B)
     assert np.all(out[0] < 1e-8)                 # one AZ pass: near the rounding floor of Z*
     assert np.all(out[2] <= 10 * ro + 1e-15)
+
+
+# ---------------------------------------------------------------- wide sketches (2D)
+
+@pytest.mark.parametrize("n,k", [(16, 128), (16, 256), (32, 512)])
+def test_wide_sketch_matches_oracle(n, k):
+    """k > 64: block Gram-Schmidt QR with TSQR panels and the block Jacobi SVD
+    of R reproduce the oracle's sketch W = (A - A Z* A) Omega of a 2D disk."""
+    azrbf, problems = _az()
+    prob = W.config_c3a(n)
+    prob.k = k
+    announce("wide sketch", n, "k", k)
+    p = problems.plan_for(prob)
+    rc = azrbf.factor(p)
+    A, idx, pts, bpts = dense.system_matrix(prob)
+    Z = periodic.zstar_normal(prob, idx)
+    Om = philox.gaussian_sketch(prob.N, p.k, prob.seed)
+    Wo = (A - A @ Z @ A) @ Om
+    Q = azrbf.get_factor(p, "Q").cpu().numpy().T
+    R = azrbf.get_factor(p, "R").cpu().numpy().T
+    sig = azrbf.get_factor(p, "sigma").cpu().numpy()
+    announce("rc", rc, "rank", p.info()["rank"], "sweeps", p.info()["sweeps"])
+    assert np.max(np.abs(Q.T @ Q - np.eye(p.k))) < 1e-12
+    assert np.max(np.abs(np.tril(R, -1))) == 0.0
+    scale = np.abs(Wo).max()
+    assert np.max(np.abs(Q @ R - Wo)) < 1e-10 * scale
+    inf = p.info()
+    floor = 20 * 2.0 ** -53 * inf["normA"] * inf["normZ"] * np.max(np.linalg.norm(A @ Om, axis=0)) * np.sqrt(k)
+    so = np.linalg.svd(Wo, compute_uv=False)
+    assert np.max(np.abs(sig - so)) < floor
+    big = so > 1e-3 * so[0]
+    assert np.max(np.abs(sig[big] - so[big]) / so[big]) < 1e-9
+    assert np.all(np.diff(sig) <= 0)
+    p.destroy()
+
+
+def test_solve_2d_disk_small():
+    info = _check(W.config_c3a(16))
+    assert info["k"] > 64
+
+
+def test_solve_2d_disk():
+    _check(W.config_c3a(32))
+
+
+def test_solve_2d_poisson_star():
+    _check(W.config_c4(32))

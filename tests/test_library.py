@@ -32,7 +32,8 @@ def test_header_declares_the_boundary():
 
 
 def test_library_exports_every_declared_symbol():
-    lib = ctypes.CDLL(_lib_path())
+    # RTLD_NOW: every undefined symbol of the library fails the load here
+    lib = ctypes.CDLL(_lib_path(), mode=os.RTLD_NOW | os.RTLD_GLOBAL)
     for name in _declared():
         assert hasattr(lib, name), name
 
