@@ -15,9 +15,12 @@ right-hand sides solved per second whose residual ||Ax - b||/||b|| is at most
 
 Also reported: the plain per-problem rate (each right-hand side its own
 plan + factor + solve), the rate with a resident factor and one right-hand
-side per call, the per-kernel roofline of the dominant kernel (HIP events
-around each launch, algorithmic bytes per launch), and the CPU oracle timed
-on a bounded sample of the same family.
+side per call, the roofline of the kernel with the largest share of GPU time
+(HIP events around each launch on its own stream, algorithmic bytes or flops
+per launch) and of the FFT passes together, a served-stream comparison
+(continuous batching with resident factors against plain FIFO solves on a
+reduced mixed 1D/2D request stream, with p50/p99 latency), and the CPU
+oracle timed on a bounded sample of the same family.
 """
 import argparse
 import json
@@ -31,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "AZ solves/sec at residual <=1e-10 (batched/served vs plain); FFT-pass HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
 
 
 def log(*a):
@@ -70,6 +74,91 @@ def cpu_baseline(n=4096, nrhs=64):
     }
 
 
+def _source_hash():
+    import hashlib
+    h = hashlib.sha1()
+    csrc = os.path.join(ROOT, "paper_2308_14490_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel):
+    """HBM bytes per launch from the stored rocprofv3 FETCH_SIZE / WRITE_SIZE
+    passes (calibrated against a copy of known size), if they were taken on
+    the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != _source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def roofline_of(r, total_ms):
+    """Roofline entry of one kernel from the per-launch profile record."""
+    avg_ms = r["ms"] / r["calls"]
+    flops = r.get("flops", 0.0)
+    if flops > 0 and flops / max(r["bytes"], 1.0) > FP64_PEAK_TFS * 1e3 / HBM_PEAK_GBS:
+        achieved = flops / r["calls"] / (avg_ms * 1e-3) / 1e12
+        out = {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+               "frac": round(achieved / FP64_PEAK_TFS, 4)}
+    else:
+        achieved = r["bytes"] / r["calls"] / (avg_ms * 1e-3) / 1e9
+        out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    out.update({"traffic": _traffic(r["name"]), "kernel": r["name"], "avg_us": round(avg_ms * 1e3, 2),
+                "bytes_per_launch": r["bytes"] / r["calls"], "share_of_gpu_time": round(r["ms"] / total_ms, 3)})
+    return out
+
+
+def served_vs_plain(count, seed, sides, log_fn):
+    """Reduced mixed stream (70% 1D N = 2^10..2^16, 30% 2D approximation on
+    disks and stars): plain FIFO per-problem solves against the
+    continuous-batching server, both closed-loop (all requests queued at the
+    start), then the server open-loop at twice the plain request rate."""
+    import torch
+    import workloads as W
+    from paper_2308_14490_amd import serve
+    be = serve.GpuBackend()
+    free, total = torch.cuda.mem_get_info()
+    budget = int(min(free * 0.8, 200 << 30))
+    reqs = W.served_stream(count=count, seed=seed, rate=1e9, sides=sides)
+    for r in reqs:
+        r.arrival = 0.0
+    # warm the kernels of every size once
+    warm = {}
+    for r in reqs:
+        key = (r.problem.dim, r.problem.n)
+        if key not in warm:
+            warm[key] = r
+    serve.run_plain(be, list(warm.values()))
+    torch.cuda.synchronize()
+    plain = serve.summarize(serve.run_plain(be, reqs))
+    log_fn(f"served stream: plain {plain['solves_per_s']:.1f} solves/s, p50 {plain['p50_ms']:.1f} ms")
+    srv = serve.Server(be, budget)
+    closed = serve.summarize(srv.run(reqs))
+    srv.close()
+    log_fn(f"served stream: served closed-loop {closed['solves_per_s']:.1f} solves/s")
+    rate = 2.0 * plain["requests"] / plain["makespan_s"]
+    open_reqs = W.served_stream(count=count, seed=seed, rate=rate, sides=sides)
+    srv = serve.Server(be, budget)
+    openl = serve.summarize(srv.run(open_reqs))
+    ticks = len(srv.ticks)
+    srv.close()
+    log_fn(f"served stream: open-loop at {rate:.1f} req/s: p50 {openl['p50_ms']:.1f} ms p99 {openl['p99_ms']:.1f} ms")
+    return {"requests": count, "seed": seed, "sides_2d": list(sides), "exps_1d": [10, 16],
+            "budget_bytes": budget, "plain": plain, "served_closed_loop": closed,
+            "served_open_loop": dict(openl, rate_req_per_s=round(rate, 2), ticks=ticks),
+            "speedup_closed_loop": round(closed["solves_per_s"] / plain["solves_per_s"], 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +169,8 @@ def main():
     ap.add_argument("--plain", type=int, default=8, help="right-hand sides timed in the plain modes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=4096)
+    ap.add_argument("--no-served", action="store_true", help="skip the served-stream comparison")
+    ap.add_argument("--serve-count", type=int, default=48)
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps only (for rocprofv3 runs)")
     args = ap.parse_args()
@@ -140,18 +231,18 @@ def main():
     azrbf.profile_enable(False)
     kern.sort(key=lambda r: -r["ms"])
     total_ms = sum(r["ms"] for r in kern)
+    dom = kern[0]
+    roofline = roofline_of(dom, total_ms)
     fft = [r for r in kern if r["name"].startswith(("col_", "row_", "fused_"))]
-    dom = fft[0] if fft else kern[0]
-    avg_ms = dom["ms"] / dom["calls"]
-    bpl = dom["bytes"] / dom["calls"]
-    achieved = bpl / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": dom["name"], "avg_us": round(avg_ms * 1e3, 2),
-                "bytes_per_launch": bpl, "share_of_gpu_time": round(dom["ms"] / total_ms, 3)}
+    fft_ms = sum(r["ms"] for r in fft)
+    fft_passes = {"kernels": len(fft), "share_of_gpu_time": round(fft_ms / total_ms, 3),
+                  "achieved": round(sum(r["bytes"] for r in fft) / (fft_ms * 1e-3) / 1e9, 1) if fft_ms else None,
+                  "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    if fft_passes["achieved"]:
+        fft_passes["frac"] = round(fft_passes["achieved"] / HBM_PEAK_GBS, 4)
     table = [{"name": r["name"], "calls": r["calls"], "avg_us": round(r["ms"] / r["calls"] * 1e3, 2),
               "GBps": round(r["bytes"] / (r["ms"] * 1e-3) / 1e9, 1) if r["ms"] > 0 else None,
-              "share": round(r["ms"] / total_ms, 3)} for r in kern[:10]]
+              "share": round(r["ms"] / total_ms, 3)} for r in kern[:12]]
     log("dominant kernel", json.dumps(roofline))
 
     # plain modes
@@ -198,8 +289,11 @@ def main():
                   "plain_resident_factor": round(plain_resident, 2),
                   "batched_resident_factor": round(batched_resident, 2)},
         "roofline": roofline,
+        "fft_passes": fft_passes,
         "kernels": table,
     }
+    if not args.no_served:
+        out["served_stream"] = served_vs_plain(args.serve_count, 2024, (64,), log)
     if not args.no_cpu_baseline:
         log(f"cpu baseline (oracle) at N={args.cpu_n}")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.nrhs)

@@ -144,9 +144,18 @@ int azrbf_factor(azrbf_plan_t plan, void* stream);
 int azrbf_solve(azrbf_plan_t plan, const double* B, int64_t ldb, int64_t nrhs,
                 double* X, int64_t ldx, double* relres, void* stream);
 
-/* Batched form of azrbf_solve over several factored plans on one stream:
- * the per-problem work is interleaved pass by pass so that small problems
- * share launches' latency.  Arrays have length nprob. */
+/* Batched form of azrbf_solve (Algorithm 1) over nprob different plans,
+ * e.g. problems of uneven sizes.  The plans' work runs concurrently on the
+ * library's internal streams (up to four, worker threads enqueue it; plans
+ * are assigned largest first to the least-loaded stream), factoring plans
+ * that are not factored yet; the work of each plan is the same as in
+ * azrbf_solve, so every result equals the one-plan call bit for bit.  The
+ * caller's stream waits for all of it; the call returns once everything is
+ * queued (a factorisation inside synchronises its internal stream).  Arrays
+ * have length nprob; relres may be NULL, or hold NULL entries.  Many
+ * right-hand sides of ONE plan belong in a single azrbf_solve call instead
+ * (they share every launch).  Errors: EINVAL (a plan listed twice, plans of
+ * another device, bad sizes), else the first failing plan's code. */
 int azrbf_solve_many(int32_t nprob, const azrbf_plan_t* plans,
                      const double* const* B, const int64_t* ldb, const int64_t* nrhs,
                      double* const* X, const int64_t* ldx, double* const* relres,

@@ -244,6 +244,7 @@ def solve(p, B, X=None, relres=None, stream=None):
         relres = torch.empty(nrhs, dtype=torch.float64, device=B.device)
     _check(_lib().azrbf_solve(p.handle, B.data_ptr(), ldb, nrhs, X.data_ptr(), ldx, relres.data_ptr(),
                               _stream(stream)), "azrbf_solve")
+    p.k = p.info()["k"]     # a first solve factors, and the width may have grown
     return X, relres
 
 
@@ -265,6 +266,8 @@ def solve_many(plans, Bs, Xs=None, stream=None):
         bp[i], xp[i], rp[i] = B.data_ptr(), X.data_ptr(), r.data_ptr()
         ldb[i], ldx[i], nr[i] = lb, lx, nrhs
     _check(_lib().azrbf_solve_many(n, hp, bp, ldb, nr, xp, ldx, rp, _stream(stream)), "azrbf_solve_many")
+    for p in plans:
+        p.k = p.info()["k"]
     return Xs, rels
 
 

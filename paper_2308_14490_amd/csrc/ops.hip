@@ -749,9 +749,13 @@ static int launch_col(const ColArgs& a) {
   const int lds = C * N1 * (int)sizeof(double2);
   const dim3 grid((unsigned)(g.N2 / C), (unsigned)a.npairs);
   const bool tw4 = g.dim == 1;
-  static const char* names[5] = {"col_fwd_A", "col_inv_A", "col_fwd_Z", "col_inv_Z", "col_fwd_C"};
-  static std::string full[5];
-  if (full[a.mode].empty()) full[a.mode] = std::string(names[a.mode]) + " n1=" + std::to_string(N1);
+  // built once per instantiation (thread-safe static initialisation)
+  static const std::vector<std::string> full = [] {
+    const char* names[5] = {"col_fwd_A", "col_inv_A", "col_fwd_Z", "col_inv_Z", "col_fwd_C"};
+    std::vector<std::string> v;
+    for (const char* n : names) v.push_back(std::string(n) + " n1=" + std::to_string(N1));
+    return v;
+  }();
   const double vc = (double)std::min<int64_t>(a.nvec - 2 * a.pair0, 2 * a.npairs);
   const double cN = 16.0 * (double)g.N * (double)a.npairs;   // one complex array per pair
   const double bmul = a.beta != 0.0 ? 2.0 : 1.0;
@@ -829,9 +833,12 @@ static int launch_row(const RowArgs& a) {
   const int lds = Lr * RowLds::stride(N2) * (int)sizeof(double2);
   const dim3 grid((unsigned)(g.N1 / Lr), (unsigned)a.npairs);
   const bool tw4 = g.dim == 1;
-  static const char* names[3] = {"row_A", "row_Z", "row_fwd_C"};
-  static std::string full[3];
-  if (full[a.mode].empty()) full[a.mode] = std::string(names[a.mode]) + " n2=" + std::to_string(N2);
+  static const std::vector<std::string> full = [] {
+    const char* names[3] = {"row_A", "row_Z", "row_fwd_C"};
+    std::vector<std::string> v;
+    for (const char* n : names) v.push_back(std::string(n) + " n2=" + std::to_string(N2));
+    return v;
+  }();
   const double cN = 16.0 * (double)g.N * (double)a.npairs;
   const double spec = g.dim == 1 ? 16.0 * (double)g.N * P.s : 0.0;
   const double bytes = a.mode == 2 ? 2.0 * cN : cN * (1.0 + P.ph) + spec;

@@ -7,6 +7,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -226,6 +227,32 @@ static void split_1d(int64_t N, int* N1, int* N2) {
   *N1 = (int)(N >> l2);
 }
 
+// Internal streams for azrbf_solve_many (default priority, non-blocking),
+// one set per device, created on first use and kept for the process.
+constexpr int kManyStreams = 4;
+struct ManyPool {
+  hipStream_t st[kManyStreams] = {};
+  hipEvent_t done[kManyStreams] = {};
+  hipEvent_t start = nullptr;
+};
+std::mutex g_many_mu;                 // one batched call at a time per process
+std::map<int, ManyPool> g_many;
+
+int many_pool(int dev, ManyPool** out) {
+  auto it = g_many.find(dev);
+  if (it == g_many.end()) {
+    ManyPool mp;
+    for (int w = 0; w < kManyStreams; ++w) {
+      if (hipStreamCreateWithFlags(&mp.st[w], hipStreamNonBlocking) != hipSuccess) return AZRBF_EHIP;
+      if (hipEventCreateWithFlags(&mp.done[w], hipEventDisableTiming) != hipSuccess) return AZRBF_EHIP;
+    }
+    if (hipEventCreateWithFlags(&mp.start, hipEventDisableTiming) != hipSuccess) return AZRBF_EHIP;
+    it = g_many.emplace(dev, mp).first;
+  }
+  *out = &it->second;
+  return AZRBF_OK;
+}
+
 }  // namespace az
 
 using az::Plan;
@@ -414,12 +441,67 @@ int azrbf_solve_many(int32_t nprob, const azrbf_plan_t* plans, const double* con
                      const int64_t* nrhs, double* const* X, const int64_t* ldx, double* const* relres,
                      void* stream) {
   if (nprob < 0 || (nprob > 0 && (!plans || !B || !ldb || !nrhs || !X || !ldx))) return AZRBF_EINVAL;
+  if (nprob == 0) return AZRBF_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return AZRBF_EHIP;
   for (int32_t i = 0; i < nprob; ++i) {
-    const int rc = azrbf_solve(plans[i], B[i], ldb[i], nrhs[i], X[i], ldx[i], relres ? relres[i] : nullptr,
-                               stream);
-    if (rc) return rc;
+    if (!plans[i] || nrhs[i] < 0) return AZRBF_EINVAL;
+    const Plan& P = plans[i]->p;
+    if (P.device != dev) return AZRBF_EINVAL;
+    if (nrhs[i] > 0 && (!B[i] || !X[i] || ldb[i] < P.Mt || ldx[i] < P.N)) return AZRBF_EINVAL;
+    for (int32_t j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return AZRBF_EINVAL;   // a plan serves one stream at a time
   }
-  return AZRBF_OK;
+  hipStream_t caller = (hipStream_t)stream;
+  if (nprob == 1)
+    return azrbf_solve(plans[0], B[0], ldb[0], nrhs[0], X[0], ldx[0], relres ? relres[0] : nullptr, stream);
+  std::lock_guard<std::mutex> lk(az::g_many_mu);
+  az::ManyPool* mp = nullptr;
+  AZ_TRY(az::many_pool(dev, &mp));
+  const int W = std::min<int>(az::kManyStreams, nprob);
+  // largest work first, each to the least-loaded worker
+  std::vector<std::pair<double, int>> cost(nprob);
+  for (int32_t i = 0; i < nprob; ++i) {
+    const Plan& P = plans[i]->p;
+    const double lg = std::log2((double)P.N + 1.0);
+    double c = (double)P.N * lg * (double)(nrhs[i] + 1);
+    if (!P.factored) c += (double)P.N * lg * 3.0 * P.k + (P.k > 64 ? 8.0 * P.Mt * (double)P.k * P.k : 0.0);
+    cost[i] = {c, i};
+  }
+  std::sort(cost.begin(), cost.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+    return a.first > b.first || (a.first == b.first && a.second < b.second);
+  });
+  std::vector<std::vector<int>> lists(W);
+  std::vector<double> load(W, 0.0);
+  for (const auto& ci : cost) {
+    const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    lists[w].push_back(ci.second);
+    load[w] += ci.first;
+  }
+  if (hipEventRecord(mp->start, caller) != hipSuccess) return AZRBF_EHIP;
+  for (int w = 0; w < W; ++w)
+    if (hipStreamWaitEvent(mp->st[w], mp->start, 0) != hipSuccess) return AZRBF_EHIP;
+  std::vector<int> rcs(nprob, AZRBF_OK);
+  std::vector<std::thread> th;
+  for (int w = 0; w < W; ++w) {
+    th.emplace_back([&, w]() {
+      if (hipSetDevice(dev) != hipSuccess) {
+        for (int i : lists[w]) rcs[i] = AZRBF_EHIP;
+        return;
+      }
+      for (int i : lists[w])
+        rcs[i] = azrbf_solve(plans[i], B[i], ldb[i], nrhs[i], X[i], ldx[i], relres ? relres[i] : nullptr,
+                             mp->st[w]);
+    });
+  }
+  for (auto& t : th) t.join();
+  int rc = AZRBF_OK;
+  for (int w = 0; w < W; ++w) {
+    if (hipEventRecord(mp->done[w], mp->st[w]) != hipSuccess || hipStreamWaitEvent(caller, mp->done[w], 0) != hipSuccess)
+      rc = AZRBF_EHIP;
+  }
+  for (int32_t i = 0; i < nprob && rc == AZRBF_OK; ++i) rc = rcs[i];
+  return rc;
 }
 
 int64_t azrbf_footprint_bytes(const azrbf_problem* pr, int64_t max_rhs) {

@@ -20,6 +20,7 @@
 // Q^T c, P t and Omega y and the FFT operators for A and Z*.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -447,13 +448,17 @@ int wide_factor(Plan& P, hipStream_t st) {
     k_eye<<<grid1((int64_t)k * k), 256, 0, st>>>(k, P.Vj);
     AZ_HIP(hipGetLastError());
   }
-  static bool lds_set = false;
   const int rot_lds = (int)(sizeof(double) * 2 * JP * (JP + 2));
   const int eig_lds = (int)(sizeof(double) * 2 * JP * (JP + 1));
-  if (!lds_set) {
-    AZ_HIP(hipFuncSetAttribute((const void*)k_jac_rot, hipFuncAttributeMaxDynamicSharedMemorySize, rot_lds));
-    AZ_HIP(hipFuncSetAttribute((const void*)k_jac_eig, hipFuncAttributeMaxDynamicSharedMemorySize, eig_lds));
-    lds_set = true;
+  {
+    static std::mutex mu;
+    static bool lds_set = false;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!lds_set) {
+      AZ_HIP(hipFuncSetAttribute((const void*)k_jac_rot, hipFuncAttributeMaxDynamicSharedMemorySize, rot_lds));
+      AZ_HIP(hipFuncSetAttribute((const void*)k_jac_eig, hipFuncAttributeMaxDynamicSharedMemorySize, eig_lds));
+      lds_set = true;
+    }
   }
   double* Hp = scr + Lx.hp;
   double* Vp = scr + Lx.vp;

@@ -22,6 +22,25 @@ def plan_for(prob, refine=1, tau=1e-12, tauZ=1e-12, k=None, stream=None):
                       k=prob.k if k is None else k, refine=refine, seed=prob.seed, stream=stream)
 
 
+def footprint_for(prob, max_rhs, mask=None, refine=1, tau=1e-12, tauZ=1e-12):
+    """Device bytes a plan for ``prob`` needs with ``max_rhs`` right-hand sides
+    per solve (azrbf_footprint_bytes)."""
+    import ctypes
+    if mask is None:
+        mask = azrbf.make_mask(prob.dim, prob.n, prob.s, prob.T, prob.domain.contains)
+    m = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
+    bp = np.ascontiguousarray(prob.bpoints(), dtype=np.float64).reshape(-1) if prob.nb else None
+    pr = azrbf._Problem()
+    pr.dim, pr.n, pr.s, pr.T = prob.dim, prob.n, prob.s, float(prob.T)
+    pr.eps, pr.tau0, pr.op, pr.k2 = float(prob.eps), 0.0, 0 if prob.op == 0 else 1, float(prob.k2)
+    pr.mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    pr.nb = prob.nb
+    pr.bpts = bp.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if prob.nb else None
+    pr.bweight, pr.tau, pr.tauZ = float(prob.bweight), float(tau), float(tauZ)
+    pr.k, pr.refine, pr.seed = int(prob.k), int(refine), int(prob.seed)
+    return azrbf.footprint_bytes(pr, max_rhs)
+
+
 def rhs_for(plan, prob, which=None, device=None):
     """Right-hand sides as a (nrhs, M + Mb) float64 tensor on ``device``."""
     pts = plan.points()

@@ -1,0 +1,107 @@
+"""GPU tests of batching and serving: azrbf_solve_many over uneven problems
+equals one-plan solves bit for bit, and every request served in a mixed
+continuous-batching run gets the same result as when solved alone (same
+residual level, same fitted values to within the residuals)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+from gpu_util import announce, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _mods():
+    require_gpu()
+    from paper_2308_14490_amd import azrbf, problems, serve
+    return azrbf, problems, serve
+
+
+def _problems():
+    return [W.family_1d(1024, 3, seed0=11, name="m1"),
+            W.family_1d(16384, 2, seed0=21, name="m2"),
+            W.family_1d(256, 5, seed0=31, name="m3"),
+            W.config_c3a(32)]
+
+
+def test_solve_many_equals_single_solves():
+    azrbf, problems, _ = _mods()
+    probs = _problems()
+    announce("solve_many", [p.name for p in probs])
+    plans_a = [problems.plan_for(p) for p in probs]
+    plans_b = [problems.plan_for(p) for p in probs]
+    Bs = [problems.rhs_for(pl, p) for pl, p in zip(plans_a, probs)]
+    single = [azrbf.solve(pl, B) for pl, B in zip(plans_a, Bs)]
+    Xs, rels = azrbf.solve_many(plans_b, Bs)           # factors inside, concurrently
+    torch.cuda.synchronize()
+    for (Xa, ra), Xb, rb, p in zip(single, Xs, rels, probs):
+        assert torch.equal(Xa, Xb), p.name
+        assert torch.equal(ra, rb), p.name
+    # a second round on the now-factored plans, with fresh right-hand sides
+    Bs2 = [B.flip(0).contiguous() for B in Bs]
+    Xs2, rels2 = azrbf.solve_many(plans_b, Bs2)
+    single2 = [azrbf.solve(pl, B) for pl, B in zip(plans_a, Bs2)]
+    torch.cuda.synchronize()
+    for (Xa, ra), Xb in zip(single2, Xs2):
+        assert torch.equal(Xa, Xb)
+    for pl in plans_a + plans_b:
+        pl.destroy()
+
+
+def test_solve_many_rejects_a_repeated_plan():
+    azrbf, problems, _ = _mods()
+    p = W.family_1d(256, 2)
+    pl = problems.plan_for(p)
+    B = problems.rhs_for(pl, p)
+    with pytest.raises(azrbf.AzrbfError):
+        azrbf.solve_many([pl, pl], [B, B])
+    pl.destroy()
+
+
+def _mixed_requests():
+    reqs = []
+    probs = [W.family_1d(2048, 2, seed0=100, name="r0"),
+             W.family_1d(2048, 3, seed0=200, name="r1"),        # same operator as r0
+             W.family_1d(16384, 1, seed0=300, name="r2"),
+             W.config_c3a(32),
+             W.family_1d(1024, 4, seed0=400, name="r4"),
+             W.family_1d(16384, 2, seed0=500, name="r5"),       # same operator as r2
+             W.config_c4(32)]
+    probs[1].seed = 7
+    for i, p in enumerate(probs):
+        reqs.append(W.Request(i, 0.002 * i, p))
+    return reqs
+
+
+def test_served_results_match_alone():
+    azrbf, problems, serve = _mods()
+    reqs = _mixed_requests()
+    announce("serve mix", len(reqs))
+    be = serve.GpuBackend(keep_x=True)
+    srv = serve.Server(be, budget_bytes=8 << 30)
+    res = srv.run(reqs)
+    assert srv.created == 5                                   # two operators were shared
+    for r in reqs:
+        p = r.problem
+        alone = problems.plan_for(p)
+        B = problems.rhs_for(alone, p)
+        Xa, ra = azrbf.solve(alone, B)
+        Xs = res[r.rid].X
+        rs = torch.from_numpy(res[r.rid].relres)
+        # fitted values at the collocation points: A x for both coefficient vectors
+        Ya = azrbf.apply_A(alone, Xa)
+        Ys = azrbf.apply_A(alone, Xs)
+        torch.cuda.synchronize()
+        nb = torch.linalg.norm(B, dim=1)
+        diff = torch.linalg.norm(Ya - Ys, dim=1) / nb
+        ra_c = ra.cpu()
+        announce(p.name, "relres alone", ra_c.numpy(), "served", rs.numpy(), "fit diff", diff.cpu().numpy())
+        assert torch.all(rs <= 10 * ra_c + 1e-15)
+        assert torch.all(ra_c <= 10 * rs + 1e-15)
+        assert torch.all(diff.cpu() <= 10 * (ra_c + rs) + 1e-13)
+        if p.dim == 1:
+            assert torch.all(rs <= 1e-10)
+        alone.destroy()
+    srv.close()
