@@ -191,6 +191,25 @@ int azrbf_dgemm(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k,
                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                 int64_t ldc, void* stream);
 
+/* Tile shapes of the FFT passes for transforms that need the three-pass
+ * engine (1D N > 8192 and all 2D plans): times apply_A followed by
+ * apply_Zstar on nvec vectors of the plan's own operator for candidate
+ * shapes (columns per block of the column passes, rows per block of the row
+ * passes, vector pairs per launch), keeps the fastest in the plan and in a
+ * process-wide table from which later plans of the same engine shape start.
+ * Synchronises the stream.  report (len bytes, may be NULL) receives a JSON
+ * object with the choice and every trial's time ({"engine": false} when the
+ * plan uses the single-kernel path).  Errors: EINVAL (nvec <= 0, report too
+ * small), ENOMEM, EHIP. */
+int azrbf_autotune(azrbf_plan_t plan, int64_t nvec, void* stream, char* report, int64_t len);
+
+/* The process-wide tile-shape table as text, one engine shape per line:
+ * "e<dim>_<N1>x<N2>_s<s> <C> <rows> <pairs>"; and loading such text (e.g. saved
+ * from an earlier process).  Loading validates every line (EINVAL on a
+ * malformed or out-of-range entry) and affects plans created afterwards. */
+int azrbf_tune_table(char* buf, int64_t len);
+int azrbf_tune_load(const char* text);
+
 /* Per-launch timing for measurement.  While enabled, every kernel launch of
  * the library (any plan, any stream) is bracketed by HIP events on its
  * stream and tagged with the bytes it must move at minimum (its algorithmic

@@ -69,6 +69,9 @@ EXPORTS = {
     "azrbf_gaussian": (ctypes.c_int, [ctypes.c_uint64, _I64, _I64, _P, _I64, _P]),
     "azrbf_dgemm": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _I64, _I64, _I64, _D, _P, _I64, _P, _I64,
                                    _D, _P, _I64, _P]),
+    "azrbf_autotune": (ctypes.c_int, [_P, _I64, _P, ctypes.c_char_p, _I64]),
+    "azrbf_tune_table": (ctypes.c_int, [ctypes.c_char_p, _I64]),
+    "azrbf_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "azrbf_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
     "azrbf_profile_report": (ctypes.c_int, [ctypes.c_char_p, _I64]),
     "azrbf_destroy": (None, [_P]),
@@ -328,6 +331,43 @@ def dgemm(A, B, C=None, transa=False, transb=False, alpha=1.0, beta=0.0, stream=
     _check(_lib().azrbf_dgemm(int(bool(transa)), int(bool(transb)), m, n, k, float(alpha), A.data_ptr(), lda,
                               B.data_ptr(), ldb, float(beta), C.data_ptr(), ldc, _stream(stream)), "azrbf_dgemm")
     return C
+
+
+def autotune(p, nvec, stream=None):
+    """Times the engine's tile shapes on the plan's operator; returns the report dict."""
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(_lib().azrbf_autotune(p.handle, int(nvec), _stream(stream), buf, len(buf)), "azrbf_autotune")
+    return json.loads(buf.value.decode())
+
+
+def tune_table():
+    """The process-wide tile-shape table: {key: (C, rows, pairs)}."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(_lib().azrbf_tune_table(buf, len(buf)), "azrbf_tune_table")
+    out = {}
+    for line in buf.value.decode().splitlines():
+        key, c, l, ch = line.split()
+        out[key] = (int(c), int(l), int(ch))
+    return out
+
+
+def tune_load(table):
+    """Loads {key: (C, rows, pairs)} into the process-wide table."""
+    text = "".join(f"{k} {c} {l} {ch}\n" for k, (c, l, ch) in table.items())
+    _check(_lib().azrbf_tune_load(text.encode()), "azrbf_tune_load")
+
+
+def tune_save_file(path):
+    import json
+    with open(path, "w") as f:
+        json.dump({k: list(v) for k, v in tune_table().items()}, f, indent=1, sort_keys=True)
+
+
+def tune_load_file(path):
+    import json
+    with open(path) as f:
+        tune_load({k: tuple(v) for k, v in json.load(f).items()})
 
 
 def profile_enable(on=True):

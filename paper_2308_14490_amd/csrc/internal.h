@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -75,6 +76,7 @@ int pool_trim();
 
 // ops.hip
 int ops_init_twiddles(int device, const double2** tw);
+bool engine_shape_ok(int N1, int N2, int C, int Lr, int chunk);
 int ops_spectra(Plan& P, hipStream_t st);
 // Y = alpha A X + beta Yin (Yin null: Yin = Y); Z = alpha Z* R + beta Zin likewise.
 int ops_apply_A(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta,
@@ -107,6 +109,12 @@ int tsqr_panel(double* W, int64_t m, int k, double* scratch, double* Q, double* 
 int relres_chunks();
 int relres_norms(const double* R, int64_t ldr, const double* B, int64_t ldb, int64_t m, int64_t ncol,
                  double* nrm, double* out, hipStream_t st);
+
+// tune.hip: engine tile shapes (table keyed by the engine shape)
+void tune_apply(Plan& P);
+int tune_plan(Plan& P, int64_t nvec, hipStream_t st, std::string* report);
+int tune_table(std::string* out);
+int tune_load(const char* text);
 
 // wide.hip: sketch widths k > 64 (multiples of 64)
 int64_t wide_factor_doubles(int64_t N, int64_t Mt, int k);
@@ -141,6 +149,10 @@ struct Plan {
   double bweight = 1;
   double normA = 0, normZ = 0;
   int zeroed = 0;
+
+  // engine tile shapes (0: defaults): columns per block of the column
+  // passes, rows per block of the row passes, vector pairs per chunk
+  int tune_C = 0, tune_L = 0, tune_chunk = 0;
 
   // FFT-engine workspace
   double2* ws1 = nullptr;

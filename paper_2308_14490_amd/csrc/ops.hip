@@ -723,6 +723,19 @@ static int row_L(int N1, int N2) {
   return Lr > N1 ? N1 : Lr;
 }
 
+// Tile shapes of the engine passes: the plan's tuned values where valid
+// (a power of two, at most 256 threads per block, dividing the other axis),
+// else the defaults above.
+bool engine_shape_ok(int N1, int N2, int C, int Lr, int chunk) {
+  auto p2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
+  if (C && (!p2(C) || C * (N1 / RADIX) > 256 || C > N2)) return false;
+  if (Lr && (!p2(Lr) || Lr * (N2 / RADIX) > 256 || Lr > N1)) return false;
+  if (chunk && (chunk < 1 || chunk > 256)) return false;
+  return true;
+}
+static int plan_C(const Plan& P) { return P.tune_C ? P.tune_C : col_C(P.geo.N1, P.geo.N2); }
+static int plan_L(const Plan& P) { return P.tune_L ? P.tune_L : row_L(P.geo.N1, P.geo.N2); }
+
 // Column-pass launchers (template on the column length N1).
 struct ColArgs {
   const Plan* P;
@@ -744,7 +757,7 @@ template <int N1>
 static int launch_col(const ColArgs& a) {
   const Plan& P = *a.P;
   const Geo& g = P.geo;
-  const int C = col_C(g.N1, g.N2);
+  const int C = plan_C(P);
   const int block = C * Col<N1>::T;
   const int lds = C * N1 * (int)sizeof(double2);
   const dim3 grid((unsigned)(g.N2 / C), (unsigned)a.npairs);
@@ -828,7 +841,7 @@ template <int N2>
 static int launch_row(const RowArgs& a) {
   const Plan& P = *a.P;
   const Geo& g = P.geo;
-  const int Lr = row_L(g.N1, g.N2);
+  const int Lr = plan_L(P);
   const int block = Lr * Row<N2>::T;
   const int lds = Lr * RowLds::stride(N2) * (int)sizeof(double2);
   const dim3 grid((unsigned)(g.N1 / Lr), (unsigned)a.npairs);
@@ -891,6 +904,7 @@ static int64_t engine_chunk(const Plan& P, int64_t npairs) {
   int64_t c = ((int64_t)64 << 20) / per;
   if (c < 1) c = 1;
   if (c > 64) c = 64;
+  if (P.tune_chunk > 0) c = P.tune_chunk;
   return npairs < c ? npairs : c;
 }
 

@@ -371,6 +371,7 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
     if (rc) { P.release(); delete h; return rc; }
   }
   P.k = az::default_k(q, P.Lax, P.N, P.Mt);
+  az::tune_apply(P);
   rc = az::ops_spectra(P, st);
   if (rc) { P.release(); delete h; return rc; }
   *out = h;
@@ -592,6 +593,34 @@ int azrbf_dgemm(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k,
     (void)hipFree(part);
   }
   return rc;
+}
+
+int azrbf_autotune(azrbf_plan_t h, int64_t nvec, void* stream, char* report, int64_t len) {
+  if (!h || nvec <= 0) return AZRBF_EINVAL;
+  Plan& P = h->p;
+  P.last_stream = (hipStream_t)stream;
+  std::string rep;
+  const int rc = az::tune_plan(P, nvec, (hipStream_t)stream, &rep);
+  if (rc) return rc;
+  if (report && len > 0) {
+    if ((int64_t)rep.size() + 1 > len) return AZRBF_EINVAL;
+    memcpy(report, rep.c_str(), rep.size() + 1);
+  }
+  return AZRBF_OK;
+}
+
+int azrbf_tune_table(char* buf, int64_t len) {
+  if (!buf || len <= 0) return AZRBF_EINVAL;
+  std::string s;
+  az::tune_table(&s);
+  if ((int64_t)s.size() + 1 > len) return AZRBF_EINVAL;
+  memcpy(buf, s.c_str(), s.size() + 1);
+  return AZRBF_OK;
+}
+
+int azrbf_tune_load(const char* text) {
+  if (!text) return AZRBF_EINVAL;
+  return az::tune_load(text);
 }
 
 int azrbf_profile_enable(int32_t on) {

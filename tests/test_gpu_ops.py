@@ -10,6 +10,7 @@ import math
 
 import numpy as np
 import pytest
+import torch
 
 import workloads as W
 from oracle import dense, grids, periodic, philox
@@ -126,4 +127,24 @@ def test_empty_and_zero_vector_calls():
     assert Y.shape == (0, p.Mt)
     Z = azrbf.apply_Zstar(p, torch.zeros((2, p.Mt), dtype=torch.float64, device="cuda"))
     assert float(Z.abs().max()) == 0.0
+    p.destroy()
+
+
+def test_autotune_keeps_results_bitwise():
+    """Tile shapes regroup independent line transforms: A X is the same bit for bit."""
+    require_gpu()
+    from paper_2308_14490_amd import azrbf, problems
+    prob = W.family_1d(16384, 2)
+    announce("autotune", prob.n)
+    p = problems.plan_for(prob)
+    X = azrbf.gaussian(3, p.N, 24)
+    Y0 = azrbf.apply_A(p, X)
+    Z0 = azrbf.apply_Zstar(p, Y0)
+    rep = azrbf.autotune(p, 24)
+    assert rep["engine"] and rep["ms"] > 0 and len(rep["trials"]) >= 4
+    Y1 = azrbf.apply_A(p, X)
+    Z1 = azrbf.apply_Zstar(p, Y1)
+    torch.cuda.synchronize()
+    assert torch.equal(Y0, Y1) and torch.equal(Z0, Z1)
+    assert rep["key"] in azrbf.tune_table()
     p.destroy()

@@ -68,3 +68,18 @@ def test_plan_rejects_bad_arguments_before_touching_the_gpu():
         pr.mask = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         setattr(pr, field, val)
         assert lib.azrbf_plan(ctypes.byref(pr), None, ctypes.byref(h)) == code
+
+
+def test_tune_table_round_trip_and_validation():
+    """The tile-shape table is host state: loading validates every line."""
+    from paper_2308_14490_amd import azrbf
+    azrbf.tune_load({"e1_256x256_s2": (8, 4, 16)})
+    assert azrbf.tune_table()["e1_256x256_s2"] == (8, 4, 16)
+    lib = azrbf._lib()
+    assert lib.azrbf_tune_load(b"e1_256x256_s2 3 4 16\n") == azrbf.EINVAL      # C not a power of two
+    assert lib.azrbf_tune_load(b"e1_256x256_s2 32 4 16\n") == azrbf.EINVAL     # 32 x 16 threads > 256
+    assert lib.azrbf_tune_load(b"e1_1024x64_s2 2 2 16\n") == azrbf.EINVAL      # N1 out of range
+    assert lib.azrbf_tune_load(b"garbage\n") == azrbf.EINVAL
+    assert lib.azrbf_tune_load(b"e2_128x128_s2 16 16 8\ne2_64x64_s2 4 8 2\n") == 0
+    t = azrbf.tune_table()
+    assert t["e2_128x128_s2"] == (16, 16, 8) and t["e2_64x64_s2"] == (4, 8, 2)
