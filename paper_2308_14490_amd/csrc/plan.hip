@@ -173,11 +173,12 @@ static int k_cap(int64_t N, int64_t Mt) {
 
 // Sketch width when the caller leaves it open.  1D: the rank of A - A Z* A
 // stays near 20 whatever N (Theorem 4.6), so 32.  2D: the rank grows with the
-// boundary (section 5.3.2); measured on disks and stars it is about 4 per
-// fine-grid boundary point at s = 2 (8 / s), plus one per boundary row; the
-// estimate takes 9 / s per boundary point and 10 more columns, rounded up to
-// a multiple of 64.  A sketch that turns out too narrow is widened by
-// the factorisation (grow_k).
+// boundary (section 5.3.2).  Measured on disks at s = 2, the retained rank per
+// fine-grid boundary point of the mask is 3.2, 5.0, 5.9, 6.4 at n = 16, 32,
+// 64, 128 (it grows like the logarithm of n, the width of the plunge region
+// in centres); the estimate takes (2.52 + 0.63 log2 n) 2/s per boundary point,
+// plus one per boundary row and 10 more, rounded up to a multiple of 64.  A
+// sketch that turns out too narrow is widened by the factorisation.
 static int default_k(const azrbf_problem& q, int64_t Lax, int64_t N, int64_t Mt) {
   if (q.k > 0) return q.k;
   if (q.dim == 1) return 32;
@@ -190,7 +191,8 @@ static int default_k(const azrbf_problem& q, int64_t Lax, int64_t N, int64_t Mt)
                         !q.mask[ix * Lax + iy - 1] || !q.mask[ix * Lax + iy + 1];
       perim += edge;
     }
-  const int64_t est = 9 * perim / q.s + q.nb + 10;
+  const double per = (2.52 + 0.63 * std::log2((double)q.n)) * 2.0 / q.s;
+  const int64_t est = (int64_t)std::ceil(per * (double)perim) + q.nb + 10;
   const int cap = k_cap(N, Mt);
   if (cap <= 64) return cap;
   const int64_t k = (est + 63) / 64 * 64;
