@@ -533,7 +533,7 @@ int relres_norms(const double* R, int64_t ldr, const double* B, int64_t ldb, int
 
 // ------------------------------------------------------------------ factor
 
-int dense_factor(Plan& P, hipStream_t st) {
+int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch) {
   const int k = P.k;
   // the Jacobi kernel pairs k/2 columns over 256 threads: 512 / k must be a shuffle width
   if (k != 16 && k != 32 && k != 64) return AZRBF_EUNSUPPORTED;
@@ -559,6 +559,8 @@ int dense_factor(Plan& P, hipStream_t st) {
   AZ_TRY(ops_apply_A(P, P.Om, N, k, 1.0, 0.0, nullptr, 0, P.Yf, Mt, st));     // Y = A Omega
   AZ_TRY(ops_apply_Z(P, P.Yf, Mt, k, 1.0, 0.0, nullptr, 0, Zy, N, st));       // Z* Y
   AZ_TRY(ops_apply_A(P, Zy, N, k, -1.0, 1.0, P.Yf, Mt, W, Mt, st));          // W = Y - A Z* Y
+  // what follows is latency-bound: work on other streams may start here
+  if (after_sketch) AZ_HIP(hipEventRecord(after_sketch, st));
   // TSQR destroys W; the QR is of the sketch, W is then free scratch
   AZ_TRY(tsqr(W, Mt, k, tq, P.Q, P.Rf, st));
   const double thr = P.tau * P.normA * sqrt((double)k);
@@ -572,19 +574,30 @@ int dense_factor(Plan& P, hipStream_t st) {
   AZ_TRY(gemm_nn(P.Yf, Mt, Mt, k, P.Pm, k, k, 1.0, nullptr, 0, 0.0, W, Mt, st));
   std::swap(P.Om, P.Om2);
   std::swap(P.Yf, P.Yf2);
-  int hinfo[2];
-  AZ_HIP(hipMemcpyAsync(hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, st));
+  P.dinfo = info;
+  return AZRBF_OK;
+}
+
+// Waits for the factor queued by dense_factor_enqueue and reads its rank (the
+// copy is queued here: a copy to pageable memory can block the host).
+int dense_factor_finish(Plan& P, hipStream_t st) {
+  AZ_HIP(hipMemcpyAsync(P.hinfo, P.dinfo, sizeof(P.hinfo), hipMemcpyDeviceToHost, st));
   AZ_HIP(hipStreamSynchronize(st));
-  P.rank = hinfo[0];
-  P.sweeps = hinfo[1];
+  P.rank = P.hinfo[0];
+  P.sweeps = P.hinfo[1];
   P.factored = true;
-  return P.rank >= k ? AZRBF_ERANK : AZRBF_OK;
+  return P.rank >= P.k ? AZRBF_ERANK : AZRBF_OK;
+}
+
+int dense_factor(Plan& P, hipStream_t st) {
+  AZ_TRY(dense_factor_enqueue(P, st, nullptr));
+  return dense_factor_finish(P, st);
 }
 
 // ------------------------------------------------------------------ solve
 
-int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx, double* relres,
-                hipStream_t st) {
+// Solve workspace for nrhs right-hand sides (k <= 64 layout).
+int dense_solve_ws(Plan& P, int64_t nrhs) {
   const int k = P.k;
   const int64_t N = P.N, Mt = P.Mt;
   const int64_t nparts = tn_blocks(Mt) * ((nrhs + TN_COLS - 1) / TN_COLS) * TN_COLS;
@@ -593,6 +606,26 @@ int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, 
     AZ_TRY(P.alloc((void**)&P.sw, sizeof(double) * (per * nrhs + nparts * k)));
     P.sw_rhs = nrhs;
   }
+  return AZRBF_OK;
+}
+
+// First stage of the first pass, independent of the factor:
+// Zr = Z* b, c = (I - A Z*) b, into the solve workspace.
+int dense_first_stage(Plan& P, const double* B, int64_t ldb, int64_t nrhs, hipStream_t st) {
+  AZ_TRY(dense_solve_ws(P, nrhs));
+  const int64_t N = P.N, Mt = P.Mt;
+  double* Zr = P.sw;
+  double* C = Zr + N * nrhs;
+  AZ_TRY(ops_apply_Z(P, B, ldb, nrhs, 1.0, 0.0, nullptr, 0, Zr, N, st));
+  AZ_TRY(ops_apply_A(P, Zr, N, nrhs, -1.0, 1.0, B, ldb, C, Mt, st));
+  return AZRBF_OK;
+}
+
+int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx, double* relres,
+                hipStream_t st, bool first_done) {
+  const int k = P.k;
+  const int64_t N = P.N, Mt = P.Mt;
+  AZ_TRY(dense_solve_ws(P, nrhs));
   double* Zr = P.sw;                   // N x nrhs
   double* C = Zr + N * nrhs;           // Mt x nrhs
   double* R1 = C + Mt * nrhs;          // Mt x nrhs
@@ -603,8 +636,10 @@ int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, 
   const double* rin = B;
   int64_t ldr = ldb;
   for (int it = 0; it <= P.refine; ++it) {
-    AZ_TRY(ops_apply_Z(P, rin, ldr, nrhs, 1.0, 0.0, nullptr, 0, Zr, N, st));        // Z* r
-    AZ_TRY(ops_apply_A(P, Zr, N, nrhs, -1.0, 1.0, rin, ldr, C, Mt, st));           // c = (I - A Z*) r
+    if (!(it == 0 && first_done)) {
+      AZ_TRY(ops_apply_Z(P, rin, ldr, nrhs, 1.0, 0.0, nullptr, 0, Zr, N, st));      // Z* r
+      AZ_TRY(ops_apply_A(P, Zr, N, nrhs, -1.0, 1.0, rin, ldr, C, Mt, st));         // c = (I - A Z*) r
+    }
     AZ_TRY(gemm_tn(P.Q, Mt, Mt, k, C, Mt, nrhs, part, Tm, st));                     // t = Q^T c
     AZ_TRY(gemm_nn(P.Om, N, N, k, Tm, k, nrhs, 1.0, X, ldx, it == 0 ? 0.0 : 1.0, X, ldx, st));  // x += x1
     AZ_TRY(gemm_nn(P.Yf, Mt, Mt, k, Tm, k, nrhs, -1.0, rin, ldr, 1.0, R1, Mt, st));            // r - A x1

@@ -122,8 +122,15 @@ int wide_factor(Plan& P, hipStream_t st);
 int wide_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx, double* relres,
                hipStream_t st);
 int dense_factor(Plan& P, hipStream_t st);
+// the factor split in two: queue it (after_sketch, if set, is recorded once
+// the sketch W is queued) and wait for it / read the rank
+int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch);
+int dense_factor_finish(Plan& P, hipStream_t st);
+int dense_solve_ws(Plan& P, int64_t nrhs);
+int dense_first_stage(Plan& P, const double* B, int64_t ldb, int64_t nrhs, hipStream_t st);
+// first_done: the first pass's Z* b and c = (I - A Z*) b are already in the workspace
 int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
-                double* relres, hipStream_t st);
+                double* relres, hipStream_t st, bool first_done = false);
 
 struct Plan {
   azrbf_problem prob{};
@@ -154,16 +161,26 @@ struct Plan {
   // passes, rows per block of the row passes, vector pairs per chunk
   int tune_C = 0, tune_L = 0, tune_chunk = 0;
 
-  // FFT-engine workspace
+  // FFT-engine workspace, and a second set for work queued on a side stream
   double2* ws1 = nullptr;
   double2* ws2 = nullptr;
   int64_t ws_pairs = 0;
+  double2* wsB1 = nullptr;
+  double2* wsB2 = nullptr;
+  int64_t wsB_pairs = 0;
+  void swap_ws() {
+    std::swap(ws1, wsB1);
+    std::swap(ws2, wsB2);
+    std::swap(ws_pairs, wsB_pairs);
+  }
 
   // factor
   int k = 0, rank = -1, refine = 0;
   double tau = 1e-12, tauZ = 1e-12;
   bool factored = false;
   int sweeps = 0;            // Jacobi sweeps of the last factor
+  int hinfo[2] = {0, 0};     // rank and sweeps, copied back by the factor
+  int* dinfo = nullptr;      // their device copy
   double* Om = nullptr;     // N x k, then Omega * P
   double* Om2 = nullptr;    // N x k scratch
   double* Yf = nullptr;     // Mt x k, A Omega, then (A Omega) * P

@@ -255,6 +255,27 @@ int many_pool(int dev, ManyPool** out) {
   return AZRBF_OK;
 }
 
+// Side streams for work that overlaps a factorisation (default priority,
+// non-blocking), a few per device, handed out in turn.
+constexpr int kSideStreams = 4;
+std::mutex g_side_mu;
+std::map<int, std::vector<hipStream_t>> g_side;
+int g_side_next = 0;
+
+int side_stream(int dev, hipStream_t* out) {
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  std::vector<hipStream_t>& v = g_side[dev];
+  if (v.empty()) {
+    for (int i = 0; i < kSideStreams; ++i) {
+      hipStream_t s = nullptr;
+      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return AZRBF_EHIP;
+      v.push_back(s);
+    }
+  }
+  *out = v[(g_side_next++) % kSideStreams];
+  return AZRBF_OK;
+}
+
 }  // namespace az
 
 using az::Plan;
@@ -432,12 +453,51 @@ int azrbf_solve(azrbf_plan_t h, const double* B, int64_t ldb, int64_t nrhs, doub
   if (nrhs == 0) return AZRBF_OK;
   if (!B || !X || ldb < P.Mt || ldx < P.N) return AZRBF_EINVAL;
   P.last_stream = (hipStream_t)stream;
+  hipStream_t st = (hipStream_t)stream;
+  if (!P.factored && P.k <= 64 && P.prob.k > 0) {
+    // The first pass's c = (I - A Z*) b does not need the factor: it runs on a
+    // side stream (with its own FFT workspace) while the latency-bound
+    // factorisation runs on the caller's stream.  (With a fixed sketch width
+    // the factor cannot be widened, so the workspace stays valid.)
+    hipStream_t side = nullptr;
+    AZ_TRY(az::side_stream(P.device, &side));
+    hipEvent_t e_in = nullptr, e_side = nullptr;
+    if (hipEventCreateWithFlags(&e_in, hipEventDisableTiming) != hipSuccess) return AZRBF_EHIP;
+    if (hipEventCreateWithFlags(&e_side, hipEventDisableTiming) != hipSuccess) {
+      (void)hipEventDestroy(e_in);
+      return AZRBF_EHIP;
+    }
+    // the side work starts once the factor's sketch (bandwidth-bound FFTs) is
+    // done, so that it runs beside the latency-bound TSQR and Jacobi kernels
+    int rc = az::dense_factor_enqueue(P, st, e_in);
+    if (rc) {
+      (void)hipStreamSynchronize(st);
+      (void)hipEventDestroy(e_in);
+      (void)hipEventDestroy(e_side);
+      return rc;
+    }
+    if (hipStreamWaitEvent(side, e_in, 0) != hipSuccess) rc = AZRBF_EHIP;
+    if (!rc) {
+      P.swap_ws();
+      rc = az::dense_first_stage(P, B, ldb, nrhs, side);
+      P.swap_ws();
+    }
+    if (!rc && hipEventRecord(e_side, side) != hipSuccess) rc = AZRBF_EHIP;
+    const int frc = az::dense_factor_finish(P, st);
+    if (!rc && frc != AZRBF_OK && frc != AZRBF_ERANK) rc = frc;
+    if (!rc && hipStreamWaitEvent(st, e_side, 0) != hipSuccess) rc = AZRBF_EHIP;
+    if (rc) (void)hipStreamSynchronize(side);
+    (void)hipEventDestroy(e_in);
+    (void)hipEventDestroy(e_side);
+    if (rc) return rc;
+    return az::dense_solve(P, B, ldb, nrhs, X, ldx, relres, st, true);
+  }
   if (!P.factored) {
-    const int rc = az::factor_plan(P, (hipStream_t)stream);
+    const int rc = az::factor_plan(P, st);
     if (rc != AZRBF_OK && rc != AZRBF_ERANK) return rc;
   }
-  if (P.k > 64) return az::wide_solve(P, B, ldb, nrhs, X, ldx, relres, (hipStream_t)stream);
-  return az::dense_solve(P, B, ldb, nrhs, X, ldx, relres, (hipStream_t)stream);
+  if (P.k > 64) return az::wide_solve(P, B, ldb, nrhs, X, ldx, relres, st);
+  return az::dense_solve(P, B, ldb, nrhs, X, ldx, relres, st);
 }
 
 int azrbf_solve_many(int32_t nprob, const azrbf_plan_t* plans, const double* const* B, const int64_t* ldb,
