@@ -23,8 +23,9 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int GT = 64;   // output tile edge
-constexpr int GK = 16;   // reduction chunk staged in LDS
+constexpr int GK = 32;   // reduction chunk staged in LDS
 constexpr int GP = GT + 2;
+constexpr int GL = GK * GT / 256;   // elements of each operand a thread stages per chunk
 
 template <bool TA>
 __device__ __forceinline__ double load_opA(const double* A, int64_t lda, int64_t i, int64_t kk) {
@@ -36,14 +37,29 @@ __device__ __forceinline__ double load_opB(const double* B, int64_t ldb, int64_t
   return TB ? B[j + ldb * kk] : B[kk + ldb * j];
 }
 
+// Staging coordinates of element q of a thread: contiguous global runs along
+// i for A and along kk for A^T (likewise B).
+template <bool T>
+__device__ __forceinline__ void stage_ik(int t, int q, int* i, int* kk) {
+  if (T) {
+    *kk = t & (GK - 1);
+    *i = (t / GK) + (256 / GK) * q;
+  } else {
+    *i = t & (GT - 1);
+    *kk = (t / GT) + (256 / GT) * q;
+  }
+}
+
 // Batch entry z / splits, reduction range [sp * kchunk, (sp + 1) * kchunk) of
 // split sp = z % splits.  With splits > 1 the raw tile sums are stored at
-// C + z * sC (ld ldc) and alpha, beta are applied by k_sum_splits.
+// C + z * sC (ld ldc) and alpha, beta are applied by k_sum_splits.  The next
+// chunk's operands are loaded into registers while the current one is
+// multiplied from LDS.
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256)
 k_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A, int64_t lda, int64_t sA,
-       const double* __restrict__ B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc, int64_t sC,
-       int splits, int64_t kchunk) {
+       const double* __restrict__ B, int64_t ldb, int64_t sB, double beta, const double* Cin, int64_t ldci,
+       int64_t sCi, double* C, int64_t ldc, int64_t sC, int splits, int64_t kchunk) {
   __shared__ double As[GK][GP];   // As[kk][i] = op(A)(i0 + i, kb + kk)
   __shared__ double Bs[GK][GP];   // Bs[kk][j] = op(B)(kb + kk, j0 + j)
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
@@ -51,6 +67,7 @@ k_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__
   A += (int64_t)bz * sA;
   B += (int64_t)bz * sB;
   C += (int64_t)(splits > 1 ? z : bz) * sC;
+  if (Cin) Cin += (int64_t)bz * sCi;
   const int64_t i0 = (int64_t)blockIdx.x * GT, j0 = (int64_t)blockIdx.y * GT;
   const int64_t k0 = (int64_t)sp * kchunk, k1 = std::min(K, k0 + kchunk);
   const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
@@ -59,20 +76,30 @@ k_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = dbl4{0.0, 0.0, 0.0, 0.0};
+  double ra[GL], rb[GL];
+  auto fetch = [&](int64_t kb) {
+#pragma unroll
+    for (int q = 0; q < GL; ++q) {
+      int ai, ak, bj, bk;
+      stage_ik<TA>(t, q, &ai, &ak);
+      stage_ik<!TB>(t, q, &bj, &bk);   // B is indexed (kk, j): its "row" runs along j
+      const int64_t gi = i0 + ai, gka = kb + ak, gj = j0 + bj, gkb = kb + bk;
+      ra[q] = (gi < M && gka < k1) ? load_opA<TA>(A, lda, gi, gka) : 0.0;
+      rb[q] = (gj < N && gkb < k1) ? load_opB<TB>(B, ldb, gkb, gj) : 0.0;
+    }
+  };
+  if (k0 < k1) fetch(k0);
   for (int64_t kb = k0; kb < k1; kb += GK) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      // contiguous global runs: along i for A, along kk for A^T (likewise B)
-      const int ai = TA ? (t >> 4) + 16 * q : (t & 63);
-      const int ak = TA ? (t & 15) : (t >> 6) + 4 * q;
-      const int64_t gi = i0 + ai, gka = kb + ak;
-      As[ak][ai] = (gi < M && gka < k1) ? load_opA<TA>(A, lda, gi, gka) : 0.0;
-      const int bj = TB ? (t & 63) : (t >> 4) + 16 * q;
-      const int bk = TB ? (t >> 6) + 4 * q : (t & 15);
-      const int64_t gj = j0 + bj, gkb = kb + bk;
-      Bs[bk][bj] = (gj < N && gkb < k1) ? load_opB<TB>(B, ldb, gkb, gj) : 0.0;
+    for (int q = 0; q < GL; ++q) {
+      int ai, ak, bj, bk;
+      stage_ik<TA>(t, q, &ai, &ak);
+      stage_ik<!TB>(t, q, &bj, &bk);
+      As[ak][ai] = ra[q];
+      Bs[bk][bj] = rb[q];
     }
     __syncthreads();
+    if (kb + GK < k1) fetch(kb + GK);
 #pragma unroll
     for (int ks = 0; ks < GK / 4; ++ks) {
       const int kk = 4 * ks + (l >> 4);
@@ -105,7 +132,7 @@ k_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__
         double* p = C + i + ldc * j;
         const double s = acc[mi][ni][v];
         if (splits > 1) *p = s;
-        else *p = beta == 0.0 ? alpha * s : fma(alpha, s, beta * *p);
+        else *p = beta == 0.0 ? alpha * s : fma(alpha, s, beta * Cin[i + ldci * j]);
       }
     }
   }
@@ -113,7 +140,8 @@ k_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__
 
 // C = alpha sum_s P_s + beta C for each batch entry; P_s at P + (b*splits+s)*sP.
 __global__ void k_sum_splits(int64_t M, int64_t N, int splits, const double* __restrict__ P, int64_t ldp,
-                             int64_t sP, double alpha, double beta, double* C, int64_t ldc, int64_t sC) {
+                             int64_t sP, double alpha, double beta, const double* Cin, int64_t ldci, int64_t sCi,
+                             double* C, int64_t ldc, int64_t sC) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= M * N) return;
   const int64_t b = blockIdx.y, i = e % M, j = e / M;
@@ -127,38 +155,48 @@ __global__ void k_sum_splits(int64_t M, int64_t N, int splits, const double* __r
   if (s < splits) s0 += p[(int64_t)s * sP];
   double* c = C + (int64_t)b * sC + i + ldc * j;
   const double v = s0 + s1;
-  *c = beta == 0.0 ? alpha * v : fma(alpha, v, beta * *c);
+  *c = beta == 0.0 ? alpha * v : fma(alpha, v, beta * Cin[(int64_t)b * sCi + i + ldci * j]);
 }
 
 template <bool TA, bool TB>
 void launch_gemm(dim3 grid, hipStream_t st, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
-                 int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C,
-                 int64_t ldc, int64_t sC, int splits, int64_t kchunk) {
-  k_gemm<TA, TB><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, splits, kchunk);
+                 int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, const double* Cin,
+                 int64_t ldci, int64_t sCi, double* C, int64_t ldc, int64_t sC, int splits, int64_t kchunk) {
+  k_gemm<TA, TB><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cin, ldci, sCi, C, ldc, sC,
+                                       splits, kchunk);
 }
 
 }  // namespace
 
-int64_t gemm_split_doubles(int64_t M, int64_t N, int64_t K, int64_t batch) {
+// Splits of the reduction when the output has few tiles: about 1024 blocks
+// in all, each reducing at least 256 rows, at most 512 splits.
+static int64_t gemm_splits(int64_t M, int64_t N, int64_t K, int64_t batch) {
   const int64_t tiles = ((M + GT - 1) / GT) * ((N + GT - 1) / GT) * batch;
-  if (tiles >= 256 || K < 2048) return 0;
-  const int64_t splits = std::min<int64_t>({64, (512 + tiles - 1) / tiles, K / 1024});
-  return splits > 1 ? splits * batch * M * N : 0;
+  if (tiles >= 256 || K < 1024) return 1;
+  const int64_t sp = std::min<int64_t>({512, (1024 + tiles - 1) / tiles, K / 256});
+  return sp > 1 ? sp : 1;
 }
 
-int gemm_mfma(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
-              int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc,
-              int64_t sC, int64_t batch, double* part, int64_t part_doubles, hipStream_t st) {
+int64_t gemm_split_doubles(int64_t M, int64_t N, int64_t K, int64_t batch) {
+  const int64_t sp = gemm_splits(M, N, K, batch);
+  return sp > 1 ? sp * batch * M * N : 0;
+}
+
+int gemm_mfma_c(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, const double* Cin, int64_t ldci,
+                int64_t sCi, double* C, int64_t ldc, int64_t sC, int64_t batch, double* part, int64_t part_doubles,
+                hipStream_t st) {
   if (M <= 0 || N <= 0 || batch <= 0) return AZRBF_OK;
   if (batch > 65535) return AZRBF_EINVAL;
+  if (beta != 0.0 && !Cin) return AZRBF_EINVAL;
   const int64_t tx = (M + GT - 1) / GT, ty = (N + GT - 1) / GT;
   if (tx > 0x7fffffff || ty > 65535) return AZRBF_EINVAL;
   int splits = 1;
   const int64_t need = gemm_split_doubles(M, N, K, batch);
-  if (need > 0 && part && need <= part_doubles) splits = (int)(need / (batch * M * N));
+  if (need > 0 && part && need <= part_doubles) splits = (int)gemm_splits(M, N, K, batch);
   int64_t kchunk = K;
   if (splits > 1) {
-    kchunk = ((K + splits - 1) / splits + GK - 1) / GK * GK;
+    kchunk = ((K + splits - 1) / splits + GK - 1) / GK * GK;   // whole chunks per split
     splits = (int)((K + kchunk - 1) / kchunk);
   }
   if ((int64_t)splits * batch > 65535) return AZRBF_EINVAL;
@@ -167,18 +205,33 @@ int gemm_mfma(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, c
   const dim3 grid((unsigned)tx, (unsigned)ty, (unsigned)(splits * batch));
   double* Cout = splits > 1 ? part : C;
   const int64_t ldo = splits > 1 ? M : ldc, so = splits > 1 ? M * N : sC;
-  if (!ta && !tb) launch_gemm<false, false>(grid, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cout, ldo, so, splits, kchunk);
-  else if (ta && !tb) launch_gemm<true, false>(grid, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cout, ldo, so, splits, kchunk);
-  else if (!ta && tb) launch_gemm<false, true>(grid, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cout, ldo, so, splits, kchunk);
-  else launch_gemm<true, true>(grid, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cout, ldo, so, splits, kchunk);
+  if (!ta && !tb)
+    launch_gemm<false, false>(grid, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cin, ldci, sCi, Cout, ldo, so,
+                              splits, kchunk);
+  else if (ta && !tb)
+    launch_gemm<true, false>(grid, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cin, ldci, sCi, Cout, ldo, so,
+                             splits, kchunk);
+  else if (!ta && tb)
+    launch_gemm<false, true>(grid, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cin, ldci, sCi, Cout, ldo, so,
+                             splits, kchunk);
+  else
+    launch_gemm<true, true>(grid, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cin, ldci, sCi, Cout, ldo, so,
+                            splits, kchunk);
   AZ_HIP(hipGetLastError());
   if (splits > 1) {
     const int64_t e = M * N;
-    k_sum_splits<<<dim3((unsigned)((e + 255) / 256), (unsigned)batch), 256, 0, st>>>(M, N, splits, part, M, M * N,
-                                                                                  alpha, beta, C, ldc, sC);
+    k_sum_splits<<<dim3((unsigned)((e + 255) / 256), (unsigned)batch), 256, 0, st>>>(
+        M, N, splits, part, M, M * N, alpha, beta, Cin, ldci, sCi, C, ldc, sC);
     AZ_HIP(hipGetLastError());
   }
   return AZRBF_OK;
+}
+
+int gemm_mfma(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+              int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc,
+              int64_t sC, int64_t batch, double* part, int64_t part_doubles, hipStream_t st) {
+  return gemm_mfma_c(ta, tb, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, C, ldc, sC, batch, part,
+                     part_doubles, st);
 }
 
 }  // namespace az

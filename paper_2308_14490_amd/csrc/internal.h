@@ -99,6 +99,11 @@ int64_t gemm_split_doubles(int64_t M, int64_t N, int64_t K, int64_t batch);
 int gemm_mfma(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
               int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, double* C, int64_t ldc,
               int64_t sC, int64_t batch, double* part, int64_t part_doubles, hipStream_t st);
+// the same with a separate input Cin (C = alpha op(A) op(B) + beta Cin; Cin may be C)
+int gemm_mfma_c(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, const double* Cin, int64_t ldci,
+                int64_t sCi, double* C, int64_t ldc, int64_t sC, int64_t batch, double* part, int64_t part_doubles,
+                hipStream_t st);
 
 // dense.hip
 int dense_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* dst, int64_t ld, hipStream_t st);

@@ -142,7 +142,9 @@ k_jac_gram(int64_t k, const double* __restrict__ G, int round, int nbj, int rspl
 // columns p, q <- c col_p - s col_q, s col_p + c col_q (rows likewise).
 // Out: the accumulated rotation V_p (64 x 64) and the number of rotations of
 // the first sweep (the outer convergence test).
-__global__ void __launch_bounds__(256)
+constexpr int EIG_THREADS = 1024;   // a round's 1024 2 x 2 blocks and 2048 V updates spread wide
+
+__global__ void __launch_bounds__(EIG_THREADS)
 k_jac_eig(const double* __restrict__ Hp, int rsplit, double tol, double* __restrict__ Vout,
           int* __restrict__ count) {
   extern __shared__ double sme[];
@@ -155,7 +157,7 @@ k_jac_eig(const double* __restrict__ Hp, int rsplit, double tol, double* __restr
   const int t = threadIdx.x;
   const int p = blockIdx.x;
   const double* src = Hp + (int64_t)p * rsplit * (JP * JP);
-  for (int e = t; e < JP * JP; e += 256) {
+  for (int e = t; e < JP * JP; e += EIG_THREADS) {
     const int i = e % JP, j = e / JP;
     const int a = i < j ? i : j, b = i < j ? j : i;   // upper triangle
     double s = 0.0;
@@ -187,7 +189,7 @@ k_jac_eig(const double* __restrict__ Hp, int rsplit, double tol, double* __restr
       }
       __syncthreads();
       // H <- J^T H J by 2 x 2 blocks (row pair u, column pair v)
-      for (int e = t; e < (JP / 2) * (JP / 2); e += 256) {
+      for (int e = t; e < (JP / 2) * (JP / 2); e += EIG_THREADS) {
         const int v = e & (JP / 2 - 1), u = e / (JP / 2);
         const int pu = pq[u][0], qu = pq[u][1], pv = pq[v][0], qv = pq[v][1];
         const double cu = cs[u][0], su = cs[u][1], cv = cs[v][0], sv = cs[v][1];
@@ -200,7 +202,7 @@ k_jac_eig(const double* __restrict__ Hp, int rsplit, double tol, double* __restr
         H[qu][qv] = su * a12 + cu * a22;
       }
       // V <- V J
-      for (int e = t; e < JP * (JP / 2); e += 256) {
+      for (int e = t; e < JP * (JP / 2); e += EIG_THREADS) {
         const int i = e % JP, v = e / JP;
         const int pv = pq[v][0], qv = pq[v][1];
         const double cv = cs[v][0], sv = cs[v][1];
@@ -221,60 +223,69 @@ k_jac_eig(const double* __restrict__ Hp, int rsplit, double tol, double* __restr
     __syncthreads();
   }
   double* out = Vout + (int64_t)p * (JP * JP);
-  for (int e = t; e < JP * JP; e += 256) out[e] = V[e % JP][e / JP];
+  for (int e = t; e < JP * JP; e += EIG_THREADS) out[e] = V[e % JP][e / JP];
   if (t == 0) count[p] = first;
 }
 
 // X_p <- X_p V_p on 64-row tiles, in place, for G (blockIdx.z = 0) and the
-// accumulated V (blockIdx.z = 1).  The tile is read whole before it is
-// written, and no other block touches it.
+// accumulated V (blockIdx.z = 1); a block takes ROT_TILES consecutive tiles
+// and loads V_p once.  A tile is read whole before it is written, and no
+// other block touches it.
+constexpr int ROT_TILES = 4;
+
 __global__ void __launch_bounds__(256)
 k_jac_rot(int64_t k, double* G, double* Vm, int round, int nbj, const double* __restrict__ Vp) {
   extern __shared__ double smj[];
-  double (*Xs)[JP + 2] = reinterpret_cast<double (*)[JP + 2]>(smj);             // Xs[c][rr]
-  double (*Rs)[JP + 2] = reinterpret_cast<double (*)[JP + 2]>(smj + JP * (JP + 2));   // Rs[c][j]
+  double (*Xs)[JP + 2] = reinterpret_cast<double (*)[JP + 2]>(smj);                     // Xs[c][rr]
+  double (*Rs)[JP + 2] = reinterpret_cast<double (*)[JP + 2]>(smj + JP * (JP + 2));      // Rs[c][j]
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int p = blockIdx.y;
   double* X = blockIdx.z == 0 ? G : Vm;
   int I, J;
   tour_pair(round, p, nbj, &I, &J);
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
   const double* vp = Vp + (int64_t)p * (JP * JP);
-  for (int e = t; e < JP * JP; e += 256) {
-    const int rr = e & 63, c = e >> 6;
-    Xs[c][rr] = X[r0 + rr + k * pair_col(c, I, J)];
-    Rs[rr][c] = vp[rr + JP * c];   // Rs[c'][j] = V_p(c', j) with c' = rr, j = c
-  }
-  __syncthreads();
+  for (int e = t; e < JP * JP; e += 256) Rs[e & 63][e >> 6] = vp[e];   // Rs[c'][j] = V_p(c', j)
   const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
-  dbl4 acc[2][2];
+  const int64_t ntiles = k / 64;
+  for (int tt = 0; tt < ROT_TILES; ++tt) {
+    const int64_t tile = (int64_t)blockIdx.x * ROT_TILES + tt;
+    if (tile >= ntiles) break;
+    const int64_t r0 = tile * 64;
+    for (int e = t; e < JP * JP; e += 256) {
+      const int rr = e & 63, c = e >> 6;
+      Xs[c][rr] = X[r0 + rr + k * pair_col(c, I, J)];
+    }
+    __syncthreads();
+    dbl4 acc[2][2];
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+    for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = dbl4{0.0, 0.0, 0.0, 0.0};
+      for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-  for (int ks = 0; ks < JP / 4; ++ks) {
-    const int kk = 4 * ks + (l >> 4);
-    double av[2], bv[2];
+    for (int ks = 0; ks < JP / 4; ++ks) {
+      const int kk = 4 * ks + (l >> 4);
+      double av[2], bv[2];
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi) av[mi] = Xs[kk][wi + 16 * mi + (l & 15)];
+      for (int mi = 0; mi < 2; ++mi) av[mi] = Xs[kk][wi + 16 * mi + (l & 15)];
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) bv[ni] = Rs[kk][wj + 16 * ni + (l & 15)];
+      for (int ni = 0; ni < 2; ++ni) bv[ni] = Rs[kk][wj + 16 * ni + (l & 15)];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[ni], av[mi], acc[mi][ni], 0, 0, 0);
+    }
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni)
-        acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[ni], av[mi], acc[mi][ni], 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rr = wi + 16 * mi + (l & 15), j = wj + 16 * ni + (l >> 4) + 4 * v;
+          X[r0 + rr + k * pair_col(j, I, J)] = acc[mi][ni][v];
+        }
+    __syncthreads();   // Xs is refilled for the next tile
   }
-#pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int rr = wi + 16 * mi + (l & 15), j = wj + 16 * ni + (l >> 4) + 4 * v;
-        X[r0 + rr + k * pair_col(j, I, J)] = acc[mi][ni][v];
-      }
 }
 
 // sigma_j = ||G(:, j)||
@@ -325,6 +336,14 @@ __global__ void k_scale_cols(int64_t k, const double* __restrict__ G, const doub
 
 int grid1(int64_t n) { return (int)((n + 255) / 256); }
 
+// Split-reduction buffer for the panel projections Q(:, 0:done)^T X over
+// every done = 64, 128, ..., k - 64.
+int64_t panel_part(int k, int64_t Mt) {
+  int64_t most = 1;
+  for (int64_t done = PB; done < k; done += PB) most = std::max(most, gemm_split_doubles(done, PB, Mt, 1));
+  return most;
+}
+
 struct WideScratch {
   int64_t tsqr, qpan, rpan, rpan2, part, hp, vp, cnt;   // offsets in doubles
   int64_t total;
@@ -345,7 +364,7 @@ WideScratch wide_layout(int64_t Mt, int k) {
   s.rpan2 = off;
   off += PB * PB;
   s.part = off;
-  off += std::max<int64_t>(gemm_split_doubles(k, PB, Mt, 1), 1);
+  off += panel_part(k, Mt);
   s.rsplit = (int)std::max<int64_t>(1, std::min<int64_t>((512 + npairs - 1) / npairs, k / 64));
   s.rch = ((k + s.rsplit - 1) / s.rsplit + 15) / 16 * 16;
   s.rsplit = (int)((k + s.rch - 1) / s.rch);
@@ -400,7 +419,7 @@ int wide_factor(Plan& P, hipStream_t st) {
     double* rpan = scr + Lx.rpan;
     double* r3 = scr + Lx.rpan2;
     double* part = scr + Lx.part;
-    const int64_t npart = std::max<int64_t>(gemm_split_doubles(k, PB, Mt, 1), 1);
+    const int64_t npart = panel_part(k, Mt);
     AZ_HIP(hipMemsetAsync(P.Rf, 0, sizeof(double) * k * k, st));
     for (int p = 0; p < k / PB; ++p) {
       double* X = P.Q + (int64_t)p * PB * Mt;
@@ -476,11 +495,12 @@ int wide_factor(Plan& P, hipStream_t st) {
       }
       {
         Prof pr("jac_eig", 8.0 * 4096 * npairs * (Lx.rsplit + 1), st);
-        k_jac_eig<<<npairs, 256, eig_lds, st>>>(Hp, Lx.rsplit, tol, Vp, cnt + (int64_t)r * npairs);
+        k_jac_eig<<<npairs, EIG_THREADS, eig_lds, st>>>(Hp, Lx.rsplit, tol, Vp, cnt + (int64_t)r * npairs);
       }
       {
         Prof pr("jac_rot", 2.0 * 16.0 * k * 64 * npairs, st, 2.0 * 2.0 * k * 64 * 64 * npairs);
-        k_jac_rot<<<dim3((unsigned)(k / 64), (unsigned)npairs, 2), 256, rot_lds, st>>>(k, P.Gj, P.Vj, r, nbj, Vp);
+        k_jac_rot<<<dim3((unsigned)((k / 64 + ROT_TILES - 1) / ROT_TILES), (unsigned)npairs, 2), 256, rot_lds, st>>>(
+            k, P.Gj, P.Vj, r, nbj, Vp);
       }
       AZ_HIP(hipGetLastError());
     }
