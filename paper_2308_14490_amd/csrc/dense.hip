@@ -77,82 +77,92 @@ __host__ __device__ constexpr int tsqr_rows(int k) { return 16384 / k; }
 // E_b = H_0 ... H_{k-1} [C_b; 0] = [C_b; 0] - V (T (V_top^T C_b)) for block b
 // (compact WY; V_top = the block's first k reflector rows, unit lower
 // triangular).  C_b is rows b*k.. of the level above's explicit Q (Cup), or
-// the identity at the top (Cup null).  Fully parallel over the block's rows.
+// the identity at the top (Cup null).  The k x k products give each thread
+// several independent outputs, and each row's k outputs accumulate side by
+// side, so no long chain of dependent FMAs forms.
+template <int K>
 __global__ void __launch_bounds__(TSQR_THREADS)
-k_tsqr_formq(const double* __restrict__ V, int64_t ldv, const double* __restrict__ Tin, int64_t m, int k,
+k_tsqr_formq(const double* __restrict__ V, int64_t ldv, const double* __restrict__ Tin, int64_t m,
              const double* __restrict__ Cup, int64_t ldc, double* __restrict__ E, int64_t lde) {
-  __shared__ double Cb[KMAX * (KMAX + 1)];
-  __shared__ double X[KMAX * (KMAX + 1)];     // V_top, then V_top^T C_b
-  __shared__ double Mm[KMAX * (KMAX + 1)];    // T, then T V_top^T C_b
-  const int ld = KMAX + 1;
-  const int RB = tsqr_rows(k);
+  constexpr int LD = K + 1;
+  constexpr int PER = K * K / TSQR_THREADS > 0 ? K * K / TSQR_THREADS : 1;   // outputs per thread
+  __shared__ double Cb[K * LD];      // C_b[l][c] at c * LD + l
+  __shared__ __align__(16) double Vt[K * LD];   // V_top[l][i] at i * LD + l
+  __shared__ double Tm[K * LD];      // T[i][l] at l * LD + i
+  __shared__ double Xs[K * LD];      // X = V_top^T C_b, X[l][c] at c * LD + l
+  double* Mr = Vt;                   // M = T X, row-major (M[l][c] at l * K + c), over V_top once used
+  const int RB = tsqr_rows(K);
   const int t = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * RB;
-  const double* Tb = Tin + (int64_t)blockIdx.x * k * k;
-  __shared__ double Vt[KMAX * (KMAX + 1)];
-  for (int e = t; e < k * k; e += TSQR_THREADS) {
-    const int r = e % k, c = e / k;
-    Cb[c * ld + r] = Cup ? Cup[(int64_t)blockIdx.x * k + r + ldc * c] : (r == c ? 1.0 : 0.0);
-    Vt[c * ld + r] = r0 + r < m ? V[r0 + r + ldv * c] : 0.0;       // unit lower, zeros above
-    Mm[c * ld + r] = Tb[e];                                         // T, upper triangular
+  const double* Tb = Tin + (int64_t)blockIdx.x * K * K;
+  for (int e = t; e < K * K; e += TSQR_THREADS) {
+    const int r = e % K, c = e / K;
+    Cb[c * LD + r] = Cup ? Cup[(int64_t)blockIdx.x * K + r + ldc * c] : (r == c ? 1.0 : 0.0);
+    Vt[c * LD + r] = r0 + r < m ? V[r0 + r + ldv * c] : 0.0;   // unit lower, zeros above
+    Tm[c * LD + r] = Tb[e];                                     // T, upper triangular
   }
   __syncthreads();
-  // X = V_top^T C_b: X[i][c] = sum_{l >= i} V_top[l][i] C_b[l][c]
-  double xv[KMAX * KMAX / TSQR_THREADS];
-  int ne = 0;
-  for (int e = t; e < k * k; e += TSQR_THREADS, ++ne) {
-    const int i = e % k, c = e / k;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int l = i;
-    for (; l + 4 <= k; l += 4) {
-      a0 = fma(Vt[i * ld + l], Cb[c * ld + l], a0);
-      a1 = fma(Vt[i * ld + l + 1], Cb[c * ld + l + 1], a1);
-      a2 = fma(Vt[i * ld + l + 2], Cb[c * ld + l + 2], a2);
-      a3 = fma(Vt[i * ld + l + 3], Cb[c * ld + l + 3], a3);
+  // thread: column c = t % K, rows i = t / K + (256 / K) q
+  const int c0 = t % K, i0 = t / K;
+  constexpr int IS = TSQR_THREADS / K > 0 ? TSQR_THREADS / K : 1;
+  if (t < K * IS) {
+    double acc[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) acc[q] = 0.0;
+#pragma unroll 4
+    for (int l = 0; l < K; ++l) {          // X[i][c] = sum_{l >= i} V_top[l][i] C_b[l][c]
+      const double cl = Cb[c0 * LD + l];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int i = i0 + IS * q;
+        acc[q] = fma(l >= i ? Vt[i * LD + l] : 0.0, cl, acc[q]);
+      }
     }
-    for (; l < k; ++l) a0 = fma(Vt[i * ld + l], Cb[c * ld + l], a0);
-    xv[ne] = (a0 + a1) + (a2 + a3);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) Xs[c0 * LD + i0 + IS * q] = acc[q];
   }
-  ne = 0;
-  for (int e = t; e < k * k; e += TSQR_THREADS, ++ne) X[(e / k) * ld + e % k] = xv[ne];
   __syncthreads();
-  // M = T X (T upper triangular): M[i][c] = sum_{l >= i} T[i][l] X[l][c]
-  ne = 0;
-  for (int e = t; e < k * k; e += TSQR_THREADS, ++ne) {
-    const int i = e % k, c = e / k;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int l = i;
-    for (; l + 4 <= k; l += 4) {
-      a0 = fma(Mm[l * ld + i], X[c * ld + l], a0);
-      a1 = fma(Mm[(l + 1) * ld + i], X[c * ld + l + 1], a1);
-      a2 = fma(Mm[(l + 2) * ld + i], X[c * ld + l + 2], a2);
-      a3 = fma(Mm[(l + 3) * ld + i], X[c * ld + l + 3], a3);
+  if (t < K * IS) {
+    double acc[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) acc[q] = 0.0;
+#pragma unroll 4
+    for (int l = 0; l < K; ++l) {          // M[i][c] = sum_{l >= i} T[i][l] X[l][c]
+      const double xl = Xs[c0 * LD + l];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int i = i0 + IS * q;
+        acc[q] = fma(l >= i ? Tm[l * LD + i] : 0.0, xl, acc[q]);
+      }
     }
-    for (; l < k; ++l) a0 = fma(Mm[l * ld + i], X[c * ld + l], a0);
-    xv[ne] = (a0 + a1) + (a2 + a3);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) Mr[(i0 + IS * q) * K + c0] = acc[q];
   }
   __syncthreads();
-  ne = 0;
-  for (int e = t; e < k * k; e += TSQR_THREADS, ++ne) Mm[(e / k) * ld + e % k] = xv[ne];
-  __syncthreads();
+  // rows: E[r][c] = C_b[r][c] (r < K) - sum_l V[r][l] M[l][c], all c at once
+  constexpr int CH = K < 32 ? K : 32;    // columns per pass (registers)
+#pragma unroll 1
   for (int r = t; r < RB; r += TSQR_THREADS) {
     const int64_t gi = r0 + r;
     if (gi >= m) break;
-    double vr[KMAX];
 #pragma unroll
-    for (int l = 0; l < KMAX; ++l) vr[l] = l < k ? V[gi + ldv * l] : 0.0;
-    for (int c = 0; c < k; ++c) {
-      double a0 = r < k ? Cb[c * ld + r] : 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int c0p = 0; c0p < K; c0p += CH) {
+      double acc[CH];
 #pragma unroll
-      for (int l = 0; l < KMAX; l += 4) {
-        if (l < k) {
-          a0 = fma(-vr[l], Mm[c * ld + l], a0);
-          a1 = fma(-vr[l + 1], Mm[c * ld + l + 1], a1);
-          a2 = fma(-vr[l + 2], Mm[c * ld + l + 2], a2);
-          a3 = fma(-vr[l + 3], Mm[c * ld + l + 3], a3);
+      for (int c = 0; c < CH; ++c) acc[c] = r < K ? Cb[(c0p + c) * LD + r] : 0.0;
+#pragma unroll 2
+      for (int l = 0; l < K; ++l) {
+        const double v = V[gi + ldv * l];   // streamed: one coalesced load per l
+        const double2* mrow = reinterpret_cast<const double2*>(Mr + l * K + c0p);
+#pragma unroll
+        for (int c = 0; c < CH; c += 2) {
+          const double2 mm = mrow[c / 2];
+          acc[c] = fma(-v, mm.x, acc[c]);
+          acc[c + 1] = fma(-v, mm.y, acc[c + 1]);
         }
       }
-      E[gi + lde * c] = (a0 + a1) + (a2 + a3);
+#pragma unroll
+      for (int c = 0; c < CH; ++c) E[gi + lde * (c0p + c)] = acc[c];
     }
   }
 }
@@ -217,7 +227,11 @@ static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double*
     const TsqrLevel& L = lv[l];
     double* E = l == 0 ? Q : Ebuf[l & 1];
     Prof pr(l == 0 ? "tsqr_formq" : "tsqr_formq (tree)", 16.0 * L.m * k + 8.0 * L.nb * k * (k + 1), st);
-    k_tsqr_formq<<<(unsigned)L.nb, TSQR_THREADS, 0, st>>>(L.A, L.m, L.tau, L.m, k, up, ldup, E, L.m);
+    switch (k) {
+      case 16: k_tsqr_formq<16><<<(unsigned)L.nb, TSQR_THREADS, 0, st>>>(L.A, L.m, L.tau, L.m, up, ldup, E, L.m); break;
+      case 32: k_tsqr_formq<32><<<(unsigned)L.nb, TSQR_THREADS, 0, st>>>(L.A, L.m, L.tau, L.m, up, ldup, E, L.m); break;
+      default: k_tsqr_formq<64><<<(unsigned)L.nb, TSQR_THREADS, 0, st>>>(L.A, L.m, L.tau, L.m, up, ldup, E, L.m); break;
+    }
     AZ_HIP(hipGetLastError());
     up = E;
     ldup = L.m;
