@@ -202,7 +202,8 @@ static int64_t tsqr_scratch_doubles(int64_t m, int k) {
 
 // W (m x k, ld m) is destroyed (level-0 reflectors); Q (m x k, ld m) and
 // R (k x k, ld k) out.
-static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double* R, hipStream_t st) {
+static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double* R, hipStream_t st,
+                hipEvent_t r_ready = nullptr) {
   std::vector<TsqrLevel> lv;
   int64_t sd, ed;
   tsqr_plan(m, k, lv, &sd, &ed);
@@ -221,6 +222,7 @@ static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double*
     AZ_TRY(tsqr_block_qr(L.A, L.m, L.m, k, L.R, L.nb * k, L.A, L.m, L.tau, st));
   }
   AZ_HIP(hipMemcpyAsync(R, lv.back().R, sizeof(double) * k * k, hipMemcpyDeviceToDevice, st));
+  if (r_ready) AZ_HIP(hipEventRecord(r_ready, st));   // R is final; Q is formed below
   const double* up = nullptr;
   int64_t ldup = 0;
   for (int l = (int)lv.size() - 1; l >= 0; --l) {
@@ -575,14 +577,33 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch) {
   AZ_TRY(ops_apply_A(P, Zy, N, k, -1.0, 1.0, P.Yf, Mt, W, Mt, st));          // W = Y - A Z* Y
   // what follows is latency-bound: work on other streams may start here
   if (after_sketch) AZ_HIP(hipEventRecord(after_sketch, st));
-  // TSQR destroys W; the QR is of the sketch, W is then free scratch
-  AZ_TRY(tsqr(W, Mt, k, tq, P.Q, P.Rf, st));
+  // TSQR destroys W; the QR is of the sketch, W is then free scratch.  The
+  // Jacobi SVD needs only R: it runs on a second stream while this one forms
+  // the explicit Q, and the products below (which overwrite W) wait for both.
   const double thr = P.tau * P.normA * sqrt((double)k);
-  {
-    Prof pj("jacobi", 8.0 * 3 * k * k, st);
-    k_jacobi<<<1, 256, 0, st>>>(P.Rf, k, thr, 4.0 * k * 1.1102230246251565e-16, 40, P.sig, P.Pm, info);
+  hipStream_t js = nullptr;
+  hipEvent_t eR = nullptr, eJ = nullptr;
+  if (side_stream(P.device, &js) == AZRBF_OK && hipEventCreateWithFlags(&eR, hipEventDisableTiming) == hipSuccess &&
+      hipEventCreateWithFlags(&eJ, hipEventDisableTiming) == hipSuccess && js != st) {
+  } else {
+    js = st;
   }
-  AZ_HIP(hipGetLastError());
+  int rc = tsqr(W, Mt, k, tq, P.Q, P.Rf, st, js != st ? eR : nullptr);
+  if (!rc && js != st && hipStreamWaitEvent(js, eR, 0) != hipSuccess) rc = AZRBF_EHIP;
+  if (!rc) {
+    Prof pj("jacobi", 8.0 * 3 * k * k, js);
+    k_jacobi<<<1, 256, 0, js>>>(P.Rf, k, thr, 4.0 * k * 1.1102230246251565e-16, 40, P.sig, P.Pm, info);
+    if (hipGetLastError() != hipSuccess) rc = AZRBF_EHIP;
+  }
+  if (!rc && js != st) {
+    if (hipEventRecord(eJ, js) != hipSuccess || hipStreamWaitEvent(st, eJ, 0) != hipSuccess) rc = AZRBF_EHIP;
+  }
+  if (eR) (void)hipEventDestroy(eR);
+  if (eJ) (void)hipEventDestroy(eJ);
+  if (rc) {
+    if (js != st) (void)hipStreamSynchronize(js);
+    return rc;
+  }
   // Omega P and (A Omega) P: the solve needs only these (y = P Q^T c)
   AZ_TRY(gemm_nn(P.Om, N, N, k, P.Pm, k, k, 1.0, nullptr, 0, 0.0, Zy, N, st));
   AZ_TRY(gemm_nn(P.Yf, Mt, Mt, k, P.Pm, k, k, 1.0, nullptr, 0, 0.0, W, Mt, st));
@@ -614,11 +635,12 @@ int dense_factor(Plan& P, hipStream_t st) {
 int dense_solve_ws(Plan& P, int64_t nrhs) {
   const int k = P.k;
   const int64_t N = P.N, Mt = P.Mt;
-  const int64_t nparts = tn_blocks(Mt) * ((nrhs + TN_COLS - 1) / TN_COLS) * TN_COLS;
-  if (nrhs > P.sw_rhs) {
-    const int64_t per = N + 3 * Mt + k + tn_blocks(Mt) * k + 2 * NORM_CHUNKS;
-    AZ_TRY(P.alloc((void**)&P.sw, sizeof(double) * (per * nrhs + nparts * k)));
+  const int64_t npart = gemm_split_doubles(k, nrhs, Mt, 1);
+  if (nrhs > P.sw_rhs || npart > P.sw_part) {
+    const int64_t per = N + 3 * Mt + k + 2 * NORM_CHUNKS;
+    AZ_TRY(P.alloc((void**)&P.sw, sizeof(double) * (per * nrhs + npart)));
     P.sw_rhs = nrhs;
+    P.sw_part = npart;
   }
   return AZRBF_OK;
 }
@@ -646,7 +668,8 @@ int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, 
   double* Rc = R1 + Mt * nrhs;         // Mt x nrhs
   double* Tm = Rc + Mt * nrhs;         // k x nrhs
   double* nrm = Tm + (int64_t)k * nrhs;            // 2 * NORM_CHUNKS x nrhs
-  double* part = nrm + 2 * NORM_CHUNKS * nrhs;     // TSQR-free GEMM partials
+  double* part = nrm + 2 * NORM_CHUNKS * nrhs;     // split-reduction partials of Q^T c
+  const int64_t npart = gemm_split_doubles(k, nrhs, Mt, 1);
   const double* rin = B;
   int64_t ldr = ldb;
   for (int it = 0; it <= P.refine; ++it) {
@@ -654,7 +677,8 @@ int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, 
       AZ_TRY(ops_apply_Z(P, rin, ldr, nrhs, 1.0, 0.0, nullptr, 0, Zr, N, st));      // Z* r
       AZ_TRY(ops_apply_A(P, Zr, N, nrhs, -1.0, 1.0, rin, ldr, C, Mt, st));         // c = (I - A Z*) r
     }
-    AZ_TRY(gemm_tn(P.Q, Mt, Mt, k, C, Mt, nrhs, part, Tm, st));                     // t = Q^T c
+    AZ_TRY(gemm_mfma_c(true, false, k, nrhs, Mt, 1.0, P.Q, Mt, 0, C, Mt, 0, 0.0, nullptr, 0, 0, Tm, k, 0, 1, part,
+                       npart, st));                                                             // t = Q^T c
     AZ_TRY(gemm_nn(P.Om, N, N, k, Tm, k, nrhs, 1.0, X, ldx, it == 0 ? 0.0 : 1.0, X, ldx, st));  // x += x1
     AZ_TRY(gemm_nn(P.Yf, Mt, Mt, k, Tm, k, nrhs, -1.0, rin, ldr, 1.0, R1, Mt, st));            // r - A x1
     AZ_TRY(ops_apply_Z(P, R1, Mt, nrhs, 1.0, 1.0, nullptr, 0, X, ldx, st));          // x += Z* (r - A x1)

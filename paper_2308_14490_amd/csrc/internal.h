@@ -73,6 +73,8 @@ struct Prof {
 };
 
 int pool_trim();
+// a library stream for work that overlaps other work (plan.hip)
+int side_stream(int device, hipStream_t* out);
 
 // ops.hip
 int ops_init_twiddles(int device, const double2** tw);
