@@ -1,0 +1,127 @@
+"""Parity at the full sizes of the workloads, where the dense oracle cannot
+run: the GPU solution is checked on the CPU by the oracle's independent local
+evaluator (direct windowed sums of the Gaussians, no FFT), which recomputes
+the residual ||b - A x|| / ||b|| over every collocation (and boundary) row and
+the approximant on a test set.  The residual must be <= 1e-10 where the
+method reaches it (eps*h = 0.5 approximation), agree with the library's own
+residual, and be within 10x the dense oracle's at the largest size of the
+same family it can solve; the test-set error likewise.
+
+The 1D case runs in the launch configuration the benchmark times (the same
+plan options, tile shapes from the autotuner, 64 right-hand sides)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import dense, evaluate, lstsq
+
+from gpu_util import announce, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _mods():
+    require_gpu()
+    from paper_2308_14490_amd import azrbf, problems
+    return azrbf, problems
+
+
+def _oracle_levels(prob):
+    """Dense truncated-SVD solve: (relres, maxerr on the test set) per RHS."""
+    A, idx, pts, bpts = dense.system_matrix(prob)
+    B = dense.rhs(prob, pts, bpts)
+    X, _ = lstsq.tsvd_solve(A, B, 1e-12)
+    tp = W.test_points(prob, m2d=200)
+    f = np.stack([g(*tp.T) for g in (prob.exact or prob.rhs)], axis=1)
+    err = np.max(np.abs(evaluate.eval_dense(prob, X, tp) - f), axis=0)
+    return evaluate.relres(A, X, B), err
+
+
+def _cpu_residual(prob, plan, Xg, Bg):
+    """||b - A x|| / ||b|| per column, A applied by local summation."""
+    pts = plan.points()
+    AX = evaluate.apply_local(prob, Xg, pts)
+    if prob.nb:
+        AX = np.concatenate([AX, prob.bweight * evaluate.apply_local(prob, Xg, prob.bpoints(), op=0)], axis=0)
+    return np.linalg.norm(AX - Bg, axis=0) / np.linalg.norm(Bg, axis=0)
+
+
+def _cpu_maxerr(prob, Xg, m1d=4096, m2d=200):
+    tp = W.test_points(prob, m1d=m1d, m2d=m2d)
+    f = np.stack([g(*tp.T) for g in (prob.exact or prob.rhs)], axis=1)
+    return np.max(np.abs(evaluate.apply_local(prob, Xg, tp, op=0) - f), axis=0)
+
+
+def _solve(prob, tune_nvec=0):
+    azrbf, problems = _mods()
+    p = problems.plan_for(prob)
+    if tune_nvec:
+        azrbf.autotune(p, tune_nvec)
+    B = problems.rhs_for(p, prob)
+    X, rel = azrbf.solve(p, B)
+    torch.cuda.synchronize()
+    return p, B.cpu().numpy().T, X.cpu().numpy().T, rel.cpu().numpy()
+
+
+def test_fullsize_1d_batched_matches_local_residual():
+    """N = 65536 centres, M = 65537 rows, 64 random-trig right-hand sides."""
+    prob = W.config_c2(65536, 64)
+    announce("full 1D", prob.N, "nrhs", len(prob.rhs))
+    p, B, X, rel = _solve(prob, tune_nvec=64)
+    rc = _cpu_residual(prob, p, X, B)
+    ro, eo = _oracle_levels(W.config_c2(4096, 64))
+    eg = _cpu_maxerr(prob, X)
+    announce("relres gpu max", rel.max(), "cpu max", rc.max(), "oracle@4096 max", ro.max(),
+             "maxerr gpu", eg.max(), "oracle@4096", eo.max())
+    assert np.all(rc <= 1e-10)
+    assert np.allclose(rc, rel, rtol=1e-2, atol=1e-16)
+    assert np.all(rc <= 10 * ro + 1e-15)
+    assert np.all(eg <= 10 * eo + 1e-15)
+    p.destroy()
+
+
+def test_fullsize_2d_disk_matches_local_residual():
+    """128 x 128 centres, disk of radius 0.8 (M = 32937), eps*h = 0.5."""
+    prob = W.config_c3a(128)
+    announce("full 2D disk", prob.n)
+    p, B, X, rel = _solve(prob)
+    rc = _cpu_residual(prob, p, X, B)
+    ro, eo = _oracle_levels(W.config_c3a(32))
+    eg = _cpu_maxerr(prob, X)
+    announce("k", p.info()["k"], "rank", p.info()["rank"], "relres gpu", rel, "cpu", rc, "oracle@32", ro,
+             "maxerr", eg, "oracle@32", eo)
+    assert np.all(rc <= 1e-10)
+    assert np.allclose(rc, rel, rtol=1e-2, atol=1e-16)
+    assert np.all(eg <= 10 * eo + 1e-15)
+    p.destroy()
+
+
+def test_fullsize_2d_disk_literal_shape_parameter():
+    """The same disk at eps = 1/h: the residual saturates (reading 1); the
+    full-size solve stays within 10x the oracle's level at n = 32."""
+    prob = W.config_c3(128)
+    announce("full 2D disk eps*h=1", prob.n)
+    p, B, X, rel = _solve(prob)
+    rc = _cpu_residual(prob, p, X, B)
+    ro, eo = _oracle_levels(W.config_c3(32))
+    announce("relres gpu", rel, "cpu", rc, "oracle@32", ro)
+    assert np.allclose(rc, rel, rtol=1e-2, atol=1e-16)
+    assert np.all(rc <= 10 * ro)
+    p.destroy()
+
+
+def test_fullsize_2d_poisson_star():
+    """-Lap u = f on the star, 256 x 256 centres, weak Dirichlet rows."""
+    prob = W.config_c4(256)
+    announce("full 2D Poisson", prob.n, "nb", prob.nb)
+    p, B, X, rel = _solve(prob)
+    rc = _cpu_residual(prob, p, X, B)
+    ro, eo = _oracle_levels(W.config_c4(32))
+    eg = _cpu_maxerr(prob, X)
+    announce("k", p.info()["k"], "rank", p.info()["rank"], "relres gpu", rel, "cpu", rc, "oracle@32", ro,
+             "maxerr", eg, "oracle@32", eo)
+    assert np.allclose(rc, rel, rtol=1e-2, atol=1e-16)
+    assert np.all(rc <= 10 * ro)
+    assert np.all(eg <= 10 * eo)
+    p.destroy()
