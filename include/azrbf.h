@@ -214,9 +214,11 @@ int azrbf_tune_load(const char* text);
  * the library (any plan, any stream) is bracketed by HIP events on its
  * stream and tagged with the bytes it must move at minimum (its algorithmic
  * reads and writes).  azrbf_profile_report waits for the recorded events,
- * writes a JSON array of {"name", "calls", "ms", "max_ms", "bytes"} totals
- * per kernel name into buf (len bytes, NUL-terminated; EINVAL if too small)
- * and clears the records. */
+ * writes a JSON array of {"name", "calls", "ms", "max_ms", "bytes", "flops"}
+ * totals per kernel name into buf (len bytes, NUL-terminated; EINVAL if too
+ * small) and clears the records.  While enabled, work the library would
+ * otherwise overlap on its side streams runs in order on the caller's stream,
+ * so that each launch's time is its own. */
 int azrbf_profile_enable(int32_t on);
 int azrbf_profile_report(char* buf, int64_t len);
 

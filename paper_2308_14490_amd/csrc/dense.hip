@@ -583,7 +583,8 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch) {
   const double thr = P.tau * P.normA * sqrt((double)k);
   hipStream_t js = nullptr;
   hipEvent_t eR = nullptr, eJ = nullptr;
-  if (side_stream(P.device, &js) == AZRBF_OK && hipEventCreateWithFlags(&eR, hipEventDisableTiming) == hipSuccess &&
+  if (!prof_enabled() && side_stream(P.device, &js) == AZRBF_OK &&
+      hipEventCreateWithFlags(&eR, hipEventDisableTiming) == hipSuccess &&
       hipEventCreateWithFlags(&eJ, hipEventDisableTiming) == hipSuccess && js != st) {
   } else {
     js = st;

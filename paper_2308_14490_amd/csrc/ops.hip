@@ -308,20 +308,22 @@ k_col_inv_A(Geo g, const double2* __restrict__ tw, const double2* __restrict__ w
   const int64_t pair = blockIdx.y;
   const int64_t v0 = 2 * (pair0 + pair);
   const int nph = g.dim == 1 ? S : S * S;
-  // one phase at a time (its line in registers): the s phases of a point are
-  // adjacent rows, so the second phase's stores fill the cache lines the
-  // first one opened
-#pragma unroll 1
-  for (int ph = 0; ph < nph; ++ph) {
-    double2 res[RADIX];
-    const double2* in = ws2 + (pair * nph + ph) * g.N;
+  for (int gx = 0; gx < nph; gx += S) {
+    double2 res[S][RADIX];
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) res[m] = in[(int64_t)(t + m * T) * g.N2 + b];
-    fft_line<N1, true>(res, lds, l, t, tw);
+    for (int ry = 0; ry < S; ++ry) {
+      const double2* in = ws2 + (pair * nph + gx + ry) * g.N;
+#pragma unroll
+      for (int m = 0; m < RADIX; ++m) res[ry][m] = in[(int64_t)(t + m * T) * g.N2 + b];
+      fft_line<N1, true>(res[ry], lds, l, t, tw);
+    }
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) {
-      const int64_t row = row_of(g, grid_index(g, ph, t + m * T, b));
-      if (row >= 0) store_pair(Y, ldy, Yin, ldyi, row, v0, nvec, res[m], alpha, beta);
+#pragma unroll
+      for (int ry = 0; ry < S; ++ry) {
+        const int64_t row = row_of(g, grid_index(g, gx + ry, t + m * T, b));
+        if (row >= 0) store_pair(Y, ldy, Yin, ldyi, row, v0, nvec, res[ry][m], alpha, beta);
+      }
     }
   }
 }
@@ -340,22 +342,27 @@ k_col_fwd_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R,
   const int64_t pair = blockIdx.y;
   const int64_t v0 = 2 * (pair0 + pair);
   const int nph = g.dim == 1 ? S : S * S;
-#pragma unroll 1
-  for (int ph = 0; ph < nph; ++ph) {   // one phase at a time, as in k_col_inv_A
-    double2 in[RADIX];
+  for (int gx = 0; gx < nph; gx += S) {
+    double2 in[S][RADIX];
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) {
-      const int64_t row = row_of(g, grid_index(g, ph, t + m * T, b));
-      in[m] = row >= 0 ? load_pair(R, ldr, row, v0, nvec) : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int ry = 0; ry < S; ++ry) {
+        const int64_t row = row_of(g, grid_index(g, gx + ry, t + m * T, b));
+        in[ry][m] = row >= 0 ? load_pair(R, ldr, row, v0, nvec) : make_double2(0.0, 0.0);
+      }
     }
-    fft_line<N1, false>(in, lds, l, t, tw);
-    double2* out = ws1 + (pair * nph + ph) * g.N;
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) {
-      const int64_t k1 = t + m * T;
-      double2 v = in[m];
-      if (TWID) v = cmul(v, tw_fwd(tw, k1 * b, g.N));
-      out[k1 * g.N2 + b] = v;
+    for (int ry = 0; ry < S; ++ry) {
+      fft_line<N1, false>(in[ry], lds, l, t, tw);
+      double2* out = ws1 + (pair * nph + gx + ry) * g.N;
+#pragma unroll
+      for (int m = 0; m < RADIX; ++m) {
+        const int64_t k1 = t + m * T;
+        double2 v = in[ry][m];
+        if (TWID) v = cmul(v, tw_fwd(tw, k1 * b, g.N));
+        out[k1 * g.N2 + b] = v;
+      }
     }
   }
 }

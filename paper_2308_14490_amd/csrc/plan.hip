@@ -454,7 +454,9 @@ int azrbf_solve(azrbf_plan_t h, const double* B, int64_t ldb, int64_t nrhs, doub
   if (!B || !X || ldb < P.Mt || ldx < P.N) return AZRBF_EINVAL;
   P.last_stream = (hipStream_t)stream;
   hipStream_t st = (hipStream_t)stream;
-  if (!P.factored && P.k <= 64 && P.prob.k > 0) {
+  // (not while per-launch timing is on: launches then run one at a time so
+  // that each one's time is its own)
+  if (!P.factored && P.k <= 64 && P.prob.k > 0 && !az::prof_enabled()) {
     // The first pass's c = (I - A Z*) b does not need the factor: it runs on a
     // side stream (with its own FFT workspace) while the latency-bound
     // factorisation runs on the caller's stream.  (With a fixed sketch width
