@@ -261,109 +261,219 @@ __device__ __forceinline__ double fast_rsq(double x) {
   return fma(0.5 * y, fma(-x * y, y, 1.0), y);
 }
 
-// One-sided Jacobi SVD of the k x k triangular factor R (k in {16, 32, 64})
-// in one block, applied to A = R^T: its columns (the rows of R) are
-// orthogonalised by plane rotations from the right, R^T V = U S, so
-// R = V S U^T and the truncated pseudo-inverse of R is sum u_i v_i^T / s_i.
-// (The transposed factor converges in about half the sweeps: its columns are
-// far closer to orthogonal than those of R.)  Round-robin (circle) schedule: in round r pair 0 is
-// (r, k-1) and pair i > 0 is ((r+i) mod (k-1), (r-i) mod (k-1)); k/2 pairs
-// per round, G = 512/k threads per pair.  A rotation is skipped when
+// Sums over groups of 8 and 16 consecutive lanes by DPP moves (quad
+// permutations, then the half-row and row mirrors).  Every lane of a group
+// ends with the same bits: each stage adds the same two values in either order.
+template <int CTRL>
+__device__ __forceinline__ double jdpp(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double sum8(double x) {
+  x += jdpp<0xB1>(x);
+  x += jdpp<0x4E>(x);
+  return x + jdpp<0x141>(x);
+}
+__device__ __forceinline__ double sum16(double x) {
+  x = sum8(x);
+  return x + jdpp<0x140>(x);
+}
+
+// Truncated pseudo-inverse of the k x k triangular factor R (k in {16, 32,
+// 64}) by a preconditioned one-sided Jacobi SVD, in one block of 8k threads.
+//
+// Preconditioning: Householder QR of the transpose, R^T = Q2 R2, with Q2
+// formed explicitly (k - 1 reflectors; per reflector one 16-lane group forms
+// the vector, then every 8-lane slot updates one column of R2 and one row of
+// Q2).  One-sided Jacobi on R2^T then converges in fewer sweeps than on R^T,
+// because the QR concentrates the weight of R2's rows on the diagonal.
+//
+// Jacobi: the columns of A = R2^T are orthogonalised by plane rotations from
+// the right, A W = U S, with W accumulated from W0 = Q2, so that
+// R = U S (Q2 W)^T and the pseudo-inverse is sum_i (Q2 W)_i u_i^T / s_i.
+// Round-robin (circle) schedule: in round r pair 0 is (r, k-1) and pair
+// i > 0 is ((r+i) mod (k-1), (r-i) mod (k-1)); k/2 pairs per round, one
+// 16-lane DPP row per pair.  A rotation is skipped when
 // |a_p . a_q| <= tol sqrt(|a_p|^2 |a_q|^2); sweeps stop when none happens.
+// The rotation angle theta solves tan 2theta = 2 a_p.a_q / (|a_q|^2 - |a_p|^2)
+// with |theta| <= pi/4; c and s come from the half-angle identities
+// c^2 = (1 + cos 2theta)/2, s = sin 2theta / (2c).
 // On exit: sig (descending), info = {rank, sweeps} with rank = #{sigma > thr},
-// Pm = sum_{i < rank} u_i v_i^T / sigma_i (the truncated pseudo-inverse of R).
-__global__ void __launch_bounds__(256)
-k_jacobi(const double* __restrict__ R, int k, double thr, double tol, int max_sweeps, double* __restrict__ sig,
+// Pm = sum_{i < rank} (Q2 W)_i u_i^T / sigma_i.
+template <int K>
+__global__ void __launch_bounds__(8 * K)
+k_jacobi(const double* __restrict__ R, double thr, double tol, int max_sweeps, double* __restrict__ sig,
          double* __restrict__ Pm, int* __restrict__ info) {
-  __shared__ double A[KMAX * (KMAX + 1)];
-  __shared__ double V[KMAX * (KMAX + 1)];
-  __shared__ double sv[KMAX];
-  __shared__ int ord[KMAX];
-  __shared__ int flag;
-  const int lda = KMAX + 1;
+  constexpr int LD = K + 1;       // column stride (doubles) of the LDS matrices
+  constexpr int NT = 8 * K;       // threads
+  constexpr int RPL = K / 16;     // rows per lane in a rotation
+  constexpr int EPL = K / 8;      // elements per lane in a reflector update
+  constexpr int KM1 = K - 1;
+  __shared__ double A[K * LD];    // A[c * LD + r] = entry (r, c)
+  __shared__ double W[K * LD];    // Q2, then Q2 W; same layout
+  __shared__ double hv[K];        // current reflector (entries j .. K-1)
+  __shared__ double sv[K], inv2[K];
+  __shared__ int ord[K];
+  __shared__ double hbeta;
   const int t = threadIdx.x;
-  for (int i = t; i < k * k; i += blockDim.x) {
-    const int r = i % k, c = i / k;
-    A[r * lda + c] = R[r + (int64_t)k * c];      // A = R^T
-    V[c * lda + r] = r == c ? 1.0 : 0.0;
+  for (int i = t; i < K * K; i += NT) {
+    const int r = i % K, c = i / K;
+    A[r * LD + c] = R[r + (int64_t)K * c];        // A = R^T
+    W[c * LD + r] = r == c ? 1.0 : 0.0;
   }
-  const int G = 512 / k;
-  const int pi = t / G, gl = t % G, km1 = k - 1;
-  int sweep = 0;
-  for (; sweep < max_sweeps; ++sweep) {
-    if (t == 0) flag = 0;
-    __syncthreads();
-    for (int round = 0; round < km1; ++round) {
-      const int p = pi == 0 ? round : (round + pi) % km1;
-      const int q = pi == 0 ? km1 : (round - pi + km1) % km1;
-      double al = 0.0, be = 0.0, ga = 0.0;
-      for (int r = gl; r < k; r += G) {
-        const double x = A[p * lda + r], y = A[q * lda + r];
-        al = fma(x, x, al);
-        be = fma(y, y, be);
-        ga = fma(x, y, ga);
+  __syncthreads();
+
+  // ---- Householder QR of A; Q2 accumulated into W from the right
+  {
+    const int slot = t >> 3, sl = t & 7;
+    for (int j = 0; j < KM1; ++j) {
+      if (t < 16) {
+        double s = 0.0;
+        for (int i = j + t; i < K; i += 16) {
+          const double x = A[j * LD + i];
+          s = fma(x, x, s);
+        }
+        s = sum16(s);
+        const double x0 = A[j * LD + j];
+        const double nrm = sqrt(s);
+        const double alpha = x0 >= 0.0 ? -nrm : nrm;
+        for (int i = j + t; i < K; i += 16) {
+          hv[i] = i == j ? x0 - alpha : A[j * LD + i];
+          A[j * LD + i] = i == j ? alpha : 0.0;
+        }
+        if (t == 0) hbeta = nrm == 0.0 ? 0.0 : 1.0 / (nrm * (nrm + fabs(x0)));
       }
-      for (int o = G / 2; o > 0; o >>= 1) {
-        al += __shfl_xor(al, o, G);
-        be += __shfl_xor(be, o, G);
-        ga += __shfl_xor(ga, o, G);
+      __syncthreads();
+      const double beta = hbeta;
+      const bool col = slot > j;                 // this slot's column of A needs the reflector
+      double vv[EPL], ac[EPL], wr[EPL];
+      double dc = 0.0, dr = 0.0;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const int i = j + sl + 8 * e;
+        const bool ok = i < K;
+        vv[e] = ok ? hv[i] : 0.0;
+        ac[e] = ok && col ? A[slot * LD + i] : 0.0;
+        wr[e] = ok ? W[i * LD + slot] : 0.0;     // entry (slot, i) of Q2
+        dc = fma(vv[e], ac[e], dc);
+        dr = fma(vv[e], wr[e], dr);
       }
-      if (ga != 0.0 && ga * ga > tol * tol * (al * be)) {
-        // tan of the rotation angle (Rutishauser): t = sign(z) / (|z| + sqrt(1 + z^2)),
-        // z = (be - al) / (2 ga); c = 1/sqrt(1 + t^2), s = c t.  For |z| > 1e8 the
-        // square would overflow the useful range and t = 1/(2z) to rounding.
-        const double zeta = (be - al) * fast_rcp(2.0 * ga);
-        const double az = fabs(zeta);
-        const double w = 1.0 + zeta * zeta;
-        const double root = az > 1e8 ? az : w * fast_rsq(w);
-        const double tt = copysign(fast_rcp(az + root), zeta);
-        const double c = fast_rsq(fma(tt, tt, 1.0)), s = c * tt;
-        if (gl == 0) flag = 1;
-        for (int r = gl; r < k; r += G) {
-          const double x = A[p * lda + r], y = A[q * lda + r];
-          A[p * lda + r] = c * x - s * y;
-          A[q * lda + r] = s * x + c * y;
-          const double vx = V[p * lda + r], vy = V[q * lda + r];
-          V[p * lda + r] = c * vx - s * vy;
-          V[q * lda + r] = s * vx + c * vy;
+      dc = sum8(dc) * beta;
+      dr = sum8(dr) * beta;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const int i = j + sl + 8 * e;
+        if (i < K) {
+          if (col) A[slot * LD + i] = fma(-dc, vv[e], ac[e]);
+          W[i * LD + slot] = fma(-dr, vv[e], wr[e]);
         }
       }
       __syncthreads();
     }
-    const int f = flag;
+    // A now holds R2 (column-major); the Jacobi works on its transpose
+    for (int i = t; i < K * K; i += NT) {
+      const int r = i % K, c = i / K;
+      if (r < c) {
+        const double a = A[c * LD + r];
+        A[c * LD + r] = A[r * LD + c];
+        A[r * LD + c] = a;
+      }
+    }
     __syncthreads();
-    if (!f) break;
   }
-  if (t < k) {
+
+  // ---- one-sided Jacobi on the columns of A
+  const int pi = t >> 4, gl = t & 15;
+  const double tol2 = tol * tol;
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    int rotated = 0;
+    for (int round = 0; round < KM1; ++round) {
+      const int p = pi == 0 ? round : (round + pi) % KM1;
+      const int q = pi == 0 ? KM1 : (round - pi + KM1) % KM1;
+      double x[RPL], y[RPL], vx[RPL], vy[RPL];
+      double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+      for (int e = 0; e < RPL; ++e) {
+        const int r = gl + 16 * e;
+        x[e] = A[p * LD + r];
+        y[e] = A[q * LD + r];
+        vx[e] = W[p * LD + r];
+        vy[e] = W[q * LD + r];
+      }
+#pragma unroll
+      for (int e = 0; e < RPL; ++e) {
+        al = fma(x[e], x[e], al);
+        be = fma(y[e], y[e], be);
+        ga = fma(x[e], y[e], ga);
+      }
+      al = sum16(al);
+      be = sum16(be);
+      ga = sum16(ga);
+      // (|ga| > 1e-150 keeps 4 ga^2 a normal number below)
+      if (ga * ga > tol2 * (al * be) && fabs(ga) > 1e-150) {
+        rotated = 1;
+        const double d = be - al, g2 = 2.0 * ga;
+        const double rq = fast_rsq(fma(d, d, g2 * g2));
+        const double cos2 = fabs(d) * rq;
+        const double sin2 = (d >= 0.0 ? g2 : -g2) * rq;
+        const double h = fma(0.5, cos2, 0.5);
+        const double rh = fast_rsq(h);
+        const double c = h * rh, s = 0.5 * sin2 * rh;
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) {
+          const int r = gl + 16 * e;
+          A[p * LD + r] = c * x[e] - s * y[e];
+          A[q * LD + r] = s * x[e] + c * y[e];
+          W[p * LD + r] = c * vx[e] - s * vy[e];
+          W[q * LD + r] = s * vx[e] + c * vy[e];
+        }
+      }
+      __syncthreads();
+    }
+    if (!__syncthreads_or(rotated)) break;
+  }
+
+  if (t < K) {
     double s2 = 0.0;
-    for (int r = 0; r < k; ++r) s2 = fma(A[t * lda + r], A[t * lda + r], s2);
+    for (int r = 0; r < K; ++r) s2 = fma(A[t * LD + r], A[t * LD + r], s2);
     sv[t] = sqrt(s2);
   }
   __syncthreads();
-  if (t < k) {   // position of column t in descending order (ties by index)
+  if (t < K) {   // position of column t in descending order (ties by index)
     int pos = 0;
-    for (int j = 0; j < k; ++j) pos += (sv[j] > sv[t]) || (sv[j] == sv[t] && j < t);
+    for (int j = 0; j < K; ++j) pos += (sv[j] > sv[t]) || (sv[j] == sv[t] && j < t);
     ord[pos] = t;
+    inv2[t] = sv[t] > 0.0 ? 1.0 / (sv[t] * sv[t]) : 0.0;
   }
   __syncthreads();
   int rank = 0;
-  for (int i = 0; i < k; ++i) rank += sv[i] > thr;
+  for (int i = 0; i < K; ++i) rank += sv[i] > thr;
   if (t == 0) {
     info[0] = rank;
     info[1] = sweep;
   }
-  if (t < k) sig[t] = sv[ord[t]];
-  // Pm[r][c] = sum_i U[r][i] V[c][i] / s_i = sum_i A[r][i] V[c][i] / s_i^2
-  for (int e = t; e < k * k; e += blockDim.x) {
-    const int r = e % k, c = e / k;
+  if (t < K) sig[t] = sv[ord[t]];
+  // Pm[r][c] = sum_i (Q2 W)[r][i] U[c][i] / s_i = sum_i (Q2 W)[r][i] A[c][i] / s_i^2
+  for (int e = t; e < K * K; e += NT) {
+    const int r = e % K, c = e / K;
     double acc = 0.0;
     for (int ii = 0; ii < rank; ++ii) {
       const int i = ord[ii];
-      const double si = sv[i];
-      acc = fma(A[i * lda + r], V[i * lda + c] / (si * si), acc);
+      acc = fma(W[i * LD + r] * inv2[i], A[i * LD + c], acc);
     }
-    Pm[r + (int64_t)k * c] = acc;
+    Pm[r + (int64_t)K * c] = acc;
   }
+}
+
+int launch_jacobi(const double* R, int k, double thr, double tol, int max_sweeps, double* sig, double* Pm, int* info,
+                  hipStream_t st) {
+  if (k == 16) k_jacobi<16><<<1, 128, 0, st>>>(R, thr, tol, max_sweeps, sig, Pm, info);
+  else if (k == 32) k_jacobi<32><<<1, 256, 0, st>>>(R, thr, tol, max_sweeps, sig, Pm, info);
+  else if (k == 64) k_jacobi<64><<<1, 512, 0, st>>>(R, thr, tol, max_sweeps, sig, Pm, info);
+  else return AZRBF_EUNSUPPORTED;
+  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
 // ------------------------------------------------------------------ skinny GEMMs
@@ -593,8 +703,7 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch) {
   if (!rc && js != st && hipStreamWaitEvent(js, eR, 0) != hipSuccess) rc = AZRBF_EHIP;
   if (!rc) {
     Prof pj("jacobi", 8.0 * 3 * k * k, js);
-    k_jacobi<<<1, 256, 0, js>>>(P.Rf, k, thr, 4.0 * k * 1.1102230246251565e-16, 40, P.sig, P.Pm, info);
-    if (hipGetLastError() != hipSuccess) rc = AZRBF_EHIP;
+    rc = launch_jacobi(P.Rf, k, thr, 4.0 * k * 1.1102230246251565e-16, 40, P.sig, P.Pm, info, js);
   }
   if (!rc && js != st) {
     if (hipEventRecord(eJ, js) != hipSuccess || hipStreamWaitEvent(st, eJ, 0) != hipSuccess) rc = AZRBF_EHIP;
