@@ -128,6 +128,18 @@ int azrbf_apply_A(azrbf_plan_t plan, const double* X, int64_t ldx, int64_t nvec,
 int azrbf_apply_Zstar(azrbf_plan_t plan, const double* R, int64_t ldr, int64_t nvec,
                       double alpha, double beta, double* Z, int64_t ldz, void* stream);
 
+/* Y = alpha * A Z* R + beta * Y: the product of the two operators above, as
+ * in the right-hand side (I - A Z*) b of step 1 of Algorithm 1.  Between
+ * the two operators the product stays in the spectrum (one row pass does Z*'s
+ * combination of the phases and A's per-phase products; Z*'s inverse and
+ * A's forward transforms cancel), so it costs about half of the two calls.
+ * R and Y are (M + Mb) x nvec; R may equal Y (same leading dimension); rows
+ * M..M+Mb-1 of R are ignored as in azrbf_apply_Zstar.  With boundary rows or
+ * on the single-kernel 1D path the plan keeps an N x nvec coefficient scratch
+ * (grown on demand, which may synchronise the stream). */
+int azrbf_apply_AZstar(azrbf_plan_t plan, const double* R, int64_t ldr, int64_t nvec,
+                       double alpha, double beta, double* Y, int64_t ldy, void* stream);
+
 /* Step 1 set-up (section 3.2.3, "low-rank solver"): the Gaussian sketch
  * Omega (N x k), W = (A - A Z* A) Omega, a Householder tall-skinny QR of W,
  * a one-sided Jacobi SVD of R and truncation at tau * normA * sqrt(k).  The

@@ -59,6 +59,7 @@ EXPORTS = {
     "azrbf_plan_info": (ctypes.c_int, [_P, ctypes.POINTER(_Info)]),
     "azrbf_apply_A": (ctypes.c_int, [_P, _P, _I64, _I64, _D, _D, _P, _I64, _P]),
     "azrbf_apply_Zstar": (ctypes.c_int, [_P, _P, _I64, _I64, _D, _D, _P, _I64, _P]),
+    "azrbf_apply_AZstar": (ctypes.c_int, [_P, _P, _I64, _I64, _D, _D, _P, _I64, _P]),
     "azrbf_factor": (ctypes.c_int, [_P, _P]),
     "azrbf_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _I64, _P, _P]),
     "azrbf_solve_many": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P),
@@ -223,6 +224,19 @@ def apply_Zstar(p, R, Z=None, alpha=1.0, beta=0.0, stream=None):
     _check(_lib().azrbf_apply_Zstar(p.handle, R.data_ptr(), ldr, nvec, alpha, beta, Z.data_ptr(), ldz,
                                     _stream(stream)), "azrbf_apply_Zstar")
     return Z
+
+
+def apply_AZstar(p, R, Y=None, alpha=1.0, beta=0.0, stream=None):
+    """Y = alpha * A Z* R + beta * Y; R (nvec, M + Mb) -> Y (nvec, M + Mb)."""
+    R, nvec, ldr = _vecs(R, p.Mt, "R")
+    if Y is None:
+        Y = torch.empty((nvec, p.Mt), dtype=torch.float64, device=R.device)
+    Y, nv2, ldy = _vecs(Y, p.Mt, "Y")
+    if nv2 != nvec:
+        raise ValueError("R and Y hold different numbers of vectors")
+    _check(_lib().azrbf_apply_AZstar(p.handle, R.data_ptr(), ldr, nvec, alpha, beta, Y.data_ptr(), ldy,
+                                     _stream(stream)), "azrbf_apply_AZstar")
+    return Y
 
 
 def factor(p, stream=None):

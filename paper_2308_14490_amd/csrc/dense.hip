@@ -683,8 +683,7 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch) {
   int* info = (int*)(tq + tsqr_scratch_doubles(Mt, k));
   AZ_TRY(dense_gaussian(P.prob.seed, N, k, P.Om, N, st));
   AZ_TRY(ops_apply_A(P, P.Om, N, k, 1.0, 0.0, nullptr, 0, P.Yf, Mt, st));     // Y = A Omega
-  AZ_TRY(ops_apply_Z(P, P.Yf, Mt, k, 1.0, 0.0, nullptr, 0, Zy, N, st));       // Z* Y
-  AZ_TRY(ops_apply_A(P, Zy, N, k, -1.0, 1.0, P.Yf, Mt, W, Mt, st));          // W = Y - A Z* Y
+  AZ_TRY(ops_apply_AZ(P, P.Yf, Mt, k, -1.0, 1.0, P.Yf, Mt, W, Mt, Zy, st));  // W = Y - A Z* Y
   // what follows is latency-bound: work on other streams may start here
   if (after_sketch) AZ_HIP(hipEventRecord(after_sketch, st));
   // TSQR destroys W; the QR is of the sketch, W is then free scratch.  The
@@ -762,8 +761,7 @@ int dense_first_stage(Plan& P, const double* B, int64_t ldb, int64_t nrhs, hipSt
   const int64_t N = P.N, Mt = P.Mt;
   double* Zr = P.sw;
   double* C = Zr + N * nrhs;
-  AZ_TRY(ops_apply_Z(P, B, ldb, nrhs, 1.0, 0.0, nullptr, 0, Zr, N, st));
-  AZ_TRY(ops_apply_A(P, Zr, N, nrhs, -1.0, 1.0, B, ldb, C, Mt, st));
+  AZ_TRY(ops_apply_AZ(P, B, ldb, nrhs, -1.0, 1.0, B, ldb, C, Mt, Zr, st));
   return AZRBF_OK;
 }
 
@@ -784,8 +782,7 @@ int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, 
   int64_t ldr = ldb;
   for (int it = 0; it <= P.refine; ++it) {
     if (!(it == 0 && first_done)) {
-      AZ_TRY(ops_apply_Z(P, rin, ldr, nrhs, 1.0, 0.0, nullptr, 0, Zr, N, st));      // Z* r
-      AZ_TRY(ops_apply_A(P, Zr, N, nrhs, -1.0, 1.0, rin, ldr, C, Mt, st));         // c = (I - A Z*) r
+      AZ_TRY(ops_apply_AZ(P, rin, ldr, nrhs, -1.0, 1.0, rin, ldr, C, Mt, Zr, st));   // c = (I - A Z*) r
     }
     AZ_TRY(gemm_mfma_c(true, false, k, nrhs, Mt, 1.0, P.Q, Mt, 0, C, Mt, 0, 0.0, nullptr, 0, 0, Tm, k, 0, 1, part,
                        npart, st));                                                             // t = Q^T c

@@ -16,8 +16,12 @@
 namespace az {
 
 constexpr int RADIX = 16;
-constexpr int TW_LOG = 17;                 // twiddle table covers n <= 2^17
+// Twiddle table: for every n = 2^l <= TW_SIZE the n roots w_n^i =
+// exp(-2 pi i i / n) are stored contiguously at offset n, so the roots one
+// transform length uses share few cache lines (2 * TW_SIZE entries in all).
+constexpr int TW_LOG = 17;
 constexpr int TW_SIZE = 1 << TW_LOG;
+constexpr int TW_ENTRIES = 2 * TW_SIZE;
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
@@ -175,10 +179,9 @@ __device__ __forceinline__ void stockham_pass(double2* a, const Lds& lds, int li
 #pragma unroll
     for (int j = 0; j < RP; ++j) v[j] = a[i + j * C];
     if (p > 1) {
-      const int step = TW_SIZE / (p * RP);
 #pragma unroll
       for (int j = 1; j < RP; ++j) {
-        double2 w = tw[(j * k) * step];
+        double2 w = tw[p * RP + j * k];
         if (INV) w.y = -w.y;
         v[j] = cmul(v[j], w);
       }
@@ -195,10 +198,9 @@ template <int N, bool INV>
 __device__ __forceinline__ void stockham_last(double2* a, int t, const double2* __restrict__ tw) {
   constexpr int P = N / RADIX;
   if (P > 1) {
-    const int step = TW_SIZE / N;
 #pragma unroll
     for (int j = 1; j < RADIX; ++j) {
-      double2 w = tw[(j * t) * step];
+      double2 w = tw[N + j * t];
       if (INV) w.y = -w.y;
       a[j] = cmul(a[j], w);
     }

@@ -85,6 +85,10 @@ int ops_apply_A(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alph
                 const double* Yin, int64_t ldyi, double* Y, int64_t ldy, hipStream_t st);
 int ops_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,
                 const double* Zin, int64_t ldzi, double* Z, int64_t ldz, hipStream_t st);
+// Out = alpha A Z* R + beta Yin (Yin null: Yin = Out); Zs is N x nvec scratch
+// (leading dimension N), overwritten with Z* R when the plan needs it.
+int ops_apply_AZ(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,
+                 const double* Yin, int64_t ldyi, double* Out, int64_t ldo, double* Zs, hipStream_t st);
 
 // tsqr.hip: Householder QR of the RB-row blocks of A (m x k, k in {16, 32,
 // 64}, RB = tsqr_block_rows(k)); R factors stacked at rows b*k of R, the
@@ -204,6 +208,9 @@ struct Plan {
   // solve workspace
   double* sw = nullptr;
   int64_t sw_rhs = 0, sw_part = 0;
+  // coefficient scratch of azrbf_apply_AZstar (N x azs_cols)
+  double* azs = nullptr;
+  int64_t azs_cols = 0;
 
   int alloc(void** p, int64_t bytes);
   void release();

@@ -38,15 +38,17 @@ int ops_init_twiddles(int device, const double2** tw) {
   std::lock_guard<std::mutex> lk(g_tw_mu);
   if (device < 0 || device >= 64) return AZRBF_EINVAL;
   if (!g_tw[device]) {
-    std::vector<double2> h(TW_SIZE);
+    std::vector<double2> h(TW_ENTRIES, make_double2(0.0, 0.0));
     const long double pi = 3.141592653589793238462643383279502884L;
-    for (int i = 0; i < TW_SIZE; ++i) {
-      const long double a = -2.0L * pi * (long double)i / (long double)TW_SIZE;
-      h[i] = make_double2((double)cosl(a), (double)sinl(a));
+    for (int n = 1; n <= TW_SIZE; n *= 2) {
+      for (int i = 0; i < n; ++i) {
+        const long double a = -2.0L * pi * (long double)i / (long double)n;
+        h[n + i] = make_double2((double)cosl(a), (double)sinl(a));
+      }
     }
     double2* d = nullptr;
-    if (hipMalloc(&d, sizeof(double2) * TW_SIZE) != hipSuccess) return AZRBF_ENOMEM;
-    if (hipMemcpy(d, h.data(), sizeof(double2) * TW_SIZE, hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMalloc(&d, sizeof(double2) * TW_ENTRIES) != hipSuccess) return AZRBF_ENOMEM;
+    if (hipMemcpy(d, h.data(), sizeof(double2) * TW_ENTRIES, hipMemcpyHostToDevice) != hipSuccess)
       return AZRBF_EHIP;
     g_tw[device] = d;
   }
@@ -230,8 +232,13 @@ struct Row {
   static constexpr int LMAX = T >= 256 ? 1 : 256 / T;
 };
 
+// w_N^e for the four-step twiddles (N = N1 N2 <= TW_SIZE): for N > 256 the
+// product w_N^(e mod 256) w_(N/256)^(e div 256) of two roots from the short
+// tables at offsets N and N/256, which stay resident in the vector cache.
 __device__ __forceinline__ double2 tw_fwd(const double2* tw, int64_t e, int64_t N) {
-  return tw[(e & (N - 1)) * (TW_SIZE / N)];
+  const int64_t r = e & (N - 1);
+  if (N <= 256) return tw[N + r];
+  return cmul(tw[N + (r & 255)], tw[(N >> 8) + (r >> 8)]);
 }
 
 // P1 of A: column DFT of the coefficient pair array, four-step twiddle.
@@ -401,10 +408,70 @@ k_row_Z(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws1,
   }
 }
 
+// P2 of A Z*: the row pass of Z* (row DFT of each phase, sum of products
+// with w conj(d_r)) followed, without leaving the spectrum, by the row pass
+// of A (product with each phase's d_r', row IDFT).  Z*'s inverse transform and
+// A's forward transform in between cancel (DFT IDFT = N I with the 1/N of
+// the inverse folded into the spectra, hence the factor N), so A Z* costs
+// three passes instead of six.  If zrows is given, Z*'s own row output is
+// stored there as well (its column IDFT gives the coefficients Z* y); it may
+// alias the phase-0 slice of ws1, which each block reads before writing.
+template <int N2, bool TWID>
+__global__ void __launch_bounds__(256)
+k_row_AZ(Geo g, const double2* __restrict__ tw, const double2* ws1, double2* __restrict__ ws2, double2* zrows,
+         int LINES) {
+  constexpr int T = Row<N2>::T;
+  extern __shared__ double2 smem[];
+  const RowLds lds{smem, RowLds::stride(N2)};
+  const int t = threadIdx.x % T, l = threadIdx.x / T;
+  const int64_t k1 = (int64_t)blockIdx.x * LINES + l;
+  const int64_t pair = blockIdx.y;
+  const int nph = g.dim == 1 ? g.s : g.s * g.s;
+  double2 acc[RADIX];
+#pragma unroll
+  for (int m = 0; m < RADIX; ++m) acc[m] = make_double2(0.0, 0.0);
+  for (int ph = 0; ph < nph; ++ph) {
+    double2 a[RADIX];
+    const double2* in = ws1 + (pair * nph + ph) * g.N + k1 * N2;
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) a[m] = in[t + m * T];
+    fft_line<N2, false>(a, lds, l, t, tw);
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) acc[m] = cadd(acc[m], cmul(a[m], specZ(g, ph, (int)k1, t + m * T)));
+  }
+  if (zrows) {
+    double2 b[RADIX];
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) b[m] = acc[m];
+    fft_line<N2, true>(b, lds, l, t, tw);
+    double2* out = zrows + pair * nph * g.N + k1 * N2;
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) {
+      double2 v = b[m];
+      if (TWID) v = cmulc(v, tw_fwd(tw, k1 * (t + m * T), g.N));
+      out[t + m * T] = v;
+    }
+  }
+  const double scale = (double)g.N;
+  for (int ph = 0; ph < nph; ++ph) {
+    double2 b[RADIX];
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) b[m] = cmul(acc[m], cscale(specA(g, ph, (int)k1, t + m * T), scale));
+    fft_line<N2, true>(b, lds, l, t, tw);
+    double2* out = ws2 + (pair * nph + ph) * g.N + k1 * N2;
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) {
+      double2 v = b[m];
+      if (TWID) v = cmulc(v, tw_fwd(tw, k1 * (t + m * T), g.N));
+      out[t + m * T] = v;
+    }
+  }
+}
+
 // P3 of Z*: column IDFT, coefficients out.
 template <int N1>
 __global__ void __launch_bounds__(256)
-k_col_inv_Z(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws2, int64_t nvec,
+k_col_inv_Z(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws2, int64_t pstride, int64_t nvec,
             int64_t pair0, double alpha, double beta, const double* Zin, int64_t ldzi, double* Z, int64_t ldz,
             int C) {
   constexpr int T = Col<N1>::T;
@@ -415,7 +482,7 @@ k_col_inv_Z(Geo g, const double2* __restrict__ tw, const double2* __restrict__ w
   const int64_t pair = blockIdx.y;
   const int64_t v0 = 2 * (pair0 + pair);
   double2 a[RADIX];
-  const double2* in = ws2 + pair * g.N;
+  const double2* in = ws2 + pair * pstride;
 #pragma unroll
   for (int m = 0; m < RADIX; ++m) a[m] = in[(int64_t)(t + m * T) * g.N2 + b];
   fft_line<N1, true>(a, lds, l, t, tw);
@@ -751,6 +818,7 @@ struct ColArgs {
   double* out;
   int64_t ldo;
   hipStream_t st;
+  int64_t pstride = 0;      // mode 3: complex elements between pairs of the input (0: N)
 };
 
 template <int N1>
@@ -812,8 +880,8 @@ static int launch_col(const ColArgs& a) {
       break;
     case 3:
       AZ_TRY(set_lds(k_col_inv_Z<N1>, lds));
-      k_col_inv_Z<N1><<<grid, block, lds, a.st>>>(g, P.tw, a.cin, a.nvec, a.pair0, a.alpha, a.beta, a.oin,
-                                                  a.ldoi, a.out, a.ldo, C);
+      k_col_inv_Z<N1><<<grid, block, lds, a.st>>>(g, P.tw, a.cin, a.pstride ? a.pstride : g.N, a.nvec, a.pair0,
+                                                  a.alpha, a.beta, a.oin, a.ldoi, a.out, a.ldo, C);
       break;
     case 4:
       if (tw4) {
@@ -830,11 +898,12 @@ static int launch_col(const ColArgs& a) {
 
 struct RowArgs {
   const Plan* P;
-  int mode;                 // 0 A, 1 Z, 2 fwd complex in place
+  int mode;                 // 0 A, 1 Z, 2 fwd complex in place, 3 A Z*
   const double2* in;
   double2* out;
   int64_t npairs;
   hipStream_t st;
+  double2* zrows = nullptr; // mode 3: Z*'s row output as well
 };
 
 template <int N2>
@@ -847,14 +916,16 @@ static int launch_row(const RowArgs& a) {
   const dim3 grid((unsigned)(g.N1 / Lr), (unsigned)a.npairs);
   const bool tw4 = g.dim == 1;
   static const std::vector<std::string> full = [] {
-    const char* names[3] = {"row_A", "row_Z", "row_fwd_C"};
+    const char* names[4] = {"row_A", "row_Z", "row_fwd_C", "row_AZ"};
     std::vector<std::string> v;
     for (const char* n : names) v.push_back(std::string(n) + " n2=" + std::to_string(N2));
     return v;
   }();
   const double cN = 16.0 * (double)g.N * (double)a.npairs;
   const double spec = g.dim == 1 ? 16.0 * (double)g.N * P.s : 0.0;
-  const double bytes = a.mode == 2 ? 2.0 * cN : cN * (1.0 + P.ph) + spec;
+  const double bytes = a.mode == 2   ? 2.0 * cN
+                       : a.mode == 3 ? cN * (2.0 * P.ph + (a.zrows ? 1.0 : 0.0)) + 2.0 * spec
+                                     : cN * (1.0 + P.ph) + spec;
   Prof pr(full[a.mode].c_str(), bytes, a.st);
   switch (a.mode) {
     case 0:
@@ -878,6 +949,15 @@ static int launch_row(const RowArgs& a) {
     case 2:
       AZ_TRY(set_lds(k_row_fwd_C<N2>, lds));
       k_row_fwd_C<N2><<<grid, block, lds, a.st>>>(g, P.tw, a.out, Lr);
+      break;
+    case 3:
+      if (tw4) {
+        AZ_TRY(set_lds(k_row_AZ<N2, true>, lds));
+        k_row_AZ<N2, true><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.out, a.zrows, Lr);
+      } else {
+        AZ_TRY(set_lds(k_row_AZ<N2, false>, lds));
+        k_row_AZ<N2, false><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.out, a.zrows, Lr);
+      }
       break;
   }
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
@@ -1048,6 +1128,44 @@ int ops_spectra(Plan& P, hipStream_t st) {
   std::memcpy(&z, &hred[2], sizeof(int));
   P.zeroed = z;
   return AZRBF_OK;
+}
+
+// Out = alpha A Z* R + beta Yin (Yin defaults to Out).  On the engine the
+// product stays in the spectrum between the two operators (k_row_AZ); with
+// boundary rows the coefficients Z* R are formed as well (into Zs, N x nvec,
+// leading dimension N), since those rows of A are applied to coefficients
+// directly.  The fused path applies the two operators in turn through Zs.
+int ops_apply_AZ(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,
+                 const double* Yin, int64_t ldyi, double* Out, int64_t ldo, double* Zs, hipStream_t st) {
+  if (nvec <= 0) return AZRBF_OK;
+  if (!Yin) {
+    Yin = Out;
+    ldyi = ldo;
+  }
+  if (P.fused) {
+    AZ_TRY(ops_apply_Z(P, R, ldr, nvec, 1.0, 0.0, nullptr, 0, Zs, P.N, st));
+    return ops_apply_A(P, Zs, P.N, nvec, alpha, beta, Yin, ldyi, Out, ldo, st);
+  }
+  const int64_t npairs = (nvec + 1) / 2;
+  const int64_t chunk = engine_chunk(P, npairs);
+  AZ_TRY(ensure_ws(P, chunk));
+  const bool coef = P.Mb > 0;
+  for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
+    const int64_t np = npairs - p0 < chunk ? npairs - p0 : chunk;
+    ColArgs c1{&P, 2, R, ldr, nullptr, P.ws1, nvec, p0, np, 0, 0, nullptr, 0, nullptr, 0, st};
+    AZ_TRY(run_col(c1));
+    RowArgs r{&P, 3, P.ws1, P.ws2, np, st, coef ? P.ws1 : nullptr};
+    AZ_TRY(run_row(r));
+    if (coef) {
+      ColArgs cz{&P, 3, nullptr, 0, P.ws1, nullptr, nvec, p0, np, 1.0, 0.0, Zs, P.N, Zs, P.N, st,
+                 (int64_t)P.ph * P.N};
+      AZ_TRY(run_col(cz));
+    }
+    ColArgs c3{&P, 1, nullptr, 0, P.ws2, nullptr, nvec, p0, np, alpha, beta, Yin, ldyi, Out, ldo, st};
+    AZ_TRY(run_col(c3));
+  }
+  if (!coef) return AZRBF_OK;
+  return boundary_rows(P, Zs, P.N, nvec, alpha, beta, Yin, ldyi, Out, ldo, st);
 }
 
 }  // namespace az

@@ -94,13 +94,14 @@ void Plan::release_one(void* ptr) {
 
 // The stream must have drained the factor's work.
 void Plan::release_factor() {
-  double** bufs[] = {&Om, &Om2, &Yf, &Yf2, &Q, &Rf, &sig, &Pm, &Gj, &Vj, &dscr, &sw};
+  double** bufs[] = {&Om, &Om2, &Yf, &Yf2, &Q, &Rf, &sig, &Pm, &Gj, &Vj, &dscr, &sw, &azs};
   for (double** b : bufs) {
     release_one(*b);
     *b = nullptr;
   }
   dscr_bytes = 0;
   sw_rhs = sw_part = 0;
+  azs_cols = 0;
   factored = false;
   rank = -1;
 }
@@ -438,6 +439,26 @@ int azrbf_apply_Zstar(azrbf_plan_t h, const double* R, int64_t ldr, int64_t nvec
   if (!R || !Z || ldr < P.Mt || ldz < P.N) return AZRBF_EINVAL;
   P.last_stream = (hipStream_t)stream;
   return az::ops_apply_Z(P, R, ldr, nvec, alpha, beta, nullptr, 0, Z, ldz, (hipStream_t)stream);
+}
+
+int azrbf_apply_AZstar(azrbf_plan_t h, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,
+                       double* Y, int64_t ldy, void* stream) {
+  if (!h || nvec < 0) return AZRBF_EINVAL;
+  Plan& P = h->p;
+  if (nvec == 0) return AZRBF_OK;
+  if (!R || !Y || ldr < P.Mt || ldy < P.Mt) return AZRBF_EINVAL;
+  if (R == Y && ldr != ldy) return AZRBF_EINVAL;
+  P.last_stream = (hipStream_t)stream;
+  if ((P.fused || P.Mb > 0) && nvec > P.azs_cols) {
+    // the previous scratch may still be in use by queued work on this stream
+    if (P.azs && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return AZRBF_EHIP;
+    P.release_one(P.azs);
+    P.azs = nullptr;
+    P.azs_cols = 0;
+    AZ_TRY(P.alloc((void**)&P.azs, sizeof(double) * P.N * nvec));
+    P.azs_cols = nvec;
+  }
+  return az::ops_apply_AZ(P, R, ldr, nvec, alpha, beta, nullptr, 0, Y, ldy, P.azs, (hipStream_t)stream);
 }
 
 int azrbf_factor(azrbf_plan_t h, void* stream) {

@@ -410,8 +410,7 @@ int wide_factor(Plan& P, hipStream_t st) {
   // 1. sketch
   AZ_TRY(dense_gaussian(P.prob.seed, N, k, P.Om, N, st));
   AZ_TRY(ops_apply_A(P, P.Om, N, k, 1.0, 0.0, nullptr, 0, P.Q, Mt, st));        // Y = A Omega
-  AZ_TRY(ops_apply_Z(P, P.Q, Mt, k, 1.0, 0.0, nullptr, 0, P.Om2, N, st));       // Z* Y
-  AZ_TRY(ops_apply_A(P, P.Om2, N, k, -1.0, 1.0, P.Q, Mt, P.Q, Mt, st));          // W = Y - A Z* Y
+  AZ_TRY(ops_apply_AZ(P, P.Q, Mt, k, -1.0, 1.0, P.Q, Mt, P.Q, Mt, P.Om2, st));  // W = Y - A Z* Y
   // 2. W = Q R
   {
     double* tq = scr + Lx.tsqr;
@@ -553,8 +552,7 @@ int wide_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, i
   const double* rin = B;
   int64_t ldr = ldb;
   for (int it = 0; it <= P.refine; ++it) {
-    AZ_TRY(ops_apply_Z(P, rin, ldr, nrhs, 1.0, 0.0, nullptr, 0, Zr, N, st));                  // Z* r
-    AZ_TRY(ops_apply_A(P, Zr, N, nrhs, -1.0, 1.0, rin, ldr, C, Mt, st));                     // c = (I - A Z*) r
+    AZ_TRY(ops_apply_AZ(P, rin, ldr, nrhs, -1.0, 1.0, rin, ldr, C, Mt, Zr, st));             // c = (I - A Z*) r
     AZ_TRY(gemm_mfma(true, false, k, nrhs, Mt, 1.0, P.Q, Mt, 0, C, Mt, 0, 0.0, Tm, k, 0, 1, part, npart, st));
     AZ_TRY(gemm_mfma(false, false, k, nrhs, k, 1.0, P.Pm, k, 0, Tm, k, 0, 0.0, Ym, k, 0, 1, nullptr, 0, st));
     AZ_TRY(gemm_mfma(false, false, N, nrhs, k, 1.0, P.Om, N, 0, Ym, k, 0, 0.0, X1, N, 0, 1, nullptr, 0, st));

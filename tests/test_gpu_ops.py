@@ -68,6 +68,15 @@ def _case(prob, nvec, ld_pad, engine, seed=0):
     Zd = to_dev(Z0)
     azrbf.apply_Zstar(p, to_dev(R), Zd, alpha=1.0, beta=1.0)
     assert rel_err(Zd, Z0 + wz) < 2 * _tol_Z(prob.N, p)
+    # A Z* (one spectral pass between the operators) and the residual form r - A Z* r
+    waz = wz @ A.T
+    Rd = to_dev(R)
+    AZ = azrbf.apply_AZstar(p, Rd)
+    assert rel_err(AZ, waz) < _tol_Z(prob.N, p), (rel_err(AZ, waz), _tol_Z(prob.N, p))
+    azrbf.apply_AZstar(p, Rd, Rd, alpha=-1.0, beta=1.0)            # in place
+    # (r - A Z* r can be far smaller than r, e.g. without oversampling: error relative to r)
+    err = np.max(np.abs(Rd.cpu().numpy() - (R - waz))) / np.max(np.abs(R))
+    assert err < 2 * _tol_Z(prob.N, p), err
     p.destroy()
 
 
