@@ -23,6 +23,14 @@ constexpr int TW_LOG = 17;
 constexpr int TW_SIZE = 1 << TW_LOG;
 constexpr int TW_ENTRIES = 2 * TW_SIZE;
 
+// v unchanged, but opaque to the optimiser: addresses derived from it inside
+// a loop are recomputed in each iteration instead of being hoisted out and
+// kept live in registers for the whole loop.
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {

@@ -64,6 +64,14 @@ __device__ __forceinline__ int64_t grid_index(const Geo& g, int ph, int64_t a, i
   return ((int64_t)g.s * a + rx) * g.L + (int64_t)g.s * b + ry;
 }
 
+// The same with the oversampling factor as a compile-time constant (S == g.s)
+// and the phase given by its coordinates (1D: rx = 0, ry = phase).
+template <int S>
+__device__ __forceinline__ int64_t grid_index_s(const Geo& g, int rx, int ry, int64_t a, int64_t b) {
+  if (g.dim == 1) return (int64_t)S * (a * g.N2 + b) + ry;
+  return ((int64_t)S * a + rx) * g.L + (int64_t)S * b + ry;
+}
+
 __device__ __forceinline__ int64_t row_of(const Geo& g, int64_t gi) {
   if (g.dim == 1) {
     const int64_t r = gi - g.i0;
@@ -285,23 +293,30 @@ k_row_A(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws1,
   for (int m = 0; m < RADIX; ++m) a[m] = in[t + m * T];
   fft_line<N2, false>(a, lds, l, t, tw);
   for (int ph = 0; ph < nph; ++ph) {
+    const int tt = opaque(t), ll = opaque(l);
+    const int64_t kk = (int64_t)blockIdx.x * LINES + ll;
     double2 b[RADIX];
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) b[m] = cmul(a[m], specA(g, ph, (int)k1, t + m * T));
-    fft_line<N2, true>(b, lds, l, t, tw);
-    double2* out = ws2 + (pair * nph + ph) * g.N + k1 * N2;
+    for (int m = 0; m < RADIX; ++m) b[m] = cmul(a[m], specA(g, ph, (int)kk, tt + m * T));
+    fft_line<N2, true>(b, lds, ll, tt, tw);
+    double2* out = ws2 + (pair * nph + ph) * g.N + kk * N2;
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) {
       double2 v = b[m];
-      if (TWID) v = cmulc(v, tw_fwd(tw, k1 * (t + m * T), g.N));
-      out[t + m * T] = v;
+      if (TWID) v = cmulc(v, tw_fwd(tw, kk * (tt + m * T), g.N));
+      out[tt + m * T] = v;
     }
   }
 }
 
 // P3 of A: column IDFT of every phase, restriction to collocation rows.
-// Phases are taken in groups of S whose fine-grid points are adjacent
-// (1D: all s phases; 2D: the s values of ry for one rx) and stored together.
+// The S phases whose fine-grid points are adjacent (1D: all s phases; 2D:
+// the s values of ry for one rx) are handled by different lines of the same
+// block, phase index fastest: thread line = column * S + phase, so the C*S
+// lines of a block cover C*S consecutive fine-grid points and every load and
+// store instruction of a wave touches contiguous rows, while each thread
+// holds one line (16 values) only.  C here is the number of lines per block;
+// in 2D the s groups of phases (one per rx) are the grid's z dimension.
 template <int N1, int S>
 __global__ void __launch_bounds__(256)
 k_col_inv_A(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws2, int64_t nvec,
@@ -310,33 +325,29 @@ k_col_inv_A(Geo g, const double2* __restrict__ tw, const double2* __restrict__ w
   constexpr int T = Col<N1>::T;
   extern __shared__ double2 smem[];
   const ColLds lds{smem, C};
-  const int l = threadIdx.x % C, t = threadIdx.x / C;
-  const int64_t b = (int64_t)blockIdx.x * C + l;
+  const int line = threadIdx.x % C, t = threadIdx.x / C;
+  const int ry = line % S;
+  const int64_t b = (int64_t)blockIdx.x * (C / S) + line / S;
   const int64_t pair = blockIdx.y;
   const int64_t v0 = 2 * (pair0 + pair);
   const int nph = g.dim == 1 ? S : S * S;
-  for (int gx = 0; gx < nph; gx += S) {
-    double2 res[S][RADIX];
+  const int gx = (int)blockIdx.z * S;     // 2D: one rx (group of S phases) per z index
+  {
+    double2 a[RADIX];
+    const double2* in = ws2 + (pair * nph + gx + ry) * g.N;
 #pragma unroll
-    for (int ry = 0; ry < S; ++ry) {
-      const double2* in = ws2 + (pair * nph + gx + ry) * g.N;
-#pragma unroll
-      for (int m = 0; m < RADIX; ++m) res[ry][m] = in[(int64_t)(t + m * T) * g.N2 + b];
-      fft_line<N1, true>(res[ry], lds, l, t, tw);
-    }
+    for (int m = 0; m < RADIX; ++m) a[m] = in[(int64_t)(t + m * T) * g.N2 + b];
+    fft_line<N1, true>(a, lds, line, t, tw);
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) {
-#pragma unroll
-      for (int ry = 0; ry < S; ++ry) {
-        const int64_t row = row_of(g, grid_index(g, gx + ry, t + m * T, b));
-        if (row >= 0) store_pair(Y, ldy, Yin, ldyi, row, v0, nvec, res[ry][m], alpha, beta);
-      }
+      const int64_t row = row_of(g, grid_index_s<S>(g, gx / S, ry, t + m * T, b));
+      if (row >= 0) store_pair(Y, ldy, Yin, ldyi, row, v0, nvec, a[m], alpha, beta);
     }
   }
 }
 
-// P1 of Z*: extension by zero to each phase grid (phases adjacent on the
-// fine grid loaded together), column DFT, twiddle.
+// P1 of Z*: extension by zero to each phase grid, column DFT, twiddle; lines
+// laid out as in k_col_inv_A (phase fastest, one line per thread).
 template <int N1, bool TWID, int S>
 __global__ void __launch_bounds__(256)
 k_col_fwd_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R, int64_t ldr,
@@ -344,32 +355,28 @@ k_col_fwd_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R,
   constexpr int T = Col<N1>::T;
   extern __shared__ double2 smem[];
   const ColLds lds{smem, C};
-  const int l = threadIdx.x % C, t = threadIdx.x / C;
-  const int64_t b = (int64_t)blockIdx.x * C + l;
+  const int line = threadIdx.x % C, t = threadIdx.x / C;
+  const int ry = line % S;
+  const int64_t b = (int64_t)blockIdx.x * (C / S) + line / S;
   const int64_t pair = blockIdx.y;
   const int64_t v0 = 2 * (pair0 + pair);
   const int nph = g.dim == 1 ? S : S * S;
-  for (int gx = 0; gx < nph; gx += S) {
-    double2 in[S][RADIX];
+  const int gx = (int)blockIdx.z * S;     // 2D: one rx (group of S phases) per z index
+  {
+    double2 a[RADIX];
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) {
-#pragma unroll
-      for (int ry = 0; ry < S; ++ry) {
-        const int64_t row = row_of(g, grid_index(g, gx + ry, t + m * T, b));
-        in[ry][m] = row >= 0 ? load_pair(R, ldr, row, v0, nvec) : make_double2(0.0, 0.0);
-      }
+      const int64_t row = row_of(g, grid_index_s<S>(g, gx / S, ry, t + m * T, b));
+      a[m] = row >= 0 ? load_pair(R, ldr, row, v0, nvec) : make_double2(0.0, 0.0);
     }
+    fft_line<N1, false>(a, lds, line, t, tw);
+    double2* out = ws1 + (pair * nph + gx + ry) * g.N;
 #pragma unroll
-    for (int ry = 0; ry < S; ++ry) {
-      fft_line<N1, false>(in[ry], lds, l, t, tw);
-      double2* out = ws1 + (pair * nph + gx + ry) * g.N;
-#pragma unroll
-      for (int m = 0; m < RADIX; ++m) {
-        const int64_t k1 = t + m * T;
-        double2 v = in[ry][m];
-        if (TWID) v = cmul(v, tw_fwd(tw, k1 * b, g.N));
-        out[k1 * g.N2 + b] = v;
-      }
+    for (int m = 0; m < RADIX; ++m) {
+      const int64_t k1 = t + m * T;
+      double2 v = a[m];
+      if (TWID) v = cmul(v, tw_fwd(tw, k1 * b, g.N));
+      out[k1 * g.N2 + b] = v;
     }
   }
 }
@@ -390,13 +397,15 @@ k_row_Z(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws1,
 #pragma unroll
   for (int m = 0; m < RADIX; ++m) acc[m] = make_double2(0.0, 0.0);
   for (int ph = 0; ph < nph; ++ph) {
+    const int tt = opaque(t), ll = opaque(l);
+    const int64_t kk = (int64_t)blockIdx.x * LINES + ll;
     double2 a[RADIX];
-    const double2* in = ws1 + (pair * nph + ph) * g.N + k1 * N2;
+    const double2* in = ws1 + (pair * nph + ph) * g.N + kk * N2;
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) a[m] = in[t + m * T];
-    fft_line<N2, false>(a, lds, l, t, tw);
+    for (int m = 0; m < RADIX; ++m) a[m] = in[tt + m * T];
+    fft_line<N2, false>(a, lds, ll, tt, tw);
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) acc[m] = cadd(acc[m], cmul(a[m], specZ(g, ph, (int)k1, t + m * T)));
+    for (int m = 0; m < RADIX; ++m) acc[m] = cadd(acc[m], cmul(a[m], specZ(g, ph, (int)kk, tt + m * T)));
   }
   fft_line<N2, true>(acc, lds, l, t, tw);
   double2* out = ws2 + pair * g.N + k1 * N2;
@@ -431,13 +440,15 @@ k_row_AZ(Geo g, const double2* __restrict__ tw, const double2* ws1, double2* __r
 #pragma unroll
   for (int m = 0; m < RADIX; ++m) acc[m] = make_double2(0.0, 0.0);
   for (int ph = 0; ph < nph; ++ph) {
+    const int tt = opaque(t), ll = opaque(l);
+    const int64_t kk = (int64_t)blockIdx.x * LINES + ll;
     double2 a[RADIX];
-    const double2* in = ws1 + (pair * nph + ph) * g.N + k1 * N2;
+    const double2* in = ws1 + (pair * nph + ph) * g.N + kk * N2;
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) a[m] = in[t + m * T];
-    fft_line<N2, false>(a, lds, l, t, tw);
+    for (int m = 0; m < RADIX; ++m) a[m] = in[tt + m * T];
+    fft_line<N2, false>(a, lds, ll, tt, tw);
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) acc[m] = cadd(acc[m], cmul(a[m], specZ(g, ph, (int)k1, t + m * T)));
+    for (int m = 0; m < RADIX; ++m) acc[m] = cadd(acc[m], cmul(a[m], specZ(g, ph, (int)kk, tt + m * T)));
   }
   if (zrows) {
     double2 b[RADIX];
@@ -454,16 +465,18 @@ k_row_AZ(Geo g, const double2* __restrict__ tw, const double2* ws1, double2* __r
   }
   const double scale = (double)g.N;
   for (int ph = 0; ph < nph; ++ph) {
+    const int tt = opaque(t), ll = opaque(l);
+    const int64_t kk = (int64_t)blockIdx.x * LINES + ll;
     double2 b[RADIX];
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) b[m] = cmul(acc[m], cscale(specA(g, ph, (int)k1, t + m * T), scale));
-    fft_line<N2, true>(b, lds, l, t, tw);
-    double2* out = ws2 + (pair * nph + ph) * g.N + k1 * N2;
+    for (int m = 0; m < RADIX; ++m) b[m] = cmul(acc[m], cscale(specA(g, ph, (int)kk, tt + m * T), scale));
+    fft_line<N2, true>(b, lds, ll, tt, tw);
+    double2* out = ws2 + (pair * nph + ph) * g.N + kk * N2;
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) {
       double2 v = b[m];
-      if (TWID) v = cmulc(v, tw_fwd(tw, k1 * (t + m * T), g.N));
-      out[t + m * T] = v;
+      if (TWID) v = cmulc(v, tw_fwd(tw, kk * (tt + m * T), g.N));
+      out[tt + m * T] = v;
     }
   }
 }
@@ -829,6 +842,13 @@ static int launch_col(const ColArgs& a) {
   const int block = C * Col<N1>::T;
   const int lds = C * N1 * (int)sizeof(double2);
   const dim3 grid((unsigned)(g.N2 / C), (unsigned)a.npairs);
+  // modes 1 and 2 spread the s phases of a column over s lines of the block:
+  // C lines are C / s columns (at least one column, then s lines)
+  const int S = g.s;
+  const int Cp = C >= S ? C : S;
+  const int block_p = Cp * Col<N1>::T;
+  const int lds_p = Cp * N1 * (int)sizeof(double2);
+  const dim3 grid_p((unsigned)(g.N2 / (Cp / S)), (unsigned)a.npairs, (unsigned)(g.dim == 1 ? 1 : S));
   const bool tw4 = g.dim == 1;
   // built once per instantiation (thread-safe static initialisation)
   static const std::vector<std::string> full = [] {
@@ -861,16 +881,16 @@ static int launch_col(const ColArgs& a) {
       break;
     case 1:
 #define AZ_COLINV(S)                                                                                    \
-  AZ_TRY(set_lds(k_col_inv_A<N1, S>, lds));                                                             \
-  k_col_inv_A<N1, S><<<grid, block, lds, a.st>>>(g, P.tw, a.cin, a.nvec, a.pair0, a.alpha, a.beta, a.oin, \
-                                                 a.ldoi, a.out, a.ldo, C);
+  AZ_TRY(set_lds(k_col_inv_A<N1, S>, lds_p));                                                           \
+  k_col_inv_A<N1, S><<<grid_p, block_p, lds_p, a.st>>>(g, P.tw, a.cin, a.nvec, a.pair0, a.alpha, a.beta,  \
+                                                       a.oin, a.ldoi, a.out, a.ldo, Cp);
       if (g.s == 1) { AZ_COLINV(1) } else if (g.s == 2) { AZ_COLINV(2) } else { AZ_COLINV(4) }
 #undef AZ_COLINV
       break;
     case 2:
 #define AZ_COLFZ(TW, S)                                                                                 \
-  AZ_TRY(set_lds(k_col_fwd_Z<N1, TW, S>, lds));                                                         \
-  k_col_fwd_Z<N1, TW, S><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.ldi, a.nvec, a.pair0, a.cout, C);
+  AZ_TRY(set_lds(k_col_fwd_Z<N1, TW, S>, lds_p));                                                       \
+  k_col_fwd_Z<N1, TW, S><<<grid_p, block_p, lds_p, a.st>>>(g, P.tw, a.in, a.ldi, a.nvec, a.pair0, a.cout, Cp);
       if (tw4) {
         if (g.s == 1) { AZ_COLFZ(true, 1) } else if (g.s == 2) { AZ_COLFZ(true, 2) } else { AZ_COLFZ(true, 4) }
       } else {
