@@ -30,6 +30,12 @@ __device__ __forceinline__ int opaque(int v) {
   asm volatile("" : "+v"(v));
   return v;
 }
+// The same, available only once dep has been computed: loads addressed from
+// the result wait for dep instead of being issued ahead of it.
+__device__ __forceinline__ int opaque_after(int v, double dep) {
+  asm volatile("" : "+v"(v) : "v"(dep));
+  return v;
+}
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }

@@ -66,10 +66,19 @@ __device__ __forceinline__ int64_t grid_index(const Geo& g, int ph, int64_t a, i
 
 // The same with the oversampling factor as a compile-time constant (S == g.s)
 // and the phase given by its coordinates (1D: rx = 0, ry = phase).
-template <int S>
+template <int S, bool D1>
 __device__ __forceinline__ int64_t grid_index_s(const Geo& g, int rx, int ry, int64_t a, int64_t b) {
-  if (g.dim == 1) return (int64_t)S * (a * g.N2 + b) + ry;
-  return ((int64_t)S * a + rx) * g.L + (int64_t)S * b + ry;
+  if constexpr (D1) return (int64_t)S * (a * g.N2 + b) + ry;
+  else return ((int64_t)S * a + rx) * g.L + (int64_t)S * b + ry;
+}
+template <bool D1>
+__device__ __forceinline__ int64_t row_of_d(const Geo& g, int64_t gi) {
+  if constexpr (D1) {
+    const int64_t r = gi - g.i0;
+    return (r >= 0 && r < g.M) ? r : -1;
+  } else {
+    return g.inv[gi];
+  }
 }
 
 __device__ __forceinline__ int64_t row_of(const Geo& g, int64_t gi) {
@@ -91,6 +100,19 @@ __device__ __forceinline__ double2 spec2d(const Geo& g, int ph, int ka, int kb) 
   const double2 d00 = cmul(x0, y0);
   double2 d = cadd(cadd(cmul(x2, y0), cmul(x0, y2)), cscale(d00, g.k2));
   return cscale(d, g.opscale);
+}
+
+// Engine kernels know the dimension at compile time (D1: 1D); the other
+// dimension's code is then not compiled into them.
+template <bool D1>
+__device__ __forceinline__ double2 specA_d(const Geo& g, int ph, int ka, int kb) {
+  if constexpr (D1) return g.spA[(int64_t)ph * g.N + (int64_t)ka * g.N2 + kb];
+  else return cscale(spec2d(g, ph, ka, kb), 1.0 / (double)g.N);
+}
+template <bool D1>
+__device__ __forceinline__ double2 specZ_d(const Geo& g, int ph, int ka, int kb) {
+  if constexpr (D1) return g.spZ[(int64_t)ph * g.N + (int64_t)ka * g.N2 + kb];
+  else return cscale(cconj(spec2d(g, ph, ka, kb)), g.w2[(int64_t)ka * g.N2 + kb]);
 }
 
 __device__ __forceinline__ double2 specA(const Geo& g, int ph, int ka, int kb) {
@@ -275,29 +297,126 @@ k_col_fwd_A(Geo g, const double2* __restrict__ tw, const double* __restrict__ X,
   }
 }
 
-// P2 of A: row DFT, product with each phase's spectrum, row IDFT.
-template <int N2, bool TWID>
+// Row passes (P2).  A: row DFT, product with each phase's spectrum d_r,
+// row IDFT per phase.  Z*: row DFT of each phase, sum of the products with
+// w conj(d_r), one row IDFT.  A Z*: Z*'s sum followed, without leaving the
+// spectrum, by A's per-phase products and IDFTs: Z*'s inverse transform and
+// A's forward transform in between cancel (DFT IDFT = N I, the 1/N of the
+// inverse being folded into the spectra, hence the factor N), so A Z* costs
+// three passes instead of six; if zrows is given, Z*'s own row output is
+// stored as well (its column IDFT gives the coefficients Z* y; it may alias
+// the phase-0 slice of ws1, which each block reads before writing).
+//
+// The phases of a row are spread over PL lines of the block (PL divides the
+// number of phases; line q takes phases q, q + PL, ...), so that a thread
+// holds one line of 16 values; the lines of a row combine through LDS (Z*:
+// sum of the partial sums; A: line 0's forward transform is shared).
+// LINES is the number of lines per block (rows per block times PL); ONE:
+// PL equals the number of phases (one phase per line, no loops: nothing but
+// the line itself is live across a transform).
+constexpr int ROW_A = 0, ROW_Z = 1, ROW_AZ = 2, ROW_AZC = 3;   // AZC: A Z* with zrows
+
+template <int N2, bool TWID, int PL, int MODE, bool ONE>
 __global__ void __launch_bounds__(256)
-k_row_A(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws1,
-        double2* __restrict__ ws2, int LINES) {
+k_row(Geo g, const double2* __restrict__ tw, const double2* ws1, double2* __restrict__ ws2, double2* zrows,
+      int LINES) {
   constexpr int T = Row<N2>::T;
   extern __shared__ double2 smem[];
   const RowLds lds{smem, RowLds::stride(N2)};
   const int t = threadIdx.x % T, l = threadIdx.x / T;
-  const int64_t k1 = (int64_t)blockIdx.x * LINES + l;
+  const int q = l % PL;
+  const int64_t k1 = (int64_t)blockIdx.x * (LINES / PL) + l / PL;
   const int64_t pair = blockIdx.y;
-  const int nph = g.dim == 1 ? g.s : g.s * g.s;
-  double2 a[RADIX];
-  const double2* in = ws1 + pair * g.N + k1 * N2;
+  const int nph = TWID ? g.s : g.s * g.s;
+  double2 acc[RADIX];
+  if (MODE == ROW_A) {
+    const double2* in = ws1 + pair * g.N + k1 * N2;
 #pragma unroll
-  for (int m = 0; m < RADIX; ++m) a[m] = in[t + m * T];
-  fft_line<N2, false>(a, lds, l, t, tw);
-  for (int ph = 0; ph < nph; ++ph) {
-    const int tt = opaque(t), ll = opaque(l);
-    const int64_t kk = (int64_t)blockIdx.x * LINES + ll;
+    for (int m = 0; m < RADIX; ++m) acc[m] = q == 0 ? in[t + m * T] : make_double2(0.0, 0.0);
+    fft_line<N2, false>(acc, lds, l, t, tw);
+  } else if (ONE) {
+    const double2* in = ws1 + (pair * nph + q) * g.N + k1 * N2;
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) acc[m] = in[t + m * T];
+    fft_line<N2, false>(acc, lds, l, t, tw);
+    const int tt = opaque(t);
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) acc[m] = cmul(acc[m], specZ_d<TWID>(g, q, (int)k1, tt + m * T));
+  } else {
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) acc[m] = make_double2(0.0, 0.0);
+    for (int ph = q; ph < nph; ph += PL) {
+      const int tt = opaque(t), ll = opaque(l);
+      const int64_t kk = (int64_t)blockIdx.x * (LINES / PL) + ll / PL;
+      double2 a[RADIX];
+      const double2* in = ws1 + (pair * nph + ph) * g.N + kk * N2;
+#pragma unroll
+      for (int m = 0; m < RADIX; ++m) a[m] = in[tt + m * T];
+      fft_line<N2, false>(a, lds, ll, tt, tw);
+#pragma unroll
+      for (int m = 0; m < RADIX; ++m) acc[m] = cadd(acc[m], cmul(a[m], specZ_d<TWID>(g, ph, (int)kk, tt + m * T)));
+    }
+  }
+  if (PL > 1) {   // combine the lines of the row (the transform's last barrier left LDS free)
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) lds.at(l, t + m * T) = acc[m];
+    __syncthreads();
+    // in groups of four values, each group's reads issued after the previous
+    // group's sums, so that few LDS reads are in flight at once
+    int tq = t;
+#pragma unroll
+    for (int m0 = 0; m0 < RADIX; m0 += 4) {
+#pragma unroll
+      for (int m = m0; m < m0 + 4; ++m) {
+        if (MODE == ROW_A) {
+          acc[m] = lds.at(l - q, tq + m * T);
+        } else {   // the same order of summation on every line of the row
+          double2 v = lds.at(l - q, tq + m * T);
+#pragma unroll
+          for (int j = 1; j < PL; ++j) v = cadd(v, lds.at(l - q + j, tq + m * T));
+          acc[m] = v;
+        }
+      }
+      tq = opaque_after(tq, acc[m0 + 3].x);
+    }
+    __syncthreads();
+  }
+  if (MODE == ROW_Z || MODE == ROW_AZC) {
     double2 b[RADIX];
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) b[m] = cmul(a[m], specA(g, ph, (int)kk, tt + m * T));
+    for (int m = 0; m < RADIX; ++m) b[m] = acc[m];
+    fft_line<N2, true>(b, lds, l, t, tw);
+    if (q == 0) {
+      double2* out = (MODE == ROW_Z ? ws2 + pair * g.N : zrows + pair * nph * g.N) + k1 * N2;
+#pragma unroll
+      for (int m = 0; m < RADIX; ++m) {
+        double2 v = b[m];
+        if (TWID) v = cmulc(v, tw_fwd(tw, k1 * (t + m * T), g.N));
+        out[t + m * T] = v;
+      }
+    }
+  }
+  if (MODE == ROW_Z) return;
+  const double scale = MODE == ROW_A ? 1.0 : (double)g.N;
+  if (ONE) {
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) acc[m] = cmul(acc[m], cscale(specA_d<TWID>(g, q, (int)k1, t + m * T), scale));
+    fft_line<N2, true>(acc, lds, l, t, tw);
+    double2* out = ws2 + (pair * nph + q) * g.N + k1 * N2;
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) {
+      double2 v = acc[m];
+      if (TWID) v = cmulc(v, tw_fwd(tw, k1 * (t + m * T), g.N));
+      out[t + m * T] = v;
+    }
+    return;
+  }
+  for (int ph = q; ph < nph; ph += PL) {
+    const int tt = opaque(t), ll = opaque(l);
+    const int64_t kk = (int64_t)blockIdx.x * (LINES / PL) + ll / PL;
+    double2 b[RADIX];
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) b[m] = cmul(acc[m], cscale(specA_d<TWID>(g, ph, (int)kk, tt + m * T), scale));
     fft_line<N2, true>(b, lds, ll, tt, tw);
     double2* out = ws2 + (pair * nph + ph) * g.N + kk * N2;
 #pragma unroll
@@ -317,7 +436,7 @@ k_row_A(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws1,
 // store instruction of a wave touches contiguous rows, while each thread
 // holds one line (16 values) only.  C here is the number of lines per block;
 // in 2D the s groups of phases (one per rx) are the grid's z dimension.
-template <int N1, int S>
+template <int N1, int S, bool D1>
 __global__ void __launch_bounds__(256)
 k_col_inv_A(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws2, int64_t nvec,
             int64_t pair0, double alpha, double beta, const double* Yin, int64_t ldyi, double* Y, int64_t ldy,
@@ -340,7 +459,7 @@ k_col_inv_A(Geo g, const double2* __restrict__ tw, const double2* __restrict__ w
     fft_line<N1, true>(a, lds, line, t, tw);
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) {
-      const int64_t row = row_of(g, grid_index_s<S>(g, gx / S, ry, t + m * T, b));
+      const int64_t row = row_of_d<D1>(g, grid_index_s<S, D1>(g, gx / S, ry, t + m * T, b));
       if (row >= 0) store_pair(Y, ldy, Yin, ldyi, row, v0, nvec, a[m], alpha, beta);
     }
   }
@@ -366,7 +485,7 @@ k_col_fwd_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R,
     double2 a[RADIX];
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) {
-      const int64_t row = row_of(g, grid_index_s<S>(g, gx / S, ry, t + m * T, b));
+      const int64_t row = row_of_d<TWID>(g, grid_index_s<S, TWID>(g, gx / S, ry, t + m * T, b));
       a[m] = row >= 0 ? load_pair(R, ldr, row, v0, nvec) : make_double2(0.0, 0.0);
     }
     fft_line<N1, false>(a, lds, line, t, tw);
@@ -377,106 +496,6 @@ k_col_fwd_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R,
       double2 v = a[m];
       if (TWID) v = cmul(v, tw_fwd(tw, k1 * b, g.N));
       out[k1 * g.N2 + b] = v;
-    }
-  }
-}
-
-// P2 of Z*: row DFT of each phase, sum of products with w conj(d_r), row IDFT.
-template <int N2, bool TWID>
-__global__ void __launch_bounds__(256)
-k_row_Z(Geo g, const double2* __restrict__ tw, const double2* __restrict__ ws1,
-        double2* __restrict__ ws2, int LINES) {
-  constexpr int T = Row<N2>::T;
-  extern __shared__ double2 smem[];
-  const RowLds lds{smem, RowLds::stride(N2)};
-  const int t = threadIdx.x % T, l = threadIdx.x / T;
-  const int64_t k1 = (int64_t)blockIdx.x * LINES + l;
-  const int64_t pair = blockIdx.y;
-  const int nph = g.dim == 1 ? g.s : g.s * g.s;
-  double2 acc[RADIX];
-#pragma unroll
-  for (int m = 0; m < RADIX; ++m) acc[m] = make_double2(0.0, 0.0);
-  for (int ph = 0; ph < nph; ++ph) {
-    const int tt = opaque(t), ll = opaque(l);
-    const int64_t kk = (int64_t)blockIdx.x * LINES + ll;
-    double2 a[RADIX];
-    const double2* in = ws1 + (pair * nph + ph) * g.N + kk * N2;
-#pragma unroll
-    for (int m = 0; m < RADIX; ++m) a[m] = in[tt + m * T];
-    fft_line<N2, false>(a, lds, ll, tt, tw);
-#pragma unroll
-    for (int m = 0; m < RADIX; ++m) acc[m] = cadd(acc[m], cmul(a[m], specZ(g, ph, (int)kk, tt + m * T)));
-  }
-  fft_line<N2, true>(acc, lds, l, t, tw);
-  double2* out = ws2 + pair * g.N + k1 * N2;
-#pragma unroll
-  for (int m = 0; m < RADIX; ++m) {
-    double2 v = acc[m];
-    if (TWID) v = cmulc(v, tw_fwd(tw, k1 * (t + m * T), g.N));
-    out[t + m * T] = v;
-  }
-}
-
-// P2 of A Z*: the row pass of Z* (row DFT of each phase, sum of products
-// with w conj(d_r)) followed, without leaving the spectrum, by the row pass
-// of A (product with each phase's d_r', row IDFT).  Z*'s inverse transform and
-// A's forward transform in between cancel (DFT IDFT = N I with the 1/N of
-// the inverse folded into the spectra, hence the factor N), so A Z* costs
-// three passes instead of six.  If zrows is given, Z*'s own row output is
-// stored there as well (its column IDFT gives the coefficients Z* y); it may
-// alias the phase-0 slice of ws1, which each block reads before writing.
-template <int N2, bool TWID>
-__global__ void __launch_bounds__(256)
-k_row_AZ(Geo g, const double2* __restrict__ tw, const double2* ws1, double2* __restrict__ ws2, double2* zrows,
-         int LINES) {
-  constexpr int T = Row<N2>::T;
-  extern __shared__ double2 smem[];
-  const RowLds lds{smem, RowLds::stride(N2)};
-  const int t = threadIdx.x % T, l = threadIdx.x / T;
-  const int64_t k1 = (int64_t)blockIdx.x * LINES + l;
-  const int64_t pair = blockIdx.y;
-  const int nph = g.dim == 1 ? g.s : g.s * g.s;
-  double2 acc[RADIX];
-#pragma unroll
-  for (int m = 0; m < RADIX; ++m) acc[m] = make_double2(0.0, 0.0);
-  for (int ph = 0; ph < nph; ++ph) {
-    const int tt = opaque(t), ll = opaque(l);
-    const int64_t kk = (int64_t)blockIdx.x * LINES + ll;
-    double2 a[RADIX];
-    const double2* in = ws1 + (pair * nph + ph) * g.N + kk * N2;
-#pragma unroll
-    for (int m = 0; m < RADIX; ++m) a[m] = in[tt + m * T];
-    fft_line<N2, false>(a, lds, ll, tt, tw);
-#pragma unroll
-    for (int m = 0; m < RADIX; ++m) acc[m] = cadd(acc[m], cmul(a[m], specZ(g, ph, (int)kk, tt + m * T)));
-  }
-  if (zrows) {
-    double2 b[RADIX];
-#pragma unroll
-    for (int m = 0; m < RADIX; ++m) b[m] = acc[m];
-    fft_line<N2, true>(b, lds, l, t, tw);
-    double2* out = zrows + pair * nph * g.N + k1 * N2;
-#pragma unroll
-    for (int m = 0; m < RADIX; ++m) {
-      double2 v = b[m];
-      if (TWID) v = cmulc(v, tw_fwd(tw, k1 * (t + m * T), g.N));
-      out[t + m * T] = v;
-    }
-  }
-  const double scale = (double)g.N;
-  for (int ph = 0; ph < nph; ++ph) {
-    const int tt = opaque(t), ll = opaque(l);
-    const int64_t kk = (int64_t)blockIdx.x * LINES + ll;
-    double2 b[RADIX];
-#pragma unroll
-    for (int m = 0; m < RADIX; ++m) b[m] = cmul(acc[m], cscale(specA(g, ph, (int)kk, tt + m * T), scale));
-    fft_line<N2, true>(b, lds, ll, tt, tw);
-    double2* out = ws2 + (pair * nph + ph) * g.N + kk * N2;
-#pragma unroll
-    for (int m = 0; m < RADIX; ++m) {
-      double2 v = b[m];
-      if (TWID) v = cmulc(v, tw_fwd(tw, kk * (tt + m * T), g.N));
-      out[tt + m * T] = v;
     }
   }
 }
@@ -880,11 +899,15 @@ static int launch_col(const ColArgs& a) {
       }
       break;
     case 1:
-#define AZ_COLINV(S)                                                                                    \
-  AZ_TRY(set_lds(k_col_inv_A<N1, S>, lds_p));                                                           \
-  k_col_inv_A<N1, S><<<grid_p, block_p, lds_p, a.st>>>(g, P.tw, a.cin, a.nvec, a.pair0, a.alpha, a.beta,  \
-                                                       a.oin, a.ldoi, a.out, a.ldo, Cp);
-      if (g.s == 1) { AZ_COLINV(1) } else if (g.s == 2) { AZ_COLINV(2) } else { AZ_COLINV(4) }
+#define AZ_COLINV(S, D1)                                                                                \
+  AZ_TRY(set_lds(k_col_inv_A<N1, S, D1>, lds_p));                                                       \
+  k_col_inv_A<N1, S, D1><<<grid_p, block_p, lds_p, a.st>>>(g, P.tw, a.cin, a.nvec, a.pair0, a.alpha,      \
+                                                           a.beta, a.oin, a.ldoi, a.out, a.ldo, Cp);
+      if (tw4) {
+        if (g.s == 1) { AZ_COLINV(1, true) } else if (g.s == 2) { AZ_COLINV(2, true) } else { AZ_COLINV(4, true) }
+      } else {
+        if (g.s == 1) { AZ_COLINV(1, false) } else if (g.s == 2) { AZ_COLINV(2, false) } else { AZ_COLINV(4, false) }
+      }
 #undef AZ_COLINV
       break;
     case 2:
@@ -947,40 +970,39 @@ static int launch_row(const RowArgs& a) {
                        : a.mode == 3 ? cN * (2.0 * P.ph + (a.zrows ? 1.0 : 0.0)) + 2.0 * spec
                                      : cN * (1.0 + P.ph) + spec;
   Prof pr(full[a.mode].c_str(), bytes, a.st);
-  switch (a.mode) {
-    case 0:
-      if (tw4) {
-        AZ_TRY(set_lds(k_row_A<N2, true>, lds));
-        k_row_A<N2, true><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.out, Lr);
-      } else {
-        AZ_TRY(set_lds(k_row_A<N2, false>, lds));
-        k_row_A<N2, false><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.out, Lr);
-      }
-      break;
-    case 1:
-      if (tw4) {
-        AZ_TRY(set_lds(k_row_Z<N2, true>, lds));
-        k_row_Z<N2, true><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.out, Lr);
-      } else {
-        AZ_TRY(set_lds(k_row_Z<N2, false>, lds));
-        k_row_Z<N2, false><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.out, Lr);
-      }
-      break;
-    case 2:
-      AZ_TRY(set_lds(k_row_fwd_C<N2>, lds));
-      k_row_fwd_C<N2><<<grid, block, lds, a.st>>>(g, P.tw, a.out, Lr);
-      break;
-    case 3:
-      if (tw4) {
-        AZ_TRY(set_lds(k_row_AZ<N2, true>, lds));
-        k_row_AZ<N2, true><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.out, a.zrows, Lr);
-      } else {
-        AZ_TRY(set_lds(k_row_AZ<N2, false>, lds));
-        k_row_AZ<N2, false><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.out, a.zrows, Lr);
-      }
-      break;
+  if (a.mode == 2) {
+    AZ_TRY(set_lds(k_row_fwd_C<N2>, lds));
+    k_row_fwd_C<N2><<<grid, block, lds, a.st>>>(g, P.tw, a.out, Lr);
+    return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
   }
-  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+  // phases spread over PL lines per row (PL divides the phase count; PL * T <= 128)
+  const int PL = P.ph < 4 ? P.ph : 4;
+  const int lines = Lr > PL ? Lr : PL;
+  const int block_p = lines * Row<N2>::T;
+  const int lds_p = lines * RowLds::stride(N2) * (int)sizeof(double2);
+  const dim3 grid_p((unsigned)(g.N1 / (lines / PL)), (unsigned)a.npairs);
+  const int mode = a.mode == 0 ? ROW_A : a.mode == 1 ? ROW_Z : a.zrows ? ROW_AZC : ROW_AZ;
+  auto go = [&](auto kern) -> int {
+    AZ_TRY(set_lds(kern, lds_p));
+    kern<<<grid_p, block_p, lds_p, a.st>>>(g, P.tw, a.in, a.out, a.zrows, lines);
+    return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+  };
+#define AZ_ROWK(TW, PLV, ONEV)                                                        \
+  if (mode == ROW_A) return go(k_row<N2, TW, PLV, ROW_A, ONEV>);                      \
+  if (mode == ROW_Z) return go(k_row<N2, TW, PLV, ROW_Z, ONEV>);                      \
+  if (mode == ROW_AZ) return go(k_row<N2, TW, PLV, ROW_AZ, ONEV>);                    \
+  return go(k_row<N2, TW, PLV, ROW_AZC, ONEV>);
+  // 1D: s phases, one per line; 2D: s^2 phases, one per line up to s = 2
+  if (tw4) {
+    if (PL == 1) { AZ_ROWK(true, 1, true) }
+    if (PL == 2) { AZ_ROWK(true, 2, true) }
+    AZ_ROWK(true, 4, true)
+  }
+  if (PL == 1) { AZ_ROWK(false, 1, true) }
+  if (P.ph == 4) { AZ_ROWK(false, 4, true) }
+  if (P.ph == 2) { AZ_ROWK(false, 2, true) }
+  AZ_ROWK(false, 4, false)
+#undef AZ_ROWK
 }
 
 static int run_col(const ColArgs& a) { AZ_SWITCH_ENGINE(a.P->geo.N1, launch_col, a) }
