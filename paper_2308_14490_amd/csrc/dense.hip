@@ -479,31 +479,39 @@ int launch_jacobi(const double* R, int k, double thr, double tol, int max_sweeps
 // ------------------------------------------------------------------ skinny GEMMs
 
 // Out = alpha * A B + beta * Cin; A is m x k (ld lda), B is k x ncol (ld ldb,
-// small), Out/Cin m x ncol.  Each thread owns one row and up to 16 columns.
+// small), Out/Cin m x ncol.  Each thread owns one row and up to NC columns;
+// B is staged in LDS with the columns of one reduction index contiguous.
+// (NC = 16 is the default: more blocks in flight beat streaming A once with
+// 64 accumulators per thread, measured on the 65536 x 32 by 32 x 64 case.)
 // Out may alias Cin (each element is read and written by the same thread).
+template <int NC>
 __global__ void __launch_bounds__(256)
 k_gemm_nn(const double* __restrict__ A, int64_t lda, int64_t m, int k, const double* __restrict__ B, int64_t ldb,
           int64_t ncol, double alpha, const double* Cin, int64_t ldci, double beta, double* Out, int64_t ldo) {
-  __shared__ double bs[KMAX * 16];
+  __shared__ double bs[KMAX * NC];   // bs[c * NC + v] = B(c, v0 + v)
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t v0 = (int64_t)blockIdx.y * 16;
-  const int nv = (int)std::min<int64_t>(16, ncol - v0);
-  for (int e = threadIdx.x; e < k * 16; e += blockDim.x) {
+  const int64_t v0 = (int64_t)blockIdx.y * NC;
+  const int nv = (int)std::min<int64_t>(NC, ncol - v0);
+  for (int e = threadIdx.x; e < k * NC; e += blockDim.x) {
     const int c = e % k, v = e / k;
-    bs[v * KMAX + c] = v < nv ? B[c + ldb * (v0 + v)] : 0.0;
+    bs[c * NC + v] = v < nv ? B[c + ldb * (v0 + v)] : 0.0;
   }
   __syncthreads();
   if (i >= m) return;
-  double acc[16];
+  double acc[NC];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) acc[v] = 0.0;
-  for (int c = 0; c < k; ++c) {
-    const double a = A[i + lda * c];
+  for (int v = 0; v < NC; ++v) acc[v] = 0.0;
+  for (int c = 0; c < k; c += 4) {   // k is a multiple of 16: four loads in flight
+    double a[4];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = fma(a, bs[v * KMAX + c], acc[v]);
+    for (int u = 0; u < 4; ++u) a[u] = A[i + lda * (c + u)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < NC; ++v) acc[v] = fma(a[u], bs[(c + u) * NC + v], acc[v]);
   }
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
+  for (int v = 0; v < NC; ++v) {
     if (v < nv) {
       const int64_t col = v0 + v;
       const double r = alpha * acc[v];
@@ -623,9 +631,15 @@ static int gemm_nn(const double* A, int64_t lda, int64_t m, int k, const double*
                    double alpha, const double* Cin, int64_t ldci, double beta, double* Out, int64_t ldo,
                    hipStream_t st) {
   if (m <= 0 || ncol <= 0) return AZRBF_OK;
-  const dim3 grid((unsigned)((m + 255) / 256), (unsigned)((ncol + 15) / 16));
+#ifndef AZ_NN_NCMAX
+#define AZ_NN_NCMAX 16
+#endif
+  const int nc = ncol > 32 && AZ_NN_NCMAX >= 64 ? 64 : ncol > 16 && AZ_NN_NCMAX >= 32 ? 32 : 16;
+  const dim3 grid((unsigned)((m + 255) / 256), (unsigned)((ncol + nc - 1) / nc));
   Prof pr("gemm_nn", 8.0 * m * (k + ncol * (beta != 0.0 ? 2.0 : 1.0)), st);
-  k_gemm_nn<<<grid, 256, 0, st>>>(A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta, Out, ldo);
+  if (nc == 64) k_gemm_nn<64><<<grid, 256, 0, st>>>(A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta, Out, ldo);
+  else if (nc == 32) k_gemm_nn<32><<<grid, 256, 0, st>>>(A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta, Out, ldo);
+  else k_gemm_nn<16><<<grid, 256, 0, st>>>(A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta, Out, ldo);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 

@@ -139,23 +139,30 @@ k_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__
 }
 
 // C = alpha sum_s P_s + beta C for each batch entry; P_s at P + (b*splits+s)*sP.
-__global__ void k_sum_splits(int64_t M, int64_t N, int splits, const double* __restrict__ P, int64_t ldp,
-                             int64_t sP, double alpha, double beta, const double* Cin, int64_t ldci, int64_t sCi,
-                             double* C, int64_t ldc, int64_t sC) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= M * N) return;
-  const int64_t b = blockIdx.y, i = e % M, j = e / M;
-  const double* p = P + (int64_t)b * splits * sP + i + ldp * j;
-  double s0 = 0.0, s1 = 0.0;
-  int s = 0;
-  for (; s + 2 <= splits; s += 2) {
-    s0 += p[(int64_t)s * sP];
-    s1 += p[(int64_t)(s + 1) * sP];
+// One wave per output element: lane l adds the partials s = l, l + 64, ...
+// in order, then the 64 lane sums are added by a fixed butterfly, so the
+// result does not depend on scheduling (and the loads of a lane are
+// independent, instead of one long chain of dependent round trips).
+__global__ void __launch_bounds__(256)
+k_sum_splits(int64_t M, int64_t N, int splits, const double* __restrict__ P, int64_t ldp, int64_t sP,
+             double alpha, double beta, const double* Cin, int64_t ldci, int64_t sCi, double* C, int64_t ldc,
+             int64_t sC) {
+  const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t b = blockIdx.y;
+  double v = 0.0;
+  if (e < M * N) {
+    const int64_t i = e % M, j = e / M;
+    const double* p = P + (int64_t)b * splits * sP + i + ldp * j;
+    for (int s = lane; s < splits; s += 64) v += p[(int64_t)s * sP];
   }
-  if (s < splits) s0 += p[(int64_t)s * sP];
-  double* c = C + (int64_t)b * sC + i + ldc * j;
-  const double v = s0 + s1;
-  *c = beta == 0.0 ? alpha * v : fma(alpha, v, beta * Cin[(int64_t)b * sCi + i + ldci * j]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (e < M * N && lane == 0) {
+    const int64_t i = e % M, j = e / M;
+    double* c = C + (int64_t)b * sC + i + ldc * j;
+    *c = beta == 0.0 ? alpha * v : fma(alpha, v, beta * Cin[(int64_t)b * sCi + i + ldci * j]);
+  }
 }
 
 template <bool TA, bool TB>
@@ -220,7 +227,8 @@ int gemm_mfma_c(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
   AZ_HIP(hipGetLastError());
   if (splits > 1) {
     const int64_t e = M * N;
-    k_sum_splits<<<dim3((unsigned)((e + 255) / 256), (unsigned)batch), 256, 0, st>>>(
+    if ((e + 3) / 4 > 0x7fffffff) return AZRBF_EINVAL;
+    k_sum_splits<<<dim3((unsigned)((e + 3) / 4), (unsigned)batch), 256, 0, st>>>(
         M, N, splits, part, M, M * N, alpha, beta, Cin, ldci, sCi, C, ldc, sC);
     AZ_HIP(hipGetLastError());
   }
