@@ -105,13 +105,22 @@ typedef struct {
 /* Step 0 of section 3.2.3: collocation index list, spectra of B (Lemma 4.2:
  * DFTs of the kernel sampled on the s^dim shifted grids) and the regularised
  * weights of B^+ (eq. B_pinv; eq. B_pinv_2d; section 6.2 for BVPs).  The
- * spectra are computed on the device.  On success *out owns the plan.
+ * spectra are computed on the device, queued on `stream` (1D: without
+ * waiting for them; work later passed another stream first waits for them).
+ * On success *out owns the plan.
  * Errors: EINVAL (bad sizes, empty mask, nb > 0 without op BVP, ...),
  * EUNSUPPORTED (n not a power of two or out of range, s not in {1,2,4}),
  * ENOMEM, EHIP. */
 int azrbf_plan(const azrbf_problem* prob, void* stream, azrbf_plan_t* out);
 
+/* The facts above.  normA, normZ and zeroed (computed on the device when
+ * the plan is made) and rank and sweeps (of a factor queued by azrbf_solve)
+ * are read back on first request, which waits for that work. */
 int azrbf_plan_info(azrbf_plan_t plan, azrbf_info* info);
+
+/* dims[0..4] = N, M, Mb, L (fine-grid points), k (current sketch width):
+ * sizes known on the host, no waiting. */
+int azrbf_plan_dims(azrbf_plan_t plan, int64_t* dims);
 
 /* Y = alpha * A X + beta * Y for nvec vectors (eq. Ax_is_b, eq. Aa_is_b_2d):
  * X is N x nvec (ldx >= N), Y is (M + Mb) x nvec (ldy >= M + Mb).  A is
@@ -151,8 +160,11 @@ int azrbf_factor(azrbf_plan_t plan, void* stream);
 /* Least-squares solve of A X = B for nrhs right-hand sides (Algorithm 1 plus
  * `refine` refinement passes on the residual).  B is (M + Mb) x nrhs, X is
  * N x nrhs.  If relres is not NULL it is a device array of nrhs doubles that
- * receives ||B - A X|| / ||B|| per column.  Factors first if needed (then
- * the call synchronises). */
+ * receives ||B - A X|| / ||B|| per column.  Factors first if needed.  With a
+ * fixed sketch width k <= 64 the call queues the factor and the solve and
+ * returns without waiting (the retained rank is read by azrbf_plan_info);
+ * otherwise (k left open, so that it may grow, or k > 64) the factor
+ * synchronises the stream. */
 int azrbf_solve(azrbf_plan_t plan, const double* B, int64_t ldb, int64_t nrhs,
                 double* X, int64_t ldx, double* relres, void* stream);
 
@@ -234,8 +246,10 @@ int azrbf_tune_load(const char* text);
 int azrbf_profile_enable(int32_t on);
 int azrbf_profile_report(char* buf, int64_t len);
 
-/* Releases a plan.  Waits for the work queued on the plan's latest stream;
- * its device blocks return to the library's memory pool for later plans. */
+/* Releases a plan without waiting: its device blocks return to the library's
+ * memory pool once the work queued on the plan's stream and latest stream has
+ * run (later plans on that same stream may reuse them at once, being ordered
+ * after it). */
 void azrbf_destroy(azrbf_plan_t plan);
 
 /* Frees the pool's cached device blocks (blocks owned by live plans stay). */

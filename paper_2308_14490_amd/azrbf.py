@@ -57,6 +57,7 @@ _D = ctypes.c_double
 EXPORTS = {
     "azrbf_plan": (ctypes.c_int, [ctypes.POINTER(_Problem), _P, ctypes.POINTER(_P)]),
     "azrbf_plan_info": (ctypes.c_int, [_P, ctypes.POINTER(_Info)]),
+    "azrbf_plan_dims": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
     "azrbf_apply_A": (ctypes.c_int, [_P, _P, _I64, _I64, _D, _D, _P, _I64, _P]),
     "azrbf_apply_Zstar": (ctypes.c_int, [_P, _P, _I64, _I64, _D, _D, _P, _I64, _P]),
     "azrbf_apply_AZstar": (ctypes.c_int, [_P, _P, _I64, _I64, _D, _D, _P, _I64, _P]),
@@ -168,9 +169,14 @@ class Plan:
         h = ctypes.c_void_p()
         _check(lib.azrbf_plan(ctypes.byref(pr), _stream(stream), ctypes.byref(h)), "azrbf_plan")
         self._h = h
-        info = self.info()
-        self.N, self.M, self.Mb, self.k = info["N"], info["M"], info["Mb"], info["k"]
+        self.N, self.M, self.Mb, _, self.k = self.dims()
         self.Mt = self.M + self.Mb
+
+    def dims(self):
+        """(N, M, Mb, L, k) without waiting for the device."""
+        d = (_I64 * 5)()
+        _check(_lib().azrbf_plan_dims(self._h, d), "azrbf_plan_dims")
+        return tuple(int(v) for v in d)
 
     def info(self):
         inf = _Info()
@@ -261,7 +267,7 @@ def solve(p, B, X=None, relres=None, stream=None):
         relres = torch.empty(nrhs, dtype=torch.float64, device=B.device)
     _check(_lib().azrbf_solve(p.handle, B.data_ptr(), ldb, nrhs, X.data_ptr(), ldx, relres.data_ptr(),
                               _stream(stream)), "azrbf_solve")
-    p.k = p.info()["k"]     # a first solve factors, and the width may have grown
+    p.k = p.dims()[4]       # a first solve factors, and the width may have grown
     return X, relres
 
 
@@ -284,7 +290,7 @@ def solve_many(plans, Bs, Xs=None, stream=None):
         ldb[i], ldx[i], nr[i] = lb, lx, nrhs
     _check(_lib().azrbf_solve_many(n, hp, bp, ldb, nr, xp, ldx, rp, _stream(stream)), "azrbf_solve_many")
     for p in plans:
-        p.k = p.info()["k"]
+        p.k = p.dims()[4]
     return Xs, rels
 
 

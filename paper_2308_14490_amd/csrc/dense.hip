@@ -200,6 +200,11 @@ static int64_t tsqr_scratch_doubles(int64_t m, int k) {
   return s + 2 * e;
 }
 
+__global__ void k_copy_doubles(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
 // W (m x k, ld m) is destroyed (level-0 reflectors); Q (m x k, ld m) and
 // R (k x k, ld k) out.
 static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double* R, hipStream_t st,
@@ -221,7 +226,9 @@ static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double*
     Prof pr(l == 0 ? "tsqr_block" : "tsqr_block (tree)", 16.0 * L.m * k + 8.0 * L.nb * k * (k + 1), st);
     AZ_TRY(tsqr_block_qr(L.A, L.m, L.m, k, L.R, L.nb * k, L.A, L.m, L.tau, st));
   }
-  AZ_HIP(hipMemcpyAsync(R, lv.back().R, sizeof(double) * k * k, hipMemcpyDeviceToDevice, st));
+  // (a kernel rather than a runtime copy: a launch does not block the host)
+  k_copy_doubles<<<(unsigned)((k * k + 255) / 256), 256, 0, st>>>(lv.back().R, R, (int64_t)k * k);
+  AZ_HIP(hipGetLastError());
   if (r_ready) AZ_HIP(hipEventRecord(r_ready, st));   // R is final; Q is formed below
   const double* up = nullptr;
   int64_t ldup = 0;
@@ -300,11 +307,11 @@ __device__ __forceinline__ double sum16(double x) {
 // with |theta| <= pi/4; c and s come from the half-angle identities
 // c^2 = (1 + cos 2theta)/2, s = sin 2theta / (2c).
 // On exit: sig (descending), info = {rank, sweeps} with rank = #{sigma > thr},
-// Pm = sum_{i < rank} (Q2 W)_i u_i^T / sigma_i.
+// thr = tau_k sqrt(max D) read from the device, Pm = sum_{i < rank} (Q2 W)_i u_i^T / sigma_i.
 template <int K>
 __global__ void __launch_bounds__(8 * K)
-k_jacobi(const double* __restrict__ R, double thr, double tol, int max_sweeps, double* __restrict__ sig,
-         double* __restrict__ Pm, int* __restrict__ info) {
+k_jacobi(const double* __restrict__ R, double tau_k, const double* __restrict__ dmax, double tol, int max_sweeps,
+         double* __restrict__ sig, double* __restrict__ Pm, int* __restrict__ info) {
   constexpr int LD = K + 1;       // column stride (doubles) of the LDS matrices
   constexpr int NT = 8 * K;       // threads
   constexpr int RPL = K / 16;     // rows per lane in a rotation
@@ -448,6 +455,7 @@ k_jacobi(const double* __restrict__ R, double thr, double tol, int max_sweeps, d
     inv2[t] = sv[t] > 0.0 ? 1.0 / (sv[t] * sv[t]) : 0.0;
   }
   __syncthreads();
+  const double thr = tau_k * sqrt(*dmax);   // tau ||A^c|| sqrt(k), ||A^c|| = sqrt(max D)
   int rank = 0;
   for (int i = 0; i < K; ++i) rank += sv[i] > thr;
   if (t == 0) {
@@ -467,11 +475,11 @@ k_jacobi(const double* __restrict__ R, double thr, double tol, int max_sweeps, d
   }
 }
 
-int launch_jacobi(const double* R, int k, double thr, double tol, int max_sweeps, double* sig, double* Pm, int* info,
-                  hipStream_t st) {
-  if (k == 16) k_jacobi<16><<<1, 128, 0, st>>>(R, thr, tol, max_sweeps, sig, Pm, info);
-  else if (k == 32) k_jacobi<32><<<1, 256, 0, st>>>(R, thr, tol, max_sweeps, sig, Pm, info);
-  else if (k == 64) k_jacobi<64><<<1, 512, 0, st>>>(R, thr, tol, max_sweeps, sig, Pm, info);
+int launch_jacobi(const double* R, int k, double tau_k, const double* dmax, double tol, int max_sweeps, double* sig,
+                  double* Pm, int* info, hipStream_t st) {
+  if (k == 16) k_jacobi<16><<<1, 128, 0, st>>>(R, tau_k, dmax, tol, max_sweeps, sig, Pm, info);
+  else if (k == 32) k_jacobi<32><<<1, 256, 0, st>>>(R, tau_k, dmax, tol, max_sweeps, sig, Pm, info);
+  else if (k == 64) k_jacobi<64><<<1, 512, 0, st>>>(R, tau_k, dmax, tol, max_sweeps, sig, Pm, info);
   else return AZRBF_EUNSUPPORTED;
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
@@ -703,7 +711,7 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch) {
   // TSQR destroys W; the QR is of the sketch, W is then free scratch.  The
   // Jacobi SVD needs only R: it runs on a second stream while this one forms
   // the explicit Q, and the products below (which overwrite W) wait for both.
-  const double thr = P.tau * P.normA * sqrt((double)k);
+  const double tau_k = P.tau * sqrt((double)k);   // threshold tau_k ||A^c||, ||A^c|| read on the device
   hipStream_t js = nullptr;
   hipEvent_t eR = nullptr, eJ = nullptr;
   if (!prof_enabled() && side_stream(P.device, &js) == AZRBF_OK &&
@@ -716,7 +724,7 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch) {
   if (!rc && js != st && hipStreamWaitEvent(js, eR, 0) != hipSuccess) rc = AZRBF_EHIP;
   if (!rc) {
     Prof pj("jacobi", 8.0 * 3 * k * k, js);
-    rc = launch_jacobi(P.Rf, k, thr, 4.0 * k * 1.1102230246251565e-16, 40, P.sig, P.Pm, info, js);
+    rc = launch_jacobi(P.Rf, k, tau_k, P.dred, 4.0 * k * 1.1102230246251565e-16, 40, P.sig, P.Pm, info, js);
   }
   if (!rc && js != st) {
     if (hipEventRecord(eJ, js) != hipSuccess || hipStreamWaitEvent(st, eJ, 0) != hipSuccess) rc = AZRBF_EHIP;
@@ -745,6 +753,16 @@ int dense_factor_finish(Plan& P, hipStream_t st) {
   P.sweeps = P.hinfo[1];
   P.factored = true;
   return P.rank >= P.k ? AZRBF_ERANK : AZRBF_OK;
+}
+
+int plan_fetch_rank(Plan& P) {
+  if (!P.rank_pending) return AZRBF_OK;
+  AZ_HIP(hipMemcpyAsync(P.hinfo, P.dinfo, sizeof(P.hinfo), hipMemcpyDeviceToHost, P.factor_stream));
+  AZ_HIP(hipStreamSynchronize(P.factor_stream));
+  P.rank = P.hinfo[0];
+  P.sweeps = P.hinfo[1];
+  P.rank_pending = false;
+  return AZRBF_OK;
 }
 
 int dense_factor(Plan& P, hipStream_t st) {

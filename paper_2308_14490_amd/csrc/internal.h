@@ -80,6 +80,15 @@ int side_stream(int device, hipStream_t* out);
 int ops_init_twiddles(int device, const double2** tw);
 bool engine_shape_ok(int N1, int N2, int C, int Lr, int chunk);
 int ops_spectra(Plan& P, hipStream_t st);
+// Host copies of the spectral norms (synchronises the stream once per plan).
+int ops_norms(Plan& P, hipStream_t st);
+// Work on a stream other than the plan's own first waits for its set-up
+// (and for a factor queued on another stream).
+int plan_on_stream(Plan& P, hipStream_t st);
+// Marks the end of set-up or factor work queued on st.
+int plan_mark_ready(Plan& P, hipStream_t st);
+// Reads back rank and sweeps of a factor queued without waiting.
+int plan_fetch_rank(Plan& P);
 // Y = alpha A X + beta Yin (Yin null: Yin = Y); Z = alpha Z* R + beta Zin likewise.
 int ops_apply_A(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta,
                 const double* Yin, int64_t ldyi, double* Y, int64_t ldy, hipStream_t st);
@@ -154,6 +163,9 @@ struct Plan {
   const double2* tw = nullptr;            // shared twiddle table (per device)
 
   hipStream_t last_stream = nullptr;      // stream of the plan's latest work
+  hipStream_t make_stream = nullptr;      // stream the plan was made on
+  hipEvent_t ready = nullptr;             // recorded after the latest set-up or factor work
+  hipStream_t ready_stream = nullptr;     // ... on this stream
 
   // device memory owned by the plan (pointer, pool size class)
   std::vector<std::pair<void*, int64_t>> allocs;
@@ -165,8 +177,10 @@ struct Plan {
   double* w2 = nullptr;
   double* bpts = nullptr;                 // Mb x dim, device
   double bweight = 1;
-  double normA = 0, normZ = 0;
+  double normA = 0, normZ = 0;   // sqrt(max D), sqrt(max w); valid once ops_norms ran
   int zeroed = 0;
+  double* dred = nullptr;          // device: max D, max w, dropped count
+  bool norms_pending = false;
 
   // engine tile shapes (0: defaults): columns per block of the column
   // passes, rows per block of the row passes, vector pairs per chunk
@@ -192,6 +206,8 @@ struct Plan {
   int sweeps = 0;            // Jacobi sweeps of the last factor
   int hinfo[2] = {0, 0};     // rank and sweeps, copied back by the factor
   int* dinfo = nullptr;      // their device copy
+  bool rank_pending = false; // the factor is queued; rank and sweeps not read back yet
+  hipStream_t factor_stream = nullptr;
   double* Om = nullptr;     // N x k, then Omega * P
   double* Om2 = nullptr;    // N x k scratch
   double* Yf = nullptr;     // Mt x k, A Omega, then (A Omega) * P
@@ -214,6 +230,9 @@ struct Plan {
 
   int alloc(void** p, int64_t bytes);
   void release();
+  // Blocks back to the pool once the work queued on st so far has run (an
+  // event guards them; plans on the same stream may take them at once).
+  void release_after(hipStream_t st);
   void release_one(void* p);   // one block back to the pool
   void release_factor();       // the factor and solve workspace back to the pool
 };

@@ -248,6 +248,12 @@ k_fused_fwd(const double2* __restrict__ tw, const double2* __restrict__ in, doub
 
 // ------------------------------------------------------------------ engine
 
+// Store of one workspace element.  (Non-temporal stores were measured: they
+// help the first pass and hurt the next one, which then misses the last-level
+// cache; net no gain.)
+__device__ __forceinline__ void ws_store(double2* p, double2 v) { *p = v; }
+
+
 // Column passes: C adjacent columns per block, T = N1/16 threads per column,
 // column index fastest (coalesced runs of C elements).
 template <int N1>
@@ -293,7 +299,7 @@ k_col_fwd_A(Geo g, const double2* __restrict__ tw, const double* __restrict__ X,
     const int64_t k1 = t + m * T;
     double2 v = a[m];
     if (TWID) v = cmul(v, tw_fwd(tw, k1 * b, g.N));
-    out[k1 * g.N2 + b] = v;
+    ws_store(&out[k1 * g.N2 + b], v);
   }
 }
 
@@ -392,7 +398,7 @@ k_row(Geo g, const double2* __restrict__ tw, const double2* ws1, double2* __rest
       for (int m = 0; m < RADIX; ++m) {
         double2 v = b[m];
         if (TWID) v = cmulc(v, tw_fwd(tw, k1 * (t + m * T), g.N));
-        out[t + m * T] = v;
+        ws_store(&out[t + m * T], v);
       }
     }
   }
@@ -407,7 +413,7 @@ k_row(Geo g, const double2* __restrict__ tw, const double2* ws1, double2* __rest
     for (int m = 0; m < RADIX; ++m) {
       double2 v = acc[m];
       if (TWID) v = cmulc(v, tw_fwd(tw, k1 * (t + m * T), g.N));
-      out[t + m * T] = v;
+      ws_store(&out[t + m * T], v);
     }
     return;
   }
@@ -423,7 +429,7 @@ k_row(Geo g, const double2* __restrict__ tw, const double2* ws1, double2* __rest
     for (int m = 0; m < RADIX; ++m) {
       double2 v = b[m];
       if (TWID) v = cmulc(v, tw_fwd(tw, kk * (tt + m * T), g.N));
-      out[tt + m * T] = v;
+      ws_store(&out[tt + m * T], v);
     }
   }
 }
@@ -495,7 +501,7 @@ k_col_fwd_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R,
       const int64_t k1 = t + m * T;
       double2 v = a[m];
       if (TWID) v = cmul(v, tw_fwd(tw, k1 * b, g.N));
-      out[k1 * g.N2 + b] = v;
+      ws_store(&out[k1 * g.N2 + b], v);
     }
   }
 }
@@ -629,8 +635,9 @@ __global__ void k_boundary_A(int dim, int n, double T, double h, double eps, int
 // Kernel phi (which = 0) or phi'' (which = 1) sampled at m * hL, m = 0..L-1,
 // split into s phases: out[r * n + j] = k[s j + r].
 __global__ void k_sample_phases(double2* out, int n, int s, double hL, double eps, double T, int mimg,
-                                int which) {
+                                int which, double* zero4) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (zero4 && i < 4) zero4[i] = 0.0;   // the reductions' accumulators (read by later launches)
   if (i >= (int64_t)n * s) return;
   const int r = (int)(i / n), j = (int)(i % n);
   double x = ((int64_t)s * j + r) * hL;
@@ -649,64 +656,98 @@ __device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
   atomicMax((unsigned long long*)addr, (unsigned long long)__double_as_longlong(v));
 }
 
+// Block-wide (256 threads) maximum of non-negative v and count of flags,
+// then one atomic per block instead of one per thread (all threads of the
+// block must call it).
+__device__ __forceinline__ void block_max_count(double v, int flag, double* vmax, int* count) {
+  __shared__ double rm[4];
+  __shared__ int rc[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v = fmax(v, __shfl_xor(v, o, 64));
+    flag += __shfl_xor(flag, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    rm[threadIdx.x >> 6] = v;
+    rc[threadIdx.x >> 6] = flag;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomic_max_nonneg(vmax, fmax(fmax(rm[0], rm[1]), fmax(rm[2], rm[3])));
+    const int c = rc[0] + rc[1] + rc[2] + rc[3];
+    if (count && c) atomicAdd(count, c);
+  }
+}
+
 // 1D: combine kernel spectra into d_r (BVP: opscale (d2 + k2 d0)), D = sum |d_r|^2.
-__global__ void k_combine_1d(double2* d, const double2* d2, int64_t N, int s, int op, double k2,
-                             double opscale, double* D, double* dmax) {
+__global__ void __launch_bounds__(256)
+k_combine_1d(double2* d, const double2* d2, int64_t N, int s, int op, double k2, double opscale, double* D,
+             double* dmax) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
   double acc = 0.0;
-  for (int r = 0; r < s; ++r) {
-    double2 v = d[(int64_t)r * N + i];
-    if (op != AZRBF_OP_APPROX) {
-      v = cscale(cadd(d2[(int64_t)r * N + i], cscale(v, k2)), opscale);
-      d[(int64_t)r * N + i] = v;
+  if (i < N) {
+    for (int r = 0; r < s; ++r) {
+      double2 v = d[(int64_t)r * N + i];
+      if (op != AZRBF_OP_APPROX) {
+        v = cscale(cadd(d2[(int64_t)r * N + i], cscale(v, k2)), opscale);
+        d[(int64_t)r * N + i] = v;
+      }
+      acc += v.x * v.x + v.y * v.y;
     }
-    acc += v.x * v.x + v.y * v.y;
+    D[i] = acc;
   }
-  D[i] = acc;
-  atomic_max_nonneg(dmax, acc);
+  block_max_count(acc, 0, dmax, nullptr);
 }
 
-__global__ void k_weights_1d(const double2* d, double2* spA, double2* spZ, const double* D, int64_t N,
-                             int s, double tauZ, const double* dmax, double* wmax, int* zeroed) {
+__global__ void __launch_bounds__(256)
+k_weights_1d(const double2* d, double2* spA, double2* spZ, const double* D, int64_t N, int s, double tauZ,
+             const double* dmax, double* wmax, int* zeroed) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double Dv = D[i];
-  const bool keep = Dv > tauZ * *dmax;
-  const double w = keep ? 1.0 / Dv : 0.0;
-  if (!keep) atomicAdd(zeroed, 1);
-  else atomic_max_nonneg(wmax, w);
-  const double inv = 1.0 / (double)N;
-  for (int r = 0; r < s; ++r) {
-    const double2 v = d[(int64_t)r * N + i];
-    spA[(int64_t)r * N + i] = cscale(v, inv);
-    spZ[(int64_t)r * N + i] = cscale(cconj(v), w * inv);
+  double w = 0.0;
+  int dropped = 0;
+  if (i < N) {
+    const double Dv = D[i];
+    const bool keep = Dv > tauZ * *dmax;
+    w = keep ? 1.0 / Dv : 0.0;
+    dropped = keep ? 0 : 1;
+    const double inv = 1.0 / (double)N;
+    for (int r = 0; r < s; ++r) {
+      const double2 v = d[(int64_t)r * N + i];
+      spA[(int64_t)r * N + i] = cscale(v, inv);
+      spZ[(int64_t)r * N + i] = cscale(cconj(v), w * inv);
+    }
   }
+  block_max_count(w, dropped, wmax, zeroed);
 }
 
-__global__ void k_D_2d(Geo g, double* D, double* dmax) {
+__global__ void __launch_bounds__(256) k_D_2d(Geo g, double* D, double* dmax) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.N) return;
-  const int ka = (int)(i / g.N2), kb = (int)(i % g.N2);
   double acc = 0.0;
-  for (int ph = 0; ph < g.s * g.s; ++ph) {
-    const double2 v = spec2d(g, ph, ka, kb);
-    acc += v.x * v.x + v.y * v.y;
+  if (i < g.N) {
+    const int ka = (int)(i / g.N2), kb = (int)(i % g.N2);
+    for (int ph = 0; ph < g.s * g.s; ++ph) {
+      const double2 v = spec2d(g, ph, ka, kb);
+      acc += v.x * v.x + v.y * v.y;
+    }
+    D[i] = acc;
   }
-  D[i] = acc;
-  atomic_max_nonneg(dmax, acc);
+  block_max_count(acc, 0, dmax, nullptr);
 }
 
-__global__ void k_weights_2d(double* w2, const double* D, int64_t N, double tauZ, const double* dmax,
-                             double* wmax, int* zeroed) {
+__global__ void __launch_bounds__(256)
+k_weights_2d(double* w2, const double* D, int64_t N, double tauZ, const double* dmax, double* wmax,
+             int* zeroed) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double Dv = D[i];
-  const bool keep = Dv > tauZ * *dmax;
-  const double w = keep ? 1.0 / Dv : 0.0;
-  if (!keep) atomicAdd(zeroed, 1);
-  else atomic_max_nonneg(wmax, w);
-  w2[i] = w / (double)N;
+  double w = 0.0;
+  int dropped = 0;
+  if (i < N) {
+    const double Dv = D[i];
+    const bool keep = Dv > tauZ * *dmax;
+    w = keep ? 1.0 / Dv : 0.0;
+    dropped = keep ? 0 : 1;
+    w2[i] = w / (double)N;
+  }
+  block_max_count(w, dropped, wmax, zeroed);
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -1126,11 +1167,10 @@ int ops_spectra(Plan& P, hipStream_t st) {
   AZ_TRY(P.alloc((void**)&fac, (int64_t)nk * s * n * sizeof(double2)));
   double* red = nullptr;   // [dmax, wmax, zeroed(int)]
   AZ_TRY(P.alloc((void**)&red, 4 * sizeof(double)));
-  AZ_HIP(hipMemsetAsync(red, 0, 4 * sizeof(double), st));
   const int64_t ns = (int64_t)n * s;
   for (int which = 0; which < nk; ++which) {
     k_sample_phases<<<(unsigned)((ns + 255) / 256), 256, 0, st>>>(samp + which * ns, n, s, P.hL, P.eps, P.T,
-                                                                  mimg, which);
+                                                                  mimg, which, which == 0 ? red : nullptr);
     AZ_HIP(hipGetLastError());
   }
   const bool engine = P.dim == 1 && !P.fused;
@@ -1161,14 +1201,38 @@ int ops_spectra(Plan& P, hipStream_t st) {
     AZ_HIP(hipGetLastError());
     P.geo.w2 = P.w2;
   }
+  // max D, max w and the count of dropped frequencies stay on the device
+  // (the factor's threshold reads max D there); the host copies are fetched
+  // on demand by ops_norms, so that making a plan does not synchronise
+  P.dred = red;
+  P.norms_pending = true;
+  return AZRBF_OK;
+}
+
+int plan_on_stream(Plan& P, hipStream_t st) {
+  if (P.ready && st != P.ready_stream) AZ_HIP(hipStreamWaitEvent(st, P.ready, 0));
+  return AZRBF_OK;
+}
+
+int plan_mark_ready(Plan& P, hipStream_t st) {
+  if (!P.ready) AZ_HIP(hipEventCreateWithFlags(&P.ready, hipEventDisableTiming));
+  AZ_HIP(hipEventRecord(P.ready, st));
+  P.ready_stream = st;
+  return AZRBF_OK;
+}
+
+int ops_norms(Plan& P, hipStream_t st) {
+  if (!P.norms_pending) return AZRBF_OK;
+  AZ_TRY(plan_on_stream(P, st));
   double hred[4];
-  AZ_HIP(hipMemcpyAsync(hred, red, sizeof(hred), hipMemcpyDeviceToHost, st));
+  AZ_HIP(hipMemcpyAsync(hred, P.dred, sizeof(hred), hipMemcpyDeviceToHost, st));
   AZ_HIP(hipStreamSynchronize(st));
-  P.normA = sqrt(hred[0] / (P.dim == 1 ? 1.0 : 1.0));
+  P.normA = sqrt(hred[0]);
   P.normZ = sqrt(hred[1]);
   int z;
   std::memcpy(&z, &hred[2], sizeof(int));
   P.zeroed = z;
+  P.norms_pending = false;
   return AZRBF_OK;
 }
 

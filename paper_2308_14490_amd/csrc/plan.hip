@@ -28,6 +28,39 @@ std::multimap<std::pair<int, int64_t>, void*> g_pool;   // (device, bytes) -> bl
 int64_t g_pool_bytes = 0;
 constexpr int64_t kPoolCap = (int64_t)16 << 30;
 
+// Blocks of destroyed plans whose queued work may still be running: they join
+// the pool when the event has completed; until then only a plan on the same
+// stream (whose work is ordered after it) may take them.
+struct PendingRelease {
+  int device;
+  hipStream_t st;
+  hipEvent_t ev;
+  std::vector<std::pair<void*, int64_t>> blocks;
+};
+std::vector<PendingRelease> g_pending;
+
+void pool_put_locked(int device, void* ptr, int64_t cls) {
+  if (g_pool_bytes + cls > kPoolCap) {
+    (void)hipFree(ptr);
+    return;
+  }
+  g_pool.insert({{device, cls}, ptr});
+  g_pool_bytes += cls;
+}
+
+void reap_locked() {
+  for (size_t i = 0; i < g_pending.size();) {
+    PendingRelease& r = g_pending[i];
+    if (hipEventQuery(r.ev) != hipSuccess) {
+      ++i;
+      continue;
+    }
+    for (auto& b : r.blocks) pool_put_locked(r.device, b.first, b.second);
+    (void)hipEventDestroy(r.ev);
+    g_pending.erase(g_pending.begin() + (long)i);
+  }
+}
+
 int64_t size_class(int64_t n) {
   if (n <= 4096) return 4096;
   int64_t c = 4096;
@@ -41,11 +74,22 @@ int Plan::alloc(void** ptr, int64_t nbytes) {
   const int64_t cls = size_class(nbytes <= 0 ? 8 : nbytes);
   {
     std::lock_guard<std::mutex> lk(g_pool_mu);
+    reap_locked();
     auto it = g_pool.find({device, cls});
     if (it != g_pool.end()) {
       *ptr = it->second;
       g_pool.erase(it);
       g_pool_bytes -= cls;
+    }
+    for (size_t i = 0; !*ptr && i < g_pending.size(); ++i) {
+      PendingRelease& r = g_pending[i];
+      if (r.device != device || r.st != last_stream) continue;
+      for (size_t j = 0; j < r.blocks.size(); ++j) {
+        if (r.blocks[j].second != cls) continue;
+        *ptr = r.blocks[j].first;
+        r.blocks.erase(r.blocks.begin() + (long)j);
+        break;
+      }
     }
   }
   if (!*ptr) {
@@ -70,6 +114,20 @@ void Plan::release() {
     g_pool.insert({{device, a.second}, a.first});
     g_pool_bytes += a.second;
   }
+  allocs.clear();
+  bytes = 0;
+}
+
+void Plan::release_after(hipStream_t st) {
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, st) != hipSuccess) {
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipStreamSynchronize(st);
+    release();
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_pending.push_back(PendingRelease{device, st, ev, allocs});
   allocs.clear();
   bytes = 0;
 }
@@ -103,11 +161,18 @@ void Plan::release_factor() {
   sw_rhs = sw_part = 0;
   azs_cols = 0;
   factored = false;
+  rank_pending = false;
   rank = -1;
 }
 
 int pool_trim() {
   std::lock_guard<std::mutex> lk(g_pool_mu);
+  for (auto& r : g_pending) {
+    (void)hipEventSynchronize(r.ev);
+    for (auto& b : r.blocks) (void)hipFree(b.first);
+    (void)hipEventDestroy(r.ev);
+  }
+  g_pending.clear();
   for (auto& kv : g_pool) (void)hipFree(kv.second);
   g_pool.clear();
   g_pool_bytes = 0;
@@ -397,21 +462,44 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
   P.k = az::default_k(q, P.Lax, P.N, P.Mt);
   az::tune_apply(P);
   rc = az::ops_spectra(P, st);
-  if (rc) { P.release(); delete h; return rc; }
+  // no synchronisation: work on this stream is ordered after the set-up, work
+  // on other streams waits for this event (plan_on_stream)
+  P.make_stream = st;
+  if (!rc) rc = az::plan_mark_ready(P, st);
+  if (rc) {
+    (void)hipStreamSynchronize(st);
+    if (P.ready) (void)hipEventDestroy(P.ready);
+    P.release();
+    delete h;
+    return rc;
+  }
   *out = h;
+  return AZRBF_OK;
+}
+
+int azrbf_plan_dims(azrbf_plan_t h, int64_t* dims) {
+  if (!h || !dims) return AZRBF_EINVAL;
+  const Plan& P = h->p;
+  dims[0] = P.N;
+  dims[1] = P.M;
+  dims[2] = P.Mb;
+  dims[3] = P.Lg;
+  dims[4] = P.k;
   return AZRBF_OK;
 }
 
 int azrbf_plan_info(azrbf_plan_t h, azrbf_info* info) {
   if (!h || !info) return AZRBF_EINVAL;
-  const Plan& P = h->p;
+  Plan& P = h->p;
   info->N = P.N;
   info->M = P.M;
   info->Mb = P.Mb;
   info->L = P.Lg;
   info->k = P.k;
+  if (az::plan_fetch_rank(P) != AZRBF_OK) return AZRBF_EHIP;
   info->rank = P.factored ? P.rank : -1;
   info->eps = P.eps;
+  if (az::ops_norms(P, P.last_stream) != AZRBF_OK) return AZRBF_EHIP;
   info->normA = P.normA;
   info->normZ = P.normZ;
   info->zeroed = P.zeroed;
@@ -428,6 +516,7 @@ int azrbf_apply_A(azrbf_plan_t h, const double* X, int64_t ldx, int64_t nvec, do
   if (nvec == 0) return AZRBF_OK;
   if (!X || !Y || ldx < P.N || ldy < P.Mt) return AZRBF_EINVAL;
   P.last_stream = (hipStream_t)stream;
+  AZ_TRY(az::plan_on_stream(P, P.last_stream));
   return az::ops_apply_A(P, X, ldx, nvec, alpha, beta, nullptr, 0, Y, ldy, (hipStream_t)stream);
 }
 
@@ -438,6 +527,7 @@ int azrbf_apply_Zstar(azrbf_plan_t h, const double* R, int64_t ldr, int64_t nvec
   if (nvec == 0) return AZRBF_OK;
   if (!R || !Z || ldr < P.Mt || ldz < P.N) return AZRBF_EINVAL;
   P.last_stream = (hipStream_t)stream;
+  AZ_TRY(az::plan_on_stream(P, P.last_stream));
   return az::ops_apply_Z(P, R, ldr, nvec, alpha, beta, nullptr, 0, Z, ldz, (hipStream_t)stream);
 }
 
@@ -449,6 +539,7 @@ int azrbf_apply_AZstar(azrbf_plan_t h, const double* R, int64_t ldr, int64_t nve
   if (!R || !Y || ldr < P.Mt || ldy < P.Mt) return AZRBF_EINVAL;
   if (R == Y && ldr != ldy) return AZRBF_EINVAL;
   P.last_stream = (hipStream_t)stream;
+  AZ_TRY(az::plan_on_stream(P, P.last_stream));
   if ((P.fused || P.Mb > 0) && nvec > P.azs_cols) {
     // the previous scratch may still be in use by queued work on this stream
     if (P.azs && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return AZRBF_EHIP;
@@ -464,6 +555,7 @@ int azrbf_apply_AZstar(azrbf_plan_t h, const double* R, int64_t ldr, int64_t nve
 int azrbf_factor(azrbf_plan_t h, void* stream) {
   if (!h) return AZRBF_EINVAL;
   h->p.last_stream = (hipStream_t)stream;
+  AZ_TRY(az::plan_on_stream(h->p, h->p.last_stream));
   return az::factor_plan(h->p, (hipStream_t)stream);
 }
 
@@ -474,6 +566,7 @@ int azrbf_solve(azrbf_plan_t h, const double* B, int64_t ldb, int64_t nrhs, doub
   if (nrhs == 0) return AZRBF_OK;
   if (!B || !X || ldb < P.Mt || ldx < P.N) return AZRBF_EINVAL;
   P.last_stream = (hipStream_t)stream;
+  AZ_TRY(az::plan_on_stream(P, P.last_stream));
   hipStream_t st = (hipStream_t)stream;
   // (not while per-launch timing is on: launches then run one at a time so
   // that each one's time is its own)
@@ -506,14 +599,24 @@ int azrbf_solve(azrbf_plan_t h, const double* B, int64_t ldb, int64_t nrhs, doub
       P.swap_ws();
     }
     if (!rc && hipEventRecord(e_side, side) != hipSuccess) rc = AZRBF_EHIP;
-    const int frc = az::dense_factor_finish(P, st);
-    if (!rc && frc != AZRBF_OK && frc != AZRBF_ERANK) rc = frc;
     if (!rc && hipStreamWaitEvent(st, e_side, 0) != hipSuccess) rc = AZRBF_EHIP;
-    if (rc) (void)hipStreamSynchronize(side);
+    // the solve needs no host-side result of the factor: it is queued at once,
+    // and the retained rank stays on the device until asked for
+    // (azrbf_plan_info), so the call returns without waiting for the GPU
+    if (!rc) {
+      P.factored = true;
+      P.rank_pending = true;
+      P.factor_stream = st;
+      rc = az::plan_mark_ready(P, st);
+    }
+    if (!rc) rc = az::dense_solve(P, B, ldb, nrhs, X, ldx, relres, st, true);
+    if (rc) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamSynchronize(side);
+    }
     (void)hipEventDestroy(e_in);
     (void)hipEventDestroy(e_side);
-    if (rc) return rc;
-    return az::dense_solve(P, B, ldb, nrhs, X, ldx, relres, st, true);
+    return rc;
   }
   if (!P.factored) {
     const int rc = az::factor_plan(P, st);
@@ -628,6 +731,7 @@ int azrbf_get_factor(azrbf_plan_t h, int32_t which, double* dst, int64_t ld, voi
   hipStream_t st = (hipStream_t)stream;
   if (!P.factored) return AZRBF_ESTATE;
   P.last_stream = st;
+  AZ_TRY(az::plan_on_stream(P, P.last_stream));
   const int k = P.k;
   switch (which) {
     case 0:
@@ -684,6 +788,7 @@ int azrbf_autotune(azrbf_plan_t h, int64_t nvec, void* stream, char* report, int
   if (!h || nvec <= 0) return AZRBF_EINVAL;
   Plan& P = h->p;
   P.last_stream = (hipStream_t)stream;
+  AZ_TRY(az::plan_on_stream(P, P.last_stream));
   std::string rep;
   const int rc = az::tune_plan(P, nvec, (hipStream_t)stream, &rep);
   if (rc) return rc;
@@ -762,9 +867,14 @@ int azrbf_profile_report(char* buf, int64_t len) {
 
 void azrbf_destroy(azrbf_plan_t h) {
   if (!h) return;
-  // the plan's blocks go back to the pool: wait for the work queued on them
-  (void)hipStreamSynchronize(h->p.last_stream);
-  h->p.release();
+  // the plan's blocks go back to the pool once the work queued on them has
+  // run: work on the plan's own stream, and on its latest stream, which first
+  // waits for the former
+  Plan& P = h->p;
+  if (P.make_stream != P.last_stream && P.ready && hipEventRecord(P.ready, P.make_stream) == hipSuccess)
+    (void)hipStreamWaitEvent(P.last_stream, P.ready, 0);
+  P.release_after(P.last_stream);
+  if (P.ready) (void)hipEventDestroy(P.ready);
   delete h;
 }
 

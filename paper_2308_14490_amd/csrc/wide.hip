@@ -514,6 +514,7 @@ int wide_factor(Plan& P, hipStream_t st) {
   double* sraw = P.sig + k;
   k_colnorms<<<k, 256, 0, st>>>(k, P.Gj, sraw);
   k_rank_sort<<<grid1(k), 256, 0, st>>>(k, sraw, P.sig);
+  AZ_TRY(ops_norms(P, st));
   const double thr = P.tau * P.normA * sqrt((double)k);
   k_scale_cols<<<grid1((int64_t)k * k), 256, 0, st>>>(k, P.Gj, sraw, thr, P.Om2);
   AZ_HIP(hipGetLastError());

@@ -26,7 +26,7 @@ def _lib_path():
 
 def test_header_declares_the_boundary():
     names = _declared()
-    for must in ["azrbf_plan", "azrbf_apply_A", "azrbf_apply_Zstar", "azrbf_apply_AZstar", "azrbf_solve", "azrbf_factor",
+    for must in ["azrbf_plan", "azrbf_apply_A", "azrbf_apply_Zstar", "azrbf_apply_AZstar", "azrbf_plan_dims", "azrbf_solve", "azrbf_factor",
                  "azrbf_destroy", "azrbf_strerror", "azrbf_footprint_bytes", "azrbf_solve_many"]:
         assert must in names
 
