@@ -6,9 +6,11 @@
 // columns in VGPRs, so the block is RB = 16384/k rows.  Column j of the
 // Householder sweep needs one block-wide reduction, D_c = sum_{r>j} a_rj a_rc
 // for every c: each lane forms its k partial sums, a butterfly
-// reduce-scatter across the wave (DPP for lane distances below 16, a swizzle
-// for 16, a permute for 32) leaves one column sum per lane, and the four
-// waves meet in LDS.  From D one gets sigma^2 = D_j, v_j^T a_c for c > j (the
+// reduce-scatter across the wave leaves one column sum per lane, and the four
+// waves meet in LDS.  The butterfly's first two stages (lane distances 32
+// and 16) exchange register halves with v_permlane32_swap / v_permlane16_swap,
+// which hand each lane exactly the partner values it adds, so they need no
+// per-lane selection; the last four (distances below 16) move values by DPP.  From D one gets sigma^2 = D_j, v_j^T a_c for c > j (the
 // rank-one update) and v_c^T v_j for c < j (the compact-WY factor T).  The
 // column loop is unrolled so that every register index is static.
 #include <utility>
@@ -25,6 +27,16 @@ struct RegQR {
   static constexpr int RB = 256 * RPT; // rows per block
 };
 
+// 1/x and 1/sqrt(x): hardware estimate and one Newton step.
+__device__ __forceinline__ double rcp_nr(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
   // every lane of the permutation is valid, so no old value is needed
@@ -33,74 +45,112 @@ __device__ __forceinline__ double dpp_d(double x) {
   return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ double swz16_d(double x) {
-  // bitmask swizzle: and 0x1f, or 0, xor 0x10 (lane ^ 16 within 32 lanes)
-  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), 0x401F);
-  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), 0x401F);
-  return __hiloint2double(hi, lo);
-}
-
-// Stage S exchanges with partner lane lane ^ X_S, X = 15, 7, 2, 1, 16, 32
-// (row mirror, half-row mirror, two quad permutations, swizzle, permute);
-// lanes of a pair differ in bit B_S = 3, 2, 1, 0, 4, 5 and agree in the
-// bits of all earlier stages.
-template <int S>
-__device__ __forceinline__ double xchg(double x) {
-  if constexpr (S == 0) return dpp_d<0x140>(x);
-  else if constexpr (S == 1) return dpp_d<0x141>(x);
-  else if constexpr (S == 2) return dpp_d<0x4E>(x);
-  else if constexpr (S == 3) return dpp_d<0xB1>(x);
-  else if constexpr (S == 4) return swz16_d(x);
-  else return __shfl_xor(x, 32, 64);
-}
-
-constexpr int stage_bit(int s) { return s == 0 ? 3 : s == 1 ? 2 : s == 2 ? 1 : s == 3 ? 0 : s == 4 ? 4 : 5; }
-
-// Halves the N live values: the lane whose bit B_S is set keeps the upper
-// half, its partner the lower half, and each adds what the other sent.
-template <int S, int N>
-__device__ __forceinline__ void rs_stage(double* v, int lane) {
-  const bool up = (lane >> stage_bit(S)) & 1;
-#pragma unroll
-  for (int q = 0; q < N / 2; ++q) {
-    const double send = up ? v[q] : v[q + N / 2];
-    const double keep = up ? v[q + N / 2] : v[q];
-    v[q] = keep + xchg<S>(send);
+// (x, y) -> lanes of the lower half of each lane pair (distance 32: lanes
+// 0-31; distance 16: rows 0 and 2) get (own x, partner's x), those of the
+// upper half (partner's y, own y).  x + y is then the pair sum of x in the
+// lower half and of y in the upper half.
+template <int D>
+__device__ __forceinline__ void swap_d(double& x, double& y) {
+  const unsigned xl = (unsigned)__double2loint(x), xh = (unsigned)__double2hiint(x);
+  const unsigned yl = (unsigned)__double2loint(y), yh = (unsigned)__double2hiint(y);
+  if constexpr (D == 32) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+    x = __hiloint2double((int)hi[0], (int)lo[0]);
+    y = __hiloint2double((int)hi[1], (int)lo[1]);
+  } else {
+    const auto lo = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+    x = __hiloint2double((int)hi[0], (int)lo[0]);
+    y = __hiloint2double((int)hi[1], (int)lo[1]);
   }
 }
 
+// Stage S = 0..5 of the butterfly pairs lanes that differ in bit B_S = 5 - S
+// (and agree in the bits of all earlier stages): S = 0, 1 by the swaps above
+// (distance 32, 16), S = 2..5 by DPP (row mirror, half-row mirror, quad
+// permutations: partner lane ^ 15, ^ 7, ^ 2, ^ 1).
+template <int S>
+__device__ __forceinline__ double xchg(double x) {
+  if constexpr (S == 2) return dpp_d<0x140>(x);
+  else if constexpr (S == 3) return dpp_d<0x141>(x);
+  else if constexpr (S == 4) return dpp_d<0x4E>(x);
+  else return dpp_d<0xB1>(x);
+}
+
+// Halves the N live values: the lane whose bit B_S is set keeps the upper
+// half, its partner the lower half, and each adds what the other holds.
+template <int S, int N>
+__device__ __forceinline__ void rs_stage(double* v, int lane) {
+  if constexpr (S < 2) {
+#pragma unroll
+    for (int q = 0; q < N / 2; ++q) {
+      double x = v[q], y = v[q + N / 2];
+      swap_d<S == 0 ? 32 : 16>(x, y);
+      v[q] = x + y;
+    }
+  } else {
+    const bool up = (lane >> (5 - S)) & 1;
+#pragma unroll
+    for (int q = 0; q < N / 2; ++q) {
+      const double send = up ? v[q] : v[q + N / 2];
+      const double keep = up ? v[q + N / 2] : v[q];
+      v[q] = keep + xchg<S>(send);
+    }
+  }
+}
+
+// Once one value is left: the pair sum in both lanes.
 template <int S>
 __device__ __forceinline__ void ar_stage(double* v) {
-  v[0] += xchg<S>(v[0]);
+  if constexpr (S < 2) {
+    double x = v[0], y = v[0];
+    swap_d<S == 0 ? 32 : 16>(x, y);
+    v[0] = x + y;
+  } else {
+    v[0] += xchg<S>(v[0]);
+  }
+}
+
+template <int S, int N>
+__device__ __forceinline__ void rs_or_ar(double* v, int lane) {
+  if constexpr (N >= 2) rs_stage<S, N>(v, lane);
+  else ar_stage<S>(v);
 }
 
 // Wave-wide sums of K values per lane; the lane is left with the sum of value
 // rs_col<K>(lane).
 template <int K>
 __device__ __forceinline__ double wave_reduce_scatter(double* v, int lane) {
-  rs_stage<0, K>(v, lane);
-  rs_stage<1, K / 2>(v, lane);
-  rs_stage<2, K / 4>(v, lane);
-  rs_stage<3, K / 8>(v, lane);
-  if constexpr (K >= 32) rs_stage<4, K / 16>(v, lane); else ar_stage<4>(v);
-  if constexpr (K >= 64) rs_stage<5, K / 32>(v, lane); else ar_stage<5>(v);
+  rs_or_ar<0, K>(v, lane);
+  rs_or_ar<1, (K >= 2 ? K / 2 : 1)>(v, lane);
+  rs_or_ar<2, (K >= 4 ? K / 4 : 1)>(v, lane);
+  rs_or_ar<3, (K >= 8 ? K / 8 : 1)>(v, lane);
+  rs_or_ar<4, (K >= 16 ? K / 16 : 1)>(v, lane);
+  rs_or_ar<5, (K >= 32 ? K / 32 : 1)>(v, lane);
   return v[0];
 }
 
+// Column held by a lane: each halving stage S with N live values adds
+// bit B_S times N/2.
 template <int K>
 __device__ __forceinline__ int rs_col(int lane) {
-  int c = ((lane >> 3) & 1) * (K / 2) + ((lane >> 2) & 1) * (K / 4) + ((lane >> 1) & 1) * (K / 8) +
-          (lane & 1) * (K / 16);
-  if constexpr (K >= 32) c += ((lane >> 4) & 1) * (K / 32);
-  if constexpr (K >= 64) c += ((lane >> 5) & 1) * (K / 64);
+  int c = 0, n = K;
+#pragma unroll
+  for (int S = 0; S < 6; ++S) {
+    if (n >= 2) {
+      c += ((lane >> (5 - S)) & 1) * (n / 2);
+      n /= 2;
+    }
+  }
   return c;
 }
 
+// One lane per column writes: the bits of the pair-sum (all-reduce) stages,
+// the last log2(64 / K) bits, are zero.
 template <int K>
 __device__ __forceinline__ bool rs_writer(int lane) {
-  if constexpr (K == 16) return lane < 16;
-  else if constexpr (K == 32) return lane < 32;
-  else return true;
+  return (lane & (64 / K - 1)) == 0;
 }
 
 template <int K>
@@ -136,9 +186,15 @@ __device__ __forceinline__ void qr_column(double (&a)[RegQR<K>::RPT][K], const Q
     const double alpha = sh.rowj[J];
     double beta = alpha, tau = 0.0, scale = 0.0;
     if (sig2 > 0.0) {
-      beta = -copysign(sqrt(fma(alpha, alpha, sig2)), alpha);
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
+      // sqrt and reciprocals from the hardware estimates refined by Newton
+      // steps: a short dependency chain on the critical path of the sweep
+      const double nn = fma(alpha, alpha, sig2);
+      const double rn = rsq_nr(nn);
+      double nrm = nn * rn;
+      nrm = fma(0.5 * rn, fma(-nrm, nrm, nn), nrm);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = fma(-alpha, rcp_nr(beta), 1.0);       // (beta - alpha) / beta
+      scale = rcp_nr(alpha - beta);
     }
     if (t == J) {
       sh.scal[0] = beta;
