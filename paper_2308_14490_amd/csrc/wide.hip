@@ -7,15 +7,17 @@
 //      finished Q (matrix-core GEMMs) and factored by the Householder TSQR,
 //      and the panel's Q is projected once more and factored again, which
 //      keeps Q orthonormal to working precision also past the numerical rank;
-//   3. the SVD of R by block one-sided Jacobi on G = R^T with 32-column
-//      blocks: in each round the disjoint block pairs form their 64 x 64
-//      Gram matrices (matrix-core products of the current columns), a
-//      two-sided Jacobi sweep diagonalises each Gram with the relative
-//      off-diagonal test |h_pq| <= tol sqrt(h_pp h_qq), and the rotation is
-//      applied to the pair's columns of G and of V; converged when a sweep
-//      needs no rotation.  Then G V... = U Sigma (columns g_i = u_i sigma_i).
+//   3. the SVD of R, preconditioned: the same QR of R^T = Q2 R2, then block
+//      one-sided Jacobi on G = R2^T with 32-column blocks: in each round the
+//      disjoint block pairs form their 64 x 64 Gram matrices (matrix-core
+//      products of the current columns), a two-sided Jacobi sweep
+//      diagonalises each Gram with the relative off-diagonal test
+//      |h_pq| <= tol sqrt(h_pp h_qq), and the rotation is applied to the
+//      pair's columns of G and of W, which starts as Q2; converged when a
+//      sweep needs no rotation.  Then G_final = U Sigma (columns
+//      g_i = u_i sigma_i) and R = U Sigma W^T.
 //   4. truncation at sigma > tau ||A^c|| sqrt(k) and
-//      P = U_r Sigma_r^-1 V_r^T = sum g_i v_i^T / sigma_i^2, so y = P Q^T c.
+//      P = R^+ = W_r Sigma_r^-1 U_r^T = sum w_i g_i^T / sigma_i^2, so y = P Q^T c.
 // The per-right-hand-side solve then runs Algorithm 1 with GEMMs for
 // Q^T c, P t and Omega y and the FFT operators for A and Z*.
 #include <algorithm>
@@ -67,11 +69,6 @@ __global__ void k_transpose(int64_t k, const double* __restrict__ R, double* __r
     const int64_t i = by + tx, j = bx + r;   // G(i, j) = R(j, i)
     if (i < k && j < k) G[i + k * j] = tile[tx][r];
   }
-}
-
-__global__ void k_eye(int64_t k, double* __restrict__ V) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < k * k) V[e] = (e % k) == (e / k) ? 1.0 : 0.0;
 }
 
 // Y += X (n x m, column-major with leading dimensions)
@@ -384,6 +381,60 @@ int64_t wide_factor_doubles(int64_t N, int64_t Mt, int k) {
   return 2 * N * k + Mt * k + 4 * (int64_t)k * k + 2 * k + wide_layout(Mt, k).total + (int64_t)k * PB + 8;
 }
 
+// Block classical Gram-Schmidt QR with reorthogonalisation (BCGS2) of the
+// m x k matrix Xq (ld m) in place: Xq becomes Q, R (k x k, ld k) the
+// triangular factor.  64-column panels: two projections against the finished
+// Q (MFMA GEMMs), a TSQR of the panel, one more projection of the panel's Q
+// and a second TSQR (see below).  The scratch is laid out for m <= its rows.
+static int wide_qr(double* Xq, int64_t m, int k, double* R, double* scr, const WideScratch& L, double* rproj,
+                   hipStream_t st) {
+  double* tq = scr + L.tsqr;
+  double* qpan = scr + L.qpan;
+  double* rpan = scr + L.rpan;
+  double* r3 = scr + L.rpan2;
+  double* part = scr + L.part;
+  const int64_t npart = panel_part(k, m);
+  AZ_HIP(hipMemsetAsync(R, 0, sizeof(double) * k * k, st));
+  for (int p = 0; p < k / PB; ++p) {
+    double* X = Xq + (int64_t)p * PB * m;
+    const int64_t done = (int64_t)p * PB;
+    double* Rcol = R + (int64_t)p * PB * k;
+    if (p > 0) {
+      AZ_TRY(gemm_mfma(true, false, done, PB, m, 1.0, Xq, m, 0, X, m, 0, 0.0, Rcol, k, 0, 1, part, npart, st));
+      AZ_TRY(gemm_mfma(false, false, m, PB, done, -1.0, Xq, m, 0, Rcol, k, 0, 1.0, X, m, 0, 1, part, npart,
+                       st));
+      AZ_TRY(gemm_mfma(true, false, done, PB, m, 1.0, Xq, m, 0, X, m, 0, 0.0, rproj, done, 0, 1, part, npart,
+                       st));
+      AZ_TRY(gemm_mfma(false, false, m, PB, done, -1.0, Xq, m, 0, rproj, done, 0, 1.0, X, m, 0, 1, part,
+                       npart, st));
+      k_axpy<<<grid1(done * PB), 256, 0, st>>>(done, PB, rproj, done, Rcol, k);
+      AZ_HIP(hipGetLastError());
+    }
+    AZ_TRY(tsqr_panel(X, m, PB, tq, qpan, rpan, st));
+    if (p == 0) {
+      AZ_HIP(hipMemcpyAsync(X, qpan, sizeof(double) * m * PB, hipMemcpyDeviceToDevice, st));
+      AZ_HIP(hipMemcpy2DAsync(Rcol, sizeof(double) * k, rpan, sizeof(double) * PB, sizeof(double) * PB, PB,
+                              hipMemcpyDeviceToDevice, st));
+      continue;
+    }
+    // Past the numerical rank the projected panel is rounding noise, and
+    // the Householder completion of its Q need not be orthogonal to the
+    // finished Q.  One more projection of the panel's Q and a second TSQR
+    // restore orthogonality:  Qp = Q S3 + Q'' R3, so the panel's R column
+    // gains S3 Rpp and its diagonal block becomes R3 Rpp.
+    AZ_TRY(gemm_mfma(true, false, done, PB, m, 1.0, Xq, m, 0, qpan, m, 0, 0.0, rproj, done, 0, 1, part, npart,
+                     st));
+    AZ_TRY(gemm_mfma(false, false, m, PB, done, -1.0, Xq, m, 0, rproj, done, 0, 1.0, qpan, m, 0, 1, part,
+                     npart, st));
+    AZ_TRY(tsqr_panel(qpan, m, PB, tq, X, r3, st));
+    AZ_TRY(gemm_mfma(false, false, done, PB, PB, 1.0, rproj, done, 0, rpan, PB, 0, 1.0, Rcol, k, 0, 1, nullptr, 0,
+                     st));
+    AZ_TRY(gemm_mfma(false, false, PB, PB, PB, 1.0, r3, PB, 0, rpan, PB, 0, 0.0, Rcol + done, k, 0, 1, nullptr,
+                     0, st));
+  }
+  return AZRBF_OK;
+}
+
 int wide_factor(Plan& P, hipStream_t st) {
   const int k = P.k;
   if (k <= 64 || k % 64 != 0) return AZRBF_EUNSUPPORTED;
@@ -412,58 +463,18 @@ int wide_factor(Plan& P, hipStream_t st) {
   AZ_TRY(ops_apply_A(P, P.Om, N, k, 1.0, 0.0, nullptr, 0, P.Q, Mt, st));        // Y = A Omega
   AZ_TRY(ops_apply_AZ(P, P.Q, Mt, k, -1.0, 1.0, P.Q, Mt, P.Q, Mt, P.Om2, st));  // W = Y - A Z* Y
   // 2. W = Q R
-  {
-    double* tq = scr + Lx.tsqr;
-    double* qpan = scr + Lx.qpan;
-    double* rpan = scr + Lx.rpan;
-    double* r3 = scr + Lx.rpan2;
-    double* part = scr + Lx.part;
-    const int64_t npart = panel_part(k, Mt);
-    AZ_HIP(hipMemsetAsync(P.Rf, 0, sizeof(double) * k * k, st));
-    for (int p = 0; p < k / PB; ++p) {
-      double* X = P.Q + (int64_t)p * PB * Mt;
-      const int64_t done = (int64_t)p * PB;
-      double* Rcol = P.Rf + (int64_t)p * PB * k;
-      if (p > 0) {
-        AZ_TRY(gemm_mfma(true, false, done, PB, Mt, 1.0, P.Q, Mt, 0, X, Mt, 0, 0.0, Rcol, k, 0, 1, part, npart, st));
-        AZ_TRY(gemm_mfma(false, false, Mt, PB, done, -1.0, P.Q, Mt, 0, Rcol, k, 0, 1.0, X, Mt, 0, 1, part, npart,
-                         st));
-        AZ_TRY(gemm_mfma(true, false, done, PB, Mt, 1.0, P.Q, Mt, 0, X, Mt, 0, 0.0, rproj, done, 0, 1, part, npart,
-                         st));
-        AZ_TRY(gemm_mfma(false, false, Mt, PB, done, -1.0, P.Q, Mt, 0, rproj, done, 0, 1.0, X, Mt, 0, 1, part,
-                         npart, st));
-        k_axpy<<<grid1(done * PB), 256, 0, st>>>(done, PB, rproj, done, Rcol, k);
-        AZ_HIP(hipGetLastError());
-      }
-      AZ_TRY(tsqr_panel(X, Mt, PB, tq, qpan, rpan, st));
-      if (p == 0) {
-        AZ_HIP(hipMemcpyAsync(X, qpan, sizeof(double) * Mt * PB, hipMemcpyDeviceToDevice, st));
-        AZ_HIP(hipMemcpy2DAsync(Rcol, sizeof(double) * k, rpan, sizeof(double) * PB, sizeof(double) * PB, PB,
-                                hipMemcpyDeviceToDevice, st));
-        continue;
-      }
-      // Past the numerical rank the projected panel is rounding noise, and
-      // the Householder completion of its Q need not be orthogonal to the
-      // finished Q.  One more projection of the panel's Q and a second TSQR
-      // restore orthogonality:  Qp = Q S3 + Q'' R3, so the panel's R column
-      // gains S3 Rpp and its diagonal block becomes R3 Rpp.
-      AZ_TRY(gemm_mfma(true, false, done, PB, Mt, 1.0, P.Q, Mt, 0, qpan, Mt, 0, 0.0, rproj, done, 0, 1, part, npart,
-                       st));
-      AZ_TRY(gemm_mfma(false, false, Mt, PB, done, -1.0, P.Q, Mt, 0, rproj, done, 0, 1.0, qpan, Mt, 0, 1, part,
-                       npart, st));
-      AZ_TRY(tsqr_panel(qpan, Mt, PB, tq, X, r3, st));
-      AZ_TRY(gemm_mfma(false, false, done, PB, PB, 1.0, rproj, done, 0, rpan, PB, 0, 1.0, Rcol, k, 0, 1, nullptr, 0,
-                       st));
-      AZ_TRY(gemm_mfma(false, false, PB, PB, PB, 1.0, r3, PB, 0, rpan, PB, 0, 0.0, Rcol + done, k, 0, 1, nullptr,
-                       0, st));
-    }
-  }
-  // 3. block one-sided Jacobi on G = R^T
+  AZ_TRY(wide_qr(P.Q, Mt, k, P.Rf, scr, Lx, rproj, st));
+  // 3. block one-sided Jacobi, preconditioned: R^T = Q2 R2 (the same QR),
+  // then Jacobi on G = R2^T with the rotations accumulated onto V = Q2
+  // (fewer sweeps: the QR concentrates the weight of R2's rows on its
+  // diagonal); R = U S (Q2 V_J)^T with U S the rotated columns of G.
   const int nbj = k / JB, npairs = nbj / 2;
   {
     dim3 tg((unsigned)((k + 31) / 32), (unsigned)((k + 31) / 32));
-    k_transpose<<<tg, 256, 0, st>>>(k, P.Rf, P.Gj);
-    k_eye<<<grid1((int64_t)k * k), 256, 0, st>>>(k, P.Vj);
+    k_transpose<<<tg, 256, 0, st>>>(k, P.Rf, P.Vj);
+    AZ_HIP(hipGetLastError());
+    AZ_TRY(wide_qr(P.Vj, k, k, P.Pm, scr, Lx, rproj, st));    // Vj = Q2, Pm = R2 (scratch until step 4)
+    k_transpose<<<tg, 256, 0, st>>>(k, P.Pm, P.Gj);
     AZ_HIP(hipGetLastError());
   }
   const int rot_lds = (int)(sizeof(double) * 2 * JP * (JP + 2));
@@ -510,15 +521,16 @@ int wide_factor(Plan& P, hipStream_t st) {
     for (int v : hcnt) tot += v;
     if (tot == 0) break;
   }
-  // 4. singular values, truncation, P = sum g_i v_i^T / sigma_i^2
+  // 4. singular values, truncation, P = R^+ = sum_i w_i g_i^T / sigma_i^2
+  // (w_i the columns of Q2 V_J, g_i = u_i sigma_i those of the rotated G)
   double* sraw = P.sig + k;
   k_colnorms<<<k, 256, 0, st>>>(k, P.Gj, sraw);
   k_rank_sort<<<grid1(k), 256, 0, st>>>(k, sraw, P.sig);
   AZ_TRY(ops_norms(P, st));
   const double thr = P.tau * P.normA * sqrt((double)k);
-  k_scale_cols<<<grid1((int64_t)k * k), 256, 0, st>>>(k, P.Gj, sraw, thr, P.Om2);
+  k_scale_cols<<<grid1((int64_t)k * k), 256, 0, st>>>(k, P.Vj, sraw, thr, P.Om2);
   AZ_HIP(hipGetLastError());
-  AZ_TRY(gemm_mfma(false, true, k, k, k, 1.0, P.Om2, k, 0, P.Vj, k, 0, 0.0, P.Pm, k, 0, 1, nullptr, 0, st));
+  AZ_TRY(gemm_mfma(false, true, k, k, k, 1.0, P.Om2, k, 0, P.Gj, k, 0, 0.0, P.Pm, k, 0, 1, nullptr, 0, st));
   std::vector<double> hs(k);
   AZ_HIP(hipMemcpyAsync(hs.data(), P.sig, sizeof(double) * k, hipMemcpyDeviceToHost, st));
   AZ_HIP(hipStreamSynchronize(st));
