@@ -227,8 +227,10 @@ k_jac_eig(const double* __restrict__ Hp, int rsplit, double tol, double* __restr
 // X_p <- X_p V_p on 64-row tiles, in place, for G (blockIdx.z = 0) and the
 // accumulated V (blockIdx.z = 1); a block takes ROT_TILES consecutive tiles
 // and loads V_p once.  A tile is read whole before it is written, and no
-// other block touches it.
-constexpr int ROT_TILES = 4;
+// other block touches it; the next tile's columns are loaded into registers
+// while the current one is multiplied.
+constexpr int ROT_TILES = 8;
+constexpr int ROT_PER = JP * JP / 256;   // tile elements staged per thread
 
 __global__ void __launch_bounds__(256)
 k_jac_rot(int64_t k, double* G, double* Vm, int round, int nbj, const double* __restrict__ Vp) {
@@ -244,15 +246,24 @@ k_jac_rot(int64_t k, double* G, double* Vm, int round, int nbj, const double* __
   for (int e = t; e < JP * JP; e += 256) Rs[e & 63][e >> 6] = vp[e];   // Rs[c'][j] = V_p(c', j)
   const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
   const int64_t ntiles = k / 64;
+  const int64_t tile0 = (int64_t)blockIdx.x * ROT_TILES;
+  // element q of this thread: rr = t & 63 (fixed), c = (t >> 6) + 4 q
+  const int rr = t & 63;
+  double reg[ROT_PER];
+  auto fetch = [&](int64_t tile) {
+    const int64_t r0 = tile * 64;
+#pragma unroll
+    for (int q = 0; q < ROT_PER; ++q) reg[q] = X[r0 + rr + k * pair_col((t >> 6) + 4 * q, I, J)];
+  };
+  if (tile0 < ntiles) fetch(tile0);
   for (int tt = 0; tt < ROT_TILES; ++tt) {
-    const int64_t tile = (int64_t)blockIdx.x * ROT_TILES + tt;
+    const int64_t tile = tile0 + tt;
     if (tile >= ntiles) break;
     const int64_t r0 = tile * 64;
-    for (int e = t; e < JP * JP; e += 256) {
-      const int rr = e & 63, c = e >> 6;
-      Xs[c][rr] = X[r0 + rr + k * pair_col(c, I, J)];
-    }
+#pragma unroll
+    for (int q = 0; q < ROT_PER; ++q) Xs[(t >> 6) + 4 * q][rr] = reg[q];
     __syncthreads();
+    if (tt + 1 < ROT_TILES && tile + 1 < ntiles) fetch(tile + 1);   // disjoint rows: in flight meanwhile
     dbl4 acc[2][2];
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
@@ -278,8 +289,8 @@ k_jac_rot(int64_t k, double* G, double* Vm, int round, int nbj, const double* __
       for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int rr = wi + 16 * mi + (l & 15), j = wj + 16 * ni + (l >> 4) + 4 * v;
-          X[r0 + rr + k * pair_col(j, I, J)] = acc[mi][ni][v];
+          const int ro = wi + 16 * mi + (l & 15), j = wj + 16 * ni + (l >> 4) + 4 * v;
+          X[r0 + ro + k * pair_col(j, I, J)] = acc[mi][ni][v];
         }
     __syncthreads();   // Xs is refilled for the next tile
   }
