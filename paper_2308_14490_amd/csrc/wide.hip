@@ -31,6 +31,12 @@ namespace az {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
+// 1/sqrt(x): hardware estimate and one Newton step.
+__device__ __forceinline__ double rsq_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
 namespace {
 
 constexpr int PB = 64;    // QR panel width
@@ -81,11 +87,16 @@ __global__ void k_axpy(int64_t n, int64_t m, const double* __restrict__ X, int64
 
 // Partial Gram matrices of the round's block pairs: block (p, sr) sums rows
 // [sr * rch, (sr+1) * rch) of X_p^T X_p, X_p = [G_I G_J] (k x 64), into
-// Hp + (p * rsplit + sr) * 4096 (64 x 64, column-major).
+// Hp + (p * rsplit + sr) * 4096 (64 x 64, column-major).  Rows go through LDS
+// in chunks of GR; the next chunk is loaded into registers while the current
+// one is multiplied.
+constexpr int GR = 32;
+constexpr int GR_PER = GR * JP / 256;   // chunk elements staged per thread
+
 __global__ void __launch_bounds__(256)
 k_jac_gram(int64_t k, const double* __restrict__ G, int round, int nbj, int rsplit, int64_t rch,
            double* __restrict__ Hp) {
-  __shared__ double Xs[16][JP + 2];   // Xs[kk][c] = X(kb + kk, c)
+  __shared__ double Xs[GR][JP + 2];   // Xs[kk][c] = X(kb + kk, c)
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const int p = blockIdx.x, sr = blockIdx.y;
   int I, J;
@@ -97,16 +108,23 @@ k_jac_gram(int64_t k, const double* __restrict__ G, int round, int nbj, int rspl
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = dbl4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t kb = r0; kb < r1; kb += 16) {
+  // element q of this thread: row kk = t % GR of the chunk, column c = t / GR + (256 / GR) q
+  const int kk0 = t % GR, c0 = t / GR;
+  double reg[GR_PER];
+  auto fetch = [&](int64_t kb) {
+    const int64_t row = kb + kk0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = t & 15, c = (t >> 4) + 16 * q;
-      const int64_t row = kb + kk;
-      Xs[kk][c] = row < r1 ? G[row + k * pair_col(c, I, J)] : 0.0;
-    }
+    for (int q = 0; q < GR_PER; ++q)
+      reg[q] = row < r1 ? G[row + k * pair_col(c0 + (256 / GR) * q, I, J)] : 0.0;
+  };
+  if (r0 < r1) fetch(r0);
+  for (int64_t kb = r0; kb < r1; kb += GR) {
+#pragma unroll
+    for (int q = 0; q < GR_PER; ++q) Xs[kk0][c0 + (256 / GR) * q] = reg[q];
     __syncthreads();
+    if (kb + GR < r1) fetch(kb + GR);
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
+    for (int ks = 0; ks < GR / 4; ++ks) {
       const int kk = 4 * ks + (l >> 4);
       double av[2], bv[2];
 #pragma unroll
@@ -134,8 +152,8 @@ k_jac_gram(int64_t k, const double* __restrict__ G, int round, int nbj, int rspl
 
 // Two-sided cyclic Jacobi on each pair's Gram H (sum of the partials, upper
 // triangle mirrored): JINNER sweeps at most, each 63 rounds of 32 disjoint
-// rotations.  Rotation of (p, q): z = (h_qq - h_pp) / (2 h_pq),
-// t = sign(z) / (|z| + sqrt(1 + z^2)), c = 1 / sqrt(1 + t^2), s = t c,
+// rotations.  Rotation of (p, q) by the angle with tan 2theta =
+// 2 h_pq / (h_qq - h_pp), |theta| <= pi/4:
 // columns p, q <- c col_p - s col_q, s col_p + c col_q (rows likewise).
 // Out: the accumulated rotation V_p (64 x 64) and the number of rotations of
 // the first sweep (the outer convergence test).
@@ -172,11 +190,18 @@ k_jac_eig(const double* __restrict__ Hp, int rsplit, double tol, double* __restr
         tour_pair(r, t, JP, &a, &b);
         const double hpp = H[a][a], hqq = H[b][b], hpq = H[a][b];
         double c = 1.0, s = 0.0;
-        if (hpq != 0.0 && fabs(hpq) > tol * sqrt(hpp * hqq)) {
-          const double z = (hqq - hpp) / (2.0 * hpq);
-          const double tt = (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(fma(z, z, 1.0)));
-          c = 1.0 / sqrt(fma(tt, tt, 1.0));
-          s = tt * c;
+        // (|hpq| > 1e-150 keeps the squares below normal numbers)
+        if (hpq * hpq > tol * tol * (hpp * hqq) && fabs(hpq) > 1e-150) {
+          // the same angle from the half-angle identities: cos 2theta = |d| / r,
+          // c^2 = (1 + cos 2theta) / 2, s = sin 2theta / 2c, two reciprocal
+          // square roots (estimate + Newton step) on the dependency chain
+          const double d = hqq - hpp, g2 = 2.0 * hpq;
+          const double rq = rsq_nr(fma(d, d, g2 * g2));
+          const double cos2 = fabs(d) * rq, sin2 = (d >= 0.0 ? g2 : -g2) * rq;
+          const double hh = fma(0.5, cos2, 0.5);
+          const double rh = rsq_nr(hh);
+          c = hh * rh;
+          s = 0.5 * sin2 * rh;
           nrot[t] += 1;
         }
         cs[t][0] = c;
@@ -374,7 +399,7 @@ WideScratch wide_layout(int64_t Mt, int k) {
   s.part = off;
   off += panel_part(k, Mt);
   s.rsplit = (int)std::max<int64_t>(1, std::min<int64_t>((512 + npairs - 1) / npairs, k / 64));
-  s.rch = ((k + s.rsplit - 1) / s.rsplit + 15) / 16 * 16;
+  s.rch = ((k + s.rsplit - 1) / s.rsplit + 31) / 32 * 32;   // whole Gram row chunks
   s.rsplit = (int)((k + s.rch - 1) / s.rch);
   s.hp = off;
   off += (int64_t)npairs * s.rsplit * JP * JP;
