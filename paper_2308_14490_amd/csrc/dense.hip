@@ -205,9 +205,9 @@ __global__ void k_copy_doubles(const double* __restrict__ a, double* __restrict_
   if (i < n) b[i] = a[i];
 }
 
-// W (m x k, ld m) is destroyed (level-0 reflectors); Q (m x k, ld m) and
-// R (k x k, ld k) out.
-static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double* R, hipStream_t st,
+// W (m x k, leading dimension ld) is destroyed (level-0 reflectors); Q (m x k,
+// ld) and R (k x k, ld k) out.
+static int tsqr(double* W, int64_t m, int64_t ld, int k, double* scratch, double* Q, double* R, hipStream_t st,
                 hipEvent_t r_ready = nullptr) {
   std::vector<TsqrLevel> lv;
   int64_t sd, ed;
@@ -224,7 +224,8 @@ static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double*
   for (size_t l = 0; l < lv.size(); ++l) {
     const TsqrLevel& L = lv[l];
     Prof pr(l == 0 ? "tsqr_block" : "tsqr_block (tree)", 16.0 * L.m * k + 8.0 * L.nb * k * (k + 1), st);
-    AZ_TRY(tsqr_block_qr(L.A, L.m, L.m, k, L.R, L.nb * k, L.A, L.m, L.tau, st));
+    const int64_t lda = l == 0 ? ld : L.m;
+    AZ_TRY(tsqr_block_qr(L.A, lda, L.m, k, L.R, L.nb * k, L.A, lda, L.tau, st));
   }
   // (a kernel rather than a runtime copy: a launch does not block the host)
   k_copy_doubles<<<(unsigned)((k * k + 255) / 256), 256, 0, st>>>(lv.back().R, R, (int64_t)k * k);
@@ -235,11 +236,12 @@ static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double*
   for (int l = (int)lv.size() - 1; l >= 0; --l) {
     const TsqrLevel& L = lv[l];
     double* E = l == 0 ? Q : Ebuf[l & 1];
+    const int64_t lda = l == 0 ? ld : L.m;
     Prof pr(l == 0 ? "tsqr_formq" : "tsqr_formq (tree)", 16.0 * L.m * k + 8.0 * L.nb * k * (k + 1), st);
     switch (k) {
-      case 16: k_tsqr_formq<16><<<(unsigned)L.nb, TSQR_THREADS, 0, st>>>(L.A, L.m, L.tau, L.m, up, ldup, E, L.m); break;
-      case 32: k_tsqr_formq<32><<<(unsigned)L.nb, TSQR_THREADS, 0, st>>>(L.A, L.m, L.tau, L.m, up, ldup, E, L.m); break;
-      default: k_tsqr_formq<64><<<(unsigned)L.nb, TSQR_THREADS, 0, st>>>(L.A, L.m, L.tau, L.m, up, ldup, E, L.m); break;
+      case 16: k_tsqr_formq<16><<<(unsigned)L.nb, TSQR_THREADS, 0, st>>>(L.A, lda, L.tau, L.m, up, ldup, E, lda); break;
+      case 32: k_tsqr_formq<32><<<(unsigned)L.nb, TSQR_THREADS, 0, st>>>(L.A, lda, L.tau, L.m, up, ldup, E, lda); break;
+      default: k_tsqr_formq<64><<<(unsigned)L.nb, TSQR_THREADS, 0, st>>>(L.A, lda, L.tau, L.m, up, ldup, E, lda); break;
     }
     AZ_HIP(hipGetLastError());
     up = E;
@@ -250,7 +252,7 @@ static int tsqr(double* W, int64_t m, int k, double* scratch, double* Q, double*
 
 int64_t tsqr_scratch(int64_t m, int k) { return tsqr_scratch_doubles(m, k); }
 int tsqr_panel(double* W, int64_t m, int k, double* scratch, double* Q, double* R, hipStream_t st) {
-  return tsqr(W, m, k, scratch, Q, R, st);
+  return tsqr(W, m, m, k, scratch, Q, R, st);
 }
 
 // ------------------------------------------------------------------ Jacobi SVD
@@ -686,12 +688,13 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch) {
   // the Jacobi kernel pairs k/2 columns over 256 threads: 512 / k must be a shuffle width
   if (k != 16 && k != 32 && k != 64) return AZRBF_EUNSUPPORTED;
   const int64_t N = P.N, Mt = P.Mt;
+  const int64_t Ld = P.Mtp;   // leading dimension of the row-space matrices (whole 128-byte lines)
   if (!P.Om) {
     AZ_TRY(P.alloc((void**)&P.Om, sizeof(double) * N * k));
     AZ_TRY(P.alloc((void**)&P.Om2, sizeof(double) * N * k));
-    AZ_TRY(P.alloc((void**)&P.Yf, sizeof(double) * Mt * k));
-    AZ_TRY(P.alloc((void**)&P.Yf2, sizeof(double) * Mt * k));
-    AZ_TRY(P.alloc((void**)&P.Q, sizeof(double) * Mt * k));
+    AZ_TRY(P.alloc((void**)&P.Yf, sizeof(double) * Ld * k));
+    AZ_TRY(P.alloc((void**)&P.Yf2, sizeof(double) * Ld * k));
+    AZ_TRY(P.alloc((void**)&P.Q, sizeof(double) * Ld * k));
     AZ_TRY(P.alloc((void**)&P.Rf, sizeof(double) * k * k));
     AZ_TRY(P.alloc((void**)&P.sig, sizeof(double) * k));
     AZ_TRY(P.alloc((void**)&P.Pm, sizeof(double) * k * k));
@@ -700,12 +703,13 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch) {
     P.dscr_bytes = sizeof(double) * sd;
   }
   double* Zy = P.Om2;                  // N x k scratch, later Omega P
-  double* W = P.Yf2;                   // Mt x k sketch, later (A Omega) P
+  double* W = P.Yf2;                   // Mt x k sketch (ld Ld), later (A Omega) P
+  P.ldq = Ld;
   double* tq = P.dscr;                 // TSQR scratch
   int* info = (int*)(tq + tsqr_scratch_doubles(Mt, k));
   AZ_TRY(dense_gaussian(P.prob.seed, N, k, P.Om, N, st));
-  AZ_TRY(ops_apply_A(P, P.Om, N, k, 1.0, 0.0, nullptr, 0, P.Yf, Mt, st));     // Y = A Omega
-  AZ_TRY(ops_apply_AZ(P, P.Yf, Mt, k, -1.0, 1.0, P.Yf, Mt, W, Mt, Zy, st));  // W = Y - A Z* Y
+  AZ_TRY(ops_apply_A(P, P.Om, N, k, 1.0, 0.0, nullptr, 0, P.Yf, Ld, st));     // Y = A Omega
+  AZ_TRY(ops_apply_AZ(P, P.Yf, Ld, k, -1.0, 1.0, P.Yf, Ld, W, Ld, Zy, st));  // W = Y - A Z* Y
   // what follows is latency-bound: work on other streams may start here
   if (after_sketch) AZ_HIP(hipEventRecord(after_sketch, st));
   // TSQR destroys W; the QR is of the sketch, W is then free scratch.  The
@@ -720,7 +724,7 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch) {
   } else {
     js = st;
   }
-  int rc = tsqr(W, Mt, k, tq, P.Q, P.Rf, st, js != st ? eR : nullptr);
+  int rc = tsqr(W, Mt, Ld, k, tq, P.Q, P.Rf, st, js != st ? eR : nullptr);
   if (!rc && js != st && hipStreamWaitEvent(js, eR, 0) != hipSuccess) rc = AZRBF_EHIP;
   if (!rc) {
     Prof pj("jacobi", 8.0 * 3 * k * k, js);
@@ -737,7 +741,7 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch) {
   }
   // Omega P and (A Omega) P: the solve needs only these (y = P Q^T c)
   AZ_TRY(gemm_nn(P.Om, N, N, k, P.Pm, k, k, 1.0, nullptr, 0, 0.0, Zy, N, st));
-  AZ_TRY(gemm_nn(P.Yf, Mt, Mt, k, P.Pm, k, k, 1.0, nullptr, 0, 0.0, W, Mt, st));
+  AZ_TRY(gemm_nn(P.Yf, Ld, Mt, k, P.Pm, k, k, 1.0, nullptr, 0, 0.0, W, Ld, st));
   std::swap(P.Om, P.Om2);
   std::swap(P.Yf, P.Yf2);
   P.dinfo = info;
@@ -778,7 +782,7 @@ int dense_solve_ws(Plan& P, int64_t nrhs) {
   const int64_t N = P.N, Mt = P.Mt;
   const int64_t npart = gemm_split_doubles(k, nrhs, Mt, 1);
   if (nrhs > P.sw_rhs || npart > P.sw_part) {
-    const int64_t per = N + 3 * Mt + k + 2 * NORM_CHUNKS;
+    const int64_t per = N + 3 * P.Mtp + k + 2 * NORM_CHUNKS;
     AZ_TRY(P.alloc((void**)&P.sw, sizeof(double) * (per * nrhs + npart)));
     P.sw_rhs = nrhs;
     P.sw_part = npart;
@@ -793,7 +797,7 @@ int dense_first_stage(Plan& P, const double* B, int64_t ldb, int64_t nrhs, hipSt
   const int64_t N = P.N, Mt = P.Mt;
   double* Zr = P.sw;
   double* C = Zr + N * nrhs;
-  AZ_TRY(ops_apply_AZ(P, B, ldb, nrhs, -1.0, 1.0, B, ldb, C, Mt, Zr, st));
+  AZ_TRY(ops_apply_AZ(P, B, ldb, nrhs, -1.0, 1.0, B, ldb, C, P.Mtp, Zr, st));
   return AZRBF_OK;
 }
 
@@ -801,12 +805,13 @@ int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, 
                 hipStream_t st, bool first_done) {
   const int k = P.k;
   const int64_t N = P.N, Mt = P.Mt;
+  const int64_t Ld = P.Mtp;   // leading dimension of the row-space matrices (whole 128-byte lines)
   AZ_TRY(dense_solve_ws(P, nrhs));
   double* Zr = P.sw;                   // N x nrhs
-  double* C = Zr + N * nrhs;           // Mt x nrhs
-  double* R1 = C + Mt * nrhs;          // Mt x nrhs
-  double* Rc = R1 + Mt * nrhs;         // Mt x nrhs
-  double* Tm = Rc + Mt * nrhs;         // k x nrhs
+  double* C = Zr + N * nrhs;           // Mt x nrhs (ld Ld)
+  double* R1 = C + Ld * nrhs;          // Mt x nrhs (ld Ld)
+  double* Rc = R1 + Ld * nrhs;         // Mt x nrhs (ld Ld)
+  double* Tm = Rc + Ld * nrhs;         // k x nrhs
   double* nrm = Tm + (int64_t)k * nrhs;            // 2 * NORM_CHUNKS x nrhs
   double* part = nrm + 2 * NORM_CHUNKS * nrhs;     // split-reduction partials of Q^T c
   const int64_t npart = gemm_split_doubles(k, nrhs, Mt, 1);
@@ -814,18 +819,18 @@ int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, 
   int64_t ldr = ldb;
   for (int it = 0; it <= P.refine; ++it) {
     if (!(it == 0 && first_done)) {
-      AZ_TRY(ops_apply_AZ(P, rin, ldr, nrhs, -1.0, 1.0, rin, ldr, C, Mt, Zr, st));   // c = (I - A Z*) r
+      AZ_TRY(ops_apply_AZ(P, rin, ldr, nrhs, -1.0, 1.0, rin, ldr, C, Ld, Zr, st));   // c = (I - A Z*) r
     }
-    AZ_TRY(gemm_mfma_c(true, false, k, nrhs, Mt, 1.0, P.Q, Mt, 0, C, Mt, 0, 0.0, nullptr, 0, 0, Tm, k, 0, 1, part,
+    AZ_TRY(gemm_mfma_c(true, false, k, nrhs, Mt, 1.0, P.Q, Ld, 0, C, Ld, 0, 0.0, nullptr, 0, 0, Tm, k, 0, 1, part,
                        npart, st));                                                             // t = Q^T c
     AZ_TRY(gemm_nn(P.Om, N, N, k, Tm, k, nrhs, 1.0, X, ldx, it == 0 ? 0.0 : 1.0, X, ldx, st));  // x += x1
-    AZ_TRY(gemm_nn(P.Yf, Mt, Mt, k, Tm, k, nrhs, -1.0, rin, ldr, 1.0, R1, Mt, st));            // r - A x1
-    AZ_TRY(ops_apply_Z(P, R1, Mt, nrhs, 1.0, 1.0, nullptr, 0, X, ldx, st));          // x += Z* (r - A x1)
-    AZ_TRY(ops_apply_A(P, X, ldx, nrhs, -1.0, 1.0, B, ldb, Rc, Mt, st));            // residual b - A x
+    AZ_TRY(gemm_nn(P.Yf, Ld, Mt, k, Tm, k, nrhs, -1.0, rin, ldr, 1.0, R1, Ld, st));            // r - A x1
+    AZ_TRY(ops_apply_Z(P, R1, Ld, nrhs, 1.0, 1.0, nullptr, 0, X, ldx, st));          // x += Z* (r - A x1)
+    AZ_TRY(ops_apply_A(P, X, ldx, nrhs, -1.0, 1.0, B, ldb, Rc, Ld, st));            // residual b - A x
     rin = Rc;
-    ldr = Mt;
+    ldr = Ld;
   }
-  if (relres) AZ_TRY(relres_norms(Rc, Mt, B, ldb, Mt, nrhs, nrm, relres, st));
+  if (relres) AZ_TRY(relres_norms(Rc, Ld, B, ldb, Mt, nrhs, nrm, relres, st));
   return AZRBF_OK;
 }
 

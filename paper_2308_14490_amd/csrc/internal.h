@@ -158,6 +158,8 @@ struct Plan {
   int dim = 1, n = 0, s = 1, ph = 1;     // ph = s^dim phases
   double T = 1, eps = 0, h = 0, hL = 0;
   int64_t N = 0, Lax = 0, Lg = 0, M = 0, Mb = 0, Mt = 0;
+  int64_t Mtp = 0;   // Mt rounded up to 16: leading dimension of internal row-space matrices
+  int64_t ldq = 0;   // leading dimension of the factor's Q
   bool fused = false;                     // 1D single-kernel path
   Geo geo{};
   const double2* tw = nullptr;            // shared twiddle table (per device)

@@ -424,6 +424,7 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
   if (M == 0) { delete h; return AZRBF_EINVAL; }
   P.M = M;
   P.Mt = M + P.Mb;
+  P.Mtp = (P.Mt + 15) / 16 * 16;
   g.M = M;
   if (P.dim == 1) {
     int64_t i0 = 0;
@@ -718,9 +719,10 @@ int64_t azrbf_footprint_bytes(const azrbf_problem* pr, int64_t max_rhs) {
     b += 8 * az::wide_factor_doubles(N, Mt, k);
     b += 8 * (max_rhs * (2 * N + 3 * Mt + 2 * k + 64) + az::gemm_split_doubles(k, max_rhs, Mt, 1) + 1);
   } else {
-    b += 8 * (2 * N * k + 3 * Mt * k + 2 * k * k);        // factor and its scratch
+    const int64_t Mtp = (Mt + 15) / 16 * 16;              // padded leading dimension
+    b += 8 * (2 * N * k + 3 * Mtp * k + 2 * k * k);       // factor and its scratch
     b += 8 * (Mt * k / 4 + Mt * k / 4);                   // TSQR tree (upper bound)
-    b += 8 * max_rhs * (N + 3 * Mt + k + ((Mt + 1023) / 1024) * k + 2);
+    b += 8 * max_rhs * (N + 3 * Mtp + k + ((Mt + 1023) / 1024) * k + 2);
   }
   return b;
 }
@@ -739,7 +741,7 @@ int azrbf_get_factor(azrbf_plan_t h, int32_t which, double* dst, int64_t ld, voi
       return az::dense_gaussian(P.prob.seed, P.N, k, dst, ld, st);
     case 1:
       if (ld < P.Mt) return AZRBF_EINVAL;
-      return hipMemcpy2DAsync(dst, 8 * ld, P.Q, 8 * P.Mt, 8 * P.Mt, k, hipMemcpyDeviceToDevice, st) == hipSuccess
+      return hipMemcpy2DAsync(dst, 8 * ld, P.Q, 8 * P.ldq, 8 * P.Mt, k, hipMemcpyDeviceToDevice, st) == hipSuccess
                  ? AZRBF_OK : AZRBF_EHIP;
     case 2:
       if (ld < k) return AZRBF_EINVAL;

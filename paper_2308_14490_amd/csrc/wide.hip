@@ -499,6 +499,7 @@ int wide_factor(Plan& P, hipStream_t st) {
   AZ_TRY(ops_apply_A(P, P.Om, N, k, 1.0, 0.0, nullptr, 0, P.Q, Mt, st));        // Y = A Omega
   AZ_TRY(ops_apply_AZ(P, P.Q, Mt, k, -1.0, 1.0, P.Q, Mt, P.Q, Mt, P.Om2, st));  // W = Y - A Z* Y
   // 2. W = Q R
+  P.ldq = Mt;
   AZ_TRY(wide_qr(P.Q, Mt, k, P.Rf, scr, Lx, rproj, st));
   // 3. block one-sided Jacobi, preconditioned: R^T = Q2 R2 (the same QR),
   // then Jacobi on G = R2^T with the rotations accumulated onto V = Q2
