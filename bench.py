@@ -225,6 +225,13 @@ def main():
     mask = azrbf.make_mask(1, prob.n, prob.s, prob.T, prob.domain.contains)
     p0 = problems.plan_for(prob)
     B = problems.rhs_for(p0, prob, device=dev).contiguous()
+    # right-hand sides stored with a leading dimension rounded up to 16 doubles
+    # (whole 128-byte lines per column, as the library's own buffers; the values
+    # are the same, only the column stride differs)
+    ldb = (B.shape[1] + 15) // 16 * 16
+    Bp = torch.zeros((B.shape[0], ldb), dtype=torch.float64, device=dev)
+    Bp[:, :B.shape[1]] = B
+    B = Bp[:, :B.shape[1]]
     M, k = p0.M, p0.k
     # tile shapes of the FFT engine for this operator and batch: the table the
     # autotuner wrote on this GPU model when it ships with the package, else a

@@ -38,6 +38,10 @@ def source_hash():
 
 def prof_name(kernel):
     """rocprofv3 kernel name -> the library's per-launch profile name."""
+    m = re.search(r"az::k_row<(\d+), \w+, \d+, (\d+)", kernel)
+    if m:   # the row pass: template arguments N2, 1D, lines per row, mode (A, Z*, A Z*, A Z* with rows)
+        mode = ("row_A", "row_Z", "row_AZ", "row_AZ")[int(m.group(2))]
+        return f"{mode} n2={m.group(1)}"
     m = re.search(r"az::k_(\w+)<(\d+)", kernel)
     if m:
         base, n = m.group(1), m.group(2)
