@@ -683,7 +683,8 @@ int relres_norms(const double* R, int64_t ldr, const double* B, int64_t ldb, int
 
 // ------------------------------------------------------------------ factor
 
-int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch) {
+int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch, const std::function<int()>& on_sketch,
+                         const std::function<int()>& before_products) {
   const int k = P.k;
   // the Jacobi kernel pairs k/2 columns over 256 threads: 512 / k must be a shuffle width
   if (k != 16 && k != 32 && k != 64) return AZRBF_EUNSUPPORTED;
@@ -712,6 +713,7 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch) {
   AZ_TRY(ops_apply_AZ(P, P.Yf, Ld, k, -1.0, 1.0, P.Yf, Ld, W, Ld, Zy, st));  // W = Y - A Z* Y
   // what follows is latency-bound: work on other streams may start here
   if (after_sketch) AZ_HIP(hipEventRecord(after_sketch, st));
+  if (on_sketch) AZ_TRY(on_sketch());
   // TSQR destroys W; the QR is of the sketch, W is then free scratch.  The
   // Jacobi SVD needs only R: it runs on a second stream while this one forms
   // the explicit Q, and the products below (which overwrite W) wait for both.
@@ -730,9 +732,9 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch) {
     Prof pj("jacobi", 8.0 * 3 * k * k, js);
     rc = launch_jacobi(P.Rf, k, tau_k, P.dred, 4.0 * k * 1.1102230246251565e-16, 40, P.sig, P.Pm, info, js);
   }
-  if (!rc && js != st) {
-    if (hipEventRecord(eJ, js) != hipSuccess || hipStreamWaitEvent(st, eJ, 0) != hipSuccess) rc = AZRBF_EHIP;
-  }
+  if (!rc && js != st && hipEventRecord(eJ, js) != hipSuccess) rc = AZRBF_EHIP;
+  if (!rc && before_products) rc = before_products();
+  if (!rc && js != st && hipStreamWaitEvent(st, eJ, 0) != hipSuccess) rc = AZRBF_EHIP;
   if (eR) (void)hipEventDestroy(eR);
   if (eJ) (void)hipEventDestroy(eJ);
   if (rc) {
@@ -801,8 +803,19 @@ int dense_first_stage(Plan& P, const double* B, int64_t ldb, int64_t nrhs, hipSt
   return AZRBF_OK;
 }
 
+int dense_first_qtc(Plan& P, int64_t nrhs, hipStream_t st) {
+  const int k = P.k;
+  const int64_t N = P.N, Mt = P.Mt, Ld = P.Mtp;
+  double* C = P.sw + N * nrhs;
+  double* Tm = C + 3 * Ld * nrhs;
+  double* part = Tm + (int64_t)k * nrhs + 2 * NORM_CHUNKS * nrhs;
+  const int64_t npart = gemm_split_doubles(k, nrhs, Mt, 1);
+  return gemm_mfma_c(true, false, k, nrhs, Mt, 1.0, P.Q, Ld, 0, C, Ld, 0, 0.0, nullptr, 0, 0, Tm, k, 0, 1, part,
+                     npart, st);
+}
+
 int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx, double* relres,
-                hipStream_t st, bool first_done) {
+                hipStream_t st, bool first_done, bool qtc_done) {
   const int k = P.k;
   const int64_t N = P.N, Mt = P.Mt;
   const int64_t Ld = P.Mtp;   // leading dimension of the row-space matrices (whole 128-byte lines)
@@ -821,8 +834,9 @@ int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, 
     if (!(it == 0 && first_done)) {
       AZ_TRY(ops_apply_AZ(P, rin, ldr, nrhs, -1.0, 1.0, rin, ldr, C, Ld, Zr, st));   // c = (I - A Z*) r
     }
-    AZ_TRY(gemm_mfma_c(true, false, k, nrhs, Mt, 1.0, P.Q, Ld, 0, C, Ld, 0, 0.0, nullptr, 0, 0, Tm, k, 0, 1, part,
-                       npart, st));                                                             // t = Q^T c
+    if (!(it == 0 && qtc_done))
+      AZ_TRY(gemm_mfma_c(true, false, k, nrhs, Mt, 1.0, P.Q, Ld, 0, C, Ld, 0, 0.0, nullptr, 0, 0, Tm, k, 0, 1, part,
+                         npart, st));                                                           // t = Q^T c
     AZ_TRY(gemm_nn(P.Om, N, N, k, Tm, k, nrhs, 1.0, X, ldx, it == 0 ? 0.0 : 1.0, X, ldx, st));  // x += x1
     AZ_TRY(gemm_nn(P.Yf, Ld, Mt, k, Tm, k, nrhs, -1.0, rin, ldr, 1.0, R1, Ld, st));            // r - A x1
     AZ_TRY(ops_apply_Z(P, R1, Ld, nrhs, 1.0, 1.0, nullptr, 0, X, ldx, st));          // x += Z* (r - A x1)

@@ -5,6 +5,7 @@
 
 #include <string>
 #include <utility>
+#include <functional>
 #include <vector>
 
 #include "../../include/azrbf.h"
@@ -142,15 +143,23 @@ int wide_factor(Plan& P, hipStream_t st);
 int wide_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx, double* relres,
                hipStream_t st);
 int dense_factor(Plan& P, hipStream_t st);
-// the factor split in two: queue it (after_sketch, if set, is recorded once
-// the sketch W is queued) and wait for it / read the rank
-int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch);
+// the factor split in two: queue it and wait for it / read the rank.  While
+// queuing, after_sketch (if set) is recorded once the sketch W is queued and
+// then on_sketch (if set) runs on the host; before_products (if set) runs
+// once the explicit Q is queued, before the stream waits for the Jacobi SVD
+// (work that needs Q but not P can be queued there, beside the SVD).
+int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch,
+                         const std::function<int()>& on_sketch = nullptr,
+                         const std::function<int()>& before_products = nullptr);
 int dense_factor_finish(Plan& P, hipStream_t st);
 int dense_solve_ws(Plan& P, int64_t nrhs);
 int dense_first_stage(Plan& P, const double* B, int64_t ldb, int64_t nrhs, hipStream_t st);
-// first_done: the first pass's Z* b and c = (I - A Z*) b are already in the workspace
+// t = Q^T c of the first pass (c from dense_first_stage) into the solve workspace
+int dense_first_qtc(Plan& P, int64_t nrhs, hipStream_t st);
+// first_done: the first pass's c = (I - A Z*) b is already in the workspace;
+// qtc_done: so is its Q^T c
 int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
-                double* relres, hipStream_t st, bool first_done = false);
+                double* relres, hipStream_t st, bool first_done = false, bool qtc_done = false);
 
 struct Plan {
   azrbf_problem prob{};

@@ -585,22 +585,21 @@ int azrbf_solve(azrbf_plan_t h, const double* B, int64_t ldb, int64_t nrhs, doub
       return AZRBF_EHIP;
     }
     // the side work starts once the factor's sketch (bandwidth-bound FFTs) is
-    // done, so that it runs beside the latency-bound TSQR and Jacobi kernels
-    int rc = az::dense_factor_enqueue(P, st, e_in);
-    if (rc) {
-      (void)hipStreamSynchronize(st);
-      (void)hipEventDestroy(e_in);
-      (void)hipEventDestroy(e_side);
-      return rc;
-    }
-    if (hipStreamWaitEvent(side, e_in, 0) != hipSuccess) rc = AZRBF_EHIP;
-    if (!rc) {
+    // done, so that it runs beside the latency-bound TSQR and Jacobi kernels;
+    // the first pass's Q^T c is queued as soon as Q is, beside the Jacobi SVD
+    auto on_sketch = [&]() -> int {
+      if (hipStreamWaitEvent(side, e_in, 0) != hipSuccess) return AZRBF_EHIP;
       P.swap_ws();
-      rc = az::dense_first_stage(P, B, ldb, nrhs, side);
+      const int r = az::dense_first_stage(P, B, ldb, nrhs, side);
       P.swap_ws();
-    }
-    if (!rc && hipEventRecord(e_side, side) != hipSuccess) rc = AZRBF_EHIP;
-    if (!rc && hipStreamWaitEvent(st, e_side, 0) != hipSuccess) rc = AZRBF_EHIP;
+      if (r) return r;
+      return hipEventRecord(e_side, side) == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+    };
+    auto before_products = [&]() -> int {
+      if (hipStreamWaitEvent(st, e_side, 0) != hipSuccess) return AZRBF_EHIP;
+      return az::dense_first_qtc(P, nrhs, st);
+    };
+    int rc = az::dense_factor_enqueue(P, st, e_in, on_sketch, before_products);
     // the solve needs no host-side result of the factor: it is queued at once,
     // and the retained rank stays on the device until asked for
     // (azrbf_plan_info), so the call returns without waiting for the GPU
@@ -610,7 +609,7 @@ int azrbf_solve(azrbf_plan_t h, const double* B, int64_t ldb, int64_t nrhs, doub
       P.factor_stream = st;
       rc = az::plan_mark_ready(P, st);
     }
-    if (!rc) rc = az::dense_solve(P, B, ldb, nrhs, X, ldx, relres, st, true);
+    if (!rc) rc = az::dense_solve(P, B, ldb, nrhs, X, ldx, relres, st, true, true);
     if (rc) {
       (void)hipStreamSynchronize(st);
       (void)hipStreamSynchronize(side);
