@@ -91,6 +91,22 @@ def _traffic(kernel):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def by_kernel(recs):
+    """Per-launch records grouped by kernel: the leaf and tree levels of the
+    TSQR (and of the Q formation) are launches of one kernel, as in a
+    rocprofv3 kernel trace."""
+    out = {}
+    for r in recs:
+        name = r["name"].replace(" (tree)", "")
+        e = out.setdefault(name, {"name": name, "calls": 0, "ms": 0.0, "max_ms": 0.0, "bytes": 0.0, "flops": 0.0})
+        e["calls"] += r["calls"]
+        e["ms"] += r["ms"]
+        e["max_ms"] = max(e["max_ms"], r.get("max_ms", 0.0))
+        e["bytes"] += r["bytes"]
+        e["flops"] += r.get("flops", 0.0)
+    return list(out.values())
+
+
 def roofline_of(r, total_ms):
     """Roofline entry of one kernel from the per-launch profile record."""
     avg_ms = r["ms"] / r["calls"]
@@ -296,7 +312,7 @@ def main():
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
-    kern = azrbf.profile_report()
+    kern = by_kernel(azrbf.profile_report())
     azrbf.profile_enable(False)
     kern.sort(key=lambda r: -r["ms"])
     total_ms = sum(r["ms"] for r in kern)

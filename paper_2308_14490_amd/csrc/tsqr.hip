@@ -158,9 +158,9 @@ struct QrShared {
   double (*red)[K];
   double* rowj;
   double* wv;
-  double* gv;
+  double* Gm;     // Gm[j * K + l] = v_l^T v_j (l < j)
   double* scal;
-  double* Tm;
+  double* Tm;     // Tm[j * K + i] = T(i, j); the loop leaves tau_j on the diagonal
 };
 
 // Column J of the sweep (J static, so every register index is static).
@@ -200,28 +200,15 @@ __device__ __forceinline__ void qr_column(double (&a)[RegQR<K>::RPT][K], const Q
       sh.scal[0] = beta;
       sh.scal[1] = tau;
       sh.scal[2] = scale;
+      sh.Tm[J * K + J] = tau;
     } else if (t > J) {
       sh.wv[t] = tau * fma(dt, scale, sh.rowj[t]);
     } else {
-      sh.gv[t] = fma(dt, scale, sh.rowj[t]);   // v_t[J] = a[J][t] sits below t's diagonal
+      sh.Gm[J * K + t] = fma(dt, scale, sh.rowj[t]);   // v_t[J] = a[J][t] sits below t's diagonal
     }
   }
   __syncthreads();
-  const double beta = sh.scal[0], tau = sh.scal[1], scale = sh.scal[2];
-  if (t < J) {   // T(t, J) = -tau_J sum_{l=t}^{J-1} T(t, l) g_l
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int l = t;
-    for (; l + 4 <= J; l += 4) {
-      a0 = fma(sh.Tm[l * K + t], sh.gv[l], a0);
-      a1 = fma(sh.Tm[(l + 1) * K + t], sh.gv[l + 1], a1);
-      a2 = fma(sh.Tm[(l + 2) * K + t], sh.gv[l + 2], a2);
-      a3 = fma(sh.Tm[(l + 3) * K + t], sh.gv[l + 3], a3);
-    }
-    for (; l < J; ++l) a0 = fma(sh.Tm[l * K + t], sh.gv[l], a0);
-    sh.Tm[J * K + t] = -tau * ((a0 + a1) + (a2 + a3));
-  } else if (t == J) {
-    sh.Tm[J * K + J] = tau;
-  }
+  const double beta = sh.scal[0], scale = sh.scal[2];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
     const int row = t + 256 * i;
@@ -260,7 +247,8 @@ k_tsqr_reg(const double* A, int64_t lda, int64_t m, double* __restrict__ Rout, i
   __shared__ double red[4][K];    // per-wave column sums
   __shared__ double rowj[K];      // the pivot row
   __shared__ double wv[K];        // tau_j v_j^T a_c, c > j
-  __shared__ double gv[K];        // v_c^T v_j, c < j
+  __shared__ double Gm[K * K];    // v_l^T v_j, l < j
+  __shared__ double Xs[K * K];    // products of the T assembly
   __shared__ double scal[4];      // beta, tau, scale
   __shared__ double Tm[K * K];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -278,9 +266,32 @@ k_tsqr_reg(const double* A, int64_t lda, int64_t m, double* __restrict__ Rout, i
   }
   const int col = rs_col<K>(lane);
   const bool writer = rs_writer<K>(lane);
-  QrShared<K> sh{red, rowj, wv, gv, scal, Tm};
+  QrShared<K> sh{red, rowj, wv, Gm, scal, Tm};
   qr_columns<K>(a, sh, t, lane, wave, col, writer, std::make_integer_sequence<int, K>{});
   __syncthreads();
+  // Compact-WY T by recursive doubling (kept out of the column loop, whose
+  // steps are the critical path): for adjacent blocks of b reflectors,
+  // H_1 H_2 = I - V T V^T with T = [T1, -T1 (V1^T V2) T2; 0, T2], formed as
+  // X = G12 T2, then T12 = -T1 X; b = 1, 2, 4, ..., K/2.
+#pragma unroll 1
+  for (int b = 1; b < K; b *= 2) {
+    for (int e = t; e < (K / 2) * b; e += 256) {
+      const int pr = e / (b * b), rem = e % (b * b);
+      const int l = 2 * b * pr + rem % b, j = 2 * b * pr + b + rem / b, j0 = 2 * b * pr + b;
+      double x = 0.0;
+      for (int q = j0; q <= j; ++q) x = fma(Gm[q * K + l], Tm[j * K + q], x);   // G(l, q) T(q, j)
+      Xs[j * K + l] = x;
+    }
+    __syncthreads();
+    for (int e = t; e < (K / 2) * b; e += 256) {
+      const int pr = e / (b * b), rem = e % (b * b);
+      const int i = 2 * b * pr + rem % b, j = 2 * b * pr + b + rem / b, i1 = 2 * b * pr + b;
+      double y = 0.0;
+      for (int l = i; l < i1; ++l) y = fma(Tm[l * K + i], Xs[j * K + l], y);      // T(i, l) X(l, j)
+      Tm[j * K + i] = -y;
+    }
+    __syncthreads();
+  }
   for (int e = t; e < K * K; e += 256) {
     const int r = e % K, c = e / K;
     Tout[(int64_t)blockIdx.x * K * K + e] = r <= c ? Tm[c * K + r] : 0.0;

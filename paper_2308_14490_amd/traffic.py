@@ -53,7 +53,9 @@ def prof_name(kernel):
             return f"{base} n={n}"
         return base
     m = re.search(r"az::(?:\(anonymous namespace\)::)?k_(\w+)", kernel)
-    return m.group(1) if m else None
+    if not m:
+        return None
+    return {"tsqr_reg": "tsqr_block"}.get(m.group(1), m.group(1))
 
 
 def counters(csvpath, counter):
