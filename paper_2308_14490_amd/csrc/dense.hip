@@ -55,7 +55,7 @@ int dense_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* dst, int64
   if (rows <= 0 || cols <= 0) return AZRBF_OK;
   const int64_t nq = (rows + 3) / 4;
   Prof pr("gaussian", 8.0 * rows * cols, st);
-  k_gaussian<<<dim3((unsigned)((nq + 255) / 256), (unsigned)cols), 256, 0, st>>>(seed, rows, cols, dst, ld);
+  launch_kernel(k_gaussian, dim3((unsigned)((nq + 255) / 256), (unsigned)cols), 256, 0, st, seed, rows, cols, dst, ld);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
@@ -228,7 +228,7 @@ static int tsqr(double* W, int64_t m, int64_t ld, int k, double* scratch, double
     AZ_TRY(tsqr_block_qr(L.A, lda, L.m, k, L.R, L.nb * k, L.A, lda, L.tau, st));
   }
   // (a kernel rather than a runtime copy: a launch does not block the host)
-  k_copy_doubles<<<(unsigned)((k * k + 255) / 256), 256, 0, st>>>(lv.back().R, R, (int64_t)k * k);
+  launch_kernel(k_copy_doubles, (unsigned)((k * k + 255) / 256), 256, 0, st, lv.back().R, R, (int64_t)k * k);
   AZ_HIP(hipGetLastError());
   if (r_ready) AZ_HIP(hipEventRecord(r_ready, st));   // R is final; Q is formed below
   const double* up = nullptr;
@@ -238,11 +238,8 @@ static int tsqr(double* W, int64_t m, int64_t ld, int k, double* scratch, double
     double* E = l == 0 ? Q : Ebuf[l & 1];
     const int64_t lda = l == 0 ? ld : L.m;
     Prof pr(l == 0 ? "tsqr_formq" : "tsqr_formq (tree)", 16.0 * L.m * k + 8.0 * L.nb * k * (k + 1), st);
-    switch (k) {
-      case 16: k_tsqr_formq<16><<<(unsigned)L.nb, TSQR_THREADS, 0, st>>>(L.A, lda, L.tau, L.m, up, ldup, E, lda); break;
-      case 32: k_tsqr_formq<32><<<(unsigned)L.nb, TSQR_THREADS, 0, st>>>(L.A, lda, L.tau, L.m, up, ldup, E, lda); break;
-      default: k_tsqr_formq<64><<<(unsigned)L.nb, TSQR_THREADS, 0, st>>>(L.A, lda, L.tau, L.m, up, ldup, E, lda); break;
-    }
+    auto formq = k == 16 ? k_tsqr_formq<16> : k == 32 ? k_tsqr_formq<32> : k_tsqr_formq<64>;
+    launch_kernel(formq, (unsigned)L.nb, TSQR_THREADS, 0, st, L.A, lda, L.tau, L.m, up, ldup, E, lda);
     AZ_HIP(hipGetLastError());
     up = E;
     ldup = L.m;
@@ -479,9 +476,9 @@ k_jacobi(const double* __restrict__ R, double tau_k, const double* __restrict__ 
 
 int launch_jacobi(const double* R, int k, double tau_k, const double* dmax, double tol, int max_sweeps, double* sig,
                   double* Pm, int* info, hipStream_t st) {
-  if (k == 16) k_jacobi<16><<<1, 128, 0, st>>>(R, tau_k, dmax, tol, max_sweeps, sig, Pm, info);
-  else if (k == 32) k_jacobi<32><<<1, 256, 0, st>>>(R, tau_k, dmax, tol, max_sweeps, sig, Pm, info);
-  else if (k == 64) k_jacobi<64><<<1, 512, 0, st>>>(R, tau_k, dmax, tol, max_sweeps, sig, Pm, info);
+  if (k == 16) launch_kernel(k_jacobi<16>, 1, 128, 0, st, R, tau_k, dmax, tol, max_sweeps, sig, Pm, info);
+  else if (k == 32) launch_kernel(k_jacobi<32>, 1, 256, 0, st, R, tau_k, dmax, tol, max_sweeps, sig, Pm, info);
+  else if (k == 64) launch_kernel(k_jacobi<64>, 1, 512, 0, st, R, tau_k, dmax, tol, max_sweeps, sig, Pm, info);
   else return AZRBF_EUNSUPPORTED;
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
@@ -647,9 +644,11 @@ static int gemm_nn(const double* A, int64_t lda, int64_t m, int k, const double*
   const int nc = ncol > 32 && AZ_NN_NCMAX >= 64 ? 64 : ncol > 16 && AZ_NN_NCMAX >= 32 ? 32 : 16;
   const dim3 grid((unsigned)((m + 255) / 256), (unsigned)((ncol + nc - 1) / nc));
   Prof pr("gemm_nn", 8.0 * m * (k + ncol * (beta != 0.0 ? 2.0 : 1.0)), st);
-  if (nc == 64) k_gemm_nn<64><<<grid, 256, 0, st>>>(A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta, Out, ldo);
-  else if (nc == 32) k_gemm_nn<32><<<grid, 256, 0, st>>>(A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta, Out, ldo);
-  else k_gemm_nn<16><<<grid, 256, 0, st>>>(A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta, Out, ldo);
+  if (nc == 64) launch_kernel(k_gemm_nn<64>, grid, 256, 0, st, A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta,
+                              Out, ldo);
+  else if (nc == 32) launch_kernel(k_gemm_nn<32>, grid, 256, 0, st, A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci,
+                                   beta, Out, ldo);
+  else launch_kernel(k_gemm_nn<16>, grid, 256, 0, st, A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta, Out, ldo);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
@@ -660,12 +659,12 @@ static int gemm_tn(const double* Q, int64_t ldq, int64_t m, int k, const double*
   const int64_t nb = tn_blocks(m);
   {
     Prof pr("gemm_tn", 8.0 * m * (k + ncol), st);
-    k_gemm_tn_part<<<dim3((unsigned)nb, (unsigned)((ncol + TN_COLS - 1) / TN_COLS)), 256, 0, st>>>(
-        Q, ldq, m, k, C, ldc, ncol, part);
+    launch_kernel(k_gemm_tn_part, dim3((unsigned)nb, (unsigned)((ncol + TN_COLS - 1) / TN_COLS)), 256, 0, st, Q, ldq,
+                  m, k, C, ldc, ncol, part);
   }
   AZ_HIP(hipGetLastError());
   const int64_t ne = (int64_t)k * ncol;
-  k_reduce_part<<<(unsigned)((ne + 255) / 256), 256, 0, st>>>(part, nb, k, ncol, T);
+  launch_kernel(k_reduce_part, (unsigned)((ne + 255) / 256), 256, 0, st, part, nb, k, ncol, T);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
@@ -673,11 +672,12 @@ int relres_norms(const double* R, int64_t ldr, const double* B, int64_t ldb, int
                         double* scratch, double* out, hipStream_t st) {
   const dim3 grid(NORM_CHUNKS, (unsigned)ncol);
   Prof pr("relres", 16.0 * m * ncol, st);
-  k_colnorm2_part<<<grid, 256, 0, st>>>(R, ldr, m, scratch);
+  launch_kernel(k_colnorm2_part, grid, 256, 0, st, R, ldr, m, scratch);
   AZ_HIP(hipGetLastError());
-  k_colnorm2_part<<<grid, 256, 0, st>>>(B, ldb, m, scratch + NORM_CHUNKS * ncol);
+  launch_kernel(k_colnorm2_part, grid, 256, 0, st, B, ldb, m, scratch + NORM_CHUNKS * ncol);
   AZ_HIP(hipGetLastError());
-  k_relres<<<(unsigned)((ncol + 255) / 256), 256, 0, st>>>(scratch, scratch + NORM_CHUNKS * ncol, out, ncol);
+  launch_kernel(k_relres, (unsigned)((ncol + 255) / 256), 256, 0, st, scratch, scratch + NORM_CHUNKS * ncol, out,
+                ncol);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 

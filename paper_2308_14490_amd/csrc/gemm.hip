@@ -169,8 +169,8 @@ template <bool TA, bool TB>
 void launch_gemm(dim3 grid, hipStream_t st, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                  int64_t lda, int64_t sA, const double* B, int64_t ldb, int64_t sB, double beta, const double* Cin,
                  int64_t ldci, int64_t sCi, double* C, int64_t ldc, int64_t sC, int splits, int64_t kchunk) {
-  k_gemm<TA, TB><<<grid, 256, 0, st>>>(M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cin, ldci, sCi, C, ldc, sC,
-                                       splits, kchunk);
+  launch_kernel(k_gemm<TA, TB>, grid, 256, 0, st, M, N, K, alpha, A, lda, sA, B, ldb, sB, beta, Cin, ldci, sCi, C,
+                ldc, sC, splits, kchunk);
 }
 
 }  // namespace
@@ -228,8 +228,8 @@ int gemm_mfma_c(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
   if (splits > 1) {
     const int64_t e = M * N;
     if ((e + 3) / 4 > 0x7fffffff) return AZRBF_EINVAL;
-    k_sum_splits<<<dim3((unsigned)((e + 3) / 4), (unsigned)batch), 256, 0, st>>>(
-        M, N, splits, part, M, M * N, alpha, beta, Cin, ldci, sCi, C, ldc, sC);
+    launch_kernel(k_sum_splits, dim3((unsigned)((e + 3) / 4), (unsigned)batch), 256, 0, st, M, N, splits, part, M,
+                  M * N, alpha, beta, Cin, ldci, sCi, C, ldc, sC);
     AZ_HIP(hipGetLastError());
   }
   return AZRBF_OK;

@@ -1,6 +1,7 @@
 // Internal declarations shared by the azrbf translation units.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include <string>
@@ -54,24 +55,52 @@ struct Geo {
 
 struct Plan;
 
-// Per-launch timing (plan.hip).  When enabled, a Prof object brackets one
-// kernel launch with HIP events on its stream and records the algorithmic
-// bytes the launch must move (what it reads and writes at minimum).
+// Per-launch timing (plan.hip).  When enabled, a Prof object brackets the
+// kernel launches of its scope with HIP events on its stream and records the
+// algorithmic bytes the launches must move (what they read and write at
+// minimum).  A scope that launches exactly one kernel is timed by events that
+// the kernel's own dispatch packet records (hipExtLaunchKernel), which is the
+// kernel's execution time alone, as a kernel trace measures it; a scope with
+// several launches is timed by the marker events around it.
 bool prof_enabled();
 int prof_begin(hipStream_t st);
 void prof_end(int slot, const char* name, double bytes, double flops, hipStream_t st);
+// Make `slot` the scope that this thread's next launches belong to; returns
+// the scope it replaces.
+int prof_enter(int slot);
+// For a launch inside the current scope: the start and stop events for the
+// kernel's dispatch packet if it is the scope's first launch, else false.
+bool prof_kernel_events(hipEvent_t* start, hipEvent_t* stop);
 struct Prof {
-  int slot;
+  int slot, prev;
   const char* name;
   double bytes, flops;
   hipStream_t st;
-  Prof(const char* n, double b, hipStream_t s, double f = 0.0) : slot(-1), name(n), bytes(b), flops(f), st(s) {
-    if (prof_enabled()) slot = prof_begin(st);
+  Prof(const char* n, double b, hipStream_t s, double f = 0.0)
+      : slot(-1), prev(-1), name(n), bytes(b), flops(f), st(s) {
+    if (prof_enabled()) {
+      slot = prof_begin(st);
+      if (slot >= 0) prev = prof_enter(slot);
+    }
   }
   ~Prof() {
-    if (slot >= 0) prof_end(slot, name, bytes, flops, st);
+    if (slot >= 0) {
+      prof_enter(prev);
+      prof_end(slot, name, bytes, flops, st);
+    }
   }
 };
+
+// Every kernel of the library is launched through this, so that a timed scope
+// knows how many kernels it holds.
+template <typename K, typename... A>
+inline void launch_kernel(K kern, dim3 grid, dim3 block, uint32_t lds, hipStream_t st, A... args) {
+  hipEvent_t e0, e1;
+  if (prof_enabled() && prof_kernel_events(&e0, &e1))
+    hipExtLaunchKernelGGL(kern, grid, block, lds, st, e0, e1, 0, args...);
+  else
+    kern<<<grid, block, lds, st>>>(args...);
+}
 
 int pool_trim();
 // a library stream for work that overlaps other work (plan.hip)

@@ -803,8 +803,8 @@ static int launch_fused_A_s(const Plan& P, const double* X, int64_t ldx, int64_t
   const int64_t blocks = (npairs + F::LINES - 1) / F::LINES;
   static const std::string name = "fused_A n=" + std::to_string(N);
   Prof pr(name.c_str(), 8.0 * nvec * (N + P.M * (beta != 0.0 ? 2.0 : 1.0)) + 16.0 * P.s * N, st);
-  k_fused_A<N, S><<<dim3((unsigned)blocks), dim3(F::BLOCK), F::LDS, st>>>(P.geo, P.tw, X, ldx, nvec, alpha,
-                                                                          beta, Yin, ldyi, Y, ldy);
+  launch_kernel(k_fused_A<N, S>, dim3((unsigned)blocks), dim3(F::BLOCK), F::LDS, st, P.geo, P.tw, X, ldx, nvec, alpha,
+                beta, Yin, ldyi, Y, ldy);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
@@ -827,8 +827,8 @@ static int launch_fused_Z_s(const Plan& P, const double* R, int64_t ldr, int64_t
   const int64_t blocks = (npairs + F::LINES - 1) / F::LINES;
   static const std::string name = "fused_Z n=" + std::to_string(N);
   Prof pr(name.c_str(), 8.0 * nvec * (P.M + N * (beta != 0.0 ? 2.0 : 1.0)) + 16.0 * P.s * N, st);
-  k_fused_Z<N, S><<<dim3((unsigned)blocks), dim3(F::BLOCK), F::LDS, st>>>(P.geo, P.tw, R, ldr, nvec, alpha,
-                                                                          beta, Zin, ldzi, Z, ldz);
+  launch_kernel(k_fused_Z<N, S>, dim3((unsigned)blocks), dim3(F::BLOCK), F::LDS, st, P.geo, P.tw, R, ldr, nvec, alpha,
+                beta, Zin, ldzi, Z, ldz);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
@@ -848,7 +848,7 @@ static int launch_fused_fwd(const double2* tw, const double2* in, double2* out, 
   using F = Fused<N>;
   AZ_TRY(set_lds(k_fused_fwd<N>, F::LDS));
   const int64_t blocks = (lines + F::LINES - 1) / F::LINES;
-  k_fused_fwd<N><<<dim3((unsigned)blocks), dim3(F::BLOCK), F::LDS, st>>>(tw, in, out, lines);
+  launch_kernel(k_fused_fwd<N>, dim3((unsigned)blocks), dim3(F::BLOCK), F::LDS, st, tw, in, out, lines);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
@@ -933,17 +933,18 @@ static int launch_col(const ColArgs& a) {
     case 0:
       if (tw4) {
         AZ_TRY(set_lds(k_col_fwd_A<N1, true>, lds));
-        k_col_fwd_A<N1, true><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.ldi, a.nvec, a.pair0, a.cout, C);
+        launch_kernel(k_col_fwd_A<N1, true>, grid, block, lds, a.st, g, P.tw, a.in, a.ldi, a.nvec, a.pair0, a.cout, C);
       } else {
         AZ_TRY(set_lds(k_col_fwd_A<N1, false>, lds));
-        k_col_fwd_A<N1, false><<<grid, block, lds, a.st>>>(g, P.tw, a.in, a.ldi, a.nvec, a.pair0, a.cout, C);
+        launch_kernel(k_col_fwd_A<N1, false>, grid, block, lds, a.st, g, P.tw, a.in, a.ldi, a.nvec, a.pair0, a.cout,
+                      C);
       }
       break;
     case 1:
 #define AZ_COLINV(S, D1)                                                                                \
   AZ_TRY(set_lds(k_col_inv_A<N1, S, D1>, lds_p));                                                       \
-  k_col_inv_A<N1, S, D1><<<grid_p, block_p, lds_p, a.st>>>(g, P.tw, a.cin, a.nvec, a.pair0, a.alpha,      \
-                                                           a.beta, a.oin, a.ldoi, a.out, a.ldo, Cp);
+  launch_kernel(k_col_inv_A<N1, S, D1>, grid_p, block_p, lds_p, a.st, g, P.tw, a.cin, a.nvec, a.pair0,       \
+                a.alpha, a.beta, a.oin, a.ldoi, a.out, a.ldo, Cp);
       if (tw4) {
         if (g.s == 1) { AZ_COLINV(1, true) } else if (g.s == 2) { AZ_COLINV(2, true) } else { AZ_COLINV(4, true) }
       } else {
@@ -954,7 +955,8 @@ static int launch_col(const ColArgs& a) {
     case 2:
 #define AZ_COLFZ(TW, S)                                                                                 \
   AZ_TRY(set_lds(k_col_fwd_Z<N1, TW, S>, lds_p));                                                       \
-  k_col_fwd_Z<N1, TW, S><<<grid_p, block_p, lds_p, a.st>>>(g, P.tw, a.in, a.ldi, a.nvec, a.pair0, a.cout, Cp);
+  launch_kernel(k_col_fwd_Z<N1, TW, S>, grid_p, block_p, lds_p, a.st, g, P.tw, a.in, a.ldi, a.nvec, a.pair0, \
+                a.cout, Cp);
       if (tw4) {
         if (g.s == 1) { AZ_COLFZ(true, 1) } else if (g.s == 2) { AZ_COLFZ(true, 2) } else { AZ_COLFZ(true, 4) }
       } else {
@@ -964,16 +966,16 @@ static int launch_col(const ColArgs& a) {
       break;
     case 3:
       AZ_TRY(set_lds(k_col_inv_Z<N1>, lds));
-      k_col_inv_Z<N1><<<grid, block, lds, a.st>>>(g, P.tw, a.cin, a.pstride ? a.pstride : g.N, a.nvec, a.pair0,
-                                                  a.alpha, a.beta, a.oin, a.ldoi, a.out, a.ldo, C);
+      launch_kernel(k_col_inv_Z<N1>, grid, block, lds, a.st, g, P.tw, a.cin, a.pstride ? a.pstride : g.N, a.nvec,
+                    a.pair0, a.alpha, a.beta, a.oin, a.ldoi, a.out, a.ldo, C);
       break;
     case 4:
       if (tw4) {
         AZ_TRY(set_lds(k_col_fwd_C<N1, true>, lds));
-        k_col_fwd_C<N1, true><<<grid, block, lds, a.st>>>(g, P.tw, a.cin, a.cout, C);
+        launch_kernel(k_col_fwd_C<N1, true>, grid, block, lds, a.st, g, P.tw, a.cin, a.cout, C);
       } else {
         AZ_TRY(set_lds(k_col_fwd_C<N1, false>, lds));
-        k_col_fwd_C<N1, false><<<grid, block, lds, a.st>>>(g, P.tw, a.cin, a.cout, C);
+        launch_kernel(k_col_fwd_C<N1, false>, grid, block, lds, a.st, g, P.tw, a.cin, a.cout, C);
       }
       break;
   }
@@ -1013,7 +1015,7 @@ static int launch_row(const RowArgs& a) {
   Prof pr(full[a.mode].c_str(), bytes, a.st);
   if (a.mode == 2) {
     AZ_TRY(set_lds(k_row_fwd_C<N2>, lds));
-    k_row_fwd_C<N2><<<grid, block, lds, a.st>>>(g, P.tw, a.out, Lr);
+    launch_kernel(k_row_fwd_C<N2>, grid, block, lds, a.st, g, P.tw, a.out, Lr);
     return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
   }
   // phases spread over PL lines per row (PL divides the phase count; PL * T <= 128)
@@ -1025,7 +1027,7 @@ static int launch_row(const RowArgs& a) {
   const int mode = a.mode == 0 ? ROW_A : a.mode == 1 ? ROW_Z : a.zrows ? ROW_AZC : ROW_AZ;
   auto go = [&](auto kern) -> int {
     AZ_TRY(set_lds(kern, lds_p));
-    kern<<<grid_p, block_p, lds_p, a.st>>>(g, P.tw, a.in, a.out, a.zrows, lines);
+    launch_kernel(kern, grid_p, block_p, lds_p, a.st, g, P.tw, a.in, a.out, a.zrows, lines);
     return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
   };
 #define AZ_ROWK(TW, PLV, ONEV)                                                        \
@@ -1080,8 +1082,8 @@ static int boundary_rows(Plan& P, const double* X, int64_t ldx, int64_t nvec, do
   if (nw > 64) return AZRBF_EUNSUPPORTED;
   const dim3 grid((unsigned)((P.Mb + 127) / 128), (unsigned)nvec);
   Prof pr("boundary_A", 8.0 * (double)P.Mb * nvec * (beta != 0.0 ? 2.0 : 1.0), st);
-  k_boundary_A<<<grid, 128, 0, st>>>(P.dim, P.n, P.T, P.h, P.eps, mimg, W, P.bpts, P.Mb, P.bweight, X, ldx,
-                                     nvec, alpha, beta, Yin, ldyi, Y, ldy, P.M);
+  launch_kernel(k_boundary_A, grid, 128, 0, st, P.dim, P.n, P.T, P.h, P.eps, mimg, W, P.bpts, P.Mb, P.bweight, X, ldx,
+                nvec, alpha, beta, Yin, ldyi, Y, ldy, P.M);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
@@ -1169,8 +1171,8 @@ int ops_spectra(Plan& P, hipStream_t st) {
   AZ_TRY(P.alloc((void**)&red, 4 * sizeof(double)));
   const int64_t ns = (int64_t)n * s;
   for (int which = 0; which < nk; ++which) {
-    k_sample_phases<<<(unsigned)((ns + 255) / 256), 256, 0, st>>>(samp + which * ns, n, s, P.hL, P.eps, P.T,
-                                                                  mimg, which, which == 0 ? red : nullptr);
+    launch_kernel(k_sample_phases, (unsigned)((ns + 255) / 256), 256, 0, st, samp + which * ns, n, s, P.hL, P.eps,
+                  P.T, mimg, which, which == 0 ? red : nullptr);
     AZ_HIP(hipGetLastError());
   }
   const bool engine = P.dim == 1 && !P.fused;
@@ -1183,10 +1185,10 @@ int ops_spectra(Plan& P, hipStream_t st) {
     AZ_TRY(P.alloc((void**)&P.spA, (int64_t)s * P.N * sizeof(double2)));
     AZ_TRY(P.alloc((void**)&P.spZ, (int64_t)s * P.N * sizeof(double2)));
     const unsigned nb = (unsigned)((P.N + 255) / 256);
-    k_combine_1d<<<nb, 256, 0, st>>>(fac, bvp ? fac + ns : nullptr, P.N, s, P.prob.op, P.prob.k2, opscale, D,
-                                     red);
+    launch_kernel(k_combine_1d, nb, 256, 0, st, fac, bvp ? fac + ns : nullptr, P.N, s, P.prob.op, P.prob.k2, opscale,
+                  D, red);
     AZ_HIP(hipGetLastError());
-    k_weights_1d<<<nb, 256, 0, st>>>(fac, P.spA, P.spZ, D, P.N, s, P.tauZ, red, red + 1, zeroed);
+    launch_kernel(k_weights_1d, nb, 256, 0, st, fac, P.spA, P.spZ, D, P.N, s, P.tauZ, red, red + 1, zeroed);
     AZ_HIP(hipGetLastError());
     P.geo.spA = P.spA;
     P.geo.spZ = P.spZ;
@@ -1195,9 +1197,9 @@ int ops_spectra(Plan& P, hipStream_t st) {
     P.geo.fac = fac;
     AZ_TRY(P.alloc((void**)&P.w2, P.N * sizeof(double)));
     const unsigned nb = (unsigned)((P.N + 255) / 256);
-    k_D_2d<<<nb, 256, 0, st>>>(P.geo, D, red);
+    launch_kernel(k_D_2d, nb, 256, 0, st, P.geo, D, red);
     AZ_HIP(hipGetLastError());
-    k_weights_2d<<<nb, 256, 0, st>>>(P.w2, D, P.N, P.tauZ, red, red + 1, zeroed);
+    launch_kernel(k_weights_2d, nb, 256, 0, st, P.w2, D, P.N, P.tauZ, red, red + 1, zeroed);
     AZ_HIP(hipGetLastError());
     P.geo.w2 = P.w2;
   }

@@ -185,9 +185,12 @@ namespace {
 struct ProfRec {
   std::string name;
   double bytes, flops;
-  hipEvent_t a, b;
+  hipEvent_t a, b;    // markers around the scope
+  hipEvent_t ka, kb;  // recorded by the first kernel's dispatch packet
+  int kernels;        // launches made inside the scope
   bool done;
 };
+thread_local int tl_prof_slot = -1;
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
@@ -209,11 +212,32 @@ bool prof_enabled() { return g_prof_on; }
 
 int prof_begin(hipStream_t st) {
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  ProfRec r{std::string(), 0.0, 0.0, pool_get(), pool_get(), false};
-  if (!r.a || !r.b) return -1;
+  ProfRec r{std::string(), 0.0, 0.0, pool_get(), pool_get(), pool_get(), pool_get(), 0, false};
+  if (!r.a || !r.b || !r.ka || !r.kb) {
+    for (hipEvent_t e : {r.a, r.b, r.ka, r.kb})
+      if (e) g_prof_pool.push_back(e);
+    return -1;
+  }
   (void)hipEventRecord(r.a, st);
   g_prof.push_back(r);
   return (int)g_prof.size() - 1;
+}
+
+int prof_enter(int slot) {
+  const int prev = tl_prof_slot;
+  tl_prof_slot = slot;
+  return prev;
+}
+
+bool prof_kernel_events(hipEvent_t* start, hipEvent_t* stop) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  const int slot = tl_prof_slot;
+  if (slot < 0 || slot >= (int)g_prof.size() || g_prof[slot].done) return false;
+  ProfRec& r = g_prof[slot];
+  if (r.kernels++ != 0) return false;
+  *start = r.ka;
+  *stop = r.kb;
+  return true;
 }
 
 void prof_end(int slot, const char* name, double bytes, double flops, hipStream_t st) {
@@ -832,7 +856,9 @@ int azrbf_profile_report(char* buf, int64_t len) {
   for (auto& r : az::g_prof) {
     if (!r.done) continue;
     float ms = 0.f;
-    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+    const bool own = r.kernels == 1;
+    if (hipEventSynchronize(r.b) != hipSuccess ||
+        hipEventElapsedTime(&ms, own ? r.ka : r.a, own ? r.kb : r.b) != hipSuccess) {
       rc = AZRBF_EHIP;
       continue;
     }
@@ -844,8 +870,8 @@ int azrbf_profile_report(char* buf, int64_t len) {
     if (ms > a.max_ms) a.max_ms = ms;
   }
   for (auto& r : az::g_prof) {
-    if (r.a) az::g_prof_pool.push_back(r.a);
-    if (r.b) az::g_prof_pool.push_back(r.b);
+    for (hipEvent_t e : {r.a, r.b, r.ka, r.kb})
+      if (e) az::g_prof_pool.push_back(e);
   }
   az::g_prof.clear();
   std::string out = "[";

@@ -315,7 +315,7 @@ template <int K>
 int launch_reg(const double* A, int64_t lda, int64_t m, double* R, int64_t ldr, double* V, int64_t ldv,
                double* T, hipStream_t st) {
   const int64_t nb = (m + RegQR<K>::RB - 1) / RegQR<K>::RB;
-  k_tsqr_reg<K><<<(unsigned)nb, 256, 0, st>>>(A, lda, m, R, ldr, V, ldv, T);
+  launch_kernel(k_tsqr_reg<K>, (unsigned)nb, 256, 0, st, A, lda, m, R, ldr, V, ldv, T);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 

@@ -443,7 +443,7 @@ static int wide_qr(double* Xq, int64_t m, int k, double* R, double* scr, const W
                        st));
       AZ_TRY(gemm_mfma(false, false, m, PB, done, -1.0, Xq, m, 0, rproj, done, 0, 1.0, X, m, 0, 1, part,
                        npart, st));
-      k_axpy<<<grid1(done * PB), 256, 0, st>>>(done, PB, rproj, done, Rcol, k);
+      launch_kernel(k_axpy, grid1(done * PB), 256, 0, st, done, PB, rproj, done, Rcol, k);
       AZ_HIP(hipGetLastError());
     }
     AZ_TRY(tsqr_panel(X, m, PB, tq, qpan, rpan, st));
@@ -508,10 +508,10 @@ int wide_factor(Plan& P, hipStream_t st) {
   const int nbj = k / JB, npairs = nbj / 2;
   {
     dim3 tg((unsigned)((k + 31) / 32), (unsigned)((k + 31) / 32));
-    k_transpose<<<tg, 256, 0, st>>>(k, P.Rf, P.Vj);
+    launch_kernel(k_transpose, tg, 256, 0, st, k, P.Rf, P.Vj);
     AZ_HIP(hipGetLastError());
     AZ_TRY(wide_qr(P.Vj, k, k, P.Pm, scr, Lx, rproj, st));    // Vj = Q2, Pm = R2 (scratch until step 4)
-    k_transpose<<<tg, 256, 0, st>>>(k, P.Pm, P.Gj);
+    launch_kernel(k_transpose, tg, 256, 0, st, k, P.Pm, P.Gj);
     AZ_HIP(hipGetLastError());
   }
   const int rot_lds = (int)(sizeof(double) * 2 * JP * (JP + 2));
@@ -537,17 +537,17 @@ int wide_factor(Plan& P, hipStream_t st) {
       {
         Prof pr("jac_gram", 8.0 * k * 64 * npairs + 8.0 * 4096 * npairs * Lx.rsplit, st,
                 2.0 * k * 64 * 64 * npairs);
-        k_jac_gram<<<dim3((unsigned)npairs, (unsigned)Lx.rsplit), 256, 0, st>>>(k, P.Gj, r, nbj, Lx.rsplit, Lx.rch,
-                                                                              Hp);
+        launch_kernel(k_jac_gram, dim3((unsigned)npairs, (unsigned)Lx.rsplit), 256, 0, st, k, P.Gj, r, nbj, Lx.rsplit,
+                      Lx.rch, Hp);
       }
       {
         Prof pr("jac_eig", 8.0 * 4096 * npairs * (Lx.rsplit + 1), st);
-        k_jac_eig<<<npairs, EIG_THREADS, eig_lds, st>>>(Hp, Lx.rsplit, tol, Vp, cnt + (int64_t)r * npairs);
+        launch_kernel(k_jac_eig, npairs, EIG_THREADS, eig_lds, st, Hp, Lx.rsplit, tol, Vp, cnt + (int64_t)r * npairs);
       }
       {
         Prof pr("jac_rot", 2.0 * 16.0 * k * 64 * npairs, st, 2.0 * 2.0 * k * 64 * 64 * npairs);
-        k_jac_rot<<<dim3((unsigned)((k / 64 + ROT_TILES - 1) / ROT_TILES), (unsigned)npairs, 2), 256, rot_lds, st>>>(
-            k, P.Gj, P.Vj, r, nbj, Vp);
+        launch_kernel(k_jac_rot, dim3((unsigned)((k / 64 + ROT_TILES - 1) / ROT_TILES), (unsigned)npairs, 2), 256,
+                      rot_lds, st, k, P.Gj, P.Vj, r, nbj, Vp);
       }
       AZ_HIP(hipGetLastError());
     }
@@ -561,11 +561,11 @@ int wide_factor(Plan& P, hipStream_t st) {
   // 4. singular values, truncation, P = R^+ = sum_i w_i g_i^T / sigma_i^2
   // (w_i the columns of Q2 V_J, g_i = u_i sigma_i those of the rotated G)
   double* sraw = P.sig + k;
-  k_colnorms<<<k, 256, 0, st>>>(k, P.Gj, sraw);
-  k_rank_sort<<<grid1(k), 256, 0, st>>>(k, sraw, P.sig);
+  launch_kernel(k_colnorms, k, 256, 0, st, k, P.Gj, sraw);
+  launch_kernel(k_rank_sort, grid1(k), 256, 0, st, k, sraw, P.sig);
   AZ_TRY(ops_norms(P, st));
   const double thr = P.tau * P.normA * sqrt((double)k);
-  k_scale_cols<<<grid1((int64_t)k * k), 256, 0, st>>>(k, P.Vj, sraw, thr, P.Om2);
+  launch_kernel(k_scale_cols, grid1((int64_t)k * k), 256, 0, st, k, P.Vj, sraw, thr, P.Om2);
   AZ_HIP(hipGetLastError());
   AZ_TRY(gemm_mfma(false, true, k, k, k, 1.0, P.Om2, k, 0, P.Gj, k, 0, 0.0, P.Pm, k, 0, 1, nullptr, 0, st));
   std::vector<double> hs(k);
@@ -611,7 +611,7 @@ int wide_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, i
       AZ_TRY(ops_apply_Z(P, R1, Mt, nrhs, 1.0, 1.0, X1, N, X, ldx, st));                     // x = x1 + x2
     } else {
       AZ_TRY(ops_apply_Z(P, R1, Mt, nrhs, 1.0, 1.0, X1, N, X1, N, st));                      // x1 + x2
-      k_axpy<<<grid1(N * nrhs), 256, 0, st>>>(N, nrhs, X1, N, X, ldx);
+      launch_kernel(k_axpy, grid1(N * nrhs), 256, 0, st, N, nrhs, X1, N, X, ldx);
       AZ_HIP(hipGetLastError());
     }
     AZ_TRY(ops_apply_A(P, X, ldx, nrhs, -1.0, 1.0, B, ldb, Rc, Mt, st));                     // b - A x
