@@ -139,27 +139,42 @@ k_tsqr_formq(const double* __restrict__ V, int64_t ldv, const double* __restrict
     for (int q = 0; q < PER; ++q) Mr[(i0 + IS * q) * K + c0] = acc[q];
   }
   __syncthreads();
-  // rows: E[r][c] = C_b[r][c] (r < K) - sum_l V[r][l] M[l][c], all c at once
+  // rows: E[r][c] = C_b[r][c] (r < K) - sum_l V[r][l] M[l][c], all c at once.
+  // The row's reflector entries are streamed LC at a time, the next LC loads
+  // issued before the current LC are used, so the loads' latency overlaps the
+  // products instead of stalling each step.
   constexpr int CH = K < 32 ? K : 32;    // columns per pass (registers)
+  constexpr int LC = 8;                  // reflector entries per load batch
 #pragma unroll 1
   for (int r = t; r < RB; r += TSQR_THREADS) {
     const int64_t gi = r0 + r;
     if (gi >= m) break;
+    const double* vrow = V + gi;
 #pragma unroll
     for (int c0p = 0; c0p < K; c0p += CH) {
       double acc[CH];
 #pragma unroll
       for (int c = 0; c < CH; ++c) acc[c] = r < K ? Cb[(c0p + c) * LD + r] : 0.0;
-#pragma unroll 2
-      for (int l = 0; l < K; ++l) {
-        const double v = V[gi + ldv * l];   // streamed: one coalesced load per l
-        const double2* mrow = reinterpret_cast<const double2*>(Mr + l * K + c0p);
+      double vb[LC];
 #pragma unroll
-        for (int c = 0; c < CH; c += 2) {
-          const double2 mm = mrow[c / 2];
-          acc[c] = fma(-v, mm.x, acc[c]);
-          acc[c + 1] = fma(-v, mm.y, acc[c + 1]);
+      for (int e = 0; e < LC; ++e) vb[e] = vrow[ldv * e];
+#pragma unroll 1
+      for (int l0 = 0; l0 < K; l0 += LC) {
+        double vn[LC];   // the next batch (wraps to the first at the end: always in bounds, unused)
+#pragma unroll
+        for (int e = 0; e < LC; ++e) vn[e] = vrow[ldv * ((l0 + LC + e) % K)];
+#pragma unroll
+        for (int e = 0; e < LC; ++e) {
+          const double2* mrow = reinterpret_cast<const double2*>(Mr + (l0 + e) * K + c0p);
+#pragma unroll
+          for (int c = 0; c < CH; c += 2) {
+            const double2 mm = mrow[c / 2];
+            acc[c] = fma(-vb[e], mm.x, acc[c]);
+            acc[c + 1] = fma(-vb[e], mm.y, acc[c + 1]);
+          }
         }
+#pragma unroll
+        for (int e = 0; e < LC; ++e) vb[e] = vn[e];
       }
 #pragma unroll
       for (int c = 0; c < CH; ++c) E[gi + lde * (c0p + c)] = acc[c];
