@@ -300,6 +300,33 @@ __device__ __forceinline__ double sum16(double x) {
   x = sum8(x);
   return x + jdpp<0x140>(x);
 }
+// The same sums for two or three values, stage by stage, so that the
+// independent DPP moves and adds of one stage overlap instead of each sum
+// waiting for the previous one (bitwise the same results as separate sums).
+template <int CTRL>
+__device__ __forceinline__ void jstage2(double& a, double& b) {
+  const double ta = jdpp<CTRL>(a), tb = jdpp<CTRL>(b);
+  a += ta;
+  b += tb;
+}
+template <int CTRL>
+__device__ __forceinline__ void jstage3(double& a, double& b, double& c) {
+  const double ta = jdpp<CTRL>(a), tb = jdpp<CTRL>(b), tc = jdpp<CTRL>(c);
+  a += ta;
+  b += tb;
+  c += tc;
+}
+__device__ __forceinline__ void sum8x2(double& a, double& b) {
+  jstage2<0xB1>(a, b);
+  jstage2<0x4E>(a, b);
+  jstage2<0x141>(a, b);
+}
+__device__ __forceinline__ void sum16x3(double& a, double& b, double& c) {
+  jstage3<0xB1>(a, b, c);
+  jstage3<0x4E>(a, b, c);
+  jstage3<0x141>(a, b, c);
+  jstage3<0x140>(a, b, c);
+}
 
 // Truncated pseudo-inverse of the k x k triangular factor R (k in {16, 32,
 // 64}) by a preconditioned one-sided Jacobi SVD, in one block of 8k threads.
@@ -380,8 +407,9 @@ k_jacobi(const double* __restrict__ R, double tau_k, const double* __restrict__ 
         dc = fma(vv[e], ac[e], dc);
         dr = fma(vv[e], wr[e], dr);
       }
-      dc = sum8(dc) * beta;
-      dr = sum8(dr) * beta;
+      sum8x2(dc, dr);
+      dc *= beta;
+      dr *= beta;
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
         const int i = j + sl + 8 * e;
@@ -429,9 +457,7 @@ k_jacobi(const double* __restrict__ R, double tau_k, const double* __restrict__ 
         be = fma(y[e], y[e], be);
         ga = fma(x[e], y[e], ga);
       }
-      al = sum16(al);
-      be = sum16(be);
-      ga = sum16(ga);
+      sum16x3(al, be, ga);
       // (|ga| > 1e-150 keeps 4 ga^2 a normal number below)
       if (ga * ga > tol2 * (al * be) && fabs(ga) > 1e-150) {
         rotated = 1;
