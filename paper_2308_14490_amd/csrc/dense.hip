@@ -360,10 +360,8 @@ k_jacobi(const double* __restrict__ R, double tau_k, const double* __restrict__ 
   constexpr int KM1 = K - 1;
   __shared__ double A[K * LD];    // A[c * LD + r] = entry (r, c)
   __shared__ double W[K * LD];    // Q2, then Q2 W; same layout
-  __shared__ double hv[K];        // current reflector (entries j .. K-1)
   __shared__ double sv[K], inv2[K];
   __shared__ int ord[K];
-  __shared__ double hbeta;
   const int t = threadIdx.x;
   for (int i = t; i < K * K; i += NT) {
     const int r = i % K, c = i / K;
@@ -374,36 +372,43 @@ k_jacobi(const double* __restrict__ R, double tau_k, const double* __restrict__ 
 
   // ---- Householder QR of A; Q2 accumulated into W from the right
   {
+    // Every 8-lane slot forms reflector j itself from column j of A (the same
+    // sums in the same order in every slot, so all slots hold the same bits),
+    // which saves a serial step and a barrier per reflector.  Column j is
+    // still being read during step j, so its final entries (alpha, zeros)
+    // are written by slot j in step j + 1, when no slot reads it.
     const int slot = t >> 3, sl = t & 7;
+    double alpha_prev = 0.0;
     for (int j = 0; j < KM1; ++j) {
-      if (t < 16) {
-        double s = 0.0;
-        for (int i = j + t; i < K; i += 16) {
-          const double x = A[j * LD + i];
-          s = fma(x, x, s);
+      if (j > 0 && slot == j - 1) {
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          const int i = j - 1 + sl + 8 * e;
+          if (i < K) A[(j - 1) * LD + i] = i == j - 1 ? alpha_prev : 0.0;
         }
-        s = sum16(s);
-        const double x0 = A[j * LD + j];
-        const double nrm = sqrt(s);
-        const double alpha = x0 >= 0.0 ? -nrm : nrm;
-        for (int i = j + t; i < K; i += 16) {
-          hv[i] = i == j ? x0 - alpha : A[j * LD + i];
-          A[j * LD + i] = i == j ? alpha : 0.0;
-        }
-        if (t == 0) hbeta = nrm == 0.0 ? 0.0 : 1.0 / (nrm * (nrm + fabs(x0)));
       }
-      __syncthreads();
-      const double beta = hbeta;
       const bool col = slot > j;                 // this slot's column of A needs the reflector
       double vv[EPL], ac[EPL], wr[EPL];
-      double dc = 0.0, dr = 0.0;
+      double ss = 0.0;
 #pragma unroll
       for (int e = 0; e < EPL; ++e) {
         const int i = j + sl + 8 * e;
         const bool ok = i < K;
-        vv[e] = ok ? hv[i] : 0.0;
+        vv[e] = ok ? A[j * LD + i] : 0.0;
         ac[e] = ok && col ? A[slot * LD + i] : 0.0;
         wr[e] = ok ? W[i * LD + slot] : 0.0;     // entry (slot, i) of Q2
+        ss = fma(vv[e], vv[e], ss);
+      }
+      const double x0 = A[j * LD + j];
+      ss = sum8(ss);
+      const double nrm = sqrt(ss);
+      const double alpha = x0 >= 0.0 ? -nrm : nrm;
+      const double beta = nrm == 0.0 ? 0.0 : 1.0 / (nrm * (nrm + fabs(x0)));
+      alpha_prev = alpha;
+      double dc = 0.0, dr = 0.0;
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        if (sl + 8 * e == 0) vv[e] = x0 - alpha;   // the entry i = j
         dc = fma(vv[e], ac[e], dc);
         dr = fma(vv[e], wr[e], dr);
       }
@@ -420,6 +425,14 @@ k_jacobi(const double* __restrict__ R, double tau_k, const double* __restrict__ 
       }
       __syncthreads();
     }
+    if (slot == KM1 - 1) {
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const int i = KM1 - 1 + sl + 8 * e;
+        if (i < K) A[(KM1 - 1) * LD + i] = i == KM1 - 1 ? alpha_prev : 0.0;
+      }
+    }
+    __syncthreads();
     // A now holds R2 (column-major); the Jacobi works on its transpose
     for (int i = t; i < K * K; i += NT) {
       const int r = i % K, c = i / K;
