@@ -224,6 +224,9 @@ def main():
     ap.add_argument("--serve-count", type=int, default=48)
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps only (for rocprofv3 runs)")
+    ap.add_argument("--only-2d", action="store_true",
+                    help="run only the full-size 2D factorisation and solve, print its figures as JSON "
+                         "(for rocprofv3 runs of the wide-sketch stage)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
@@ -237,6 +240,9 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
+    if args.only_2d:
+        print(json.dumps(wide_2d(log)), flush=True)
+        return 0
     prob = W.config_c2(n=args.n, nrhs=args.nrhs)
     mask = azrbf.make_mask(1, prob.n, prob.s, prob.T, prob.domain.contains)
     p0 = problems.plan_for(prob)
