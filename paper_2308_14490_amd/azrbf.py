@@ -265,6 +265,9 @@ def solve(p, B, X=None, relres=None, stream=None):
         raise ValueError("B and X hold different numbers of vectors")
     if relres is None:
         relres = torch.empty(nrhs, dtype=torch.float64, device=B.device)
+    if (relres.dtype != torch.float64 or not relres.is_cuda or not relres.is_contiguous()
+            or relres.numel() < nrhs):
+        raise ValueError(f"relres must be a contiguous float64 CUDA tensor of at least {nrhs} entries")
     _check(_lib().azrbf_solve(p.handle, B.data_ptr(), ldb, nrhs, X.data_ptr(), ldx, relres.data_ptr(),
                               _stream(stream)), "azrbf_solve")
     p.k = p.dims()[4]       # a first solve factors, and the width may have grown

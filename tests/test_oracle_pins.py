@@ -422,3 +422,91 @@ def test_local_evaluator_matches_dense():
         M = idx.size
         got = evaluate.apply_local(prob, x, pts)
         assert np.max(np.abs(got - A[:M] @ x)) < 1e-13 * np.abs(A[:M] @ x).max()
+
+
+# ---------------------------------------------------------------- BVP right-hand sides
+
+def _bvp_1d_manufactured(n):
+    """u = sin(k x) + x^2 on [-1, 1] with k = n/5 solves -(u'' + k^2 u) = f
+    for f = -(2 + k^2 x^2), u(+-1) = sin(+-k) + 1 (section 6.1 setting: T = 1.5,
+    s = 2, tau0 = 1e-10).  Returns the problem, the oracle's system and u."""
+    T = 1.5
+    eps = rbf.shape_parameter(1e-10, n, T)
+    kk = n / 5.0
+
+    def u(x):
+        return np.sin(kk * x) + x * x
+
+    def f(x):
+        return -(2.0 + kk * kk * x * x)
+    p = W.Problem("m1", 1, n, 2, T, eps * 2 * T / n, W.interval(-1.0, 1.0), [f],
+                  op=W.HELMHOLTZ, k2=kk * kk, bnd=[u], nb=2, exact=[u])
+    A, idx, pts, bpts = dense.system_matrix(p)
+    return p, A, idx, dense.rhs(p, pts, bpts)[:, 0], u
+
+
+def _bvp_err(p, A, b, u, svd=None):
+    x, _ = lstsq.tsvd_solve(A, b, svd=svd)
+    tp = W.test_points(p, m2d=100)
+    return np.abs(evaluate.eval_dense(p, x, tp) - u(*tp.T)).max()
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_bvp_1d_rhs_scaling_manufactured_solution(n):
+    """The interior data must carry the same factor as the operator rows
+    (f / (2 eps^2) in 1D): the oracle then recovers a manufactured solution
+    with nonzero f to the accuracy of the section 6.3 experiment (max error
+    below 1e-8).  The same system with the interior data's sign flipped, or
+    left unscaled, misses u by O(1) or more, so either mistake in the
+    oracle's right-hand side would fail here."""
+    p, A, idx, b, u = _bvp_1d_manufactured(n)
+    M = idx.size
+    svd = lstsq.tsvd(A)
+    assert _bvp_err(p, A, b, u, svd) < 1e-8
+    flip = b.copy()
+    flip[:M] *= -1.0
+    assert _bvp_err(p, A, flip, u, svd) > 1.0
+    raw = b.copy()
+    raw[:M] *= 2.0 * p.eps ** 2          # f itself, the factor dropped
+    assert _bvp_err(p, A, raw, u, svd) > 1.0
+
+
+@pytest.mark.parametrize("k2", [0.0, 5.0])
+def test_bvp_2d_rhs_scaling_manufactured_solution(k2):
+    """Poisson (k2 = 0) and Helmholtz (k2 = 5) on the star r = 0.7 + 0.1 cos 5t
+    at n = 32 with weak Dirichlet rows: u = sin 2x cos 3y has -Lap u = 13 u,
+    so f = (13 - k2) u.  The oracle's solution matches u to 1e-5 (measured
+    4e-6); a flipped sign of the interior data, the factor 1/(4 eps^2)
+    dropped, or the 1D factor 1/(2 eps^2) in its place each leave an error
+    above 0.1."""
+    p = W.config_c4(32)
+    p.k2 = k2
+
+    def u(x, y):
+        return np.sin(2 * x) * np.cos(3 * y)
+    p.rhs = [lambda x, y: (13.0 - k2) * u(x, y)]
+    p.bnd = [u]
+    A, idx, pts, bpts = dense.system_matrix(p)
+    b = dense.rhs(p, pts, bpts)[:, 0]
+    M = idx.size
+    f_direct = (13.0 - k2) * u(pts[:, 0], pts[:, 1]) / (4.0 * p.eps ** 2)
+    assert np.max(np.abs(b[:M] - f_direct)) <= 1e-15 * np.max(np.abs(f_direct))
+    assert np.array_equal(b[M:], u(bpts[:, 0], bpts[:, 1]))
+    svd = lstsq.tsvd(A)
+    assert _bvp_err(p, A, b, u, svd) < 1e-5
+    for fac in (-1.0, 4.0 * p.eps ** 2, 2.0):
+        bad = b.copy()
+        bad[:M] *= fac
+        assert _bvp_err(p, A, bad, u, svd) > 0.1, fac
+
+
+def test_nyquist_minimum_is_smallest_diagonal_entry():
+    """Lemma 4.3: the first diagonal of B is smallest at the Nyquist index;
+    ``nyquist_minimum`` returns that entry, which equals the minimum of the
+    diagonal taken from the explicit block-diagonal form of the matrix."""
+    for n in [16, 32]:
+        p = W.Problem("t", 1, n, 1, 1.0, rbf.shape_parameter(1e-10, n, 1.0) * 2 / n, W.box(1.0), [])
+        d = periodic.diagonals(periodic.block_diagonal_form(p), p.N)[0].real
+        got = spectra.nyquist_minimum(n, 1.0, p.eps)
+        assert abs(got - d.min()) <= 1e-12 * np.abs(d).max()
+        assert np.argmin(d) == n // 2
