@@ -50,7 +50,8 @@ enum {
   AZRBF_ENOMEM = -3,        /* device allocation failed                      */
   AZRBF_EHIP = -4,          /* a HIP runtime call failed                     */
   AZRBF_ERANK = -5,         /* sketch not rank-revealing at the largest k    */
-  AZRBF_ESTATE = -6         /* call not valid in the plan's current state    */
+  AZRBF_ESTATE = -6,        /* call not valid in the plan's current state    */
+  AZRBF_ESCRATCH = -7       /* request exceeds a fixed scratch buffer         */
 };
 
 enum {
@@ -214,6 +215,21 @@ int azrbf_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* dst, int64
 int azrbf_dgemm(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k, double alpha,
                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
                 int64_t ldc, void* stream);
+
+/* azrbf_dgemm without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, arithmetic and split of the reduction as
+ * azrbf_dgemm (so the same result bit for bit), but the split-K partial tiles
+ * live in a fixed device array of the library, 2^20 doubles (8 MiB) per GPU,
+ * held from the first call on that GPU until the process ends; a product
+ * whose split needs more returns AZRBF_ESCRATCH and computes nothing.  The
+ * call is stream-ordered and does not synchronise.  The array belongs to the
+ * current device (the stream must be one of its streams); every call on that
+ * GPU shares it, so calls that may overlap on one GPU (different streams,
+ * host threads) race and must be ordered by the caller. */
+int azrbf_dgemm_noalloc(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k, double alpha,
+                        const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                        int64_t ldc, void* stream);
 
 /* Tile shapes of the FFT passes for transforms that need the three-pass
  * engine (1D N > 8192 and all 2D plans): times apply_A followed by

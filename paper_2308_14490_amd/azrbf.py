@@ -18,7 +18,7 @@ import torch   # imported before the library: the process keeps one HIP runtime
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libazrbf.so")
 
-OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ERANK, ESTATE = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, ERANK, ESTATE, ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
 OP_APPROX, OP_BVP = 0, 1
 
 
@@ -71,6 +71,8 @@ EXPORTS = {
     "azrbf_gaussian": (ctypes.c_int, [ctypes.c_uint64, _I64, _I64, _P, _I64, _P]),
     "azrbf_dgemm": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _I64, _I64, _I64, _D, _P, _I64, _P, _I64,
                                    _D, _P, _I64, _P]),
+    "azrbf_dgemm_noalloc": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _I64, _I64, _I64, _D, _P, _I64, _P,
+                                           _I64, _D, _P, _I64, _P]),
     "azrbf_autotune": (ctypes.c_int, [_P, _I64, _P, ctypes.c_char_p, _I64]),
     "azrbf_tune_table": (ctypes.c_int, [ctypes.c_char_p, _I64]),
     "azrbf_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
@@ -337,9 +339,10 @@ def _colmajor(t, name):
     return t.shape[1], t.shape[0], max(t.stride(0), t.shape[1], 1)
 
 
-def dgemm(A, B, C=None, transa=False, transb=False, alpha=1.0, beta=0.0, stream=None):
+def dgemm(A, B, C=None, transa=False, transb=False, alpha=1.0, beta=0.0, stream=None, noalloc=False):
     """C = alpha op(A) op(B) + beta C on the matrix cores.  Matrices are
-    column-major, held as (cols, rows) tensors (tensor row j = column j)."""
+    column-major, held as (cols, rows) tensors (tensor row j = column j).
+    noalloc: use azrbf_dgemm_noalloc (no device allocation; C must be given)."""
     ra, ca, lda = _colmajor(A, "A")
     rb, cb, ldb = _colmajor(B, "B")
     m, k = (ca, ra) if transa else (ra, ca)
@@ -351,8 +354,10 @@ def dgemm(A, B, C=None, transa=False, transb=False, alpha=1.0, beta=0.0, stream=
     rc_, cc_, ldc = _colmajor(C, "C")
     if (rc_, cc_) != (m, n):
         raise ValueError(f"C must hold a {m} x {n} matrix")
-    _check(_lib().azrbf_dgemm(int(bool(transa)), int(bool(transb)), m, n, k, float(alpha), A.data_ptr(), lda,
-                              B.data_ptr(), ldb, float(beta), C.data_ptr(), ldc, _stream(stream)), "azrbf_dgemm")
+    fn = _lib().azrbf_dgemm_noalloc if noalloc else _lib().azrbf_dgemm
+    _check(fn(int(bool(transa)), int(bool(transb)), m, n, k, float(alpha), A.data_ptr(), lda,
+              B.data_ptr(), ldb, float(beta), C.data_ptr(), ldc, _stream(stream)),
+           "azrbf_dgemm_noalloc" if noalloc else "azrbf_dgemm")
     return C
 
 

@@ -13,6 +13,7 @@
 // over blocks: each writes a partial tile, and k_sum_splits adds them in a
 // fixed order, so results do not depend on scheduling.
 #include <algorithm>
+#include <mutex>
 
 #include "internal.h"
 
@@ -243,3 +244,92 @@ int gemm_mfma(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha, c
 }
 
 }  // namespace az
+
+// --------------------------------------------------------------- C ABI
+
+namespace {
+
+int dgemm_args(int64_t m, int64_t n, int64_t k, int32_t transa, int32_t transb, const double* A, int64_t lda,
+               const double* B, int64_t ldb, const double* C, int64_t ldc) {
+  if (m < 0 || n < 0 || k < 0) return AZRBF_EINVAL;
+  if (m == 0 || n == 0) return AZRBF_OK;
+  if (!C || ldc < m) return AZRBF_EINVAL;
+  if (k > 0) {
+    if (!A || !B) return AZRBF_EINVAL;
+    if (lda < std::max<int64_t>(1, transa ? k : m) || ldb < std::max<int64_t>(1, transb ? n : k))
+      return AZRBF_EINVAL;
+  }
+  return AZRBF_OK;
+}
+
+// Split-K partial tiles of azrbf_dgemm_noalloc: one fixed array per GPU.
+constexpr int64_t kScratchDoubles = int64_t(1) << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+std::mutex scratch_mu;
+double* scratch_dev[kMaxDevices];   // device address of `scratch` per device
+
+// The address of this device's copy of `scratch`, looked up once per device
+// with that device current (the host-side name is not a device address).
+int scratch_ptr(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return AZRBF_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return AZRBF_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return AZRBF_EHIP;
+    }
+    scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = scratch_dev[dev];
+  return AZRBF_OK;
+}
+
+}  // namespace
+
+extern "C" int azrbf_dgemm(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k, double alpha,
+                           const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+                           int64_t ldc, void* stream) {
+  const int bad = dgemm_args(m, n, k, transa, transb, A, lda, B, ldb, C, ldc);
+  if (bad || m == 0 || n == 0) return bad;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t need = az::gemm_split_doubles(m, n, k, 1);
+  double* part = nullptr;
+  if (need > 0 && hipMalloc((void**)&part, sizeof(double) * need) != hipSuccess) {
+    (void)hipGetLastError();
+    part = nullptr;   // unsplit fallback: the same product, fewer blocks
+  }
+  int rc = az::gemm_mfma(transa != 0, transb != 0, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1,
+                         part, part ? need : 0, st);
+  if (part) {
+    if (hipStreamSynchronize(st) != hipSuccess) rc = AZRBF_EHIP;
+    (void)hipFree(part);
+  }
+  return rc;
+}
+
+extern "C" int azrbf_dgemm_noalloc(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k,
+                                   double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                                   double beta, double* C, int64_t ldc, void* stream) {
+  const int bad = dgemm_args(m, n, k, transa, transb, A, lda, B, ldb, C, ldc);
+  if (bad || m == 0 || n == 0) return bad;
+  const int64_t need = az::gemm_split_doubles(m, n, k, 1);
+  if (need > kScratchDoubles) return AZRBF_ESCRATCH;
+  double* part = nullptr;
+  if (need > 0) {
+    const int rc = scratch_ptr(&part);
+    if (rc) return rc;
+  }
+  // every partial tile is written before k_sum_splits reads it: nothing to clear
+  return az::gemm_mfma(transa != 0, transb != 0, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1,
+                       part, need, (hipStream_t)stream);
+}

@@ -381,6 +381,7 @@ const char* azrbf_strerror(int code) {
     case AZRBF_EHIP: return "HIP runtime error";
     case AZRBF_ERANK: return "sketch not rank-revealing: all sketch directions retained";
     case AZRBF_ESTATE: return "call not valid in the plan's state";
+    case AZRBF_ESCRATCH: return "needs more than the fixed scratch buffer of the allocation-free entry point";
     default: return "unknown error";
   }
 }
@@ -780,33 +781,6 @@ int azrbf_get_factor(azrbf_plan_t h, int32_t which, double* dst, int64_t ld, voi
 int azrbf_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* dst, int64_t ld, void* stream) {
   if (rows < 0 || cols < 0 || (rows > 0 && cols > 0 && (!dst || ld < rows))) return AZRBF_EINVAL;
   return az::dense_gaussian(seed, rows, cols, dst, ld, (hipStream_t)stream);
-}
-
-int azrbf_dgemm(int32_t transa, int32_t transb, int64_t m, int64_t n, int64_t k, double alpha,
-                const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
-                int64_t ldc, void* stream) {
-  if (m < 0 || n < 0 || k < 0) return AZRBF_EINVAL;
-  if (m == 0 || n == 0) return AZRBF_OK;
-  if (!C || ldc < m) return AZRBF_EINVAL;
-  if (k > 0) {
-    if (!A || !B) return AZRBF_EINVAL;
-    if (lda < std::max<int64_t>(1, transa ? k : m) || ldb < std::max<int64_t>(1, transb ? n : k))
-      return AZRBF_EINVAL;
-  }
-  hipStream_t st = (hipStream_t)stream;
-  const int64_t need = az::gemm_split_doubles(m, n, k, 1);
-  double* part = nullptr;
-  if (need > 0 && hipMalloc((void**)&part, sizeof(double) * need) != hipSuccess) {
-    (void)hipGetLastError();
-    part = nullptr;   // unsplit fallback: same result, fewer blocks
-  }
-  int rc = az::gemm_mfma(transa != 0, transb != 0, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1,
-                         part, part ? need : 0, st);
-  if (part) {
-    if (hipStreamSynchronize(st) != hipSuccess) rc = AZRBF_EHIP;
-    (void)hipFree(part);
-  }
-  return rc;
 }
 
 int azrbf_autotune(azrbf_plan_t h, int64_t nvec, void* stream, char* report, int64_t len) {
