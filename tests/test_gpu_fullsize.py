@@ -125,3 +125,55 @@ def test_fullsize_2d_poisson_star():
     assert np.all(rc <= 10 * ro)
     assert np.all(eg <= 10 * eo)
     p.destroy()
+
+
+# ------------------------------------------------ element-wise, full-size kernels
+
+U = 2.0 ** -53
+
+
+def _sample_rows(M, rng, count=3000, edge=256):
+    """First and last rows (the ragged ends of the tiles) and a random sample."""
+    pick = rng.choice(M, size=min(count, M), replace=False)
+    return np.unique(np.concatenate([np.arange(min(edge, M)), np.arange(max(0, M - edge), M), pick]))
+
+
+def _apply_elementwise(prob, nvec, tune=False):
+    """A X at full size against the oracle's windowed direct sums on sampled
+    rows (every boundary row included).  FFT rounding gives a relative error
+    of about u log2 N; the bound is 20 u log2 N of the largest entry."""
+    azrbf, problems = _mods()
+    if tune:
+        import os
+        azrbf.tune_load_file(os.path.join(os.path.dirname(azrbf.__file__), "tune_mi355x.json"))
+    p = problems.plan_for(prob)
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((nvec, prob.N))
+    announce("apply_A full size", prob.name, prob.n, "nvec", nvec, "M", p.M, "Mb", p.Mb)
+    Y = azrbf.apply_A(p, torch.from_numpy(X).cuda()).cpu().numpy()
+    rows = _sample_rows(p.M, rng)
+    want = evaluate.apply_local(prob, X.T, p.points()[rows]).T
+    got = Y[:, rows]
+    if prob.nb:
+        want = np.concatenate([want, prob.bweight * evaluate.apply_local(prob, X.T, prob.bpoints(), op=0).T], axis=1)
+        got = np.concatenate([got, Y[:, p.M:]], axis=1)
+    err = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    tol = 20 * U * np.log2(prob.N)
+    announce("rows", got.shape[1], "rel err", err, "tol", tol)
+    assert err < tol
+    p.destroy()
+
+
+def test_apply_A_elementwise_full_1d():
+    """N = 65536, M = 65537, 64 vectors with the tile shapes the benchmark
+    loads: the four-step kernels the benchmark times."""
+    _apply_elementwise(W.config_c2(65536, 1), 64, tune=True)
+
+
+def test_apply_A_elementwise_full_2d_disk():
+    _apply_elementwise(W.config_c3a(128), 8)
+
+
+def test_apply_A_elementwise_full_2d_poisson_star():
+    """n = 256 Poisson rows -(Lap) phi / (4 eps^2) and the 2517 Dirichlet rows."""
+    _apply_elementwise(W.config_c4(256), 4)

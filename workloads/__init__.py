@@ -21,7 +21,7 @@ from typing import Callable, Optional
 import numpy as np
 
 __all__ = [
-    "Domain", "interval", "disk", "star", "box",
+    "Domain", "interval", "disk", "star", "box", "shape_parameter_eh",
     "Problem", "trig_sum_1d", "trig_sum_2d",
     "config_c1", "config_c1a", "config_c2", "config_c3", "config_c3a",
     "config_c4", "family_1d", "served_stream", "test_points",
@@ -55,10 +55,20 @@ def interval(a: float, b: float) -> Domain:
                   lambda x: (x >= a) & (x <= b), bounds=(a, b), area=b - a)
 
 
-def box(T: float = 1.0) -> Domain:
-    """The whole periodic box (the periodic problem of section 3.1)."""
+def box(T: float = 1.0, dim: int = 1) -> Domain:
+    """The whole periodic box (the periodic problems of sections 3.1 and 5.1)."""
+    if dim == 2:
+        return Domain("box", 2, lambda x, y: np.ones(np.shape(x), dtype=bool),
+                      bounds=(-T, T), area=4 * T * T)
     return Domain("box", 1, lambda x: np.ones(np.shape(x), dtype=bool),
                   bounds=(-T, T), area=2 * T)
+
+
+def shape_parameter_eh(tau0: float) -> float:
+    """eps*h of the paper's shape-parameter rule (eq. constant_shapeparam):
+    pi / sqrt(2 log(1 + tau0^-2)), which makes the smallest entry of the
+    kernel's symbol about tau0 (Lemma 4.3)."""
+    return math.pi / math.sqrt(2.0 * math.log1p(tau0 ** -2))
 
 
 def disk(R: float) -> Domain:
