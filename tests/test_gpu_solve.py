@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import workloads as W
-from oracle import dense, evaluate, lstsq, periodic, philox
+from oracle import dense, evaluate, lstsq, periodic, philox, spectra
 
 from gpu_util import announce, engine_path, require_gpu
 
@@ -35,6 +35,30 @@ def _maxerr(prob, X):
     tp = W.test_points(prob, m2d=200)
     f = np.stack([g(*tp.T) for g in (prob.exact or prob.rhs)], axis=1)
     return np.max(np.abs(evaluate.eval_dense(prob, X, tp) - f), axis=0)
+
+
+def _norms(prob, tauZ=1e-12):
+    """||A^c||_2 and ||Z*||_2 from the oracle's symbol D = sum_r |d_r|^2 of the
+    periodic operator (Lemma 4.2): the singular values of A^c are sqrt(D) and
+    those of the regularised Z* are 1/sqrt(D) on the kept modes."""
+    if prob.dim == 1 and prob.op == 0:
+        D = sum(np.abs(spectra.diag_closed_form(prob.n, prob.s, prob.T, prob.eps, r)) ** 2 for r in range(prob.s))
+    else:
+        _, D = periodic.symbol_weights(prob, tauZ)
+    keep = D > tauZ * D.max()
+    return float(np.sqrt(D.max())), float(1.0 / np.sqrt(D[keep].min()))
+
+
+def _sigma_floor(prob, A, Om, k=1):
+    """Rounding floor of the sketch's singular values.  Both sketches are
+    W = (A - A Z* A) Omega computed in floating point: each column's error is
+    about u ||A^c|| ||Z*|| ||A Omega e_j|| (Z* applied to A Omega, A to the
+    result), and W is a difference of nearly equal terms, so this is far above
+    u sigma_1(W).  By Weyl's inequality the singular values of the two
+    computed sketches differ by at most the sum of the two errors' norms,
+    which the bound takes as 20 u ||A^c|| ||Z*|| max_j ||A Omega e_j|| sqrt(k)."""
+    normA, normZ = _norms(prob)
+    return 20 * 2.0 ** -53 * normA * normZ * np.max(np.linalg.norm(A @ Om, axis=0)) * np.sqrt(k)
 
 
 def _check(prob, engine=False, refine=1):
@@ -104,11 +128,9 @@ def test_sketch_matches_oracle(n, k):
     assert np.max(np.abs(np.tril(R, -1))) == 0.0
     scale = np.abs(Wo).max()
     assert np.max(np.abs(Q @ R - Wo)) < 1e-10 * scale
-    # Both sketches carry rounding of size u ||A^c|| ||Z*|| ||(A Omega)_c|| per
-    # column (Z* is applied to A Omega, A to the result), growing like sqrt(N):
-    # singular values agree to that floor, the leading ones to 1e-9 relative.
-    inf = p.info()
-    floor = 20 * 2.0 ** -53 * inf["normA"] * inf["normZ"] * np.max(np.linalg.norm(A @ Om, axis=0))
+    # singular values agree to the sketch's rounding floor, the leading ones
+    # to 1e-9 relative
+    floor = _sigma_floor(prob, A, Om)
     so = np.linalg.svd(Wo, compute_uv=False)
     assert np.max(np.abs(sig - so)) < floor
     big = so > 1e-3 * so[0]
@@ -175,8 +197,7 @@ def test_wide_sketch_matches_oracle(n, k):
     assert np.max(np.abs(np.tril(R, -1))) == 0.0
     scale = np.abs(Wo).max()
     assert np.max(np.abs(Q @ R - Wo)) < 1e-10 * scale
-    inf = p.info()
-    floor = 20 * 2.0 ** -53 * inf["normA"] * inf["normZ"] * np.max(np.linalg.norm(A @ Om, axis=0)) * np.sqrt(k)
+    floor = _sigma_floor(prob, A, Om, k)
     so = np.linalg.svd(Wo, compute_uv=False)
     assert np.max(np.abs(sig - so)) < floor
     big = so > 1e-3 * so[0]
