@@ -49,7 +49,7 @@ enum {
   AZRBF_EUNSUPPORTED = -2,  /* valid but not implemented (e.g. n not 2^k)    */
   AZRBF_ENOMEM = -3,        /* device allocation failed                      */
   AZRBF_EHIP = -4,          /* a HIP runtime call failed                     */
-  AZRBF_ERANK = -5,         /* sketch not rank-revealing at the largest k    */
+  AZRBF_ERANK = -5,         /* sketch too narrow: >90% of it retained        */
   AZRBF_ESTATE = -6,        /* call not valid in the plan's current state    */
   AZRBF_ESCRATCH = -7       /* request exceeds a fixed scratch buffer         */
 };
@@ -132,6 +132,21 @@ int azrbf_plan_dims(azrbf_plan_t plan, int64_t* dims);
 int azrbf_apply_A(azrbf_plan_t plan, const double* X, int64_t ldx, int64_t nvec,
                   double alpha, double beta, double* Y, int64_t ldy, void* stream);
 
+/* Right-hand sides of the least-squares system from the problem's data
+ * (section 2.3; for boundary value problems the section 6.1 example and
+ * section 6.2): B[i, v] = c f[i, v] for the M collocation rows, where f holds
+ * the data at the collocation points (the function to approximate, or the
+ * source term of -(Lap + k2) u = f) and c = 1 for AZRBF_OP_APPROX, c =
+ * 1 / (2 dim eps^2) for AZRBF_OP_BVP (the same normalisation as the interior
+ * rows, so that the scaled equations keep their solution); B[M + j, v] =
+ * bweight g[j, v] for the Mb boundary rows (Dirichlet data).  Device
+ * pointers: f is M x nrhs (ldf >= M), g is Mb x nrhs (ldg >= Mb; unread and
+ * may be NULL when Mb = 0), B is (M + Mb) x nrhs (ldb >= M + Mb).  B may be f
+ * itself (same leading dimension) but must not otherwise overlap f or g.
+ * Stream-ordered, no synchronisation.  Errors: EINVAL. */
+int azrbf_rhs(azrbf_plan_t plan, const double* f, int64_t ldf, const double* g, int64_t ldg,
+              int64_t nrhs, double* B, int64_t ldb, void* stream);
+
 /* Z = alpha * Z* R + beta * Z with Z* = F B^+ P E (section 3.2.2); rows
  * M..M+Mb-1 of R (boundary rows) are ignored: Z* has zero columns there
  * (section 6.1.2).  R is (M + Mb) x nvec, Z is N x nvec. */
@@ -154,8 +169,11 @@ int azrbf_apply_AZstar(azrbf_plan_t plan, const double* R, int64_t ldr, int64_t 
  * Omega (N x k), W = (A - A Z* A) Omega, a Householder tall-skinny QR of W,
  * a one-sided Jacobi SVD of R and truncation at tau * normA * sqrt(k).  The
  * factor stays resident in the plan.  Synchronises the stream (the retained
- * rank is read back).  Returns ERANK if all k directions are retained (the
- * sketch may be too narrow; the factor is still usable). */
+ * rank is read back).  A sketch that retains more than 90 % of its k
+ * directions is too narrow to resolve them all; with the width left open
+ * (problem k = 0) the factorisation then widens it to 1.25 times the
+ * retained rank and starts again (up to three times), else it returns ERANK
+ * (the factor is still usable, at reduced accuracy). */
 int azrbf_factor(azrbf_plan_t plan, void* stream);
 
 /* Least-squares solve of A X = B for nrhs right-hand sides (Algorithm 1 plus

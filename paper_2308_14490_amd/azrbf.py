@@ -60,6 +60,7 @@ EXPORTS = {
     "azrbf_plan_dims": (ctypes.c_int, [_P, ctypes.POINTER(_I64)]),
     "azrbf_apply_A": (ctypes.c_int, [_P, _P, _I64, _I64, _D, _D, _P, _I64, _P]),
     "azrbf_apply_Zstar": (ctypes.c_int, [_P, _P, _I64, _I64, _D, _D, _P, _I64, _P]),
+    "azrbf_rhs": (ctypes.c_int, [_P, _P, _I64, _P, _I64, _I64, _P, _I64, _P]),
     "azrbf_apply_AZstar": (ctypes.c_int, [_P, _P, _I64, _I64, _D, _D, _P, _I64, _P]),
     "azrbf_factor": (ctypes.c_int, [_P, _P]),
     "azrbf_solve": (ctypes.c_int, [_P, _P, _I64, _I64, _P, _I64, _P, _P]),
@@ -255,6 +256,29 @@ def factor(p, stream=None):
     inf = p.info()
     p.k = inf["k"]          # the width may have grown
     return inf["rank"]
+
+
+def rhs(p, F, G=None, B=None, stream=None):
+    """Right-hand sides from interior data F (nrhs, M) and boundary data G
+    (nrhs, Mb) (azrbf_rhs); returns B (nrhs, M + Mb)."""
+    F, nrhs, ldf = _vecs(F, p.M, "F")
+    if p.Mb:
+        if G is None:
+            raise ValueError("boundary data G is required for a plan with boundary rows")
+        G, ng, ldg = _vecs(G, p.Mb, "G")
+        if ng != nrhs:
+            raise ValueError("F and G hold different numbers of vectors")
+        gp = G.data_ptr()
+    else:
+        gp, ldg = None, 0
+    if B is None:
+        B = torch.empty((nrhs, p.Mt), dtype=torch.float64, device=F.device)
+    B, nb2, ldb = _vecs(B, p.Mt, "B")
+    if nb2 != nrhs:
+        raise ValueError("F and B hold different numbers of vectors")
+    _check(_lib().azrbf_rhs(p.handle, F.data_ptr(), ldf, gp, ldg, nrhs, B.data_ptr(), ldb, _stream(stream)),
+           "azrbf_rhs")
+    return B
 
 
 def solve(p, B, X=None, relres=None, stream=None):

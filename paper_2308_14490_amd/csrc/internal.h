@@ -124,6 +124,9 @@ int ops_apply_A(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alph
                 const double* Yin, int64_t ldyi, double* Y, int64_t ldy, hipStream_t st);
 int ops_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,
                 const double* Zin, int64_t ldzi, double* Z, int64_t ldz, hipStream_t st);
+// Right-hand sides from interior data f (M x nrhs) and boundary data g (Mb x nrhs).
+int ops_rhs(const Plan& P, const double* f, int64_t ldf, const double* g, int64_t ldg, int64_t nrhs, double* B,
+            int64_t ldb, hipStream_t st);
 // Out = alpha A Z* R + beta Yin (Yin null: Yin = Out); Zs is N x nvec scratch
 // (leading dimension N), overwritten with Z* R when the plan needs it.
 int ops_apply_AZ(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,

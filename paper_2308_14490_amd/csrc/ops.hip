@@ -630,6 +630,32 @@ __global__ void k_boundary_A(int dim, int n, double T, double h, double eps, int
   Y[M + i + ldy * v] = beta == 0.0 ? alpha * bw * acc : fma(alpha * bw, acc, beta * Yin[M + i + ldyi * v]);
 }
 
+// ------------------------------------------------------------------ right-hand sides
+
+// B[i, v] = c f[i, v] (collocation rows), B[M + j, v] = bw g[j, v] (boundary rows).
+__global__ void k_assemble_rhs(int64_t M, int64_t Mb, const double* f, int64_t ldf, double c, const double* g,
+                               int64_t ldg, double bw, double* B, int64_t ldb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t v = blockIdx.y;
+  if (i < M) B[i + ldb * v] = c * f[i + ldf * v];
+  else if (i < M + Mb) B[i + ldb * v] = bw * g[(i - M) + ldg * v];
+}
+
+int ops_rhs(const Plan& P, const double* f, int64_t ldf, const double* g, int64_t ldg, int64_t nrhs, double* B,
+            int64_t ldb, hipStream_t st) {
+  if (nrhs <= 0 || P.Mt == 0) return AZRBF_OK;
+  if (nrhs > 65535) return AZRBF_EINVAL;
+  // the collocation rows of a boundary value problem carry the operator's
+  // normalisation 1 / (2 dim eps^2) (the factor -2 eps^2 of the section 6.1
+  // example, applied to -(Lap + k2) u = f), so that the scaled equations keep
+  // the solution u
+  const double c = P.prob.op == AZRBF_OP_APPROX ? 1.0 : 1.0 / (2.0 * P.dim * P.eps * P.eps);
+  const dim3 grid((unsigned)((P.Mt + 255) / 256), (unsigned)nrhs);
+  Prof pr("assemble_rhs", 16.0 * (double)P.Mt * nrhs, st);
+  launch_kernel(k_assemble_rhs, grid, 256, 0, st, P.M, P.Mb, f, ldf, c, g, ldg, P.bweight, B, ldb);
+  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+}
+
 // ------------------------------------------------------------------ spectra set-up
 
 // Kernel phi (which = 0) or phi'' (which = 1) sampled at m * hL, m = 0..L-1,

@@ -263,12 +263,18 @@ static int k_cap(int64_t N, int64_t Mt) {
 
 // Sketch width when the caller leaves it open.  1D: the rank of A - A Z* A
 // stays near 20 whatever N (Theorem 4.6), so 32.  2D: the rank grows with the
-// boundary (section 5.3.2).  Measured on disks at s = 2, the retained rank per
-// fine-grid boundary point of the mask is 3.2, 5.0, 5.9, 6.4 at n = 16, 32,
-// 64, 128 (it grows like the logarithm of n, the width of the plunge region
-// in centres); the estimate takes (2.52 + 0.63 log2 n) 2/s per boundary point,
-// plus one per boundary row and 10 more, rounded up to a multiple of 64.  A
-// sketch that turns out too narrow is widened by the factorisation.
+// boundary (section 5.3.2).  Measured at s = 2 with wide sketches, the number
+// of directions a sketch retains per fine-grid boundary point of the mask is
+// 6.5 +- 0.2 on the disk (approximation, n = 128), the Poisson star (n = 128
+// and 256, with 2.2 weak boundary rows per boundary point) and the Helmholtz
+// unit disk (n = 64): the boundary rows add no rank of their own.  The
+// estimate is r = 6.6 (2/s) per boundary point.  A Gaussian sketch of width k
+// shrinks the smallest of r directions by about sqrt(k) - sqrt(r) instead of
+// sqrt(k), so directions just above the truncation threshold are lost unless
+// k exceeds r by a margin: k = 1.25 r + 10, rounded up to a multiple of 64
+// (at k = 1.1 r the residual was 2-3x larger on the disk and the Helmholtz
+// disk).  A sketch that still turns out too narrow is widened by the
+// factorisation.
 static int default_k(const azrbf_problem& q, int64_t Lax, int64_t N, int64_t Mt) {
   if (q.k > 0) return q.k;
   if (q.dim == 1) return 32;
@@ -281,25 +287,26 @@ static int default_k(const azrbf_problem& q, int64_t Lax, int64_t N, int64_t Mt)
                         !q.mask[ix * Lax + iy - 1] || !q.mask[ix * Lax + iy + 1];
       perim += edge;
     }
-  const double per = (2.52 + 0.63 * std::log2((double)q.n)) * 2.0 / q.s;
-  const int64_t est = (int64_t)std::ceil(per * (double)perim) + q.nb + 10;
+  const double r = 6.6 * 2.0 / q.s * (double)perim;
+  const int64_t est = (int64_t)std::ceil(1.25 * r) + 10;
   const int cap = k_cap(N, Mt);
   if (cap <= 64) return cap;
   const int64_t k = (est + 63) / 64 * 64;
   return (int)std::max<int64_t>(64, std::min<int64_t>(k, cap));
 }
 
-// Factor with the plan's sketch width; a sketch that keeps more than k - 10
-// directions is widened by a quarter (up to three times) when the width was
-// not fixed by the caller.
+// Factor with the plan's sketch width.  A sketch that retains more than 90 %
+// of its directions is too narrow to resolve them all (see default_k); when
+// the width was not fixed by the caller it is widened to 1.25 times the
+// retained rank (at least by a quarter), up to three times.
 static int factor_plan(Plan& P, hipStream_t st) {
   for (int attempt = 0;; ++attempt) {
     const int rc = P.k > 64 ? wide_factor(P, st) : dense_factor(P, st);
     if (rc != AZRBF_ERANK || P.prob.k > 0 || attempt >= 3) return rc;
     const int cap = k_cap(P.N, P.Mt);
     if (P.k >= cap) return rc;
-    int nk = P.k <= 64 ? 64 : (int)(((int64_t)P.k * 5 / 4 + 63) / 64 * 64);
-    if (P.k < 64 && nk > cap) nk = cap;
+    const int64_t want = std::max<int64_t>((int64_t)P.k * 5 / 4, ((int64_t)P.rank * 5 + 3) / 4 + 10);
+    int nk = P.k < 64 && want <= 64 ? 64 : (int)((want + 63) / 64 * 64);
     if (nk > cap) nk = cap;
     if (nk <= P.k) return rc;
     if (hipStreamSynchronize(st) != hipSuccess) return AZRBF_EHIP;
@@ -379,7 +386,7 @@ const char* azrbf_strerror(int code) {
     case AZRBF_EUNSUPPORTED: return "unsupported problem size or option";
     case AZRBF_ENOMEM: return "device memory allocation failed";
     case AZRBF_EHIP: return "HIP runtime error";
-    case AZRBF_ERANK: return "sketch not rank-revealing: all sketch directions retained";
+    case AZRBF_ERANK: return "sketch too narrow: more than 90% of its directions retained";
     case AZRBF_ESTATE: return "call not valid in the plan's state";
     case AZRBF_ESCRATCH: return "needs more than the fixed scratch buffer of the allocation-free entry point";
     default: return "unknown error";
@@ -544,6 +551,19 @@ int azrbf_apply_A(azrbf_plan_t h, const double* X, int64_t ldx, int64_t nvec, do
   P.last_stream = (hipStream_t)stream;
   AZ_TRY(az::plan_on_stream(P, P.last_stream));
   return az::ops_apply_A(P, X, ldx, nvec, alpha, beta, nullptr, 0, Y, ldy, (hipStream_t)stream);
+}
+
+int azrbf_rhs(azrbf_plan_t h, const double* f, int64_t ldf, const double* g, int64_t ldg, int64_t nrhs,
+              double* B, int64_t ldb, void* stream) {
+  if (!h || nrhs < 0) return AZRBF_EINVAL;
+  Plan& P = h->p;
+  if (nrhs == 0) return AZRBF_OK;
+  if (!f || !B || ldf < P.M || ldb < P.Mt || (P.Mb > 0 && (!g || ldg < P.Mb))) return AZRBF_EINVAL;
+  if (f != B && ((f < B + ldb * nrhs) && (B < f + ldf * nrhs))) return AZRBF_EINVAL;   // partial overlap
+  if (f == B && ldf != ldb) return AZRBF_EINVAL;
+  if (g && P.Mb > 0 && (g < B + ldb * nrhs) && (B < g + ldg * nrhs)) return AZRBF_EINVAL;
+  P.last_stream = (hipStream_t)stream;
+  return az::ops_rhs(P, f, ldf, g, ldg, nrhs, B, ldb, (hipStream_t)stream);
 }
 
 int azrbf_apply_Zstar(azrbf_plan_t h, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,

@@ -576,7 +576,7 @@ int wide_factor(Plan& P, hipStream_t st) {
   P.rank = rank;
   P.sweeps = sweeps;
   P.factored = true;
-  return rank > k - 10 ? AZRBF_ERANK : AZRBF_OK;
+  return 10 * (int64_t)rank > 9 * (int64_t)k ? AZRBF_ERANK : AZRBF_OK;   // too narrow: see factor_plan
 }
 
 int wide_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx, double* relres,
