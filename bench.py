@@ -158,10 +158,11 @@ def served_vs_plain(count, seed, sides, log_fn):
     openl = serve.summarize(srv.run(open_reqs))
     ticks = len(srv.ticks)
     srv.close()
+    be.close()
     log_fn(f"served stream: open-loop at {rate:.1f} req/s: p50 {openl['p50_ms']:.1f} ms p99 {openl['p99_ms']:.1f} ms")
     return {"requests": count, "seed": seed, "sides_2d": list(sides), "exps_1d": [10, 16],
             "budget_bytes": budget, "plain": plain, "served_closed_loop": closed,
-            "served_open_loop": dict(openl, rate_req_per_s=round(rate, 2), ticks=ticks),
+            "served_open_loop": dict(openl, rate_req_per_s=round(rate, 2), groups=ticks),
             "speedup_closed_loop": round(closed["solves_per_s"] / plain["solves_per_s"], 3)}
 
 
@@ -202,6 +203,149 @@ def wide_2d(log_fn, n=128):
            "mfma_TFLOPs_overall": round(tot_f / (tot_ms * 1e-3) / 1e12, 2) if tot_ms else None}
     log_fn(f"2D n={n}: factor {out['factor_s']} s (k {inf['k']}, rank {inf['rank']}), relres {out['relres']:.2e}, "
            f"matrix-core kernels {out['mfma_TFLOPs_overall']} TF/s")
+    return out
+
+
+def beyond_cache(log_fn, nvec=512, pairs_per_launch=256):
+    """The FFT passes with every pass's working set past the 256 MB Infinity
+    Cache: A, Z* and A Z* on nvec vectors at N = 65536 with all of them in
+    one launch per pass (each pass reads and writes 0.5-1.1 GB), per-launch
+    HIP-event timing.  Rates here are HBM rates."""
+    import torch
+    import workloads as W
+    from paper_2308_14490_amd import azrbf, problems
+    prob = W.config_c2(65536, 1)
+    key = "e1_256x256_s2"
+    saved = azrbf.tune_table()
+    shape = saved.get(key, (16, 4, 0))
+    azrbf.tune_load({key: (shape[0], shape[1], pairs_per_launch)})
+    p = problems.plan_for(prob)
+    X = azrbf.gaussian(7, p.N, nvec)
+    Y = azrbf.apply_A(p, X)
+    Z = azrbf.apply_Zstar(p, Y)
+    azrbf.apply_AZstar(p, Y, Y, alpha=-1.0, beta=1.0)
+    torch.cuda.synchronize()
+    azrbf.profile_enable(True)
+    for _ in range(2):
+        azrbf.apply_A(p, X, Y)
+        azrbf.apply_Zstar(p, Y, Z)
+        azrbf.apply_AZstar(p, Y, Y, alpha=-1.0, beta=1.0)
+    torch.cuda.synchronize()
+    rep = azrbf.profile_report()
+    azrbf.profile_enable(False)
+    p.destroy()
+    del X, Y, Z
+    azrbf.tune_load({key: shape})
+    azrbf.release_cached_memory()
+    fft = [r for r in rep if r["name"].startswith(("col_", "row_"))]
+    b = sum(r["bytes"] for r in fft)
+    ms = sum(r["ms"] for r in fft)
+    kern = {r["name"]: {"calls": r["calls"], "avg_us": round(r["ms"] / r["calls"] * 1e3, 1),
+                        "MB_per_launch": round(r["bytes"] / r["calls"] / 1e6, 1),
+                        "GBps": round(r["bytes"] / (r["ms"] * 1e-3) / 1e9, 1),
+                        "frac": round(r["bytes"] / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)} for r in fft}
+    out = {"workload": f"apply_A, apply_Zstar, apply_AZstar on {nvec} vectors, N=65536, s=2, "
+                       f"{pairs_per_launch} vector pairs per launch",
+           "achieved": round(b / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "kernels": kern}
+    log_fn(f"FFT passes past the cache ({nvec} vectors): {out['achieved']} GB/s ({out['frac']})")
+    return out
+
+
+def bvp_2d(log_fn, n=256, nrhs=64):
+    """The 2D Poisson workload at full size (star 0.7 + 0.1 cos 5t, n x n
+    centres, weak Dirichlet rows): factor time, and solves per second with the
+    factor resident, one right-hand side per call against nrhs per call (the
+    workload's manufactured data plus seeded random-trig interior and
+    boundary data), plus the plain per-problem rate (factor + one solve)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2308_14490_amd import azrbf, problems
+    prob = W.config_c4(n)
+    prob.rhs = prob.rhs + [W.trig_sum_2d(3000 + i) for i in range(nrhs - 1)]
+    prob.bnd = prob.bnd + [W.trig_sum_2d(5000 + i) for i in range(nrhs - 1)]
+    p = problems.plan_for(prob)
+    B = problems.rhs_for(p, prob)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    azrbf.factor(p)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    X1, r1 = azrbf.solve(p, B[:1].contiguous())
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    reps = 4
+    for _ in range(reps):
+        X1, r1 = azrbf.solve(p, B[:1].contiguous())
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    X, rel = azrbf.solve(p, B)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    for _ in range(2):
+        X, rel = azrbf.solve(p, B)
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    inf = p.info()
+    rels = rel.cpu().numpy()
+    good_b = int(np.sum(rels <= 1e-10))
+    good_1 = int(float(r1.max()) <= 1e-10)
+    one = (t3 - t2) / reps
+    out = {"workload": f"2D Poisson star R=0.7+0.1cos5t, {n}x{n} centres, eps*h=0.5, M={inf['M']}, Mb={inf['Mb']}, "
+                       f"refine={p._prob.refine}",
+           "k": inf["k"], "rank": inf["rank"], "sweeps": inf["sweeps"], "factor_s": round(t1 - t0, 3),
+           "solve_1rhs_s": round(one, 4), "solve_batch_s": round((t5 - t4) / 2, 4), "nrhs_batch": nrhs,
+           "relres_workload_rhs": float(rels[0]), "max_relres": float(rels.max()),
+           "solves_per_s": {"plain_per_problem": round(good_1 / (t1 - t0 + one), 3),
+                            "plain_resident_factor": round(good_1 / one, 2),
+                            "batched_resident_factor": round(good_b / ((t5 - t4) / 2), 2)}}
+    p.destroy()
+    azrbf.release_cached_memory()
+    log_fn(f"2D Poisson n={n}: factor {out['factor_s']} s (k {inf['k']}, rank {inf['rank']}), "
+           f"relres {out['relres_workload_rhs']:.2e}, solves/s {out['solves_per_s']}")
+    return out
+
+
+def copies_1d(log_fn, copies=4096, plain=64):
+    """The 256-centre 1D problem (eps*h = 0.5, f = e^x sin 7x + x^2) solved for
+    `copies` right-hand sides at once on one plan (one launch sequence for all
+    of them) against the plain per-problem solve (plan + factor + solve per
+    copy), both gated on the residual."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2308_14490_amd import azrbf, problems
+    prob = W.config_c1a(256)
+    p = problems.plan_for(prob)
+    b = problems.rhs_for(p, prob)
+    B = b.expand(copies, -1).contiguous()
+    X, rel = azrbf.solve(p, B)
+    torch.cuda.synchronize()
+    p.destroy()
+    reps = 3
+    rels = torch.empty((reps, copies), dtype=torch.float64, device=B.device)
+    t0 = time.perf_counter()
+    for i in range(reps):
+        p = problems.plan_for(prob)
+        azrbf.solve(p, B, X, rels[i])
+        p.destroy()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rp = torch.empty((plain, 1), dtype=torch.float64, device=B.device)
+    Xp = torch.empty((1, p.N), dtype=torch.float64, device=B.device)
+    t2 = time.perf_counter()
+    for i in range(plain):
+        q = problems.plan_for(prob)
+        azrbf.solve(q, b, Xp, rp[i])
+        q.destroy()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    out = {"workload": f"1D N=256, eps*h=0.5, M=257, f=e^x sin7x+x^2; {copies} copies per call",
+           "batched_per_problem": round(int((rels <= 1e-10).sum()) / (t1 - t0), 1),
+           "plain_per_problem": round(int((rp <= 1e-10).sum()) / (t3 - t2), 1),
+           "max_relres": float(rels.max())}
+    log_fn(f"1D N=256 copies: batched {out['batched_per_problem']}/s, plain {out['plain_per_problem']}/s")
     return out
 
 
@@ -391,8 +535,11 @@ def main():
     }
     if not args.no_served:
         out["served_stream"] = served_vs_plain(args.serve_count, 2024, (64,), log)
+    out["fft_passes_beyond_cache"] = beyond_cache(log)
+    out["copies_1d_n256"] = copies_1d(log)
     if not args.no_2d:
         out["wide_2d"] = wide_2d(log)
+        out["poisson_2d_n256"] = bvp_2d(log)
     if not args.no_cpu_baseline:
         log(f"cpu baseline (oracle) at N={args.cpu_n}")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.nrhs)

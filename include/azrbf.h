@@ -161,7 +161,8 @@ int azrbf_apply_Zstar(azrbf_plan_t plan, const double* R, int64_t ldr, int64_t n
  * R and Y are (M + Mb) x nvec; R may equal Y (same leading dimension); rows
  * M..M+Mb-1 of R are ignored as in azrbf_apply_Zstar.  With boundary rows or
  * on the single-kernel 1D path the plan keeps an N x nvec coefficient scratch
- * (grown on demand, which may synchronise the stream). */
+ * (grown on demand; the replaced one returns to the library's pool once the
+ * work queued before it on the stream has run). */
 int azrbf_apply_AZstar(azrbf_plan_t plan, const double* R, int64_t ldr, int64_t nvec,
                        double alpha, double beta, double* Y, int64_t ldy, void* stream);
 

@@ -833,13 +833,15 @@ int dense_factor(Plan& P, hipStream_t st) {
 // ------------------------------------------------------------------ solve
 
 // Solve workspace for nrhs right-hand sides (k <= 64 layout).
-int dense_solve_ws(Plan& P, int64_t nrhs) {
+int dense_solve_ws(Plan& P, int64_t nrhs, hipStream_t st) {
   const int k = P.k;
   const int64_t N = P.N, Mt = P.Mt;
   const int64_t npart = gemm_split_doubles(k, nrhs, Mt, 1);
   if (nrhs > P.sw_rhs || npart > P.sw_part) {
     const int64_t per = N + 3 * P.Mtp + k + 2 * NORM_CHUNKS;
+    double* old = P.sw;
     AZ_TRY(P.alloc((void**)&P.sw, sizeof(double) * (per * nrhs + npart)));
+    P.release_one_after(old, st);
     P.sw_rhs = nrhs;
     P.sw_part = npart;
   }
@@ -849,7 +851,7 @@ int dense_solve_ws(Plan& P, int64_t nrhs) {
 // First stage of the first pass, independent of the factor:
 // Zr = Z* b, c = (I - A Z*) b, into the solve workspace.
 int dense_first_stage(Plan& P, const double* B, int64_t ldb, int64_t nrhs, hipStream_t st) {
-  AZ_TRY(dense_solve_ws(P, nrhs));
+  AZ_TRY(dense_solve_ws(P, nrhs, st));
   const int64_t N = P.N;
   double* Zr = P.sw;
   double* C = Zr + N * nrhs;
@@ -873,7 +875,7 @@ int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, 
   const int k = P.k;
   const int64_t N = P.N, Mt = P.Mt;
   const int64_t Ld = P.Mtp;   // leading dimension of the row-space matrices (whole 128-byte lines)
-  AZ_TRY(dense_solve_ws(P, nrhs));
+  AZ_TRY(dense_solve_ws(P, nrhs, st));
   double* Zr = P.sw;                   // N x nrhs
   double* C = Zr + N * nrhs;           // Mt x nrhs (ld Ld)
   double* R1 = C + Ld * nrhs;          // Mt x nrhs (ld Ld)

@@ -184,7 +184,7 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch,
                          const std::function<int()>& on_sketch = nullptr,
                          const std::function<int()>& before_products = nullptr);
 int dense_factor_finish(Plan& P, hipStream_t st);
-int dense_solve_ws(Plan& P, int64_t nrhs);
+int dense_solve_ws(Plan& P, int64_t nrhs, hipStream_t st);
 int dense_first_stage(Plan& P, const double* B, int64_t ldb, int64_t nrhs, hipStream_t st);
 // t = Q^T c of the first pass (c from dense_first_stage) into the solve workspace
 int dense_first_qtc(Plan& P, int64_t nrhs, hipStream_t st);
@@ -278,6 +278,7 @@ struct Plan {
   void release_after(hipStream_t st);
   void release_one(void* p);   // one block back to the pool
   void release_factor();       // the factor and solve workspace back to the pool
+  void release_one_after(void* ptr, hipStream_t st);   // a replaced block, once st's work is done
 };
 
 }  // namespace az

@@ -462,11 +462,31 @@ k_col_inv_A(Geo g, const double2* __restrict__ tw, const double2* __restrict__ w
     const double2* in = ws2 + (pair * nph + gx + ry) * g.N;
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) a[m] = in[(int64_t)(t + m * T) * g.N2 + b];
-    fft_line<N1, true>(a, lds, line, t, tw);
+    // rows of the line's outputs, and with beta != 0 the rows of Yin they
+    // combine with, fetched before the transform so that their latency
+    // overlaps it (Yin may be Y: each element is read before it is written,
+    // by the same thread)
+    int rows[RADIX];
+    double2 yin[RADIX];
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) {
-      const int64_t row = row_of_d<D1>(g, grid_index_s<S, D1>(g, gx / S, ry, t + m * T, b));
-      if (row >= 0) store_pair(Y, ldy, Yin, ldyi, row, v0, nvec, a[m], alpha, beta);
+      rows[m] = (int)row_of_d<D1>(g, grid_index_s<S, D1>(g, gx / S, ry, t + m * T, b));
+      yin[m] = make_double2(0.0, 0.0);
+    }
+    if (beta != 0.0) {
+#pragma unroll
+      for (int m = 0; m < RADIX; ++m)
+        if (rows[m] >= 0) yin[m] = load_pair(Yin, ldyi, rows[m], v0, nvec);
+    }
+    fft_line<N1, true>(a, lds, line, t, tw);
+    if (v0 < nvec) {
+#pragma unroll
+      for (int m = 0; m < RADIX; ++m) {
+        if (rows[m] < 0) continue;
+        double* p0 = Y + rows[m] + ldy * v0;
+        *p0 = beta == 0.0 ? alpha * a[m].x : fma(alpha, a[m].x, beta * yin[m].x);
+        if (v0 + 1 < nvec) p0[ldy] = beta == 0.0 ? alpha * a[m].y : fma(alpha, a[m].y, beta * yin[m].y);
+      }
     }
   }
 }
@@ -1077,12 +1097,16 @@ static int launch_row(const RowArgs& a) {
 static int run_col(const ColArgs& a) { AZ_SWITCH_ENGINE(a.P->geo.N1, launch_col, a) }
 static int run_row(const RowArgs& a) { AZ_SWITCH_ENGINE(a.P->geo.N2, launch_row, a) }
 
-static int ensure_ws(Plan& P, int64_t pairs) {
+// Grows the FFT workspace to `pairs` vector pairs; the replaced buffers go
+// back to the pool once the work queued on st before the growth is done.
+static int ensure_ws(Plan& P, int64_t pairs, hipStream_t st) {
   if (pairs <= P.ws_pairs) return AZRBF_OK;
   const int64_t per = (int64_t)P.ph * P.N * (int64_t)sizeof(double2);
   void *a = nullptr, *b = nullptr;
   AZ_TRY(P.alloc(&a, per * pairs));
   AZ_TRY(P.alloc(&b, per * pairs));
+  P.release_one_after(P.ws1, st);
+  P.release_one_after(P.ws2, st);
   P.ws1 = (double2*)a;
   P.ws2 = (double2*)b;
   P.ws_pairs = pairs;
@@ -1131,7 +1155,7 @@ int ops_apply_A(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alph
   }
   const int64_t npairs = (nvec + 1) / 2;
   const int64_t chunk = engine_chunk(P, npairs);
-  AZ_TRY(ensure_ws(P, chunk));
+  AZ_TRY(ensure_ws(P, chunk, st));
   for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
     const int64_t np = npairs - p0 < chunk ? npairs - p0 : chunk;
     ColArgs c1{&P, 0, X, ldx, nullptr, P.ws1, nvec, p0, np, 0, 0, nullptr, 0, nullptr, 0, st};
@@ -1160,7 +1184,7 @@ int ops_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alph
   if (P.fused) return fused_Z(P, R, ldr, nvec, alpha, beta, Zin, ldzi, Z, ldz, st);
   const int64_t npairs = (nvec + 1) / 2;
   const int64_t chunk = engine_chunk(P, npairs);
-  AZ_TRY(ensure_ws(P, chunk));
+  AZ_TRY(ensure_ws(P, chunk, st));
   for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
     const int64_t np = npairs - p0 < chunk ? npairs - p0 : chunk;
     ColArgs c1{&P, 2, R, ldr, nullptr, P.ws1, nvec, p0, np, 0, 0, nullptr, 0, nullptr, 0, st};
@@ -1282,7 +1306,7 @@ int ops_apply_AZ(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alp
   }
   const int64_t npairs = (nvec + 1) / 2;
   const int64_t chunk = engine_chunk(P, npairs);
-  AZ_TRY(ensure_ws(P, chunk));
+  AZ_TRY(ensure_ws(P, chunk, st));
   const bool coef = P.Mb > 0;
   for (int64_t p0 = 0; p0 < npairs; p0 += chunk) {
     const int64_t np = npairs - p0 < chunk ? npairs - p0 : chunk;

@@ -150,6 +150,29 @@ void Plan::release_one(void* ptr) {
   }
 }
 
+// A block replaced by a larger one while work queued on st may still use it:
+// it joins the pending releases (the pool takes it once that work is done).
+void Plan::release_one_after(void* ptr, hipStream_t st) {
+  if (!ptr) return;
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, st) != hipSuccess) {
+    if (ev) (void)hipEventDestroy(ev);
+    (void)hipGetLastError();
+    (void)hipStreamSynchronize(st);
+    release_one(ptr);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  for (size_t i = 0; i < allocs.size(); ++i) {
+    if (allocs[i].first != ptr) continue;
+    g_pending.push_back(PendingRelease{device, st, ev, {allocs[i]}});
+    bytes -= allocs[i].second;
+    allocs.erase(allocs.begin() + (long)i);
+    return;
+  }
+  (void)hipEventDestroy(ev);
+}
+
 // The stream must have drained the factor's work.
 void Plan::release_factor() {
   double** bufs[] = {&Om, &Om2, &Yf, &Yf2, &Q, &Rf, &sig, &Pm, &Gj, &Vj, &dscr, &sw, &azs};
@@ -588,11 +611,9 @@ int azrbf_apply_AZstar(azrbf_plan_t h, const double* R, int64_t ldr, int64_t nve
   AZ_TRY(az::plan_on_stream(P, P.last_stream));
   if ((P.fused || P.Mb > 0) && nvec > P.azs_cols) {
     // the previous scratch may still be in use by queued work on this stream
-    if (P.azs && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return AZRBF_EHIP;
-    P.release_one(P.azs);
-    P.azs = nullptr;
-    P.azs_cols = 0;
+    double* old = P.azs;
     AZ_TRY(P.alloc((void**)&P.azs, sizeof(double) * P.N * nvec));
+    P.release_one_after(old, (hipStream_t)stream);
     P.azs_cols = nvec;
   }
   return az::ops_apply_AZ(P, R, ldr, nvec, alpha, beta, nullptr, 0, Y, ldy, P.azs, (hipStream_t)stream);

@@ -586,7 +586,9 @@ int wide_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, i
   const int64_t npart = std::max<int64_t>(gemm_split_doubles(k, nrhs, Mt, 1), 1);
   if (nrhs > P.sw_rhs || npart > P.sw_part) {
     const int64_t per = 2 * N + 3 * Mt + 2 * (int64_t)k + 2 * relres_chunks();
+    double* old = P.sw;
     AZ_TRY(P.alloc((void**)&P.sw, sizeof(double) * (per * nrhs + npart)));
+    P.release_one_after(old, st);
     P.sw_rhs = nrhs;
     P.sw_part = npart;
   }

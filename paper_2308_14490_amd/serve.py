@@ -7,28 +7,36 @@ plans resident in HBM, keyed by the operator: spectra, index list, the sketch
 Omega, the explicit Q of the sketch and the truncated pseudo-inverse of R.
 Later requests with the same operator only run the solve.
 
-Scheduling is iteration-level ("ticks"):
-  * a tick admits, in arrival order, requests that have arrived, while the
-    bytes of the plans they need (resident ones plus new ones, with their solve
-    workspace) fit the memory budget; resident plans that the tick does not
-    use are evicted, least recently used first, to make room;
-  * the admitted requests are grouped by operator: the right-hand sides of a
-    group are concatenated and solved in one call, so they share every
-    launch; different groups run concurrently (``azrbf_solve_many`` spreads
-    them over the library's internal streams);
-  * requests that arrive while a tick is on the GPU wait for the next tick.
+Scheduling is continuous: the run loop never waits for the GPU as a whole.
+  * Arrived requests queue in arrival order.  Each pass of the loop admits,
+    in that order, the requests whose operator is not already on the GPU and
+    whose memory fits the budget: the resident plans, the reservations of the
+    groups in flight and the new group's needs (a new plan's whole footprint,
+    or a resident plan's workspace growth for the group's right-hand sides).
+    Idle resident plans are evicted, least recently used first, to make room.
+    A request whose operator is busy waits for that group; requests of other
+    operators behind it go ahead.
+  * The admitted requests are grouped by operator; a group's right-hand sides
+    are concatenated and solved in one call (they share every launch).  Each
+    group is handed to the backend at once and runs on its own stream, beside
+    the groups already in flight (a 1D solve does not wait for a 2D
+    factorisation that started before it).
+  * Completion is polled through per-group events; a finished group's
+    results are recorded and its plan becomes idle and resident.
 
-Every solve of a request, alone or in a tick, runs the same kernels on the
+Every solve of a request, alone or in a group, runs the same kernels on the
 same plan arithmetic; only the sketch seed of a shared plan (the first
 request's) and the pairing of right-hand sides in the FFTs differ, so results
 agree within rounding and the residual test.
 
 The scheduling logic talks to a backend (``GpuBackend`` here; tests also use
-a host-only fake), so it can be checked without a GPU.
+a host-only fake with a simulated clock), so it can be checked without a GPU.
 """
 import collections
+import concurrent.futures
 import dataclasses
 import hashlib
+import threading
 import time
 
 import numpy as np
@@ -62,10 +70,39 @@ def operator_key(prob, mask, k=0, tau=1e-12, tauZ=1e-12, refine=1):
     return h.hexdigest()
 
 
-class GpuBackend:
-    """Plans, right-hand sides and batched solves on the current HIP device."""
+class _GpuGroup:
+    """A group in flight: the worker's future, then the completion event."""
 
-    def __init__(self, refine=1, keep_x=False):
+    def __init__(self, future, keep_x):
+        self.future = future
+        self.keep_x = keep_x
+
+    def done(self):
+        if not self.future.done():
+            return False
+        if self.future.exception() is not None:
+            return True
+        return self.future.result()[4].query()
+
+    def result(self):
+        """(plan, [(X or None, relres)] per request) once done()."""
+        plan, X, rel, sizes, ev = self.future.result()
+        ev.synchronize()
+        rr = rel.cpu().numpy()
+        parts, o = [], 0
+        for n in sizes:
+            parts.append((X[o:o + n] if self.keep_x else None, rr[o:o + n]))
+            o += n
+        return plan, parts
+
+
+class GpuBackend:
+    """Plans, right-hand sides and solves on the current HIP device.  Each
+    group is queued by a worker thread on that thread's own stream (default
+    priority), so a group whose factorisation waits on the host inside the
+    library does not hold up the others or the run loop."""
+
+    def __init__(self, refine=None, keep_x=False, streams=4):
         import torch
         from . import azrbf, problems
         self.torch, self.azrbf, self.problems = torch, azrbf, problems
@@ -73,6 +110,8 @@ class GpuBackend:
         self.keep_x = keep_x
         self.dev = torch.device("cuda", torch.cuda.current_device())
         self._masks = {}
+        self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=streams)
+        self._local = threading.local()
 
     def mask(self, prob):
         mk = id(prob)
@@ -80,41 +119,42 @@ class GpuBackend:
             self._masks[mk] = self.azrbf.make_mask(prob.dim, prob.n, prob.s, prob.T, prob.domain.contains)
         return self._masks[mk]
 
+    def _refine(self, prob):
+        return self.problems.default_refine(prob) if self.refine is None else self.refine
+
     def key(self, prob):
-        return operator_key(prob, self.mask(prob), refine=self.refine)
+        return operator_key(prob, self.mask(prob), refine=self._refine(prob))
 
     def footprint(self, prob, nrhs):
-        return self.problems.footprint_for(prob, nrhs, mask=self.mask(prob))
-
-    def create(self, prob):
-        return self.problems.plan_for(prob, refine=self.refine)
+        return self.problems.footprint_for(prob, nrhs, mask=self.mask(prob), refine=self._refine(prob))
 
     def nbytes(self, plan):
         return plan.info()["device_bytes"]
 
-    def rhs(self, plan, prob):
-        return self.problems.rhs_for(plan, prob, device=self.dev)
+    def _stream(self):
+        st = getattr(self._local, "stream", None)
+        if st is None:
+            self.torch.cuda.set_device(self.dev)
+            st = self._local.stream = self.torch.cuda.Stream(device=self.dev)
+        return st
 
-    def solve_groups(self, groups):
-        """groups: list of (plan, [B tensors]).  Returns per group the list of
-        (X, relres) slices in the same order, after the device finished."""
+    def _work(self, plan, probs):
         torch = self.torch
-        plans, Bs, sizes = [], [], []
-        for plan, blist in groups:
-            plans.append(plan)
-            Bs.append(torch.cat(blist, 0).contiguous() if len(blist) > 1 else blist[0])
-            sizes.append([b.shape[0] for b in blist])
-        Xs, rels = self.azrbf.solve_many(plans, Bs)
-        torch.cuda.synchronize()
-        out = []
-        for X, r, sz in zip(Xs, rels, sizes):
-            rr = r.cpu().numpy()
-            parts, o = [], 0
-            for n in sz:
-                parts.append((X[o:o + n] if self.keep_x else None, rr[o:o + n]))
-                o += n
-            out.append(parts)
-        return out
+        st = self._stream()
+        with torch.cuda.stream(st):
+            if plan is None:
+                plan = self.problems.plan_for(probs[0], refine=self._refine(probs[0]), stream=st)
+            Bs = [self.problems.rhs_for(plan, p, device=self.dev) for p in probs]
+            B = torch.cat(Bs, 0).contiguous() if len(Bs) > 1 else Bs[0]
+            X, rel = self.azrbf.solve(plan, B, stream=st)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return plan, X, rel, [b.shape[0] for b in Bs], ev
+
+    def launch(self, plan, probs):
+        """Queues the solve of the problems' right-hand sides (one operator;
+        plan None: make it first).  Returns a handle with done()/result()."""
+        return _GpuGroup(self._pool.submit(self._work, plan, probs), self.keep_x)
 
     def destroy(self, plan):
         plan.destroy()
@@ -122,10 +162,25 @@ class GpuBackend:
     def now(self):
         return time.perf_counter()
 
-    def sleep_until(self, t):
-        d = t - time.perf_counter()
+    def wait(self, until):
+        """Sleeps until the time `until` (perf_counter) or briefly while groups
+        are in flight (the loop polls their events)."""
+        d = min(until - time.perf_counter(), 2e-4)
         if d > 0:
             time.sleep(d)
+
+    def close(self):
+        self._pool.shutdown(wait=True)
+
+
+@dataclasses.dataclass
+class _Flight:
+    key: str
+    reqs: list
+    handle: object
+    t_admit: float
+    new: bool
+    reserve: int
 
 
 class Server:
@@ -135,86 +190,106 @@ class Server:
         self.be = backend
         self.budget = int(budget_bytes)
         self.max_batch = max_batch
-        self.cache = collections.OrderedDict()   # key -> (plan, bytes), LRU order
-        self.ticks = []                          # (t_start, t_end, n_requests, n_groups, n_new_plans)
+        self.cache = collections.OrderedDict()   # key -> (plan, bytes), LRU order; idle or busy
+        self.flights = {}                        # key -> _Flight (its plan is busy)
+        self.ticks = []                          # per launched group: (t_admit, t_done, n_requests, new plan)
         self.evictions = 0
         self.created = 0
+        self.peak_committed = 0
 
     def resident_bytes(self):
         return sum(b for _, b in self.cache.values())
 
-    def _evict(self, need, keep):
-        """Evict unused plans (LRU first) until need bytes fit; False if not possible."""
+    def committed_bytes(self):
+        """Resident plans plus the reservations of the groups in flight."""
+        return self.resident_bytes() + sum(f.reserve for f in self.flights.values())
+
+    def _fit(self, need, keep):
+        """Evict idle plans (LRU first, none in keep) until need more bytes fit
+        beside the committed ones."""
         for key in list(self.cache):
-            if self.resident_bytes() + need <= self.budget:
+            if self.committed_bytes() + need <= self.budget:
                 return True
-            if key in keep:
+            if key in keep or key in self.flights:
                 continue
             plan, _ = self.cache.pop(key)
             self.be.destroy(plan)
             self.evictions += 1
-        return self.resident_bytes() + need <= self.budget
+        return self.committed_bytes() + need <= self.budget
 
     def _admit(self, queue):
-        """Takes requests from the head of the queue while their plans fit."""
-        batch, groups, new_bytes = [], {}, 0
-        while queue and len(batch) < self.max_batch:
-            req = queue[0]
+        """Requests from the queue, in order, grouped by operator: {key:
+        (requests, bytes to reserve)}.  Busy operators are skipped; admission
+        stops at the first request that does not fit."""
+        groups = {}
+        count = 0
+        for req in list(queue):
+            if count >= self.max_batch:
+                break
             key = self.be.key(req.problem)
-            nrhs = len(req.problem.rhs)
-            extra = 0 if (key in self.cache or key in groups) else self.be.footprint(req.problem, max(nrhs, 1))
+            if key in self.flights:
+                continue
+            reqs, reserve = groups.get(key, ([], 0))
+            nrhs = sum(len(r.problem.rhs) for r in reqs) + len(req.problem.rhs)
+            full = self.be.footprint(req.problem, max(nrhs, 1))
+            resident = self.cache[key][1] if key in self.cache else 0
+            want = max(full - resident, 0)
             keep = set(groups) | {key}
-            if not self._evict(new_bytes + extra, keep):
-                if batch:
-                    break                      # waits for the next tick
-                if extra > self.budget:
-                    raise MemoryError(f"request {req.rid} needs {extra} bytes, budget {self.budget}")
-            batch.append(req)
-            groups.setdefault(key, []).append(req)
-            new_bytes += extra
-            queue.popleft()
-        return batch, groups
+            admitted = sum(g[1] for g in groups.values())   # reserved by this pass so far
+            if not self._fit(admitted + want - reserve, keep):
+                if not groups and not self.flights and want > self.budget - self.resident_bytes():
+                    if full > self.budget:
+                        raise MemoryError(f"request {req.rid} needs {full} bytes, budget {self.budget}")
+                break
+            groups[key] = (reqs + [req], want)
+            queue.remove(req)
+            count += 1
+        return groups
 
     def run(self, requests, start=None):
         """Serves requests (objects with rid, arrival, problem) in real time.
         Arrival times are seconds from the start of the run."""
         be = self.be
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
-        queue = collections.deque()
+        queue = []
         results = {}
         t0 = be.now() if start is None else start
-        while pending or queue:
+        while pending or queue or self.flights:
             now = be.now() - t0
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
-            if not queue:
-                be.sleep_until(t0 + pending[0].arrival)
-                continue
-            t_admit = be.now() - t0
-            batch, groups = self._admit(queue)
-            new = 0
-            order = []
-            for key, reqs in groups.items():
-                if key not in self.cache:
-                    plan = be.create(reqs[0].problem)
-                    self.cache[key] = (plan, 0)
-                    self.created += 1
-                    new += 1
-                self.cache.move_to_end(key)
-                order.append((key, reqs))
-            work = []
-            for key, reqs in order:
-                plan = self.cache[key][0]
-                work.append((plan, [be.rhs(plan, r.problem) for r in reqs]))
-            outs = be.solve_groups(work)
-            t_done = be.now() - t0
-            for (key, reqs), parts in zip(order, outs):
-                plan = self.cache[key][0]
+            progressed = False
+            for key, fl in list(self.flights.items()):
+                if not fl.handle.done():
+                    continue
+                plan, parts = fl.handle.result()
+                t_done = be.now() - t0
+                del self.flights[key]
                 self.cache[key] = (plan, be.nbytes(plan))
-                for r, (X, rel) in zip(reqs, parts):
-                    results[r.rid] = Result(r.rid, len(r.problem.rhs), r.arrival, t_admit, t_done,
+                self.cache.move_to_end(key)
+                for r, (X, rel) in zip(fl.reqs, parts):
+                    results[r.rid] = Result(r.rid, len(r.problem.rhs), r.arrival, fl.t_admit, t_done,
                                             np.asarray(rel), X, key)
-            self.ticks.append((t_admit, t_done, len(batch), len(order), new))
+                self.ticks.append((fl.t_admit, t_done, len(fl.reqs), fl.new))
+                progressed = True
+            if queue:
+                t_admit = be.now() - t0
+                for key, (reqs, reserve) in self._admit(queue).items():
+                    new = key not in self.cache
+                    if new:
+                        self.created += 1
+                    else:
+                        self.cache.move_to_end(key)
+                    plan = None if new else self.cache[key][0]
+                    handle = be.launch(plan, [r.problem for r in reqs])
+                    self.flights[key] = _Flight(key, reqs, handle, t_admit, new, reserve)
+                    progressed = True
+                self.peak_committed = max(self.peak_committed, self.committed_bytes())
+            if progressed:
+                continue
+            if queue and not self.flights:
+                raise MemoryError("queued requests do not fit the budget")
+            be.wait(t0 + pending[0].arrival if pending else float("inf"))
         return results
 
     def close(self):
@@ -229,11 +304,14 @@ def run_plain(backend, requests, start=None):
     results = {}
     t0 = be.now() if start is None else start
     for r in sorted(requests, key=lambda r: (r.arrival, r.rid)):
-        be.sleep_until(t0 + r.arrival)
+        while be.now() < t0 + r.arrival:
+            be.wait(t0 + r.arrival)
         ta = be.now() - t0
-        plan = be.create(r.problem)
-        out = be.solve_groups([(plan, [be.rhs(plan, r.problem)])])
-        X, rel = out[0][0]
+        h = be.launch(None, [r.problem])
+        while not h.done():
+            be.wait(float("inf"))
+        plan, parts = h.result()
+        X, rel = parts[0]
         td = be.now() - t0
         be.destroy(plan)
         results[r.rid] = Result(r.rid, len(r.problem.rhs), r.arrival, ta, td, np.asarray(rel), X)

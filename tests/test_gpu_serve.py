@@ -105,3 +105,34 @@ def test_served_results_match_alone():
             assert torch.all(rs <= 1e-10)
         alone.destroy()
     srv.close()
+
+
+def test_1d_request_overtakes_a_2d_factorisation():
+    """Continuous batching: a 1D request that arrives while a 2D factorisation
+    (the 128 x 128 disk, about a second) is on the GPU is launched at once on
+    another stream and finishes first, and its result is the same as alone."""
+    azrbf, problems, serve = _mods()
+    big = W.Request(0, 0.0, W.config_c3a(128))
+    small = W.Request(1, 0.05, W.family_1d(4096, 3, seed0=900, name="late1d"))
+    announce("overtake")
+    be = serve.GpuBackend(keep_x=True)
+    srv = serve.Server(be, budget_bytes=64 << 30)
+    res = srv.run([big, small])
+    announce("2D done", res[0].done, "1D admitted", res[1].admitted, "1D done", res[1].done)
+    assert res[1].admitted < res[0].done
+    assert res[1].done < res[0].done
+    p = small.problem
+    alone = problems.plan_for(p)
+    B = problems.rhs_for(alone, p)
+    Xa, ra = azrbf.solve(alone, B)
+    Ys = azrbf.apply_A(alone, res[1].X)
+    Ya = azrbf.apply_A(alone, Xa)
+    torch.cuda.synchronize()
+    rs = torch.from_numpy(res[1].relres)
+    diff = (torch.linalg.norm(Ya - Ys, dim=1) / torch.linalg.norm(B, dim=1)).cpu()
+    assert torch.all(rs <= 1e-10) and torch.all(ra.cpu() <= 1e-10)
+    assert torch.all(diff <= 10 * (ra.cpu() + rs) + 1e-13)
+    assert np.all(res[0].relres <= 1e-10)
+    alone.destroy()
+    srv.close()
+    be.close()

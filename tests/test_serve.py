@@ -1,6 +1,7 @@
 """Host-side tests of the continuous-batching scheduler (no GPU): a fake
-backend with a simulated clock records what the server asks for."""
-import collections
+backend with a simulated clock records what the server asks for.  Groups in
+flight overlap: each finishes at its own time (a new plan's factorisation,
+then the solve), like work on separate streams."""
 import dataclasses
 
 import numpy as np
@@ -14,6 +15,8 @@ class FakeProblem:
     op_id: str
     nbytes: int
     rhs: list
+    factor_s: float = 1.0
+    rhs_bytes: int = 0          # workspace per right-hand side
 
 
 @dataclasses.dataclass
@@ -24,43 +27,65 @@ class FakeRequest:
 
 
 class FakePlan:
-    def __init__(self, key, nbytes):
-        self.key, self.nbytes, self.alive = key, nbytes, True
+    def __init__(self, prob):
+        self.key, self.nbytes, self.alive, self.prob = prob.op_id, prob.nbytes, True, prob
+
+
+class FakeHandle:
+    def __init__(self, be, plan, probs, finish):
+        self.be, self.plan, self.probs, self.finish = be, plan, probs, finish
+
+    def done(self):
+        return self.be.t >= self.finish
+
+    def result(self):
+        assert self.done()
+        self.be.live_handles.remove(self)
+        return self.plan, [(None, np.full(len(p.rhs), 1e-15)) for p in self.probs]
 
 
 class FakeBackend:
-    """Factor costs 1.0 s, a solve group 0.1 s, all groups of a tick overlap."""
+    """A new plan costs its problem's factor_s, a solve 0.1 s; the device
+    bytes of a plan grow with the largest group it has solved."""
 
-    def __init__(self):
+    def __init__(self, budget=1e18):
         self.t = 0.0
-        self.created, self.destroyed, self.ticks = [], [], []
-        self.live = {}
+        self._budget = budget
+        self.created, self.destroyed, self.launches = [], [], []
+        self.live, self.live_handles = {}, []
+        self.peak_bytes = 0
 
     def key(self, prob):
         return prob.op_id
 
     def footprint(self, prob, nrhs):
-        return prob.nbytes
-
-    def create(self, prob):
-        self.t += 1.0
-        p = FakePlan(prob.op_id, prob.nbytes)
-        self.created.append(prob.op_id)
-        self.live[id(p)] = p
-        return p
+        return prob.nbytes + prob.rhs_bytes * nrhs
 
     def nbytes(self, plan):
         return plan.nbytes
 
-    def rhs(self, plan, prob):
-        assert plan.alive and plan.key == prob.op_id
-        return np.asarray(prob.rhs, dtype=float)
+    def _account(self):
+        b = sum(p.nbytes for p in self.live.values())
+        self.peak_bytes = max(self.peak_bytes, b)
+        assert b <= self._budget, (b, self._budget)
 
-    def solve_groups(self, groups):
-        self.t += 0.1
-        self.ticks.append([(g[0].key, sum(len(b) for b in g[1])) for g in groups])
-        assert sum(p.nbytes for p in self.live.values()) <= self._budget
-        return [[(None, np.full(len(b), 1e-15)) for b in blist] for plan, blist in groups]
+    def launch(self, plan, probs):
+        for p in probs:
+            assert p.op_id == probs[0].op_id
+        cost = 0.1
+        if plan is None:
+            plan = FakePlan(probs[0])
+            self.created.append(plan.key)
+            self.live[id(plan)] = plan
+            cost += probs[0].factor_s
+        assert plan.alive
+        nrhs = sum(len(p.rhs) for p in probs)
+        plan.nbytes = max(plan.nbytes, probs[0].nbytes + probs[0].rhs_bytes * nrhs)
+        self._account()
+        self.launches.append((plan.key, nrhs, self.t))
+        h = FakeHandle(self, plan, probs, self.t + cost)
+        self.live_handles.append(h)
+        return h
 
     def destroy(self, plan):
         plan.alive = False
@@ -70,13 +95,14 @@ class FakeBackend:
     def now(self):
         return self.t
 
-    def sleep_until(self, t):
-        self.t = max(self.t, t)
+    def wait(self, until):
+        nxt = min([h.finish for h in self.live_handles] + [until])
+        assert nxt < float("inf"), "waiting with nothing to wait for"
+        self.t = max(self.t, nxt)
 
 
 def _server(budget):
-    be = FakeBackend()
-    be._budget = budget
+    be = FakeBackend(budget)
     return be, serve.Server(be, budget)
 
 
@@ -86,22 +112,35 @@ def test_groups_requests_by_operator_and_reuses_factors():
     res = srv.run(reqs)
     assert sorted(res) == list(range(6))
     assert be.created == ["B", "A"]                    # one factor per operator
-    assert be.ticks == [[("B", 1 + 3 + 5), ("A", 2 + 4 + 6)]]
+    assert [(k, n) for k, n, _ in be.launches] == [("B", 1 + 3 + 5), ("A", 2 + 4 + 6)]
     assert all(r.nrhs == i + 1 for i, r in sorted(res.items()))
     assert all(len(r.relres) == r.nrhs for r in res.values())
 
 
-def test_requests_arriving_during_a_tick_wait_for_the_next():
+def test_request_for_a_busy_operator_waits_for_its_group():
     be, srv = _server(100)
     reqs = [FakeRequest(0, 0.0, FakeProblem("A", 10, [1.0])),
             FakeRequest(1, 0.5, FakeProblem("A", 10, [1.0])),      # arrives during the first factor
             FakeRequest(2, 5.0, FakeProblem("A", 10, [1.0]))]
     res = srv.run(reqs)
-    assert [len(t) for t in be.ticks] == [1, 1, 1]
-    assert res[1].admitted >= res[0].done                   # joined the second tick
+    assert [n for _, n, _ in be.launches] == [1, 1, 1]
+    assert res[1].admitted >= res[0].done                   # the plan was busy until then
     assert res[2].admitted >= 5.0
     assert be.created == ["A"]                               # the factor stayed resident
     assert res[2].done - res[2].arrival == pytest.approx(0.1)
+
+
+def test_fast_request_overtakes_a_running_factorisation():
+    """A cheap operator arriving while an expensive factorisation runs is
+    launched at once and finishes first (continuous batching)."""
+    be, srv = _server(100)
+    reqs = [FakeRequest(0, 0.0, FakeProblem("2D", 10, [1.0], factor_s=2.0)),
+            FakeRequest(1, 0.2, FakeProblem("1D", 10, [1.0, 2.0], factor_s=0.05))]
+    res = srv.run(reqs)
+    assert res[1].admitted == pytest.approx(0.2)
+    assert res[1].done < res[0].done
+    assert res[1].done == pytest.approx(0.35)
+    assert res[0].done == pytest.approx(2.1)
 
 
 def test_memory_budget_evicts_least_recently_used():
@@ -121,8 +160,28 @@ def test_admission_stops_at_the_budget_and_resumes():
     reqs = [FakeRequest(i, 0.0, FakeProblem(k, 10, [1.0])) for i, k in enumerate("ABC")]
     res = srv.run(reqs)
     assert len(res) == 3
-    assert [len(t) for t in be.ticks] == [2, 1]             # C did not fit beside A and B
+    assert [t for _, _, t in be.launches] == pytest.approx([0.0, 0.0, 1.1])   # C did not fit beside A and B
     assert res[2].admitted >= res[0].done
+
+
+def test_same_operator_requests_reserve_their_workspace():
+    """Many right-hand sides of one operator in one group: the reservation
+    covers the group's concatenated right-hand sides, and a resident plan's
+    workspace growth is reserved too, so the device bytes never exceed the
+    budget (the fake asserts it at every launch)."""
+    be, srv = _server(100)
+    reqs = [FakeRequest(i, 0.0, FakeProblem("A", 40, [1.0] * 4, rhs_bytes=2)) for i in range(5)]
+    reqs += [FakeRequest(5, 0.0, FakeProblem("B", 30, [1.0], rhs_bytes=2))]
+    reqs += [FakeRequest(6 + i, 3.0, FakeProblem("A", 40, [1.0] * 8, rhs_bytes=2)) for i in range(4)]
+    res = srv.run(reqs)
+    assert len(res) == 10
+    assert be.peak_bytes <= 100 and srv.peak_committed <= 100
+    # A's first group: 5 x 4 = 20 right-hand sides -> 80 bytes; B (32) does not fit beside it
+    assert be.launches[0][:2] == ("A", 20)
+    assert ("B", 1) in [(k, n) for k, n, _ in be.launches]
+    # the later group of A (32 right-hand sides, 104 bytes) exceeds the budget as one
+    # group: it is split across launches that each fit
+    assert all(40 + 2 * n <= 100 for k, n, _ in be.launches if k == "A")
 
 
 def test_request_larger_than_budget_is_rejected():
@@ -133,7 +192,6 @@ def test_request_larger_than_budget_is_rejected():
 
 def test_plain_mode_factors_every_request():
     be = FakeBackend()
-    be._budget = 1e9
     reqs = [FakeRequest(i, 0.0, FakeProblem("A", 10, [1.0, 2.0])) for i in range(3)]
     res = serve.run_plain(be, reqs)
     assert be.created == ["A", "A", "A"] and be.destroyed == ["A", "A", "A"]
