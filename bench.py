@@ -307,6 +307,39 @@ def bvp_2d(log_fn, n=256, nrhs=64):
     return out
 
 
+def million_1d(log_fn, n=1 << 20, nrhs=64):
+    """The 1D family at N = 2^20 centres (M = 2^20 + 1; the paper solves up to
+    N = 10^6): plan + factor + solve of one right-hand side, and of nrhs."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2308_14490_amd import azrbf, problems
+    prob = W.family_1d(n, nrhs)
+    p = problems.plan_for(prob)
+    B = problems.rhs_for(p, prob)
+    X, rel = azrbf.solve(p, B)         # warm-up: first launches at this size
+    torch.cuda.synchronize()
+    p.destroy()
+    out = {"workload": f"1D N={n}, M={p.M}, eps*h=0.5, s=2, random-trig RHS, k=32"}
+    for cnt in (1, nrhs):
+        Bc = B[:cnt].contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = problems.plan_for(prob)
+        X, rel = azrbf.solve(p, Bc)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        good = int((rel <= 1e-10).sum())
+        out[f"plan_factor_solve_{cnt}rhs_s"] = round(dt, 5)
+        out[f"solves_per_s_{cnt}rhs"] = round(good / dt, 1)
+        out[f"max_relres_{cnt}rhs"] = float(rel.max())
+        p.destroy()
+    azrbf.release_cached_memory()
+    log_fn(f"1D N={n}: plan+factor+solve 1 RHS {out['plan_factor_solve_1rhs_s'] * 1e3:.1f} ms, "
+           f"{nrhs} RHS {out[f'plan_factor_solve_{nrhs}rhs_s'] * 1e3:.1f} ms")
+    return out
+
+
 def copies_1d(log_fn, copies=4096, plain=64):
     """The 256-centre 1D problem (eps*h = 0.5, f = e^x sin 7x + x^2) solved for
     `copies` right-hand sides at once on one plan (one launch sequence for all
@@ -543,6 +576,7 @@ def main():
         out["served_stream"] = served_vs_plain(args.serve_count, 2024, (64,), log)
     out["fft_passes_beyond_cache"] = beyond_cache(log)
     out["copies_1d_n256"] = copies_1d(log)
+    out["million_1d"] = million_1d(log)
     if not args.no_2d:
         out["wide_2d"] = wide_2d(log)
         out["poisson_2d_n256"] = bvp_2d(log)

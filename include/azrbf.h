@@ -67,7 +67,8 @@ typedef struct azrbf_plan_s* azrbf_plan_t;
 typedef struct {
   int32_t dim;            /* 1 or 2                                          */
   int32_t n;              /* centres per axis: a power of two, 16 <= n,      */
-                          /* n <= 65536 (1D), n <= 512 (2D)                  */
+                          /* n <= 2^20 (1D; s <= 2 above 2^19), n <= 512     */
+                          /* (2D)                                             */
   int32_t s;              /* oversampling factor per axis: 1, 2 or 4         */
   double T;               /* half-width of the periodic box [-T, T)^dim      */
   double eps;             /* shape parameter; if <= 0 it follows             */

@@ -16,11 +16,14 @@
 namespace az {
 
 constexpr int RADIX = 16;
-// Twiddle table: for every n = 2^l <= TW_SIZE the n roots w_n^i =
+// Twiddle table: for every n = 2^l <= TW_FULL the n roots w_n^i =
 // exp(-2 pi i i / n) are stored contiguously at offset n, so the roots one
-// transform length uses share few cache lines (2 * TW_SIZE entries in all).
-constexpr int TW_LOG = 17;
+// transform length uses share few cache lines.  Longer lengths n <= TW_SIZE
+// only ever need their first 256 roots (the four-step twiddle takes w_n^e as
+// w_n^(e mod 256) w_(n/256)^(e div 256)), which sit at offset n as well.
+constexpr int TW_LOG = 20;
 constexpr int TW_SIZE = 1 << TW_LOG;
+constexpr int TW_FULL = 1 << 13;
 constexpr int TW_ENTRIES = 2 * TW_SIZE;
 
 // v unchanged, but opaque to the optimiser: addresses derived from it inside

@@ -41,7 +41,8 @@ int ops_init_twiddles(int device, const double2** tw) {
     std::vector<double2> h(TW_ENTRIES, make_double2(0.0, 0.0));
     const long double pi = 3.141592653589793238462643383279502884L;
     for (int n = 1; n <= TW_SIZE; n *= 2) {
-      for (int i = 0; i < n; ++i) {
+      const int used = n <= TW_FULL ? n : 256;
+      for (int i = 0; i < used; ++i) {
         const long double a = -2.0L * pi * (long double)i / (long double)n;
         h[n + i] = make_double2((double)cosl(a), (double)sinl(a));
       }
@@ -840,6 +841,15 @@ static int set_lds(K kern, int bytes) {
     default: return AZRBF_EUNSUPPORTED;                                            \
   }
 
+// Column passes also take the longer columns of 1D transforms up to 2^20
+// (N1 = N / 512).
+#define AZ_SWITCH_COL(n, F, ...)                                                   \
+  switch (n) {                                                                     \
+    case 1024: return F<1024>(__VA_ARGS__);                                        \
+    case 2048: return F<2048>(__VA_ARGS__);                                        \
+    default: AZ_SWITCH_ENGINE(n, F, __VA_ARGS__)                                   \
+  }
+
 template <int N, int S>
 static int launch_fused_A_s(const Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha,
                             double beta, const double* Yin, int64_t ldyi, double* Y, int64_t ldy, hipStream_t st) {
@@ -1094,7 +1104,7 @@ static int launch_row(const RowArgs& a) {
 #undef AZ_ROWK
 }
 
-static int run_col(const ColArgs& a) { AZ_SWITCH_ENGINE(a.P->geo.N1, launch_col, a) }
+static int run_col(const ColArgs& a) { AZ_SWITCH_COL(a.P->geo.N1, launch_col, a) }
 static int run_row(const RowArgs& a) { AZ_SWITCH_ENGINE(a.P->geo.N2, launch_row, a) }
 
 // Grows the FFT workspace to `pairs` vector pairs; the replaced buffers go
@@ -1113,10 +1123,11 @@ static int ensure_ws(Plan& P, int64_t pairs, hipStream_t st) {
   return AZRBF_OK;
 }
 
-// Pairs per engine chunk: about 64 MiB of each workspace buffer.
+// Pairs per engine chunk: at most 64, each workspace buffer at most 256 MiB
+// (at N = 65536, s = 2 a pair takes 2 MiB; at N = 2^20, 32 MiB).
 static int64_t engine_chunk(const Plan& P, int64_t npairs) {
   const int64_t per = (int64_t)P.ph * P.N * (int64_t)sizeof(double2);
-  int64_t c = ((int64_t)64 << 20) / per;
+  int64_t c = ((int64_t)256 << 20) / per;
   if (c < 1) c = 1;
   if (c > 64) c = 64;
   if (P.tune_chunk > 0) c = P.tune_chunk;

@@ -339,12 +339,13 @@ static int factor_plan(Plan& P, hipStream_t st) {
 }
 
 // Four-step split of a 1D transform of length N > 8192 (or forced): N = N1 * N2.
+// Rows (the second factor) are at most 512 long; the columns take the rest,
+// up to 2048 (N = 2^20).
 static void split_1d(int64_t N, int* N1, int* N2) {
   int lg = 0;
   while ((1LL << lg) < N) ++lg;
   int l2 = (lg + 1) / 2;
   if (l2 > 9) l2 = 9;
-  if (lg - l2 > 9) l2 = lg - 9;
   *N2 = 1 << l2;
   *N1 = (int)(N >> l2);
 }
@@ -427,7 +428,10 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
   if (!(q.tau > 0) || q.tauZ < 0 || q.refine < 0 || q.refine > 8 || q.k < 0) return AZRBF_EINVAL;
   if (q.eps <= 0 && !(q.tau0 > 0 && q.tau0 < 1)) return AZRBF_EINVAL;
   if (!az::pow2(q.n) || q.n < 16) return AZRBF_EUNSUPPORTED;
-  if ((q.dim == 1 && q.n > 65536) || (q.dim == 2 && q.n > 512)) return AZRBF_EUNSUPPORTED;
+  if ((q.dim == 1 && q.n > (1 << 20)) || (q.dim == 2 && q.n > 512)) return AZRBF_EUNSUPPORTED;
+  // a column pass puts the s phases of a column in one block of at most 256
+  // threads, n1 / 16 per phase (1D: n1 = n / 512 once n > 2^18)
+  if (q.dim == 1 && q.n > (1 << 18) && q.s * (q.n >> 9) / 16 > 256) return AZRBF_EUNSUPPORTED;
   if (q.s != 1 && q.s != 2 && q.s != 4) return AZRBF_EUNSUPPORTED;
 
   azrbf_plan_s* h = new (std::nothrow) azrbf_plan_s();
@@ -494,7 +498,7 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
       g.N2 = (int)P.N;
     } else {
       az::split_1d(P.N, &g.N1, &g.N2);
-      if (g.N1 < 16 || g.N2 < 16 || g.N1 > 512 || g.N2 > 512) { delete h; return AZRBF_EUNSUPPORTED; }
+      if (g.N1 < 16 || g.N2 < 16 || g.N1 > 2048 || g.N2 > 512) { delete h; return AZRBF_EUNSUPPORTED; }
     }
   } else {
     g.N1 = g.N2 = P.n;
@@ -776,10 +780,12 @@ int64_t azrbf_footprint_bytes(const azrbf_problem* pr, int64_t max_rhs) {
   int64_t b = 0;
   b += 2 * ph * N * 16;                                 // spectra (1D) or factors + weights (2D)
   b += pr->dim == 2 ? Lg * 4 : 0;                       // inverse map
-  int64_t chunk = ((int64_t)64 << 20) / (ph * N * 16);
+  int64_t chunk = ((int64_t)256 << 20) / (ph * N * 16);   // as engine_chunk
   chunk = chunk < 1 ? 1 : (chunk > 64 ? 64 : chunk);
   const int64_t pairs = (std::max<int64_t>(k, max_rhs) + 1) / 2;
-  if (!(pr->dim == 1 && N <= 8192)) b += 2 * ph * N * 16 * std::min<int64_t>(chunk, pairs);
+  // FFT workspace; a 1D solve with k <= 64 keeps a second set for its side stream
+  const int64_t wsets = pr->dim == 1 && k <= 64 ? 2 : 1;
+  if (!(pr->dim == 1 && N <= 8192)) b += wsets * 2 * ph * N * 16 * std::min<int64_t>(chunk, pairs);
   if (k > 64) {
     b += 8 * az::wide_factor_doubles(N, Mt, k);
     b += 8 * (max_rhs * (2 * N + 3 * Mt + 2 * k + 64) + az::gemm_split_doubles(k, max_rhs, Mt, 1) + 1);

@@ -165,7 +165,10 @@ int tune_load(const char* text) {
     int C = 0, L = 0, ch = 0, n = 0;
     if (sscanf(p, "%95s %d %d %d%n", key, &C, &L, &ch, &n) != 4) return AZRBF_EINVAL;
     int dim = 0, N1 = 0, N2 = 0, s = 0;
-    if (sscanf(key, "e%d_%dx%d_s%d", &dim, &N1, &N2, &s) != 4 || N1 < 16 || N2 < 16 || N1 > 512 || N2 > 512)
+    // engine shapes: rows up to 512; columns up to 512, or up to 2048 beside
+    // 512-long rows (1D transforms of 2^19 and 2^20)
+    if (sscanf(key, "e%d_%dx%d_s%d", &dim, &N1, &N2, &s) != 4 || N1 < 16 || N2 < 16 || N2 > 512 ||
+        N1 > (dim == 1 && N2 == 512 ? 2048 : 512) || (N1 & (N1 - 1)) || (N2 & (N2 - 1)))
       return AZRBF_EINVAL;
     if (!engine_shape_ok(N1, N2, C, L, ch)) return AZRBF_EINVAL;
     g_tune[key] = Shape{C, L, ch};

@@ -198,3 +198,50 @@ def test_apply_A_elementwise_full_2d_disk():
 def test_apply_A_elementwise_full_2d_poisson_star():
     """n = 256 Poisson rows -(Lap) phi / (4 eps^2) and the 2517 Dirichlet rows."""
     _apply_elementwise(W.config_c4(256), 4)
+
+
+# ------------------------------------------------ 1D transforms up to 2^20 centres
+
+@pytest.mark.parametrize("n", [1 << 18, 1 << 20])
+def test_apply_A_elementwise_1d_to_a_million(n):
+    """N = 2^18 (columns of 512) and 2^20 (columns of 2048, rows of 512):
+    A X element by element against the windowed direct sums."""
+    _apply_elementwise(W.family_1d(n, 1), 4)
+
+
+def test_zstar_inverts_the_periodic_matrix_at_a_million():
+    """Z* A^c X = X on the periodic box at N = 2^20 (no weight zeroed at
+    eps*h = 0.5, s = 2)."""
+    import math
+    azrbf, problems = _mods()
+    n = 1 << 20
+    prob = W.Problem("box", 1, n, 2, 1.0, 0.5, W.box(1.0), [])
+    p = problems.plan_for(prob)
+    X = torch.from_numpy(np.random.default_rng(8).standard_normal((3, n))).cuda()
+    Z = azrbf.apply_Zstar(p, azrbf.apply_A(p, X))
+    err = float((Z - X).abs().max() / X.abs().max())
+    from oracle import spectra
+    D = sum(np.abs(spectra.diag_closed_form(n, 2, 1.0, prob.eps, r)) ** 2 for r in range(2))
+    assert D.min() > 1e-12 * D.max()                 # nothing zeroed
+    tol = 20 * U * math.log2(n) * math.sqrt(D.max() / D.min())     # ||A^c|| ||Z*|| (Lemma 4.3)
+    announce("box identity 2^20", "err", err, "tol", tol)
+    assert err < tol
+    p.destroy()
+
+
+def test_fullsize_1d_solve_at_a_million():
+    """The 1D batched family at N = 2^20 (M = 2^20 + 1): residual <= 1e-10
+    over every row by the local evaluator, equal to the library's, and the
+    test-set error within 10x the dense oracle's at N = 4096 (flat in N)."""
+    prob = W.family_1d(1 << 20, 4)
+    announce("1D 2^20", prob.N)
+    p, B, X, rel = _solve(prob)
+    rc = _cpu_residual(prob, p, X, B)
+    ro, eo = _oracle_levels(W.family_1d(4096, 4))
+    eg = _cpu_maxerr(prob, X)
+    announce("rank", p.info()["rank"], "relres gpu", rel, "cpu", rc, "oracle@4096", ro, "maxerr", eg, eo)
+    assert np.all(rc <= 1e-10)
+    assert np.allclose(rc, rel, rtol=1e-2, atol=1e-16)
+    assert np.all(rc <= 10 * ro + 1e-15)
+    assert np.all(eg <= 10 * eo + 1e-15)
+    p.destroy()

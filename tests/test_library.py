@@ -62,12 +62,19 @@ def test_plan_rejects_bad_arguments_before_touching_the_gpu():
     mask = np.ones(64, dtype=np.uint8)
     h = ctypes.c_void_p()
     for field, val, code in [("n", 24, azrbf.EUNSUPPORTED), ("s", 3, azrbf.EUNSUPPORTED),
-                             ("dim", 3, azrbf.EINVAL), ("tau", 0.0, azrbf.EINVAL)]:
+                             ("dim", 3, azrbf.EINVAL), ("tau", 0.0, azrbf.EINVAL),
+                             ("n", 1 << 21, azrbf.EUNSUPPORTED)]:
         pr = azrbf._Problem()
         pr.dim, pr.n, pr.s, pr.T, pr.eps, pr.tau, pr.tauZ = 1, 32, 2, 1.0, 8.0, 1e-12, 1e-12
         pr.mask = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
         setattr(pr, field, val)
         assert lib.azrbf_plan(ctypes.byref(pr), None, ctypes.byref(h)) == code
+    # n = 2^20 with s = 4: a column pass would need 512 threads for the 4 phases
+    big = np.ones(4 << 20, dtype=np.uint8)
+    pr = azrbf._Problem()
+    pr.dim, pr.n, pr.s, pr.T, pr.eps, pr.tau, pr.tauZ = 1, 1 << 20, 4, 1.0, 8.0, 1e-12, 1e-12
+    pr.mask = big.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    assert lib.azrbf_plan(ctypes.byref(pr), None, ctypes.byref(h)) == azrbf.EUNSUPPORTED
 
 
 def test_tune_table_round_trip_and_validation():
@@ -79,6 +86,8 @@ def test_tune_table_round_trip_and_validation():
     assert lib.azrbf_tune_load(b"e1_256x256_s2 3 4 16\n") == azrbf.EINVAL      # C not a power of two
     assert lib.azrbf_tune_load(b"e1_256x256_s2 32 4 16\n") == azrbf.EINVAL     # 32 x 16 threads > 256
     assert lib.azrbf_tune_load(b"e1_1024x64_s2 2 2 16\n") == azrbf.EINVAL      # N1 out of range
+    assert lib.azrbf_tune_load(b"e1_4096x512_s2 1 2 16\n") == azrbf.EINVAL     # N1 out of range
+    assert lib.azrbf_tune_load(b"e1_2048x512_s2 2 2 8\n") == 0                  # a 2^20 transform
     assert lib.azrbf_tune_load(b"garbage\n") == azrbf.EINVAL
     assert lib.azrbf_tune_load(b"e2_128x128_s2 16 16 8\ne2_64x64_s2 4 8 2\n") == 0
     t = azrbf.tune_table()
