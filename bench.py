@@ -385,8 +385,8 @@ def copies_1d(log_fn, copies=4096, plain=64):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--plain", type=int, default=8, help="right-hand sides timed in the plain modes")

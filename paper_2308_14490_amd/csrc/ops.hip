@@ -336,6 +336,22 @@ k_row(Geo g, const double2* __restrict__ tw, const double2* ws1, double2* __rest
   const int64_t pair = blockIdx.y;
   const int nph = TWID ? g.s : g.s * g.s;
   double2 acc[RADIX];
+  // One phase per line: the spectral values this line multiplies by are
+  // fetched before its transforms, so that their latency overlaps them (A Z*
+  // prefetches Z*'s spectrum only, and not at all when Z*'s rows are stored as
+  // well: no registers to spare at two waves per SIMD).
+  constexpr bool PRE = ONE && MODE != ROW_AZC;
+  constexpr bool PRE_Z = PRE && MODE != ROW_A, PRE_A = PRE && MODE == ROW_A;
+  double2 sz[PRE_Z ? RADIX : 1], sa[PRE_A ? RADIX : 1];
+  if constexpr (PRE_Z) {
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) sz[m] = specZ_d<TWID>(g, q, (int)k1, t + m * T);
+  }
+  if constexpr (PRE_A) {
+    const double sc = MODE == ROW_A ? 1.0 : (double)g.N;
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) sa[m] = cscale(specA_d<TWID>(g, q, (int)k1, t + m * T), sc);
+  }
   if (MODE == ROW_A) {
     const double2* in = ws1 + pair * g.N + k1 * N2;
 #pragma unroll
@@ -346,9 +362,14 @@ k_row(Geo g, const double2* __restrict__ tw, const double2* ws1, double2* __rest
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) acc[m] = in[t + m * T];
     fft_line<N2, false>(acc, lds, l, t, tw);
-    const int tt = opaque(t);
+    if constexpr (PRE_Z) {
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) acc[m] = cmul(acc[m], specZ_d<TWID>(g, q, (int)k1, tt + m * T));
+      for (int m = 0; m < RADIX; ++m) acc[m] = cmul(acc[m], sz[m]);
+    } else {
+      const int tt = opaque(t);
+#pragma unroll
+      for (int m = 0; m < RADIX; ++m) acc[m] = cmul(acc[m], specZ_d<TWID>(g, q, (int)k1, tt + m * T));
+    }
   } else {
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) acc[m] = make_double2(0.0, 0.0);
@@ -406,8 +427,14 @@ k_row(Geo g, const double2* __restrict__ tw, const double2* ws1, double2* __rest
   if (MODE == ROW_Z) return;
   const double scale = MODE == ROW_A ? 1.0 : (double)g.N;
   if (ONE) {
+    if constexpr (PRE_A) {
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) acc[m] = cmul(acc[m], cscale(specA_d<TWID>(g, q, (int)k1, t + m * T), scale));
+      for (int m = 0; m < RADIX; ++m) acc[m] = cmul(acc[m], sa[m]);
+    } else {
+#pragma unroll
+      for (int m = 0; m < RADIX; ++m)
+        acc[m] = cmul(acc[m], cscale(specA_d<TWID>(g, q, (int)k1, t + m * T), scale));
+    }
     fft_line<N2, true>(acc, lds, l, t, tw);
     double2* out = ws2 + (pair * nph + q) * g.N + k1 * N2;
 #pragma unroll
@@ -544,10 +571,25 @@ k_col_inv_Z(Geo g, const double2* __restrict__ tw, const double2* __restrict__ w
   const double2* in = ws2 + pair * pstride;
 #pragma unroll
   for (int m = 0; m < RADIX; ++m) a[m] = in[(int64_t)(t + m * T) * g.N2 + b];
-  fft_line<N1, true>(a, lds, l, t, tw);
+  // with beta != 0 the coefficients combined with are fetched before the
+  // transform, so that their latency overlaps it (Zin may be Z: each element
+  // is read before it is written, by the same thread)
+  double2 zin[RADIX];
 #pragma unroll
-  for (int m = 0; m < RADIX; ++m)
-    store_pair(Z, ldz, Zin, ldzi, (int64_t)(t + m * T) * g.N2 + b, v0, nvec, a[m], alpha, beta);
+  for (int m = 0; m < RADIX; ++m) zin[m] = make_double2(0.0, 0.0);
+  if (beta != 0.0) {
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) zin[m] = load_pair(Zin, ldzi, (int64_t)(t + m * T) * g.N2 + b, v0, nvec);
+  }
+  fft_line<N1, true>(a, lds, l, t, tw);
+  if (v0 < nvec) {
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) {
+      double* p0 = Z + (int64_t)(t + m * T) * g.N2 + b + ldz * v0;
+      *p0 = beta == 0.0 ? alpha * a[m].x : fma(alpha, a[m].x, beta * zin[m].x);
+      if (v0 + 1 < nvec) p0[ldz] = beta == 0.0 ? alpha * a[m].y : fma(alpha, a[m].y, beta * zin[m].y);
+    }
+  }
 }
 
 // Plain forward FFT of complex N1 x N2 arrays in the engine's layout (spectra set-up):
