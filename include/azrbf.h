@@ -69,7 +69,7 @@ typedef struct {
   int32_t n;              /* centres per axis: a power of two, 16 <= n,      */
                           /* n <= 2^20 (1D; s <= 2 above 2^19), n <= 512     */
                           /* (2D)                                             */
-  int32_t s;              /* oversampling factor per axis: 1, 2 or 4         */
+  int32_t s;              /* oversampling factor per axis: 1, 2, 3 or 4      */
   double T;               /* half-width of the periodic box [-T, T)^dim      */
   double eps;             /* shape parameter; if <= 0 it follows             */
                           /* eq. constant_shapeparam from tau0               */
@@ -111,7 +111,7 @@ typedef struct {
  * waiting for them; work later passed another stream first waits for them).
  * On success *out owns the plan.
  * Errors: EINVAL (bad sizes, empty mask, nb > 0 without op BVP, ...),
- * EUNSUPPORTED (n not a power of two or out of range, s not in {1,2,4}),
+ * EUNSUPPORTED (n not a power of two or out of range, s not in {1,2,3,4}),
  * ENOMEM, EHIP. */
 int azrbf_plan(const azrbf_problem* prob, void* stream, azrbf_plan_t* out);
 

@@ -912,6 +912,7 @@ static int launch_fused_A(const Plan& P, const double* X, int64_t ldx, int64_t n
   switch (P.s) {
     case 1: return launch_fused_A_s<N, 1>(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st);
     case 2: return launch_fused_A_s<N, 2>(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st);
+    case 3: return launch_fused_A_s<N, 3>(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st);
     default: return launch_fused_A_s<N, 4>(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st);
   }
 }
@@ -936,6 +937,7 @@ static int launch_fused_Z(const Plan& P, const double* R, int64_t ldr, int64_t n
   switch (P.s) {
     case 1: return launch_fused_Z_s<N, 1>(P, R, ldr, nvec, alpha, beta, Zin, ldzi, Z, ldz, st);
     case 2: return launch_fused_Z_s<N, 2>(P, R, ldr, nvec, alpha, beta, Zin, ldzi, Z, ldz, st);
+    case 3: return launch_fused_Z_s<N, 3>(P, R, ldr, nvec, alpha, beta, Zin, ldzi, Z, ldz, st);
     default: return launch_fused_Z_s<N, 4>(P, R, ldr, nvec, alpha, beta, Zin, ldzi, Z, ldz, st);
   }
 }
@@ -1001,9 +1003,12 @@ static int launch_col(const ColArgs& a) {
   const int lds = C * N1 * (int)sizeof(double2);
   const dim3 grid((unsigned)(g.N2 / C), (unsigned)a.npairs);
   // modes 1 and 2 spread the s phases of a column over s lines of the block:
-  // C lines are C / s columns (at least one column, then s lines)
+  // the block takes the largest power-of-two number of whole columns that
+  // fits in C lines (at least one column), s lines each
   const int S = g.s;
-  const int Cp = C >= S ? C : S;
+  int ncols = 1;
+  while (2 * ncols * S <= C) ncols *= 2;
+  const int Cp = ncols * S;
   const int block_p = Cp * Col<N1>::T;
   const int lds_p = Cp * N1 * (int)sizeof(double2);
   const dim3 grid_p((unsigned)(g.N2 / (Cp / S)), (unsigned)a.npairs, (unsigned)(g.dim == 1 ? 1 : S));
@@ -1044,9 +1049,11 @@ static int launch_col(const ColArgs& a) {
   launch_kernel(k_col_inv_A<N1, S, D1>, grid_p, block_p, lds_p, a.st, g, P.tw, a.cin, a.nvec, a.pair0,       \
                 a.alpha, a.beta, a.oin, a.ldoi, a.out, a.ldo, Cp);
       if (tw4) {
-        if (g.s == 1) { AZ_COLINV(1, true) } else if (g.s == 2) { AZ_COLINV(2, true) } else { AZ_COLINV(4, true) }
+        if (g.s == 1) { AZ_COLINV(1, true) } else if (g.s == 2) { AZ_COLINV(2, true) }
+        else if (g.s == 3) { AZ_COLINV(3, true) } else { AZ_COLINV(4, true) }
       } else {
-        if (g.s == 1) { AZ_COLINV(1, false) } else if (g.s == 2) { AZ_COLINV(2, false) } else { AZ_COLINV(4, false) }
+        if (g.s == 1) { AZ_COLINV(1, false) } else if (g.s == 2) { AZ_COLINV(2, false) }
+        else if (g.s == 3) { AZ_COLINV(3, false) } else { AZ_COLINV(4, false) }
       }
 #undef AZ_COLINV
       break;
@@ -1056,9 +1063,11 @@ static int launch_col(const ColArgs& a) {
   launch_kernel(k_col_fwd_Z<N1, TW, S>, grid_p, block_p, lds_p, a.st, g, P.tw, a.in, a.ldi, a.nvec, a.pair0, \
                 a.cout, Cp);
       if (tw4) {
-        if (g.s == 1) { AZ_COLFZ(true, 1) } else if (g.s == 2) { AZ_COLFZ(true, 2) } else { AZ_COLFZ(true, 4) }
+        if (g.s == 1) { AZ_COLFZ(true, 1) } else if (g.s == 2) { AZ_COLFZ(true, 2) }
+        else if (g.s == 3) { AZ_COLFZ(true, 3) } else { AZ_COLFZ(true, 4) }
       } else {
-        if (g.s == 1) { AZ_COLFZ(false, 1) } else if (g.s == 2) { AZ_COLFZ(false, 2) } else { AZ_COLFZ(false, 4) }
+        if (g.s == 1) { AZ_COLFZ(false, 1) } else if (g.s == 2) { AZ_COLFZ(false, 2) }
+        else if (g.s == 3) { AZ_COLFZ(false, 3) } else { AZ_COLFZ(false, 4) }
       }
 #undef AZ_COLFZ
       break;
@@ -1116,9 +1125,13 @@ static int launch_row(const RowArgs& a) {
     launch_kernel(k_row_fwd_C<N2>, grid, block, lds, a.st, g, P.tw, a.out, Lr);
     return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
   }
-  // phases spread over PL lines per row (PL divides the phase count; PL * T <= 128)
-  const int PL = P.ph < 4 ? P.ph : 4;
-  const int lines = Lr > PL ? Lr : PL;
+  // phases spread over PL lines per row (PL divides the phase count: 1, 2,
+  // 3 or 4; the 9 phases of 2D s = 3 take three lines); the block takes the
+  // largest power-of-two number of whole rows that fits in Lr lines
+  const int PL = P.ph % 3 == 0 ? 3 : (P.ph < 4 ? P.ph : 4);
+  int nrows = 1;
+  while (2 * nrows * PL <= Lr) nrows *= 2;
+  const int lines = nrows * PL;
   const int block_p = lines * Row<N2>::T;
   const int lds_p = lines * RowLds::stride(N2) * (int)sizeof(double2);
   const dim3 grid_p((unsigned)(g.N1 / (lines / PL)), (unsigned)a.npairs);
@@ -1137,11 +1150,13 @@ static int launch_row(const RowArgs& a) {
   if (tw4) {
     if (PL == 1) { AZ_ROWK(true, 1, true) }
     if (PL == 2) { AZ_ROWK(true, 2, true) }
+    if (PL == 3) { AZ_ROWK(true, 3, true) }
     AZ_ROWK(true, 4, true)
   }
   if (PL == 1) { AZ_ROWK(false, 1, true) }
   if (P.ph == 4) { AZ_ROWK(false, 4, true) }
   if (P.ph == 2) { AZ_ROWK(false, 2, true) }
+  if (P.ph == 9) { AZ_ROWK(false, 3, false) }
   AZ_ROWK(false, 4, false)
 #undef AZ_ROWK
 }

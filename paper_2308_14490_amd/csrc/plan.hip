@@ -432,7 +432,7 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
   // a column pass puts the s phases of a column in one block of at most 256
   // threads, n1 / 16 per phase (1D: n1 = n / 512 once n > 2^18)
   if (q.dim == 1 && q.n > (1 << 18) && q.s * (q.n >> 9) / 16 > 256) return AZRBF_EUNSUPPORTED;
-  if (q.s != 1 && q.s != 2 && q.s != 4) return AZRBF_EUNSUPPORTED;
+  if (q.s < 1 || q.s > 4) return AZRBF_EUNSUPPORTED;
 
   azrbf_plan_s* h = new (std::nothrow) azrbf_plan_s();
   if (!h) return AZRBF_ENOMEM;

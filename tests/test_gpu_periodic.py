@@ -67,14 +67,15 @@ def _periodic_case(dim, n, s, tau0, f):
     return W.Problem(f"periodic{dim}d", dim, n, s, 1.0, eh, W.box(1.0, dim), [f], k=32 if dim == 1 else 0)
 
 
-@pytest.mark.parametrize("n", [256, 1024])
-def test_periodic_1d_solve_matches_oracle_and_paper(n):
-    """f = sin([N/5] pi x) on the periodic box, T = 1, tau0 = 1e-10 (the first
-    experiment of section 3.3, with s = 2 where the paper takes s = 3): the
-    paper reports a maximum error below 1e-12."""
+@pytest.mark.parametrize("n,s", [(256, 2), (1024, 2), (256, 3), (1024, 3)])
+def test_periodic_1d_solve_matches_oracle_and_paper(n, s):
+    """f = sin([N/5] pi x) on the periodic box, T = 1, tau0 = 1e-10: the first
+    experiment of section 3.3 (s = 3, Fig. 3.1), and the same at s = 2.  The
+    paper reports a maximum error below 1e-12 and a coefficient norm
+    ||a|| / sqrt(N) of about 5 (checked within a factor 1.5 at s = 3)."""
     azrbf, problems = _mods()
     kk = math.floor(n / 5)
-    prob = _periodic_case(1, n, 2, 1e-10, lambda x: np.sin(kk * np.pi * x))
+    prob = _periodic_case(1, n, s, 1e-10, lambda x: np.sin(kk * np.pi * x))
     p = problems.plan_for(prob)
     B = problems.rhs_for(p, prob)
     X, rel = azrbf.solve(p, B)
@@ -88,9 +89,12 @@ def test_periodic_1d_solve_matches_oracle_and_paper(n):
     eg = np.abs(evaluate.eval_dense(prob, Xg, tp)[:, 0] - f).max()
     eo = np.abs(evaluate.eval_dense(prob, Xo, tp)[:, 0] - f).max()
     rg, ro = evaluate.relres(A, Xg, Bo), evaluate.relres(A, Xo, Bo)
-    announce("periodic 1D", n, "rank", p.info()["rank"], "relres", rg, ro, "maxerr", eg, eo)
+    cn = np.linalg.norm(Xg) / math.sqrt(n)
+    announce("periodic 1D", n, "s", s, "rank", p.info()["rank"], "relres", rg, ro, "maxerr", eg, eo, "||a||/sqrt(N)", cn)
     assert np.all(rg <= 10 * ro + 1e-15)
     assert eg <= 10 * eo + 1e-15 and eg < 1e-12
+    if s == 3:
+        assert 5.0 / 1.5 < cn < 5.0 * 1.5
     p.destroy()
 
 
