@@ -3,6 +3,7 @@
 1D approximation (section 2.3):  A_ij = phi_j(x_i) = phi_per(x_i - c_j).
 2D approximation (section 5.2, eq. Aa_is_b_2d): the basis function
     phi_j(x, y) = phi_per(x - cx_m) phi_per(y - cy_n),  j = m*Ny + n
+(each axis periodized with its own box half-width T^x, T^y).
 (the Gaussian is a product of univariate Gaussians, section 5).
 Boundary value problems (section 6): interior rows apply the operator to the
 basis, boundary rows evaluate it at boundary points (eq. Ai_2d_bvp and the
@@ -39,12 +40,13 @@ def interior_rows(prob, pts):
         a2 = basis_1d(x, n, T, eps, 2)
         a0 = basis_1d(x, n, T, eps, 0)
         return -(a2 + prob.k2 * a0) / (2.0 * eps * eps)
+    ny, Ty = prob.n_y, prob.T_y
     ax0 = basis_1d(pts[:, 0], n, T, eps)
-    ay0 = basis_1d(pts[:, 1], n, T, eps)
+    ay0 = basis_1d(pts[:, 1], ny, Ty, eps)
     if prob.op == 0:
         return _rowkron(ax0, ay0)
     ax2 = basis_1d(pts[:, 0], n, T, eps, 2)
-    ay2 = basis_1d(pts[:, 1], n, T, eps, 2)
+    ay2 = basis_1d(pts[:, 1], ny, Ty, eps, 2)
     lap = _rowkron(ax2, ay0) + _rowkron(ax0, ay2)
     return -(lap + prob.k2 * _rowkron(ax0, ay0)) / (4.0 * eps * eps)
 
@@ -57,7 +59,7 @@ def boundary_rows(prob, bpts):
     if prob.dim == 1:
         return prob.bweight * basis_1d(bpts[:, 0], n, T, eps)
     return prob.bweight * _rowkron(basis_1d(bpts[:, 0], n, T, eps),
-                                   basis_1d(bpts[:, 1], n, T, eps))
+                                   basis_1d(bpts[:, 1], prob.n_y, prob.T_y, eps))
 
 
 def system_matrix(prob):

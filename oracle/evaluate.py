@@ -70,16 +70,17 @@ def apply_local(prob, coef, pts, op=None):
             _, vx2 = _window_1d(pts[:, 0], n, T, eps, 2)
             out = np.einsum("mw,mwr->mr", -(vx2 + prob.k2 * vx) / (2 * eps * eps), C[jx])
         return out if coef.ndim == 2 else out[:, 0]
-    C3 = C.reshape(n, n, -1)
+    ny, Ty = prob.n_y, prob.T_y
+    C3 = C.reshape(n, ny, -1)
     jx, vx = _window_1d(pts[:, 0], n, T, eps, 0)
-    jy, vy = _window_1d(pts[:, 1], n, T, eps, 0)
+    jy, vy = _window_1d(pts[:, 1], ny, Ty, eps, 0)
     out = np.zeros((pts.shape[0], C.shape[1]))
     if op == 0:
         for a in range(jx.shape[1]):
             out += vx[:, a:a + 1] * np.einsum("mw,mwr->mr", vy, C3[jx[:, a:a + 1], jy])
     else:
         _, vx2 = _window_1d(pts[:, 0], n, T, eps, 2)
-        _, vy2 = _window_1d(pts[:, 1], n, T, eps, 2)
+        _, vy2 = _window_1d(pts[:, 1], ny, Ty, eps, 2)
         s = -1.0 / (4 * eps * eps)
         for a in range(jx.shape[1]):
             g = C3[jx[:, a:a + 1], jy]             # (m, Wy, r)

@@ -40,7 +40,8 @@ def periodic_matrix(prob):
     xt = grids.fine_grid(prob.n, prob.s, prob.T)
     if prob.dim == 1:
         return dense.interior_rows(prob, xt[:, None])
-    X, Y = np.meshgrid(xt, xt, indexing="ij")
+    yt = grids.fine_grid(prob.n_y, prob.s, prob.T_y)
+    X, Y = np.meshgrid(xt, yt, indexing="ij")
     return dense.interior_rows(prob, np.stack([X.ravel(), Y.ravel()], axis=1))
 
 
@@ -48,19 +49,21 @@ def _pi_full(prob):
     p1 = pi_perm(prob.n, prob.s)
     if prob.dim == 1:
         return p1
-    L = prob.n * prob.s
-    return (p1[:, None] * L + p1[None, :]).ravel()
+    p2 = pi_perm(prob.n_y, prob.s)
+    Ly = prob.n_y * prob.s
+    return (p1[:, None] * Ly + p2[None, :]).ravel()
 
 
 def _F_full(prob):
     F1 = dft_matrix(prob.n)
-    return F1 if prob.dim == 1 else np.kron(F1, F1)
+    return F1 if prob.dim == 1 else np.kron(F1, dft_matrix(prob.n_y))
 
 
 def _P_full(prob):
-    F1 = dft_matrix(prob.n)
-    P1 = np.kron(np.eye(prob.s), F1.conj().T)
-    return P1 if prob.dim == 1 else np.kron(P1, P1)
+    P1 = np.kron(np.eye(prob.s), dft_matrix(prob.n).conj().T)
+    if prob.dim == 1:
+        return P1
+    return np.kron(P1, np.kron(np.eye(prob.s), dft_matrix(prob.n_y).conj().T))
 
 
 def _block_rows(prob):
@@ -68,14 +71,15 @@ def _block_rows(prob):
 
     In 1D the rows of P Pi A^c F already come in s blocks of N.  In 2D the
     Kronecker product interleaves them: block (rx, ry) = D^x_rx (x) D^y_ry
-    sits at rows (rx n + kx) s n + ry n + ky.  Listing, for each block, its
-    rows in (kx, ky) order groups them.
+    sits at rows (rx n_x + kx) s n_y + ry n_y + ky.  Listing, for each block,
+    its rows in (kx, ky) order groups them.
     """
     n, s = prob.n, prob.s
     if prob.dim == 1:
         return np.arange(s * n)
-    kx, ky = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
-    return np.concatenate([((rx * n + kx) * (s * n) + ry * n + ky).ravel()
+    ny = prob.n_y
+    kx, ky = np.meshgrid(np.arange(n), np.arange(ny), indexing="ij")
+    return np.concatenate([((rx * n + kx) * (s * ny) + ry * ny + ky).ravel()
                            for rx in range(s) for ry in range(s)])
 
 
@@ -108,7 +112,7 @@ def zstar(prob, idx, tauZ=1e-12, nb=0):
     N = prob.N
     B = block_diagonal_form(prob)
     Bp = bpinv(diagonals(B, N), tauZ)
-    L = (prob.n * prob.s) ** prob.dim
+    L = prob.N * prob.s ** prob.dim
     E = np.zeros((L, idx.size))
     E[idx, np.arange(idx.size)] = 1.0
     PE = _P_full(prob) @ E[_pi_full(prob)]
@@ -133,7 +137,7 @@ def symbol_weights(prob, tauZ=1e-12):
     if prob.dim == 1:
         D = sum(np.abs(np.fft.fft(col[r::s])) ** 2 for r in range(s))
     else:
-        g = col.reshape(s * n, s * n)
+        g = col.reshape(s * n, s * prob.n_y)
         D = sum(np.abs(np.fft.fft2(g[rx::s, ry::s])) ** 2
                 for rx in range(s) for ry in range(s)).ravel()
     return np.where(D > tauZ * D.max(), 1.0 / np.where(D > 0, D, 1.0), 0.0), D
@@ -152,9 +156,9 @@ def zstar_normal(prob, idx, tauZ=1e-12, nb=0):
     if prob.dim == 1:
         Z = np.real(np.fft.ifft(w[:, None] * np.fft.fft(G, axis=0), axis=0))
     else:
-        n = prob.n
-        G3 = G.reshape(n, n, -1)
-        Z = np.real(np.fft.ifft2(w.reshape(n, n)[:, :, None] *
+        n, ny = prob.n, prob.n_y
+        G3 = G.reshape(n, ny, -1)
+        Z = np.real(np.fft.ifft2(w.reshape(n, ny)[:, :, None] *
                                  np.fft.fft2(G3, axes=(0, 1)), axes=(0, 1)))
         Z = Z.reshape(N, -1)
     if nb:

@@ -21,10 +21,10 @@ from typing import Callable, Optional
 import numpy as np
 
 __all__ = [
-    "Domain", "interval", "disk", "star", "box", "shape_parameter_eh",
+    "Domain", "interval", "disk", "star", "ellipse", "box", "shape_parameter_eh",
     "Problem", "trig_sum_1d", "trig_sum_2d",
     "config_c1", "config_c1a", "config_c2", "config_c3", "config_c3a",
-    "config_c4", "family_1d", "served_stream", "test_points",
+    "config_c4", "config_ellipse", "family_1d", "served_stream", "test_points",
 ]
 
 
@@ -55,11 +55,12 @@ def interval(a: float, b: float) -> Domain:
                   lambda x: (x >= a) & (x <= b), bounds=(a, b), area=b - a)
 
 
-def box(T: float = 1.0, dim: int = 1) -> Domain:
+def box(T: float = 1.0, dim: int = 1, Ty: Optional[float] = None) -> Domain:
     """The whole periodic box (the periodic problems of sections 3.1 and 5.1)."""
     if dim == 2:
+        ty = T if Ty is None else Ty
         return Domain("box", 2, lambda x, y: np.ones(np.shape(x), dtype=bool),
-                      bounds=(-T, T), area=4 * T * T)
+                      bounds=(-T, T), area=4 * T * ty)
     return Domain("box", 1, lambda x: np.ones(np.shape(x), dtype=bool),
                   bounds=(-T, T), area=2 * T)
 
@@ -77,6 +78,19 @@ def disk(R: float) -> Domain:
                   radius=lambda t: np.full(np.shape(t), R, dtype=np.float64),
                   dradius=lambda t: np.zeros(np.shape(t), dtype=np.float64),
                   area=math.pi * R * R)
+
+
+def ellipse(a: float, b: float) -> Domain:
+    """Ellipse x^2/a^2 + y^2/b^2 <= 1 (the domain of section 5.4's
+    non-periodic experiment is a = 1, b = 1/2)."""
+    def radius(t):
+        return 1.0 / np.sqrt((np.cos(t) / a) ** 2 + (np.sin(t) / b) ** 2)
+
+    def dradius(t):
+        r = radius(t)
+        return -r ** 3 * np.sin(t) * np.cos(t) * (1.0 / (b * b) - 1.0 / (a * a))
+    return Domain(f"ellipse(a={a},b={b})", 2, lambda x, y: (x / a) ** 2 + (y / b) ** 2 <= 1.0,
+                  radius=radius, dradius=dradius, area=math.pi * a * b)
 
 
 def star(R: float, amp: float = 0.1, petals: int = 5) -> Domain:
@@ -151,9 +165,10 @@ APPROX, POISSON, HELMHOLTZ = 0, 1, 2
 class Problem:
     """One least-squares RBF problem on the box [-T, T)^dim.
 
-    n      centres per axis (N = n^dim unknowns)
+    n      centres per axis (N = n^dim unknowns); in 2D along x
     s      oversampling factor per axis (L = s*n grid points per axis)
-    T      half-width of the periodic box
+    T      half-width of the periodic box; in 2D along x
+    ny, Ty 2D only: centres and half-width along y (None: n and T)
     eh     shape parameter times centre spacing, eps*h (eps = eh / h)
     op     APPROX: rows phi_j(x_i).  POISSON/HELMHOLTZ: interior rows of
            -(Laplacian + k2) phi_j, boundary rows phi_j at boundary points.
@@ -178,9 +193,12 @@ class Problem:
     k: int = 0                        # sketch width (0: solver's estimate)
     p: int = 10                       # sketch oversampling
     seed: int = 42                    # sketch seed
+    ny: Optional[int] = None          # 2D: centres along y (None: n)
+    Ty: Optional[float] = None        # 2D: half-width along y (None: T)
 
     @property
     def h(self) -> float:
+        """Centre spacing along x (the shape parameter is eh / h)."""
         return 2 * self.T / self.n
 
     @property
@@ -188,8 +206,20 @@ class Problem:
         return self.eh / self.h
 
     @property
+    def n_y(self) -> int:
+        return self.n if self.ny is None else self.ny
+
+    @property
+    def T_y(self) -> float:
+        return self.T if self.Ty is None else self.Ty
+
+    def axes(self):
+        """[(n, T) per axis]."""
+        return [(self.n, self.T)] if self.dim == 1 else [(self.n, self.T), (self.n_y, self.T_y)]
+
+    @property
     def N(self) -> int:
-        return self.n ** self.dim
+        return self.n if self.dim == 1 else self.n * self.n_y
 
     def bpoints(self) -> np.ndarray:
         if self.nb == 0:
@@ -238,6 +268,21 @@ def config_c3a(n: int = 128) -> Problem:
     return config_c3(n, 0.5)
 
 
+def _f_e6(nx, ny):
+    def f(x, y):
+        return np.sin(nx / 10.0 * x + ny / 10.0 * y)
+    return f
+
+
+def config_ellipse(nx: int = 128, ny: int = 64, eh: Optional[float] = None) -> Problem:
+    """Section 5.4's non-periodic experiment on an anisotropic box: the
+    ellipse x^2 + 4 y^2 <= 1 in [-1.4, 1.4] x [-0.7, 0.7] (equal spacing on
+    both axes when ny = nx / 2), s = 2, f = sin(nx x / 10 + ny y / 10), shape
+    parameter from tau0 = 1e-5 unless eh is given."""
+    return Problem(f"ellipse{nx}x{ny}", 2, nx, 2, 1.4, shape_parameter_eh(1e-5) if eh is None else eh,
+                   ellipse(1.0, 0.5), [_f_e6(nx, ny)], ny=ny, Ty=0.7, p=10)
+
+
 def _u_c4(x, y):
     return np.sin(2 * x) * np.cos(3 * y)
 
@@ -264,14 +309,16 @@ def config_c4(n: int = 256, eh: float = 0.5, R: float = 0.7) -> Problem:
 
 def test_points(prob: Problem, m1d: int = 4096, m2d: int = 1024) -> np.ndarray:
     """Fine test set: 1D linspace over the interval, 2D a cell-centred
-    m2d x m2d lattice on [-1, 1]^2 intersected with the domain."""
+    m2d x m2d lattice on the box [-T, T] x [-T_y, T_y] intersected with the
+    domain."""
     if prob.dim == 1:
         lo, hi = prob.domain.bounds
         if prob.domain.name == "box":
             return np.linspace(lo, hi, m1d, endpoint=False)[:, None]
         return np.linspace(lo, hi, m1d)[:, None]
     t = -prob.T + (np.arange(m2d) + 0.5) * (2.0 * prob.T / m2d)
-    X, Y = np.meshgrid(t, t, indexing="ij")
+    u = -prob.T_y + (np.arange(m2d) + 0.5) * (2.0 * prob.T_y / m2d)
+    X, Y = np.meshgrid(t, u, indexing="ij")
     keep = prob.domain.contains(X, Y)
     return np.stack([X[keep], Y[keep]], axis=1)
 
