@@ -23,11 +23,11 @@
  *   - Matrices of vectors are column-major FP64 with a leading dimension:
  *     element (i, v) of X is X[i + ld * v].  Such pointers are DEVICE
  *     pointers owned by the caller and must not alias one another.
- *   - Coefficient vectors have N entries; in 2D entry jx * n + jy belongs to
- *     the centre (jx, jy) (x slow, y fast; section 5.1).
+ *   - Coefficient vectors have N entries; in 2D entry jx * ny + jy belongs
+ *     to the centre (jx, jy) (x slow, y fast; section 5.1).
  *   - Row vectors have M + Mb entries: the M collocation points in ascending
- *     fine-grid order (index ix * L + iy in 2D), then the Mb boundary points
- *     in the order given.
+ *     fine-grid order (index ix * Ly + iy in 2D, Ly = s ny), then the Mb
+ *     boundary points in the order given.
  *   - Work is queued on the given HIP stream (hipStream_t passed as void*;
  *     NULL is the default stream) and returns without synchronising, except
  *     where stated.  A plan owns its device memory.  A plan may be used from
@@ -63,7 +63,10 @@ enum {
 typedef struct azrbf_plan_s* azrbf_plan_t;
 
 /* Problem description (section 2.2 / 5.1 / 6).  All pointers are HOST
- * pointers, read during azrbf_plan only. */
+ * pointers, read during azrbf_plan only.  In 2D the box may be anisotropic
+ * (section 5.1: its own centre count and half-width per axis, fields ny, Ty);
+ * the Gaussian is radial, so eps is one value (with eps <= 0 it follows
+ * eq. constant_shapeparam on the x axis). */
 typedef struct {
   int32_t dim;            /* 1 or 2                                          */
   int32_t n;              /* centres per axis: a power of two, 16 <= n,      */
@@ -76,8 +79,8 @@ typedef struct {
   double tau0;            /* used only when eps <= 0                         */
   int32_t op;             /* AZRBF_OP_*                                      */
   double k2;              /* k^2 of -(Lap + k2) for AZRBF_OP_BVP             */
-  const uint8_t* mask;    /* L^dim bytes, nonzero marks a collocation point; */
-                          /* 2D index ix * L + iy                            */
+  const uint8_t* mask;    /* L (1D) or Lx * Ly bytes (L = s n), nonzero     */
+                          /* marks a collocation point; 2D index ix * Ly + iy */
   int64_t nb;             /* number of boundary points (BVP only)            */
   const double* bpts;     /* nb x dim coordinates, point i at bpts[i*dim+a]  */
   double bweight;         /* weight of the boundary rows                     */
@@ -87,6 +90,9 @@ typedef struct {
   int32_t k;              /* sketch width; 0 = estimate from n               */
   int32_t refine;         /* extra AZ passes on the residual (0, 1, ...)     */
   uint64_t seed;          /* seed of the Gaussian sketch                     */
+  int32_t ny;             /* 2D: centres along y (a power of two, 16..512);  */
+                          /* 0 = n.  n and T above are then the x axis       */
+  double Ty;              /* 2D: half-width of the box along y; 0 = T        */
 } azrbf_problem;
 
 /* Read-only facts about a plan. */

@@ -36,7 +36,7 @@ class _Problem(ctypes.Structure):
         ("mask", ctypes.POINTER(ctypes.c_uint8)), ("nb", ctypes.c_int64),
         ("bpts", ctypes.POINTER(ctypes.c_double)), ("bweight", ctypes.c_double),
         ("tau", ctypes.c_double), ("tauZ", ctypes.c_double), ("k", ctypes.c_int32),
-        ("refine", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("refine", ctypes.c_int32), ("seed", ctypes.c_uint64), ("ny", ctypes.c_int32), ("Ty", ctypes.c_double),
     ]
 
 
@@ -129,23 +129,26 @@ def fine_grid(n, s, T):
     return -T + np.arange(L, dtype=np.float64) * (2.0 * T / L)
 
 
-def make_mask(dim, n, s, T, contains):
-    """Collocation mask on the fine grid: 1 where ``contains`` holds (2D: ix*L + iy)."""
+def make_mask(dim, n, s, T, contains, ny=None, Ty=None):
+    """Collocation mask on the fine grid: 1 where ``contains`` holds (2D:
+    ix*Ly + iy; the y axis has ny centres on [-Ty, Ty), default n and T)."""
     xt = fine_grid(n, s, T)
     if dim == 1:
         return np.ascontiguousarray(contains(xt), dtype=np.uint8)
-    X, Y = np.meshgrid(xt, xt, indexing="ij")
+    yt = fine_grid(ny or n, s, Ty or T)
+    X, Y = np.meshgrid(xt, yt, indexing="ij")
     return np.ascontiguousarray(contains(X, Y), dtype=np.uint8).ravel()
 
 
-def collocation_points(dim, n, s, T, mask):
+def collocation_points(dim, n, s, T, mask, ny=None, Ty=None):
     """Coordinates of the collocation rows, (M, dim), in row order."""
     xt = fine_grid(n, s, T)
     idx = np.nonzero(np.asarray(mask).ravel())[0]
     if dim == 1:
         return xt[idx][:, None]
-    L = xt.size
-    return np.stack([xt[idx // L], xt[idx % L]], axis=1)
+    yt = fine_grid(ny or n, s, Ty or T)
+    Ly = yt.size
+    return np.stack([xt[idx // Ly], yt[idx % Ly]], axis=1)
 
 
 # ------------------------------------------------------------------ plan
@@ -154,9 +157,11 @@ class Plan:
     """An azrbf plan (owns device memory until ``destroy`` or garbage collection)."""
 
     def __init__(self, dim, n, s, T, mask, eps=0.0, tau0=0.0, op=OP_APPROX, k2=0.0, bpts=None,
-                 bweight=1.0, tau=1e-12, tauZ=1e-12, k=0, refine=1, seed=42, stream=None):
+                 bweight=1.0, tau=1e-12, tauZ=1e-12, k=0, refine=1, seed=42, stream=None, ny=0, Ty=0.0):
+        """ny, Ty: the y axis of a 2D box (0: the same as n, T)."""
         lib = _lib()
         self.dim, self.n, self.s, self.T = dim, n, s, T
+        self.ny, self.Ty = int(ny or 0), float(Ty or 0.0)
         self._mask = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
         bp = np.zeros((0, dim)) if bpts is None else np.ascontiguousarray(bpts, dtype=np.float64)
         self._bpts = np.ascontiguousarray(bp.reshape(-1, dim))
@@ -168,6 +173,7 @@ class Plan:
         pr.bpts = self._bpts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if pr.nb else None
         pr.bweight, pr.tau, pr.tauZ = float(bweight), float(tau), float(tauZ)
         pr.k, pr.refine, pr.seed = int(k), int(refine), int(seed)
+        pr.ny, pr.Ty = self.ny, self.Ty
         self._prob = pr
         h = ctypes.c_void_p()
         _check(lib.azrbf_plan(ctypes.byref(pr), _stream(stream), ctypes.byref(h)), "azrbf_plan")
@@ -202,7 +208,7 @@ class Plan:
         return self._h
 
     def points(self):
-        return collocation_points(self.dim, self.n, self.s, self.T, self._mask)
+        return collocation_points(self.dim, self.n, self.s, self.T, self._mask, self.ny, self.Ty)
 
 
 def plan(*args, **kw):

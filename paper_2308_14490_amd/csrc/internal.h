@@ -44,10 +44,12 @@ struct Geo {
   // 1D spectra, [phase][N], frequency layout as above, 1/N folded in:
   const double2* spA;        // d_r / N
   const double2* spZ;        // w * conj(d_r) / N
-  // 2D: per-axis factors fac[deriv 0|1][phase][n] (unnormalised DFTs of the
-  // kernel and of its second derivative on the shifted 1D grids), and the
-  // regularised weights w2 = 1/(N D) on the n x n frequency grid.
+  // 2D: per-axis factors fac[deriv 0|1][phase][N1] (x) and facy[deriv
+  // 0|1][phase][N2] (y) (unnormalised DFTs of the kernel and of its second
+  // derivative on the shifted 1D grids of each axis), and the regularised
+  // weights w2 = 1/(N D) on the N1 x N2 frequency grid.
   const double2* fac;
+  const double2* facy;
   const double* w2;
   int op;                    // AZRBF_OP_*
   double k2, opscale;        // BVP: spectrum = opscale*(d2 d0 + d0 d2 + k2 d0 d0)
@@ -196,9 +198,12 @@ int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, 
 struct Plan {
   azrbf_problem prob{};
   int device = 0;
-  int dim = 1, n = 0, s = 1, ph = 1;     // ph = s^dim phases
+  int dim = 1, n = 0, s = 1, ph = 1;     // ph = s^dim phases; n, T, h, hL: x axis
+  int ny = 0;                             // 2D: centres along y
   double T = 1, eps = 0, h = 0, hL = 0;
+  double Ty = 1, hy = 0, hLy = 0;         // 2D: y axis
   int64_t N = 0, Lax = 0, Lg = 0, M = 0, Mb = 0, Mt = 0;
+  int64_t Lay = 0;                        // 2D: fine-grid points along y
   int64_t Mtp = 0;   // Mt rounded up to 16: leading dimension of internal row-space matrices
   int64_t ldq = 0;   // leading dimension of the factor's Q
   bool fused = false;                     // 1D single-kernel path
@@ -217,6 +222,7 @@ struct Plan {
   double2* spA = nullptr;
   double2* spZ = nullptr;
   double2* fac = nullptr;
+  double2* facy = nullptr;                // 2D: y-axis factors (fac itself on a square box)
   double* w2 = nullptr;
   double* bpts = nullptr;                 // Mb x dim, device
   double bweight = 1;

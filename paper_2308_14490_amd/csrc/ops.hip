@@ -93,11 +93,10 @@ __device__ __forceinline__ int64_t row_of(const Geo& g, int64_t gi) {
 // Unnormalised 2D spectrum of phase ph at frequency (ka, kb).
 __device__ __forceinline__ double2 spec2d(const Geo& g, int ph, int ka, int kb) {
   const int rx = ph / g.s, ry = ph - rx * g.s;
-  const int n = g.N2;
-  const double2 x0 = g.fac[rx * n + ka], y0 = g.fac[ry * n + kb];
+  const int n1 = g.N1, n2 = g.N2;
+  const double2 x0 = g.fac[rx * n1 + ka], y0 = g.facy[ry * n2 + kb];
   if (g.op == AZRBF_OP_APPROX) return cmul(x0, y0);
-  const double2* f2 = g.fac + (int64_t)g.s * n;
-  const double2 x2 = f2[rx * n + ka], y2 = f2[ry * n + kb];
+  const double2 x2 = g.fac[(g.s + rx) * n1 + ka], y2 = g.facy[(g.s + ry) * n2 + kb];
   const double2 d00 = cmul(x0, y0);
   double2 d = cadd(cadd(cmul(x2, y0), cmul(x0, y2)), cscale(d00, g.k2));
   return cscale(d, g.opscale);
@@ -648,45 +647,45 @@ __device__ __forceinline__ double phi_per_dev(double d, double eps, double T, in
   return s;
 }
 
-__global__ void k_boundary_A(int dim, int n, double T, double h, double eps, int mimg, int W,
-                             const double* __restrict__ bp, int64_t Mb, double bw, const double* __restrict__ X,
-                             int64_t ldx, int64_t nvec, double alpha, double beta, const double* Yin,
-                             int64_t ldyi, double* Y, int64_t ldy, int64_t M) {
+// One axis of a boundary point's window: the nw centres from j0 on (taken
+// modulo n) and the periodized kernel at their distances.
+struct AxisWin {
+  int n, mimg, W;
+  double T, h;
+};
+
+__device__ __forceinline__ int axis_window(const AxisWin& a, double x, double eps, double* w) {
+  const int nw = 2 * a.W + 2 < a.n ? 2 * a.W + 2 : a.n;
+  const int j0 = (int)floor((x + a.T) / a.h) - a.W;
+  for (int o = 0; o < nw; ++o) {
+    const int j = ((j0 + o) % a.n + a.n) % a.n;
+    double d = x - (-a.T + j * a.h);
+    d -= 2.0 * a.T * nearbyint(d / (2.0 * a.T));
+    w[o] = phi_per_dev(d, eps, a.T, a.mimg);
+  }
+  return j0;
+}
+
+__global__ void k_boundary_A(int dim, AxisWin ax, AxisWin ay, double eps, const double* __restrict__ bp, int64_t Mb,
+                             double bw, const double* __restrict__ X, int64_t ldx, int64_t nvec, double alpha,
+                             double beta, const double* Yin, int64_t ldyi, double* Y, int64_t ldy, int64_t M) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t v = blockIdx.y;
   if (i >= Mb || v >= nvec) return;
-  const int nw = 2 * W + 2 < n ? 2 * W + 2 : n;
+  const int nwx = 2 * ax.W + 2 < ax.n ? 2 * ax.W + 2 : ax.n;
+  const int nwy = 2 * ay.W + 2 < ay.n ? 2 * ay.W + 2 : ay.n;
   double wx[64], wy[64];
-  int jx0, jy0 = 0;
-  {
-    const double x = bp[i * dim];
-    jx0 = (int)floor((x + T) / h) - W;
-    for (int o = 0; o < nw; ++o) {
-      const int j = ((jx0 + o) % n + n) % n;
-      double d = x - (-T + j * h);
-      d -= 2.0 * T * nearbyint(d / (2.0 * T));
-      wx[o] = phi_per_dev(d, eps, T, mimg);
-    }
-  }
-  if (dim == 2) {
-    const double y = bp[i * dim + 1];
-    jy0 = (int)floor((y + T) / h) - W;
-    for (int o = 0; o < nw; ++o) {
-      const int j = ((jy0 + o) % n + n) % n;
-      double d = y - (-T + j * h);
-      d -= 2.0 * T * nearbyint(d / (2.0 * T));
-      wy[o] = phi_per_dev(d, eps, T, mimg);
-    }
-  }
+  const int jx0 = axis_window(ax, bp[i * dim], eps, wx);
+  const int jy0 = dim == 2 ? axis_window(ay, bp[i * dim + 1], eps, wy) : 0;
   const double* x = X + ldx * v;
   double acc = 0.0;
   if (dim == 1) {
-    for (int o = 0; o < nw; ++o) acc = fma(wx[o], x[((jx0 + o) % n + n) % n], acc);
+    for (int o = 0; o < nwx; ++o) acc = fma(wx[o], x[((jx0 + o) % ax.n + ax.n) % ax.n], acc);
   } else {
-    for (int ox = 0; ox < nw; ++ox) {
-      const int jx = ((jx0 + ox) % n + n) % n;
+    for (int ox = 0; ox < nwx; ++ox) {
+      const int jx = ((jx0 + ox) % ax.n + ax.n) % ax.n;
       double r = 0.0;
-      for (int oy = 0; oy < nw; ++oy) r = fma(wy[oy], x[(int64_t)jx * n + ((jy0 + oy) % n + n) % n], r);
+      for (int oy = 0; oy < nwy; ++oy) r = fma(wy[oy], x[(int64_t)jx * ay.n + ((jy0 + oy) % ay.n + ay.n) % ay.n], r);
       acc = fma(wx[ox], r, acc);
     }
   }
@@ -1194,14 +1193,22 @@ static int64_t engine_chunk(const Plan& P, int64_t npairs) {
 static int boundary_rows(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta,
                          const double* Yin, int64_t ldyi, double* Y, int64_t ldy, hipStream_t st) {
   if (P.Mb == 0) return AZRBF_OK;
-  const int mimg = (int)ceil(6.8 / (2.0 * P.eps * P.T)) + 2;
-  const int W = (int)ceil(6.8 / (P.eps * P.h)) + 1;
-  const int nw = 2 * W + 2 < P.n ? 2 * W + 2 : P.n;   // window length, must fit k_boundary_A's arrays
-  if (nw > 64) return AZRBF_EUNSUPPORTED;
+  auto axis = [&](int n, double T, double h) {
+    AxisWin a;
+    a.n = n;
+    a.T = T;
+    a.h = h;
+    a.mimg = (int)ceil(6.8 / (2.0 * P.eps * T)) + 2;
+    a.W = (int)ceil(6.8 / (P.eps * h)) + 1;
+    return a;
+  };
+  const AxisWin ax = axis(P.n, P.T, P.h), ay = P.dim == 2 ? axis(P.ny, P.Ty, P.hy) : ax;
+  // window lengths must fit k_boundary_A's arrays
+  if (std::min(2 * ax.W + 2, ax.n) > 64 || std::min(2 * ay.W + 2, ay.n) > 64) return AZRBF_EUNSUPPORTED;
   const dim3 grid((unsigned)((P.Mb + 127) / 128), (unsigned)nvec);
   Prof pr("boundary_A", 8.0 * (double)P.Mb * nvec * (beta != 0.0 ? 2.0 : 1.0), st);
-  launch_kernel(k_boundary_A, grid, 128, 0, st, P.dim, P.n, P.T, P.h, P.eps, mimg, W, P.bpts, P.Mb, P.bweight, X, ldx,
-                nvec, alpha, beta, Yin, ldyi, Y, ldy, P.M);
+  launch_kernel(k_boundary_A, grid, 128, 0, st, P.dim, ax, ay, P.eps, P.bpts, P.Mb, P.bweight, X, ldx, nvec, alpha,
+                beta, Yin, ldyi, Y, ldy, P.M);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
@@ -1311,8 +1318,26 @@ int ops_spectra(Plan& P, hipStream_t st) {
     P.geo.spA = P.spA;
     P.geo.spZ = P.spZ;
   } else {
+    // the y axis has its own samples and factors unless the box is square
+    double2* facy = fac;
+    if (P.ny != P.n || P.Ty != P.T) {
+      const int ny = P.ny;
+      const int mimgy = (int)ceil(6.8 / (2.0 * P.eps * P.Ty)) + 2;
+      const int64_t nsy = (int64_t)ny * s;
+      double2* sampy = nullptr;
+      AZ_TRY(P.alloc((void**)&sampy, nk * nsy * (int64_t)sizeof(double2)));
+      AZ_TRY(P.alloc((void**)&facy, nk * nsy * (int64_t)sizeof(double2)));
+      for (int which = 0; which < nk; ++which) {
+        launch_kernel(k_sample_phases, (unsigned)((nsy + 255) / 256), 256, 0, st, sampy + which * nsy, ny, s, P.hLy,
+                      P.eps, P.Ty, mimgy, which, nullptr);
+        AZ_HIP(hipGetLastError());
+      }
+      AZ_TRY(fft_lines_fwd(P, sampy, facy, ny, (int64_t)nk * s, false, st));
+    }
     P.fac = fac;
+    P.facy = facy;
     P.geo.fac = fac;
+    P.geo.facy = facy;
     AZ_TRY(P.alloc((void**)&P.w2, P.N * sizeof(double)));
     const unsigned nb = (unsigned)((P.N + 255) / 256);
     launch_kernel(k_D_2d, nb, 256, 0, st, P.geo, D, red);

@@ -298,16 +298,16 @@ static int k_cap(int64_t N, int64_t Mt) {
 // (at k = 1.1 r the residual was 2-3x larger on the disk and the Helmholtz
 // disk).  A sketch that still turns out too narrow is widened by the
 // factorisation.
-static int default_k(const azrbf_problem& q, int64_t Lax, int64_t N, int64_t Mt) {
+static int default_k(const azrbf_problem& q, int64_t Lax, int64_t Lay, int64_t N, int64_t Mt) {
   if (q.k > 0) return q.k;
   if (q.dim == 1) return 32;
   int64_t perim = 0;
   for (int64_t ix = 0; ix < Lax; ++ix)
-    for (int64_t iy = 0; iy < Lax; ++iy) {
-      if (!q.mask[ix * Lax + iy]) continue;
-      const bool edge = ix == 0 || iy == 0 || ix == Lax - 1 || iy == Lax - 1 ||
-                        !q.mask[(ix - 1) * Lax + iy] || !q.mask[(ix + 1) * Lax + iy] ||
-                        !q.mask[ix * Lax + iy - 1] || !q.mask[ix * Lax + iy + 1];
+    for (int64_t iy = 0; iy < Lay; ++iy) {
+      if (!q.mask[ix * Lay + iy]) continue;
+      const bool edge = ix == 0 || iy == 0 || ix == Lax - 1 || iy == Lay - 1 ||
+                        !q.mask[(ix - 1) * Lay + iy] || !q.mask[(ix + 1) * Lay + iy] ||
+                        !q.mask[ix * Lay + iy - 1] || !q.mask[ix * Lay + iy + 1];
       perim += edge;
     }
   const double r = 6.6 * 2.0 / q.s * (double)perim;
@@ -429,6 +429,8 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
   if (q.eps <= 0 && !(q.tau0 > 0 && q.tau0 < 1)) return AZRBF_EINVAL;
   if (!az::pow2(q.n) || q.n < 16) return AZRBF_EUNSUPPORTED;
   if ((q.dim == 1 && q.n > (1 << 20)) || (q.dim == 2 && q.n > 512)) return AZRBF_EUNSUPPORTED;
+  if (q.ny < 0 || q.Ty < 0 || (q.dim == 1 && (q.ny > 0 || q.Ty > 0))) return AZRBF_EINVAL;
+  if (q.dim == 2 && q.ny > 0 && (!az::pow2(q.ny) || q.ny < 16 || q.ny > 512)) return AZRBF_EUNSUPPORTED;
   // a column pass puts the s phases of a column in one block of at most 256
   // threads, n1 / 16 per phase (1D: n1 = n / 512 once n > 2^18)
   if (q.dim == 1 && q.n > (1 << 18) && q.s * (q.n >> 9) / 16 > 256) return AZRBF_EUNSUPPORTED;
@@ -450,6 +452,10 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
   P.T = q.T;
   P.h = 2.0 * q.T / q.n;
   P.hL = P.h / q.s;
+  P.ny = q.dim == 2 ? (q.ny > 0 ? q.ny : q.n) : 1;
+  P.Ty = q.dim == 2 && q.Ty > 0 ? q.Ty : q.T;
+  P.hy = 2.0 * P.Ty / P.ny;
+  P.hLy = P.hy / q.s;
   if (q.eps > 0) {
     P.eps = q.eps;
   } else {   // eq. constant_shapeparam: eps = c N, c = pi / (2 T sqrt(2 log(1 + tau0^-2)))
@@ -460,9 +466,10 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
   P.tauZ = q.tauZ;
   P.refine = q.refine;
   P.bweight = q.bweight;
-  P.N = q.dim == 1 ? (int64_t)q.n : (int64_t)q.n * q.n;
+  P.N = q.dim == 1 ? (int64_t)q.n : (int64_t)q.n * P.ny;
   P.Lax = (int64_t)q.s * q.n;
-  P.Lg = q.dim == 1 ? P.Lax : P.Lax * P.Lax;
+  P.Lay = q.dim == 1 ? 1 : (int64_t)q.s * P.ny;
+  P.Lg = q.dim == 1 ? P.Lax : P.Lax * P.Lay;
   P.Mb = q.nb;
 
   int rc = az::ops_init_twiddles(P.device, &P.tw);
@@ -471,7 +478,7 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
   az::Geo& g = P.geo;
   g.dim = P.dim;
   g.s = P.s;
-  g.L = (int)P.Lax;
+  g.L = (int)(q.dim == 1 ? P.Lax : P.Lay);   // 2D: fine-grid points per x line
   g.N = P.N;
   g.op = q.op;
   g.k2 = q.k2;
@@ -501,7 +508,8 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
       if (g.N1 < 16 || g.N2 < 16 || g.N1 > 2048 || g.N2 > 512) { delete h; return AZRBF_EUNSUPPORTED; }
     }
   } else {
-    g.N1 = g.N2 = P.n;
+    g.N1 = P.n;
+    g.N2 = P.ny;
     std::vector<int32_t> inv(P.Lg);
     int64_t m = 0;
     for (int64_t i = 0; i < P.Lg; ++i) inv[i] = q.mask[i] ? (int32_t)m++ : -1;
@@ -519,7 +527,7 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
     if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = AZRBF_EHIP;
     if (rc) { P.release(); delete h; return rc; }
   }
-  P.k = az::default_k(q, P.Lax, P.N, P.Mt);
+  P.k = az::default_k(q, P.Lax, P.Lay, P.N, P.Mt);
   az::tune_apply(P);
   rc = az::ops_spectra(P, st);
   // no synchronisation: work on this stream is ordered after the set-up, work
@@ -766,9 +774,10 @@ int azrbf_solve_many(int32_t nprob, const azrbf_plan_t* plans, const double* con
 int64_t azrbf_footprint_bytes(const azrbf_problem* pr, int64_t max_rhs) {
   if (!pr || pr->n <= 0 || pr->s <= 0 || (pr->dim != 1 && pr->dim != 2) || max_rhs < 0) return -1;
   const int64_t n = pr->n, s = pr->s;
-  const int64_t N = pr->dim == 1 ? n : n * n;
-  const int64_t Lax = s * n;
-  const int64_t Lg = pr->dim == 1 ? Lax : Lax * Lax;
+  const int64_t ny = pr->dim == 2 && pr->ny > 0 ? pr->ny : n;
+  const int64_t N = pr->dim == 1 ? n : n * ny;
+  const int64_t Lax = s * n, Lay = pr->dim == 1 ? 1 : s * ny;
+  const int64_t Lg = Lax * Lay;
   const int64_t ph = pr->dim == 1 ? s : s * s;
   int64_t M = 0;
   if (pr->mask)
@@ -776,7 +785,7 @@ int64_t azrbf_footprint_bytes(const azrbf_problem* pr, int64_t max_rhs) {
   else
     M = Lg;
   const int64_t Mt = M + pr->nb;
-  int k = pr->k > 0 ? pr->k : (pr->dim == 1 || !pr->mask ? 32 : az::default_k(*pr, Lax, N, Mt));
+  int k = pr->k > 0 ? pr->k : (pr->dim == 1 || !pr->mask ? 32 : az::default_k(*pr, Lax, Lay, N, Mt));
   int64_t b = 0;
   b += 2 * ph * N * 16;                                 // spectra (1D) or factors + weights (2D)
   b += pr->dim == 2 ? Lg * 4 : 0;                       // inverse map

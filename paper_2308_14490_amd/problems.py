@@ -21,12 +21,13 @@ def default_refine(prob):
 
 def plan_for(prob, refine=None, tau=1e-12, tauZ=1e-12, k=None, stream=None):
     refine = default_refine(prob) if refine is None else refine
-    mask = azrbf.make_mask(prob.dim, prob.n, prob.s, prob.T, prob.domain.contains)
+    mask = azrbf.make_mask(prob.dim, prob.n, prob.s, prob.T, prob.domain.contains, prob.ny, prob.Ty)
     bpts = prob.bpoints() if prob.nb else None
     return azrbf.Plan(prob.dim, prob.n, prob.s, prob.T, mask, eps=prob.eps,
                       op=azrbf.OP_APPROX if prob.op == 0 else azrbf.OP_BVP, k2=prob.k2,
                       bpts=bpts, bweight=prob.bweight, tau=tau, tauZ=tauZ,
-                      k=prob.k if k is None else k, refine=refine, seed=prob.seed, stream=stream)
+                      k=prob.k if k is None else k, refine=refine, seed=prob.seed, stream=stream,
+                      ny=prob.ny or 0, Ty=prob.Ty or 0.0)
 
 
 def footprint_for(prob, max_rhs, mask=None, refine=None, tau=1e-12, tauZ=1e-12):
@@ -34,7 +35,7 @@ def footprint_for(prob, max_rhs, mask=None, refine=None, tau=1e-12, tauZ=1e-12):
     per solve (azrbf_footprint_bytes)."""
     import ctypes
     if mask is None:
-        mask = azrbf.make_mask(prob.dim, prob.n, prob.s, prob.T, prob.domain.contains)
+        mask = azrbf.make_mask(prob.dim, prob.n, prob.s, prob.T, prob.domain.contains, prob.ny, prob.Ty)
     m = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
     bp = np.ascontiguousarray(prob.bpoints(), dtype=np.float64).reshape(-1) if prob.nb else None
     pr = azrbf._Problem()
@@ -46,6 +47,7 @@ def footprint_for(prob, max_rhs, mask=None, refine=None, tau=1e-12, tauZ=1e-12):
     pr.bweight, pr.tau, pr.tauZ = float(prob.bweight), float(tau), float(tauZ)
     refine = default_refine(prob) if refine is None else refine
     pr.k, pr.refine, pr.seed = int(prob.k), int(refine), int(prob.seed)
+    pr.ny, pr.Ty = int(prob.ny or 0), float(prob.Ty or 0.0)
     return azrbf.footprint_bytes(pr, max_rhs)
 
 

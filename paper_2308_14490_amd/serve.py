@@ -63,7 +63,8 @@ def operator_key(prob, mask, k=0, tau=1e-12, tauZ=1e-12, refine=1):
     sketch seed (any Gaussian sketch of the same width serves)."""
     h = hashlib.sha1()
     h.update(repr((prob.dim, prob.n, prob.s, float(prob.T), float(prob.eps), int(prob.op), float(prob.k2),
-                   float(prob.bweight), int(prob.k or k), tau, tauZ, refine)).encode())
+                   float(prob.bweight), int(prob.k or k), tau, tauZ, refine,
+                   getattr(prob, "ny", None), getattr(prob, "Ty", None))).encode())
     h.update(np.ascontiguousarray(mask, dtype=np.uint8).tobytes())
     if prob.nb:
         h.update(np.ascontiguousarray(prob.bpoints(), dtype=np.float64).tobytes())
@@ -116,7 +117,8 @@ class GpuBackend:
     def mask(self, prob):
         mk = id(prob)
         if mk not in self._masks:
-            self._masks[mk] = self.azrbf.make_mask(prob.dim, prob.n, prob.s, prob.T, prob.domain.contains)
+            self._masks[mk] = self.azrbf.make_mask(prob.dim, prob.n, prob.s, prob.T, prob.domain.contains,
+                                                   prob.ny, prob.Ty)
         return self._masks[mk]
 
     def _refine(self, prob):

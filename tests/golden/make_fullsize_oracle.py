@@ -9,7 +9,9 @@ from the repository root:
     python tests/golden/make_fullsize_oracle.py [case ...]
 
 Cases: c3a128 (disk R = 0.8, n = 128, eps*h = 0.5), c3_128 (the same at
-eps*h = 1), c4_96 and c4_128 (Poisson star, weak Dirichlet rows).  Each case
+eps*h = 1), c4_96 and c4_128 (Poisson star, weak Dirichlet rows),
+ellipse128x64 (the ellipse x^2 + 4 y^2 <= 1 on the anisotropic box
+[-1.4, 1.4] x [-0.7, 0.7], 128 x 64 centres).  Each case
 is written as soon as it finishes, so a long run can be resumed by naming the
 remaining cases.  The test-set error uses the 200 x 200 cell-centred lattice
 restricted to the domain, as the full-size GPU tests do.
@@ -33,6 +35,7 @@ OUT = os.path.join(HERE, "fullsize_oracle.json")
 M2D = 200
 
 CASES = {
+    "ellipse128x64": lambda: W.config_ellipse(128, 64),
     "c3a128": lambda: W.config_c3a(128),
     "c3_128": lambda: W.config_c3(128),
     "c4_96": lambda: W.config_c4(96),
@@ -54,7 +57,7 @@ def run(name):
     f = np.stack([g(*tp.T) for g in (prob.exact or prob.rhs)], axis=1)
     err = np.max(np.abs(evaluate.eval_dense(prob, X, tp) - f), axis=0)
     return {
-        "config": prob.name, "n": prob.n, "N": prob.N, "M": int(idx.size), "Mb": int(bpts.shape[0]),
+        "config": prob.name, "n": prob.n, "ny": prob.n_y, "N": prob.N, "M": int(idx.size), "Mb": int(bpts.shape[0]),
         "eh": prob.eh, "s": prob.s, "domain": prob.domain.name, "tau": 1e-12,
         "rank": int(rank), "relres": [float(v) for v in np.atleast_1d(rel)],
         "maxerr": [float(v) for v in err], "test_lattice": M2D,

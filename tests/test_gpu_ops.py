@@ -184,3 +184,22 @@ def test_autotune_keeps_results_bitwise():
     assert torch.equal(Y0, Y1) and torch.equal(Z0, Z1)
     assert rep["key"] in azrbf.tune_table()
     p.destroy()
+
+
+@pytest.mark.parametrize("nx,ny,nvec", [(32, 16, 3), (16, 32, 2), (64, 32, 2)])
+def test_apply_2d_anisotropic_ellipse(nx, ny, nvec):
+    """Section 5.1's anisotropic box: the ellipse x^2 + 4 y^2 <= 1 in
+    [-1.4, 1.4] x [-0.7, 0.7] with nx x ny centres (equal spacing when
+    ny = nx / 2, else different spacing per axis)."""
+    _case(W.config_ellipse(nx, ny), nvec, ld_pad=1, engine=False)
+
+
+def test_apply_2d_anisotropic_poisson():
+    """-Lap on the same ellipse with weak Dirichlet rows at 120 points."""
+    base = W.config_ellipse(32, 16)
+
+    def u(x, y):
+        return np.sin(2 * x) * np.cos(3 * y)
+    prob = W.Problem("ellipse-poisson", 2, 32, 2, 1.4, base.eh, base.domain, [lambda x, y: 13 * u(x, y)],
+                     op=W.POISSON, bnd=[u], nb=120, exact=[u], ny=16, Ty=0.7)
+    _case(prob, 2, ld_pad=0, engine=False)

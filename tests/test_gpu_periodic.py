@@ -122,3 +122,28 @@ def test_periodic_2d_solve_matches_oracle_and_paper():
     assert np.all(rg <= 10 * ro + 1e-15)
     assert eg <= 10 * eo + 1e-15 and eg < 1e-11
     p.destroy()
+
+
+def test_zstar_inverts_the_periodic_matrix_anisotropic():
+    """Z* A^c = I on the kept modes of the anisotropic box [-1.4, 1.4] x
+    [-0.7, 0.7] with 256 x 128 centres."""
+    azrbf, problems = _mods()
+    nx, ny = 256, 128
+    prob = W.Problem("box-aniso", 2, nx, 2, 1.4, 0.5, W.box(1.4, 2, 0.7), [], ny=ny, Ty=0.7)
+    p = problems.plan_for(prob)
+    assert p.M == 4 * nx * ny
+    Dx = _symbol_1d(nx, 2, 1.4, prob.eps)
+    Dy = _symbol_1d(ny, 2, 0.7, prob.eps)
+    D = np.outer(Dx, Dy).ravel()
+    keep = D > 1e-12 * D.max()
+    normA, normZ = math.sqrt(D.max()), 1.0 / math.sqrt(D[keep].min())
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((3, prob.N))
+    Xf = np.fft.fft2(X.reshape(3, nx, ny)) * keep.reshape(nx, ny)
+    X = np.real(np.fft.ifft2(Xf)).reshape(3, -1)
+    Z = azrbf.apply_Zstar(p, azrbf.apply_A(p, torch.from_numpy(X).cuda())).cpu().numpy()
+    err = np.max(np.abs(Z - X)) / np.max(np.abs(X))
+    tol = 20 * U * math.log2(prob.N) * normA * normZ
+    announce("aniso box identity", "zeroed", int((~keep).sum()), "err", err, "tol", tol)
+    assert err < tol
+    p.destroy()

@@ -226,3 +226,21 @@ def test_solve_1d_s3():
 
 def test_solve_2d_poisson_star():
     _check(W.config_c4(32))
+
+
+def test_solve_2d_anisotropic_ellipse():
+    """The ellipse on the anisotropic box [-1.4, 1.4] x [-0.7, 0.7]
+    (section 5.4), 64 x 32 centres."""
+    _check(W.config_ellipse(64, 32))
+
+
+def test_solve_2d_anisotropic_helmholtz():
+    """Helmholtz k2 = 5 on the ellipse with its own spacing per axis (32 x 32
+    centres on the 2.8 x 1.4 box) and weak Dirichlet rows."""
+    base = W.config_ellipse(32, 32)
+
+    def u(x, y):
+        return np.sin(2 * x) * np.cos(3 * y)
+    prob = W.Problem("ellipse-helm", 2, 32, 2, 1.4, 0.5, base.domain, [lambda x, y: 8.0 * u(x, y)],
+                     op=W.HELMHOLTZ, k2=5.0, bnd=[u], nb=150, exact=[u], ny=32, Ty=0.7)
+    _check(prob)
