@@ -70,11 +70,10 @@ def main(names):
     if os.path.exists(OUT):
         with open(OUT) as fh:
             data = json.load(fh)
-    data["generated_by"] = "python tests/golden/make_fullsize_oracle.py " + " ".join(names)
     data["host"] = {"machine": platform.machine(), "cores": len(os.sched_getaffinity(0))}
     for name in names:
         print(f"[oracle] {name} ...", flush=True)
-        data.setdefault("cases", {})[name] = run(name)
+        data.setdefault("cases", {})[name] = dict(run(name), command="python tests/golden/make_fullsize_oracle.py " + name)
         print(f"[oracle] {name}: {json.dumps(data['cases'][name])}", flush=True)
         with open(OUT, "w") as fh:
             json.dump(data, fh, indent=1)

@@ -245,3 +245,22 @@ def test_fullsize_1d_solve_at_a_million():
     assert np.all(rc <= 10 * ro + 1e-15)
     assert np.all(eg <= 10 * eo + 1e-15)
     p.destroy()
+
+
+def test_fullsize_2d_ellipse_anisotropic():
+    """The ellipse x^2 + 4 y^2 <= 1 on the anisotropic box [-1.4, 1.4] x
+    [-0.7, 0.7] with 128 x 64 centres (section 5.4's experiment at powers of
+    two), against the dense oracle at the same size."""
+    prob = W.config_ellipse(128, 64)
+    announce("full 2D ellipse", prob.n, prob.n_y)
+    p, B, X, rel = _solve(prob)
+    rc = _cpu_residual(prob, p, X, B)
+    ro, eo, ref = _golden("ellipse128x64")
+    assert ref["M"] == p.M and ref["N"] == prob.N
+    eg = _cpu_maxerr(prob, X)
+    announce("k", p.info()["k"], "rank", p.info()["rank"], "relres gpu", rel, "cpu", rc, "oracle", ro,
+             "maxerr", eg, "oracle", eo)
+    assert np.allclose(rc, rel, rtol=1e-2, atol=1e-16)
+    assert np.all(rc <= 10 * ro)
+    assert np.all(eg <= 10 * eo)
+    p.destroy()
