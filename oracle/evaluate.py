@@ -12,7 +12,7 @@ import math
 import numpy as np
 
 from . import dense
-from .rbf import phi, phi2
+from .rbf import phi, phi1, phi2
 
 
 def relres(A, x, b):
@@ -47,7 +47,7 @@ def _window_1d(t, n, T, eps, deriv):
     j = j0[:, None] + off[None, :]
     d = t[:, None] - (-T + j * h)                # unreduced distance, |d| <= (W+1)h
     jj = np.mod(j, n)
-    f = phi if deriv == 0 else phi2
+    f = (phi, phi1, phi2)[deriv]
     v = f(d, eps)
     if (W + 1) * h * 2 > 2 * T:
         raise ValueError("window wider than the box; use dense evaluation")
@@ -88,4 +88,41 @@ def apply_local(prob, coef, pts, op=None):
             t2 = np.einsum("mw,mwr->mr", vy2, g)
             out += s * (vx2[:, a:a + 1] * t0 + vx[:, a:a + 1] * t2
                         + prob.k2 * vx[:, a:a + 1] * t0)
+    return out if coef.ndim == 2 else out[:, 0]
+
+
+def apply_boundary_local(prob, coef, bpts=None, types=None, normals=None):
+    """The boundary rows of dense.boundary_rows applied to coef (N,) or
+    (N, nrhs) by local sums: w_b u(x_b) at Dirichlet points, w_b n . grad
+    u(x_b) / eps at Neumann points."""
+    bpts = prob.bpoints() if bpts is None else bpts
+    types = prob.btypes() if types is None else np.asarray(types)
+    normals = prob.bnormals() if normals is None else normals
+    n, T, eps = prob.n, prob.T, prob.eps
+    C = coef if coef.ndim == 2 else coef[:, None]
+    neu = (types != 0)[:, None]
+    if prob.dim == 1:
+        jx, vx = _window_1d(bpts[:, 0], n, T, eps, 0)
+        _, vx1 = _window_1d(bpts[:, 0], n, T, eps, 1)
+        val = np.einsum("mw,mwr->mr", vx, C[jx])
+        dn = normals[:, :1] * np.einsum("mw,mwr->mr", vx1, C[jx]) / eps
+    else:
+        ny, Ty = prob.n_y, prob.T_y
+        C3 = C.reshape(n, ny, -1)
+        jx, vx = _window_1d(bpts[:, 0], n, T, eps, 0)
+        jy, vy = _window_1d(bpts[:, 1], ny, Ty, eps, 0)
+        _, vx1 = _window_1d(bpts[:, 0], n, T, eps, 1)
+        _, vy1 = _window_1d(bpts[:, 1], ny, Ty, eps, 1)
+        val = np.zeros((bpts.shape[0], C.shape[1]))
+        dx = np.zeros_like(val)
+        dy = np.zeros_like(val)
+        for a in range(jx.shape[1]):
+            g = C3[jx[:, a:a + 1], jy]
+            t0 = np.einsum("mw,mwr->mr", vy, g)
+            t1 = np.einsum("mw,mwr->mr", vy1, g)
+            val += vx[:, a:a + 1] * t0
+            dx += vx1[:, a:a + 1] * t0
+            dy += vx[:, a:a + 1] * t1
+        dn = (normals[:, :1] * dx + normals[:, 1:2] * dy) / eps
+    out = prob.bweight * np.where(neu, dn, val)
     return out if coef.ndim == 2 else out[:, 0]

@@ -3,6 +3,7 @@
 phi(r) = exp(-eps^2 r^2)                       eq. (rbf)
 phi_per(x) = sum_m phi(x - 2 m T)              eq. (periodic_rbf)
 phi''(r) = -2 eps^2 exp(-eps^2 r^2)(1 - 2 eps^2 r^2)   (section 6.1, Example)
+phi'(r) = -2 eps^2 r exp(-eps^2 r^2)                  (Neumann rows, section 6.3)
 
 The infinite image sum is truncated: for |x| <= 2T every omitted image lies
 at distance > 6.8/eps, where the Gaussian is below exp(-46.24) < 1e-20.
@@ -15,6 +16,13 @@ import numpy as np
 def phi(r, eps):
     r = np.asarray(r, dtype=np.float64)
     return np.exp(-(eps * r) ** 2)
+
+
+def phi1(r, eps):
+    """First derivative of the Gaussian with respect to its argument."""
+    r = np.asarray(r, dtype=np.float64)
+    e2 = eps * eps
+    return -2.0 * e2 * r * np.exp(-e2 * r * r)
 
 
 def phi2(r, eps):
@@ -47,6 +55,10 @@ def periodize(f, x, eps, T):
 
 def phi_per(x, eps, T):
     return periodize(phi, x, eps, T)
+
+
+def phi1_per(x, eps, T):
+    return periodize(phi1, x, eps, T)
 
 
 def phi2_per(x, eps, T):

@@ -565,3 +565,83 @@ def test_paper_E6_ellipse():
     # (the paper's coefficient norm, about 20 per sqrt(N), belongs to its
     # solvers: coefficients of a frame are not unique and the truncated SVD
     # returns the small-norm one, 0.045 per sqrt(N), so it is not compared)
+
+
+# ---------------------------------------------------------------- Neumann rows (section 6.3)
+
+def test_neumann_rows_are_normal_derivatives_of_the_basis():
+    """A Neumann row is w_b n . grad phi_j(x_b) / eps.  Checked against a
+    central difference of Dirichlet rows along the normal (a route that never
+    calls the derivative code): a wrong sign, axis or scale fails here."""
+    p = W.config_flower(32, manufactured=True)
+    bp, nv, t = p.bpoints(), p.bnormals(), p.btypes()
+    R = dense.boundary_rows(p, bp)
+    dirich = np.zeros(bp.shape[0], dtype=np.uint8)
+    d = 1e-5
+    fd = (dense.boundary_rows(p, bp + d * nv, dirich, nv) - dense.boundary_rows(p, bp - d * nv, dirich, nv)) / (2 * d)
+    neu = t != 0
+    assert neu.sum() == 200 and (~neu).sum() == 100
+    scale = np.abs(R[neu]).max()
+    assert np.abs(R[neu] - fd[neu] / p.eps).max() < 1e-6 * scale
+    assert np.array_equal(R[~neu], dense.boundary_rows(p, bp, dirich, nv)[~neu])
+    # 1D: the outward normals are -1 at the left end and +1 at the right end
+    q = W.Problem("n1", 1, 64, 2, 1.5, 0.5, W.interval(-1.0, 1.0), [lambda x: 0 * x], op=W.HELMHOLTZ,
+                  bnd=[lambda x: 0 * x], nb=2, bc_outer="N")
+    x = q.bpoints()
+    R1 = dense.boundary_rows(q, x)
+    fd1 = (dense.boundary_rows(q, x + d, np.zeros(2, np.uint8)) - dense.boundary_rows(q, x - d, np.zeros(2, np.uint8))) / (2 * d)
+    assert np.abs(R1[0] + fd1[0] / q.eps).max() < 1e-6 * np.abs(R1).max()
+    assert np.abs(R1[1] - fd1[1] / q.eps).max() < 1e-6 * np.abs(R1).max()
+
+
+def test_flower_normals_point_out_of_the_domain():
+    p = W.config_flower(32)
+    bp, nv = p.bpoints(), p.bnormals()
+    assert np.allclose(np.linalg.norm(nv, axis=1), 1.0, atol=1e-14)
+    out = bp + 1e-4 * nv
+    inn = bp - 1e-4 * nv
+    assert not np.any(p.domain.contains(out[:, 0], out[:, 1]))
+    assert np.all(p.domain.contains(inn[:, 0], inn[:, 1]))
+    # the hole is cut out: its centre is not a collocation point candidate
+    assert not p.domain.contains(np.array([0.0]), np.array([0.0]))[0]
+
+
+def test_mixed_bvp_on_the_multiply_connected_flower():
+    """Section 6.3's last setting with manufactured data: Helmholtz k^2 = 4,
+    Neumann data on the flower's outer curve, Dirichlet data on the circle
+    cut out of it.  The dense oracle recovers u; the same system with the
+    Neumann data's sign flipped, or without its 1/eps, misses u by O(1)."""
+    p = W.config_flower(48, manufactured=True)
+    A, idx, pts, bpts = dense.system_matrix(p)
+    b = dense.rhs(p, pts, bpts)[:, 0]
+    svd = lstsq.tsvd(A)
+    u = p.exact[0]
+    assert _bvp_err(p, A, b, u, svd) < 1e-5
+    neu = np.concatenate([np.zeros(idx.size, bool), p.btypes() != 0])
+    flip = b.copy()
+    flip[neu] *= -1.0
+    assert _bvp_err(p, A, flip, u, svd) > 1.0
+    raw = b.copy()
+    raw[neu] *= p.eps
+    assert _bvp_err(p, A, raw, u, svd) > 1.0
+
+
+def test_mixed_bvp_1d_neumann_left_dirichlet_right():
+    """u = sin(k x) + x^2 on [-1, 1] with u'(-1) given (Neumann, outward
+    normal -1) and u(1) given: the oracle reaches the section 6.3 accuracy."""
+    n = 128
+    T = 1.5
+    eps = rbf.shape_parameter(1e-10, n, T)
+    kk = n / 5.0
+
+    def u(x):
+        return np.sin(kk * x) + x * x
+
+    def du_n(x, nx):
+        return (kk * np.cos(kk * x) + 2 * x) * nx
+    p = W.Problem("m1n", 1, n, 2, T, eps * 2 * T / n, W.interval(-1.0, 1.0), [lambda x: -(2.0 + kk * kk * x * x)],
+                  op=W.HELMHOLTZ, k2=kk * kk, bnd=[u], bnd_n=[du_n], nb=2, bc_outer="ND", exact=[u])
+    assert list(p.btypes()) == [1, 0]
+    A, idx, pts, bpts = dense.system_matrix(p)
+    b = dense.rhs(p, pts, bpts)[:, 0]
+    assert _bvp_err(p, A, b, u) < 1e-8

@@ -21,10 +21,10 @@ from typing import Callable, Optional
 import numpy as np
 
 __all__ = [
-    "Domain", "interval", "disk", "star", "ellipse", "box", "shape_parameter_eh",
+    "Domain", "interval", "disk", "star", "ellipse", "box", "flower", "with_hole", "shape_parameter_eh",
     "Problem", "trig_sum_1d", "trig_sum_2d",
     "config_c1", "config_c1a", "config_c2", "config_c3", "config_c3a",
-    "config_c4", "config_ellipse", "family_1d", "served_stream", "test_points",
+    "config_c4", "config_ellipse", "config_flower", "family_1d", "served_stream", "test_points",
 ]
 
 
@@ -40,6 +40,8 @@ class Domain:
     inclusive (points on the boundary belong to the domain).  For 2D domains
     that are star-shaped about the origin, ``radius`` gives the boundary as
     r(theta) and ``dradius`` its derivative; they define boundary points.
+    ``holes`` lists circles (cx, cy, r) cut out of a 2D domain (a multiply
+    connected domain); their circles are part of the boundary.
     """
     name: str
     dim: int
@@ -48,6 +50,7 @@ class Domain:
     radius: Optional[Callable[[np.ndarray], np.ndarray]] = None
     dradius: Optional[Callable[[np.ndarray], np.ndarray]] = None
     area: Optional[float] = None
+    holes: tuple = ()
 
 
 def interval(a: float, b: float) -> Domain:
@@ -103,6 +106,28 @@ def star(R: float, amp: float = 0.1, petals: int = 5) -> Domain:
                   area=math.pi * (R * R + 0.5 * amp * amp))
 
 
+def with_hole(dom: Domain, cx: float, cy: float, r: float) -> Domain:
+    """``dom`` with the open disk of radius r about (cx, cy) cut out (points
+    on the circle stay in the domain)."""
+    inner = dom.contains
+
+    def contains(x, y):
+        return inner(x, y) & ((x - cx) ** 2 + (y - cy) ** 2 >= r * r)
+    return dataclasses.replace(dom, name=f"{dom.name}-hole({cx},{cy},{r})", contains=contains,
+                               area=None if dom.area is None else dom.area - math.pi * r * r,
+                               holes=dom.holes + ((cx, cy, r),))
+
+
+def flower(R: float = 0.69, amp: float = 0.1, petals: int = 5, hole: float = 0.1) -> Domain:
+    """The multiply connected domain of section 6.3's last experiment: a
+    smooth flower r(theta) = R + amp cos(petals theta) with a circle of
+    radius ``hole`` (diameter 0.2 in the paper) cut out about the origin.
+    The paper does not define the flower or the circle's position; these
+    are this workload's choices."""
+    return dataclasses.replace(with_hole(star(R, amp, petals), 0.0, 0.0, hole),
+                               name=f"flower(R={R},a={amp},p={petals},hole={hole})")
+
+
 def boundary_length(dom: Domain, nquad: int = 1 << 16) -> float:
     """Perimeter of a star-shaped boundary by the periodic trapezoid rule."""
     t = 2 * math.pi * np.arange(nquad) / nquad
@@ -115,6 +140,27 @@ def boundary_points(dom: Domain, count: int) -> np.ndarray:
     t = 2 * math.pi * np.arange(count) / count
     r = dom.radius(t)
     return np.stack([r * np.cos(t), r * np.sin(t)], axis=1)
+
+
+def boundary_normals(dom: Domain, count: int) -> np.ndarray:
+    """Unit outward normals at the points of ``boundary_points``: the
+    tangent r'(cos, sin) + r(-sin, cos) of the counter-clockwise curve
+    turned clockwise by a right angle."""
+    t = 2 * math.pi * np.arange(count) / count
+    r, dr = dom.radius(t), dom.dradius(t)
+    tx = dr * np.cos(t) - r * np.sin(t)
+    ty = dr * np.sin(t) + r * np.cos(t)
+    nrm = np.sqrt(tx * tx + ty * ty)
+    return np.stack([ty / nrm, -tx / nrm], axis=1)
+
+
+def hole_points(hole: tuple, count: int):
+    """``count`` points on a hole's circle and the domain's outward normals
+    there (pointing into the hole), ((count, 2), (count, 2))."""
+    cx, cy, r = hole
+    t = 2 * math.pi * np.arange(count) / count
+    u = np.stack([np.cos(t), np.sin(t)], axis=1)
+    return np.array([cx, cy]) + r * u, -u
 
 
 # --------------------------------------------------------------------------
@@ -174,7 +220,15 @@ class Problem:
            -(Laplacian + k2) phi_j, boundary rows phi_j at boundary points.
     rhs    list of callables f(x) or f(x, y) giving interior data
     bnd    for BVPs, callables g giving Dirichlet data (same length as rhs)
-    nb     number of boundary points (BVPs), placed by ``boundary_points``
+    nb     number of boundary points (BVPs): on the outer curve
+           (``boundary_points``), the last ``nb_hole`` of them on the holes
+    bc_outer, bc_hole
+           boundary condition of the points on the outer curve and on the
+           holes: "D" (Dirichlet, rows phi_j) or "N" (Neumann, rows of the
+           normal derivative); in 1D one letter per end ("DN": Dirichlet at
+           the left end) or one for both
+    bnd_n  for Neumann points, callables h(x, y, nx, ny) (1D: h(x, nx)) giving
+           the normal derivative data (same length as rhs; None: zero)
     """
     name: str
     dim: int
@@ -195,6 +249,10 @@ class Problem:
     seed: int = 42                    # sketch seed
     ny: Optional[int] = None          # 2D: centres along y (None: n)
     Ty: Optional[float] = None        # 2D: half-width along y (None: T)
+    nb_hole: int = 0                  # boundary points on the holes (last nb_hole of nb)
+    bc_outer: str = "D"
+    bc_hole: str = "D"
+    bnd_n: Optional[list] = None
 
     @property
     def h(self) -> float:
@@ -222,11 +280,56 @@ class Problem:
         return self.n if self.dim == 1 else self.n * self.n_y
 
     def bpoints(self) -> np.ndarray:
-        if self.nb == 0:
-            return np.zeros((0, self.dim))
+        return self._boundary()[0]
+
+    def bnormals(self) -> np.ndarray:
+        """Unit outward normals at the boundary points, (nb, dim)."""
+        return self._boundary()[1]
+
+    def btypes(self) -> np.ndarray:
+        """0 (Dirichlet) or 1 (Neumann) per boundary point, uint8."""
         if self.dim == 1:
-            return np.array([[-1.0], [1.0]])[: self.nb]
-        return boundary_points(self.domain, self.nb)
+            bc = self.bc_outer * 2 if len(self.bc_outer) == 1 else self.bc_outer
+            return np.array([c == "N" for c in bc[: self.nb]], dtype=np.uint8)
+        nout = self.nb - self.nb_hole
+        return np.array([self.bc_outer == "N"] * nout + [self.bc_hole == "N"] * self.nb_hole, dtype=np.uint8)
+
+    @property
+    def has_neumann(self) -> bool:
+        return bool(self.nb) and bool(np.any(self.btypes()))
+
+    def _boundary(self):
+        if self.nb == 0:
+            return np.zeros((0, self.dim)), np.zeros((0, self.dim))
+        if self.dim == 1:
+            return np.array([[-1.0], [1.0]])[: self.nb], np.array([[-1.0], [1.0]])[: self.nb]
+        nout = self.nb - self.nb_hole
+        pts = [boundary_points(self.domain, nout)]
+        nrm = [boundary_normals(self.domain, nout)]
+        holes = self.domain.holes
+        if self.nb_hole:
+            if not holes:
+                raise ValueError("nb_hole > 0 on a domain without holes")
+            per = [self.nb_hole // len(holes) + (i < self.nb_hole % len(holes)) for i in range(len(holes))]
+            for hole, c in zip(holes, per):
+                p, q = hole_points(hole, c)
+                pts.append(p)
+                nrm.append(q)
+        return np.concatenate(pts, axis=0), np.concatenate(nrm, axis=0)
+
+    def bdata(self, i: int, bp: Optional[np.ndarray] = None) -> np.ndarray:
+        """Boundary data of right-hand side i at the boundary points:
+        g (Dirichlet points) or the normal derivative h (Neumann points)."""
+        bp = self.bpoints() if bp is None else bp
+        types = self.btypes()
+        out = np.zeros(bp.shape[0])
+        d = types == 0
+        if np.any(d):
+            out[d] = self.bnd[i](*bp[d].T)
+        if np.any(~d) and self.bnd_n is not None:
+            nv = self.bnormals()
+            out[~d] = self.bnd_n[i](*bp[~d].T, *nv[~d].T)
+        return out
 
 
 def _f_c1(x):
@@ -301,6 +404,46 @@ def config_c4(n: int = 256, eh: float = 0.5, R: float = 0.7) -> Problem:
     nb = int(round(4 * boundary_length(dom) / h))
     return Problem("C4", 2, n, 2, 1.0, eh, dom, [_f_c4], op=POISSON, k2=0.0,
                    bnd=[_u_c4], nb=nb, exact=[_u_c4], p=10)
+
+
+def _f_flower(x, y):
+    # -(Lap + 4) u = -exp(-4((x+0.3)^2 + y^2)^2): the source of section 6.3's
+    # last experiment written for the operator -(Lap + k2)
+    return -np.exp(-4.0 * ((x + 0.3) ** 2 + y * y) ** 2)
+
+
+def _u_flower_m(x, y):
+    return np.sin(2 * x) * np.cos(3 * y) + 0.5 * x * y
+
+
+def _f_flower_m(x, y):
+    # -(Lap + 4) u with Lap(sin 2x cos 3y) = -13 sin 2x cos 3y, Lap(x y) = 0
+    return 9.0 * np.sin(2 * x) * np.cos(3 * y) - 2.0 * x * y
+
+
+def _dn_flower_m(x, y, nx, ny):
+    ux = 2 * np.cos(2 * x) * np.cos(3 * y) + 0.5 * y
+    uy = -3 * np.sin(2 * x) * np.sin(3 * y) + 0.5 * x
+    return ux * nx + uy * ny
+
+
+def config_flower(n: int = 128, eh: float = 0.5, manufactured: bool = False,
+                  nb_outer: int = 200, nb_hole: int = 100) -> Problem:
+    """Section 6.3's last experiment: Helmholtz (Lap + 4) u = exp(-4((x+0.3)^2
+    + y^2)^2) on the flower with a hole (``flower``), homogeneous Neumann
+    data on the outer curve and homogeneous Dirichlet data on the circle,
+    200 and 100 boundary points, box [-1, 1]^2, s = 2.  The paper uses
+    100 x 100 centres; n is a power of two here.  ``manufactured`` swaps in
+    u = sin 2x cos 3y + xy/2 with its source, normal derivative (outer curve)
+    and values (circle), for error checks."""
+    dom = flower()
+    common = dict(op=HELMHOLTZ, k2=4.0, nb=nb_outer + nb_hole, nb_hole=nb_hole,
+                  bc_outer="N", bc_hole="D", p=10)
+    if manufactured:
+        return Problem("E9m", 2, n, 2, 1.0, eh, dom, [_f_flower_m], bnd=[_u_flower_m],
+                       bnd_n=[_dn_flower_m], exact=[_u_flower_m], **common)
+    return Problem("E9", 2, n, 2, 1.0, eh, dom, [_f_flower], bnd=[lambda x, y: 0.0 * x],
+                   bnd_n=[lambda x, y, nx, ny: 0.0 * x], **common)
 
 
 # --------------------------------------------------------------------------
