@@ -93,6 +93,14 @@ typedef struct {
   int32_t ny;             /* 2D: centres along y (a power of two, 16..512);  */
                           /* 0 = n.  n and T above are then the x axis       */
   double Ty;              /* 2D: half-width of the box along y; 0 = T        */
+  const uint8_t* btype;   /* nb entries or NULL (all Dirichlet): 0 marks a   */
+                          /* Dirichlet point (row bweight phi_j(x_b)), 1 a   */
+                          /* Neumann point (section 6.3: row bweight         */
+                          /* n . grad phi_j(x_b) / eps, the 1/eps making its */
+                          /* size match the Dirichlet rows)                  */
+  const double* bnormal;  /* nb x dim unit outward normals n (read at        */
+                          /* Neumann points; may be NULL when there are      */
+                          /* none), point i at bnormal[i*dim+a]              */
 } azrbf_problem;
 
 /* Read-only facts about a plan. */
@@ -116,7 +124,8 @@ typedef struct {
  * spectra are computed on the device, queued on `stream` (1D: without
  * waiting for them; work later passed another stream first waits for them).
  * On success *out owns the plan.
- * Errors: EINVAL (bad sizes, empty mask, nb > 0 without op BVP, ...),
+ * Errors: EINVAL (bad sizes, empty mask, nb > 0 without op BVP, a Neumann
+ * point without a unit normal, ...),
  * EUNSUPPORTED (n not a power of two or out of range, s not in {1,2,3,4}),
  * ENOMEM, EHIP. */
 int azrbf_plan(const azrbf_problem* prob, void* stream, azrbf_plan_t* out);
@@ -146,7 +155,9 @@ int azrbf_apply_A(azrbf_plan_t plan, const double* X, int64_t ldx, int64_t nvec,
  * source term of -(Lap + k2) u = f) and c = 1 for AZRBF_OP_APPROX, c =
  * 1 / (2 dim eps^2) for AZRBF_OP_BVP (the same normalisation as the interior
  * rows, so that the scaled equations keep their solution); B[M + j, v] =
- * bweight g[j, v] for the Mb boundary rows (Dirichlet data).  Device
+ * bweight g[j, v] for the Mb boundary rows at Dirichlet points (g the values
+ * of u) and bweight g[j, v] / eps at Neumann points (g the normal derivative
+ * of u, scaled as the Neumann rows).  Device
  * pointers: f is M x nrhs (ldf >= M), g is Mb x nrhs (ldg >= Mb; unread and
  * may be NULL when Mb = 0), B is (M + Mb) x nrhs (ldb >= M + Mb).  B may be f
  * itself (same leading dimension) but must not otherwise overlap f or g.

@@ -37,6 +37,7 @@ class _Problem(ctypes.Structure):
         ("bpts", ctypes.POINTER(ctypes.c_double)), ("bweight", ctypes.c_double),
         ("tau", ctypes.c_double), ("tauZ", ctypes.c_double), ("k", ctypes.c_int32),
         ("refine", ctypes.c_int32), ("seed", ctypes.c_uint64), ("ny", ctypes.c_int32), ("Ty", ctypes.c_double),
+        ("btype", ctypes.POINTER(ctypes.c_uint8)), ("bnormal", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -157,8 +158,11 @@ class Plan:
     """An azrbf plan (owns device memory until ``destroy`` or garbage collection)."""
 
     def __init__(self, dim, n, s, T, mask, eps=0.0, tau0=0.0, op=OP_APPROX, k2=0.0, bpts=None,
-                 bweight=1.0, tau=1e-12, tauZ=1e-12, k=0, refine=1, seed=42, stream=None, ny=0, Ty=0.0):
-        """ny, Ty: the y axis of a 2D box (0: the same as n, T)."""
+                 bweight=1.0, tau=1e-12, tauZ=1e-12, k=0, refine=1, seed=42, stream=None, ny=0, Ty=0.0,
+                 btype=None, bnormal=None):
+        """ny, Ty: the y axis of a 2D box (0: the same as n, T).  btype: per
+        boundary point 0 (Dirichlet) or 1 (Neumann; None: all Dirichlet);
+        bnormal: (nb, dim) unit outward normals, needed at Neumann points."""
         lib = _lib()
         self.dim, self.n, self.s, self.T = dim, n, s, T
         self.ny, self.Ty = int(ny or 0), float(Ty or 0.0)
@@ -174,6 +178,17 @@ class Plan:
         pr.bweight, pr.tau, pr.tauZ = float(bweight), float(tau), float(tauZ)
         pr.k, pr.refine, pr.seed = int(k), int(refine), int(seed)
         pr.ny, pr.Ty = self.ny, self.Ty
+        self._btype = self._bnormal = None
+        if btype is not None and pr.nb:
+            self._btype = np.ascontiguousarray(btype, dtype=np.uint8).ravel()
+            if self._btype.size != pr.nb:
+                raise ValueError("btype needs one entry per boundary point")
+            pr.btype = self._btype.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        if bnormal is not None and pr.nb:
+            self._bnormal = np.ascontiguousarray(np.asarray(bnormal, dtype=np.float64).reshape(-1, dim))
+            if self._bnormal.shape[0] != pr.nb:
+                raise ValueError("bnormal needs one normal per boundary point")
+            pr.bnormal = self._bnormal.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         self._prob = pr
         h = ctypes.c_void_p()
         _check(lib.azrbf_plan(ctypes.byref(pr), _stream(stream), ctypes.byref(h)), "azrbf_plan")

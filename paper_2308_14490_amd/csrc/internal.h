@@ -225,6 +225,8 @@ struct Plan {
   double2* facy = nullptr;                // 2D: y-axis factors (fac itself on a square box)
   double* w2 = nullptr;
   double* bpts = nullptr;                 // Mb x dim, device
+  uint8_t* btype = nullptr;               // Mb, device: 1 at Neumann points (null: all Dirichlet)
+  double* bnorm = nullptr;                // Mb x dim, device: unit outward normals (with btype)
   double bweight = 1;
   double normA = 0, normZ = 0;   // sqrt(max D), sqrt(max w); valid once ops_norms ran
   int zeroed = 0;

@@ -635,15 +635,21 @@ k_row_fwd_C(Geo g, const double2* __restrict__ tw, double2* __restrict__ data, i
 
 // ------------------------------------------------------------------ boundary rows
 
-// Y[M + i] = alpha * bweight * sum_j phi_j(x_b) X[j] + beta * Y[M + i]:
-// direct summation over the centres within the Gaussian's numerical support
-// (phi < 1e-20), periodized images included.
-__device__ __forceinline__ double phi_per_dev(double d, double eps, double T, int mimg) {
-  double s = 0.0;
+// Y[M + i] = alpha * bweight * r_i . X + beta * Y[M + i] with the boundary
+// row r_i = (phi_j(x_b))_j at a Dirichlet point and (n . grad phi_j(x_b) /
+// eps)_j at a Neumann point (section 6.3): direct summation over the centres
+// within the Gaussian's numerical support (phi < 1e-20), periodized images
+// included.  phi'(d) = -2 eps^2 d exp(-eps^2 d^2).
+__device__ __forceinline__ double phi_per_dev(double d, double eps, double T, int mimg, double* dphi) {
+  double s = 0.0, ds = 0.0;
   for (int m = -mimg; m <= mimg; ++m) {
-    const double x = eps * (d - 2.0 * T * m);
-    s += exp(-x * x);
+    const double dm = d - 2.0 * T * m;
+    const double x = eps * dm;
+    const double e = exp(-x * x);
+    s += e;
+    ds = fma(-2.0 * eps * eps * dm, e, ds);
   }
+  *dphi = ds;
   return s;
 }
 
@@ -654,19 +660,21 @@ struct AxisWin {
   double T, h;
 };
 
-__device__ __forceinline__ int axis_window(const AxisWin& a, double x, double eps, double* w) {
+// w: the periodized kernel at the window's centres; dw: its derivative in x.
+__device__ __forceinline__ int axis_window(const AxisWin& a, double x, double eps, double* w, double* dw) {
   const int nw = 2 * a.W + 2 < a.n ? 2 * a.W + 2 : a.n;
   const int j0 = (int)floor((x + a.T) / a.h) - a.W;
   for (int o = 0; o < nw; ++o) {
     const int j = ((j0 + o) % a.n + a.n) % a.n;
     double d = x - (-a.T + j * a.h);
     d -= 2.0 * a.T * nearbyint(d / (2.0 * a.T));
-    w[o] = phi_per_dev(d, eps, a.T, a.mimg);
+    w[o] = phi_per_dev(d, eps, a.T, a.mimg, &dw[o]);
   }
   return j0;
 }
 
-__global__ void k_boundary_A(int dim, AxisWin ax, AxisWin ay, double eps, const double* __restrict__ bp, int64_t Mb,
+__global__ void k_boundary_A(int dim, AxisWin ax, AxisWin ay, double eps, const double* __restrict__ bp,
+                             const uint8_t* __restrict__ btype, const double* __restrict__ bnorm, int64_t Mb,
                              double bw, const double* __restrict__ X, int64_t ldx, int64_t nvec, double alpha,
                              double beta, const double* Yin, int64_t ldyi, double* Y, int64_t ldy, int64_t M) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -674,19 +682,27 @@ __global__ void k_boundary_A(int dim, AxisWin ax, AxisWin ay, double eps, const 
   if (i >= Mb || v >= nvec) return;
   const int nwx = 2 * ax.W + 2 < ax.n ? 2 * ax.W + 2 : ax.n;
   const int nwy = 2 * ay.W + 2 < ay.n ? 2 * ay.W + 2 : ay.n;
-  double wx[64], wy[64];
-  const int jx0 = axis_window(ax, bp[i * dim], eps, wx);
-  const int jy0 = dim == 2 ? axis_window(ay, bp[i * dim + 1], eps, wy) : 0;
+  double wx[64], wy[64], dwx[64], dwy[64];
+  const int jx0 = axis_window(ax, bp[i * dim], eps, wx, dwx);
+  const int jy0 = dim == 2 ? axis_window(ay, bp[i * dim + 1], eps, wy, dwy) : 0;
+  // Neumann: n . grad / eps = (nx / eps) d/dx + (ny / eps) d/dy of the product basis
+  const bool neu = btype && btype[i];
+  const double cx = neu ? bnorm[i * dim] / eps : 0.0;
+  const double cy = neu && dim == 2 ? bnorm[i * dim + 1] / eps : 0.0;
   const double* x = X + ldx * v;
   double acc = 0.0;
   if (dim == 1) {
-    for (int o = 0; o < nwx; ++o) acc = fma(wx[o], x[((jx0 + o) % ax.n + ax.n) % ax.n], acc);
+    for (int o = 0; o < nwx; ++o) acc = fma(neu ? cx * dwx[o] : wx[o], x[((jx0 + o) % ax.n + ax.n) % ax.n], acc);
   } else {
     for (int ox = 0; ox < nwx; ++ox) {
       const int jx = ((jx0 + ox) % ax.n + ax.n) % ax.n;
-      double r = 0.0;
-      for (int oy = 0; oy < nwy; ++oy) r = fma(wy[oy], x[(int64_t)jx * ay.n + ((jy0 + oy) % ay.n + ay.n) % ay.n], r);
-      acc = fma(wx[ox], r, acc);
+      double r = 0.0, rd = 0.0;
+      for (int oy = 0; oy < nwy; ++oy) {
+        const double xv = x[(int64_t)jx * ay.n + ((jy0 + oy) % ay.n + ay.n) % ay.n];
+        r = fma(wy[oy], xv, r);
+        rd = fma(dwy[oy], xv, rd);
+      }
+      acc = neu ? fma(cx * dwx[ox], r, fma(cy * wx[ox], rd, acc)) : fma(wx[ox], r, acc);
     }
   }
   Y[M + i + ldy * v] = beta == 0.0 ? alpha * bw * acc : fma(alpha * bw, acc, beta * Yin[M + i + ldyi * v]);
@@ -694,13 +710,19 @@ __global__ void k_boundary_A(int dim, AxisWin ax, AxisWin ay, double eps, const 
 
 // ------------------------------------------------------------------ right-hand sides
 
-// B[i, v] = c f[i, v] (collocation rows), B[M + j, v] = bw g[j, v] (boundary rows).
+// B[i, v] = c f[i, v] (collocation rows), B[M + j, v] = bw g[j, v] (boundary
+// rows; bw g[j, v] / eps at Neumann points, as their rows).
 __global__ void k_assemble_rhs(int64_t M, int64_t Mb, const double* f, int64_t ldf, double c, const double* g,
-                               int64_t ldg, double bw, double* B, int64_t ldb) {
+                               int64_t ldg, double bw, const uint8_t* __restrict__ btype, double eps, double* B,
+                               int64_t ldb) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t v = blockIdx.y;
-  if (i < M) B[i + ldb * v] = c * f[i + ldf * v];
-  else if (i < M + Mb) B[i + ldb * v] = bw * g[(i - M) + ldg * v];
+  if (i < M) {
+    B[i + ldb * v] = c * f[i + ldf * v];
+  } else if (i < M + Mb) {
+    const double gv = g[(i - M) + ldg * v];
+    B[i + ldb * v] = btype && btype[i - M] ? bw * gv / eps : bw * gv;
+  }
 }
 
 int ops_rhs(const Plan& P, const double* f, int64_t ldf, const double* g, int64_t ldg, int64_t nrhs, double* B,
@@ -714,7 +736,7 @@ int ops_rhs(const Plan& P, const double* f, int64_t ldf, const double* g, int64_
   const double c = P.prob.op == AZRBF_OP_APPROX ? 1.0 : 1.0 / (2.0 * P.dim * P.eps * P.eps);
   const dim3 grid((unsigned)((P.Mt + 255) / 256), (unsigned)nrhs);
   Prof pr("assemble_rhs", 16.0 * (double)P.Mt * nrhs, st);
-  launch_kernel(k_assemble_rhs, grid, 256, 0, st, P.M, P.Mb, f, ldf, c, g, ldg, P.bweight, B, ldb);
+  launch_kernel(k_assemble_rhs, grid, 256, 0, st, P.M, P.Mb, f, ldf, c, g, ldg, P.bweight, P.btype, P.eps, B, ldb);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
@@ -1207,8 +1229,8 @@ static int boundary_rows(Plan& P, const double* X, int64_t ldx, int64_t nvec, do
   if (std::min(2 * ax.W + 2, ax.n) > 64 || std::min(2 * ay.W + 2, ay.n) > 64) return AZRBF_EUNSUPPORTED;
   const dim3 grid((unsigned)((P.Mb + 127) / 128), (unsigned)nvec);
   Prof pr("boundary_A", 8.0 * (double)P.Mb * nvec * (beta != 0.0 ? 2.0 : 1.0), st);
-  launch_kernel(k_boundary_A, grid, 128, 0, st, P.dim, ax, ay, P.eps, P.bpts, P.Mb, P.bweight, X, ldx, nvec, alpha,
-                beta, Yin, ldyi, Y, ldy, P.M);
+  launch_kernel(k_boundary_A, grid, 128, 0, st, P.dim, ax, ay, P.eps, P.bpts, P.btype, P.bnorm, P.Mb, P.bweight, X,
+                ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, P.M);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 

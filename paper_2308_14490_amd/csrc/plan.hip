@@ -435,6 +435,18 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
   // threads, n1 / 16 per phase (1D: n1 = n / 512 once n > 2^18)
   if (q.dim == 1 && q.n > (1 << 18) && q.s * (q.n >> 9) / 16 > 256) return AZRBF_EUNSUPPORTED;
   if (q.s < 1 || q.s > 4) return AZRBF_EUNSUPPORTED;
+  bool neumann = false;
+  if (q.nb > 0 && q.btype) {
+    for (int64_t i = 0; i < q.nb; ++i) {
+      if (q.btype[i] > 1) return AZRBF_EINVAL;
+      if (!q.btype[i]) continue;
+      neumann = true;
+      if (!q.bnormal) return AZRBF_EINVAL;
+      double nn = 0.0;
+      for (int a = 0; a < q.dim; ++a) nn += q.bnormal[i * q.dim + a] * q.bnormal[i * q.dim + a];
+      if (!(std::fabs(nn - 1.0) <= 1e-8)) return AZRBF_EINVAL;   // a unit normal (NaN fails too)
+    }
+  }
 
   azrbf_plan_s* h = new (std::nothrow) azrbf_plan_s();
   if (!h) return AZRBF_ENOMEM;
@@ -444,6 +456,8 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
   P.prob = q;
   P.prob.mask = nullptr;
   P.prob.bpts = nullptr;
+  P.prob.btype = nullptr;
+  P.prob.bnormal = nullptr;
   if (hipGetDevice(&P.device) != hipSuccess) { delete h; return AZRBF_EHIP; }
   P.dim = q.dim;
   P.n = q.n;
@@ -524,6 +538,14 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
     rc = P.alloc((void**)&P.bpts, sizeof(double) * P.Mb * P.dim);
     if (!rc && hipMemcpyAsync(P.bpts, q.bpts, sizeof(double) * P.Mb * P.dim, hipMemcpyHostToDevice, st) != hipSuccess)
       rc = AZRBF_EHIP;
+    if (!rc && neumann) {   // types and normals: read by the boundary rows and the right-hand sides
+      rc = P.alloc((void**)&P.btype, P.Mb);
+      if (!rc) rc = P.alloc((void**)&P.bnorm, sizeof(double) * P.Mb * P.dim);
+      if (!rc && hipMemcpyAsync(P.btype, q.btype, P.Mb, hipMemcpyHostToDevice, st) != hipSuccess) rc = AZRBF_EHIP;
+      if (!rc && hipMemcpyAsync(P.bnorm, q.bnormal, sizeof(double) * P.Mb * P.dim, hipMemcpyHostToDevice, st) !=
+                     hipSuccess)
+        rc = AZRBF_EHIP;
+    }
     if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = AZRBF_EHIP;
     if (rc) { P.release(); delete h; return rc; }
   }
@@ -789,6 +811,7 @@ int64_t azrbf_footprint_bytes(const azrbf_problem* pr, int64_t max_rhs) {
   int64_t b = 0;
   b += 2 * ph * N * 16;                                 // spectra (1D) or factors + weights (2D)
   b += pr->dim == 2 ? Lg * 4 : 0;                       // inverse map
+  b += pr->nb * (16 * pr->dim + 1);                     // boundary points, normals, types
   int64_t chunk = ((int64_t)256 << 20) / (ph * N * 16);   // as engine_chunk
   chunk = chunk < 1 ? 1 : (chunk > 64 ? 64 : chunk);
   const int64_t pairs = (std::max<int64_t>(k, max_rhs) + 1) / 2;

@@ -3,7 +3,8 @@
 The collocation mask comes from the plan's own fine grid (eq. set_Xtilde)
 and the domain's membership test; right-hand sides are the workload's
 functions sampled at the plan's collocation points (and, for boundary value
-problems, the Dirichlet data at the boundary points), assembled into the
+problems, the boundary data: values at Dirichlet points, normal derivatives
+at Neumann points), assembled into the
 system's right-hand side by the library.
 """
 import numpy as np
@@ -23,11 +24,13 @@ def plan_for(prob, refine=None, tau=1e-12, tauZ=1e-12, k=None, stream=None):
     refine = default_refine(prob) if refine is None else refine
     mask = azrbf.make_mask(prob.dim, prob.n, prob.s, prob.T, prob.domain.contains, prob.ny, prob.Ty)
     bpts = prob.bpoints() if prob.nb else None
+    neu = prob.has_neumann
     return azrbf.Plan(prob.dim, prob.n, prob.s, prob.T, mask, eps=prob.eps,
                       op=azrbf.OP_APPROX if prob.op == 0 else azrbf.OP_BVP, k2=prob.k2,
                       bpts=bpts, bweight=prob.bweight, tau=tau, tauZ=tauZ,
                       k=prob.k if k is None else k, refine=refine, seed=prob.seed, stream=stream,
-                      ny=prob.ny or 0, Ty=prob.Ty or 0.0)
+                      ny=prob.ny or 0, Ty=prob.Ty or 0.0,
+                      btype=prob.btypes() if neu else None, bnormal=prob.bnormals() if neu else None)
 
 
 def footprint_for(prob, max_rhs, mask=None, refine=None, tau=1e-12, tauZ=1e-12):
@@ -54,7 +57,8 @@ def footprint_for(prob, max_rhs, mask=None, refine=None, tau=1e-12, tauZ=1e-12):
 def rhs_for(plan, prob, which=None, device=None):
     """Right-hand sides as a (nrhs, M + Mb) float64 tensor on ``device``: the
     workload's functions sampled at the plan's collocation points (and its
-    Dirichlet data at the boundary points), assembled by the library
+    boundary data: values at Dirichlet points, normal derivatives at Neumann
+    points), assembled by the library
     (azrbf_rhs), which applies the boundary value problems' row
     normalisation."""
     pts = plan.points()
@@ -65,6 +69,6 @@ def rhs_for(plan, prob, which=None, device=None):
     Gd = None
     if plan.Mb:
         bp = prob.bpoints()
-        G = np.stack([prob.bnd[i](*bp.T) for i in idx], axis=0)
+        G = np.stack([prob.bdata(i, bp) for i in idx], axis=0)
         Gd = torch.from_numpy(np.ascontiguousarray(G)).to(dev)
     return azrbf.rhs(plan, Fd, Gd)

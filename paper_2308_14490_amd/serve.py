@@ -68,6 +68,9 @@ def operator_key(prob, mask, k=0, tau=1e-12, tauZ=1e-12, refine=1):
     h.update(np.ascontiguousarray(mask, dtype=np.uint8).tobytes())
     if prob.nb:
         h.update(np.ascontiguousarray(prob.bpoints(), dtype=np.float64).tobytes())
+        if prob.has_neumann:
+            h.update(prob.btypes().tobytes())
+            h.update(np.ascontiguousarray(prob.bnormals(), dtype=np.float64).tobytes())
     return h.hexdigest()
 
 

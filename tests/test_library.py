@@ -77,6 +77,30 @@ def test_plan_rejects_bad_arguments_before_touching_the_gpu():
     assert lib.azrbf_plan(ctypes.byref(pr), None, ctypes.byref(h)) == azrbf.EUNSUPPORTED
 
 
+def test_plan_rejects_neumann_points_without_unit_normals():
+    """Neumann rows need a unit outward normal at every Neumann point; the
+    checks run on the host before any GPU call."""
+    import numpy as np
+    from paper_2308_14490_amd import azrbf
+    lib = azrbf._lib()
+    mask = np.ones(64, dtype=np.uint8)
+    bp = np.array([-1.0, 1.0])
+    h = ctypes.c_void_p()
+    for types, normals in [([1, 0], None), ([0, 1], [-1.0, 0.5]), ([2, 0], [-1.0, 1.0]),
+                           ([1, 0], [np.nan, 1.0])]:
+        pr = azrbf._Problem()
+        pr.dim, pr.n, pr.s, pr.T, pr.eps, pr.tau, pr.tauZ = 1, 32, 2, 1.0, 8.0, 1e-12, 1e-12
+        pr.op = azrbf.OP_BVP
+        pr.mask = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        pr.nb = 2
+        pr.bpts = bp.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        t = np.array(types, dtype=np.uint8)
+        pr.btype = t.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        nv = None if normals is None else np.array(normals, dtype=np.float64)
+        pr.bnormal = None if nv is None else nv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        assert lib.azrbf_plan(ctypes.byref(pr), None, ctypes.byref(h)) == azrbf.EINVAL
+
+
 def test_tune_table_round_trip_and_validation():
     """The tile-shape table is host state: loading validates every line."""
     from paper_2308_14490_amd import azrbf
