@@ -102,3 +102,49 @@ def test_helmholtz_2d_star_nonzero_source():
                      op=W.HELMHOLTZ, k2=5.0, bnd=[u], nb=base.nb, exact=[u])
     eg = _run(prob)
     assert np.all(eg < 1e-4)
+
+
+# ---------------------------------------------------------------- Neumann rows (section 6.3)
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_mixed_neumann_dirichlet_flower(n):
+    """Section 6.3's last setting with manufactured data: the multiply
+    connected flower, Helmholtz k^2 = 4, Neumann rows on the outer curve
+    (200 points) and Dirichlet rows on the circle cut out (100 points).
+    Right-hand sides, residual and error as the oracle's."""
+    eg = _run(W.config_flower(n, manufactured=True))
+    if n == 64:
+        assert np.all(eg < 1e-5)
+
+
+def test_helmholtz_ode_neumann_left_end():
+    """u = sin(kx) + x^2 with u'(-1) imposed by a Neumann row (outward normal
+    -1) and u(1) by a Dirichlet row."""
+    n = 128
+    kk = n / 5.0
+    prob = _ode(n, f=lambda x: -(2.0 + kk * kk * x * x), u=lambda x: np.sin(kk * x) + x * x)
+    prob.bc_outer = "ND"
+    prob.bnd_n = [lambda x, nx: (kk * np.cos(kk * x) + 2 * x) * nx]
+    eg = _run(prob)
+    assert np.all(eg < 1e-8)
+
+
+def test_neumann_rows_match_the_oracle_element_by_element():
+    """apply_A's boundary rows at Neumann and Dirichlet points against the
+    oracle's dense rows (flower, n = 32, eight vectors)."""
+    azrbf, problems = _mods()
+    prob = W.config_flower(32, manufactured=True)
+    p = problems.plan_for(prob)
+    A, idx, pts, bpts = dense.system_matrix(prob)
+    Xc = np.random.default_rng(11).standard_normal((8, prob.N))
+    Y = azrbf.apply_A(p, torch.from_numpy(Xc).cuda())
+    torch.cuda.synchronize()
+    got = Y.cpu().numpy().T
+    want = A @ Xc.T
+    M = idx.size
+    scale = np.abs(want).max()
+    announce("flower rows", "interior", np.abs(got[:M] - want[:M]).max(), "boundary",
+             np.abs(got[M:] - want[M:]).max(), "scale", scale)
+    assert np.abs(got[M:] - want[M:]).max() <= 1e-13 * scale
+    assert np.abs(got[:M] - want[:M]).max() <= 1e-12 * scale
+    p.destroy()

@@ -131,6 +131,20 @@ def test_apply_2d_disk_other_oversampling(n, s, nvec):
     _case(prob, nvec, ld_pad=1, engine=False)
 
 
+@pytest.mark.parametrize("n,nvec", [(16, 2), (32, 3)])
+def test_apply_2d_flower_mixed_boundary(n, nvec):
+    """The multiply connected flower of section 6.3: Neumann rows on the
+    outer curve, Dirichlet rows on the hole, Helmholtz k^2 = 4."""
+    _case(W.config_flower(n, manufactured=True), nvec, ld_pad=1, engine=False)
+
+
+def test_apply_1d_neumann_rows():
+    prob = W.Problem("ode-nd", 1, 256, 2, 1.5, W.shape_parameter_eh(1e-10), W.interval(-1.0, 1.0),
+                     [lambda x: 0 * x], op=W.HELMHOLTZ, k2=(256 / 5.0) ** 2, bnd=[lambda x: 0 * x],
+                     bnd_n=[lambda x, nx: 0 * x], nb=2, bc_outer="ND")
+    _case(prob, 2, ld_pad=0, engine=False)
+
+
 def test_apply_2d_poisson_star_s3():
     prob = W.config_c4(16)
     prob.s = 3
