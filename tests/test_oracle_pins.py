@@ -645,3 +645,14 @@ def test_mixed_bvp_1d_neumann_left_dirichlet_right():
     A, idx, pts, bpts = dense.system_matrix(p)
     b = dense.rhs(p, pts, bpts)[:, 0]
     assert _bvp_err(p, A, b, u) < 1e-8
+
+
+def test_paper_E9_flower_system_size():
+    """The invented flower has the paper's system size at the paper's
+    resolution (100 x 100 centres, 200 + 100 boundary points)."""
+    g = _golden("paper_values.json")["E9_flower_mixed"]
+    p = W.config_flower(g["n"], nb_outer=g["nb_outer"], nb_hole=g["nb_hole"])
+    idx, pts = grids.collocation(p)
+    rows = idx.size + p.nb
+    assert p.N == g["cols"]
+    assert abs(rows - g["rows"]) <= g["rows_rel_tolerance"] * g["rows"]
