@@ -656,3 +656,36 @@ def test_paper_E9_flower_system_size():
     rows = idx.size + p.nb
     assert p.N == g["cols"]
     assert abs(rows - g["rows"]) <= g["rows_rel_tolerance"] * g["rows"]
+
+
+# ---------------------------------------------------------------- centre counts that are not powers of two
+
+@pytest.mark.parametrize("n,s", [(12, 2), (15, 3), (14, 1), (20, 2)])
+def test_closed_form_diagonals_and_periodic_inverse_any_n(n, s):
+    """Lemma 4.2 and section 4.1 hold for any centre count: B's diagonals
+    equal the closed form (DFT of the sampled kernel by Poisson summation)
+    and Z* inverts the periodic matrix, for n = 12, 15, 14, 20 (the sizes the
+    mixed-radix path covers: products of 2, 3, 5 and 7)."""
+    p = W.Problem("t", 1, n, s, 1.0, 0.5, W.box(1.0), [])
+    B = periodic.block_diagonal_form(p)
+    d = periodic.diagonals(B, p.N)
+    scale = np.abs(d).max()
+    for r in range(s):
+        cf = spectra.diag_closed_form(p.n, s, p.T, p.eps, r)
+        assert np.max(np.abs(cf - d[r])) < 1e-14 * scale
+    idx = np.arange(p.n * s)
+    Z, imag = periodic.zstar(p, idx, tauZ=0.0)
+    Ac = periodic.periodic_matrix(p)
+    assert imag < 1e-12 * np.abs(Z).max()
+    assert np.max(np.abs(Z @ Ac - np.eye(p.N))) < 1e-10
+
+
+def test_zstar_2d_any_n_normal_form():
+    """2D box with 10 x 6 centres (s = 2): the literal Z* equals the normal
+    form and inverts the periodic matrix."""
+    p = W.Problem("t2", 2, 10, 2, 1.0, 0.6, W.box(1.0, 2, 0.6), [], ny=6, Ty=0.6)
+    idx = np.arange(p.N * 4)
+    Z, imag = periodic.zstar(p, idx, tauZ=0.0)
+    Zn = periodic.zstar_normal(p, idx, tauZ=0.0)
+    assert np.max(np.abs(Z - Zn)) < 1e-10 * np.abs(Zn).max()
+    assert np.max(np.abs(Z @ periodic.periodic_matrix(p) - np.eye(p.N))) < 1e-9
