@@ -129,6 +129,16 @@ int ops_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alph
 // Right-hand sides from interior data f (M x nrhs) and boundary data g (Mb x nrhs).
 int ops_rhs(const Plan& P, const double* f, int64_t ldf, const double* g, int64_t ldg, int64_t nrhs, double* B,
             int64_t ldb, hipStream_t st);
+// generic.hip: the operators for centre counts that are not powers of two
+// (n = 2^a 3^b 5^c 7^d), by mixed-radix FFTs in global memory.
+bool gfft_supported(int64_t n);
+int64_t gen_ws_bytes(int64_t N, int64_t npairs);
+// Forward DFTs of `lines` contiguous n-point lines, in -> out (tmp: scratch of the same size).
+int gfft_lines_fwd(const double2* in, double2* out, double2* tmp, int n, int64_t lines, hipStream_t st);
+int gen_apply_A(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta,
+                const double* Yin, int64_t ldyi, double* Y, int64_t ldy, hipStream_t st);
+int gen_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta, const double* Zin,
+                int64_t ldzi, double* Z, int64_t ldz, hipStream_t st);
 // Out = alpha A Z* R + beta Yin (Yin null: Yin = Out); Zs is N x nvec scratch
 // (leading dimension N), overwritten with Z* R when the plan needs it.
 int ops_apply_AZ(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta,
@@ -207,6 +217,7 @@ struct Plan {
   int64_t Mtp = 0;   // Mt rounded up to 16: leading dimension of internal row-space matrices
   int64_t ldq = 0;   // leading dimension of the factor's Q
   bool fused = false;                     // 1D single-kernel path
+  bool generic = false;                   // a centre count is not a power of two: mixed-radix path
   Geo geo{};
   const double2* tw = nullptr;            // shared twiddle table (per device)
 
@@ -244,10 +255,17 @@ struct Plan {
   double2* wsB1 = nullptr;
   double2* wsB2 = nullptr;
   int64_t wsB_pairs = 0;
+  // workspace of the mixed-radix path (three N-point buffers per pair), and its second set
+  double2* gws = nullptr;
+  int64_t gws_pairs = 0;
+  double2* gwsB = nullptr;
+  int64_t gwsB_pairs = 0;
   void swap_ws() {
     std::swap(ws1, wsB1);
     std::swap(ws2, wsB2);
     std::swap(ws_pairs, wsB_pairs);
+    std::swap(gws, gwsB);
+    std::swap(gws_pairs, gwsB_pairs);
   }
 
   // factor

@@ -25,6 +25,7 @@
 #include <string>
 
 #include "fft.h"
+#include "geo.h"
 #include "internal.h"
 
 namespace az {
@@ -57,73 +58,6 @@ int ops_init_twiddles(int device, const double2** tw) {
   return AZRBF_OK;
 }
 
-// ------------------------------------------------------------------ helpers
-
-__device__ __forceinline__ int64_t grid_index(const Geo& g, int ph, int64_t a, int64_t b) {
-  if (g.dim == 1) return (int64_t)g.s * (a * g.N2 + b) + ph;
-  const int rx = ph / g.s, ry = ph - rx * g.s;
-  return ((int64_t)g.s * a + rx) * g.L + (int64_t)g.s * b + ry;
-}
-
-// The same with the oversampling factor as a compile-time constant (S == g.s)
-// and the phase given by its coordinates (1D: rx = 0, ry = phase).
-template <int S, bool D1>
-__device__ __forceinline__ int64_t grid_index_s(const Geo& g, int rx, int ry, int64_t a, int64_t b) {
-  if constexpr (D1) return (int64_t)S * (a * g.N2 + b) + ry;
-  else return ((int64_t)S * a + rx) * g.L + (int64_t)S * b + ry;
-}
-template <bool D1>
-__device__ __forceinline__ int64_t row_of_d(const Geo& g, int64_t gi) {
-  if constexpr (D1) {
-    const int64_t r = gi - g.i0;
-    return (r >= 0 && r < g.M) ? r : -1;
-  } else {
-    return g.inv[gi];
-  }
-}
-
-__device__ __forceinline__ int64_t row_of(const Geo& g, int64_t gi) {
-  if (g.dim == 1) {
-    const int64_t r = gi - g.i0;
-    return (r >= 0 && r < g.M) ? r : -1;
-  }
-  return g.inv[gi];
-}
-
-// Unnormalised 2D spectrum of phase ph at frequency (ka, kb).
-__device__ __forceinline__ double2 spec2d(const Geo& g, int ph, int ka, int kb) {
-  const int rx = ph / g.s, ry = ph - rx * g.s;
-  const int n1 = g.N1, n2 = g.N2;
-  const double2 x0 = g.fac[rx * n1 + ka], y0 = g.facy[ry * n2 + kb];
-  if (g.op == AZRBF_OP_APPROX) return cmul(x0, y0);
-  const double2 x2 = g.fac[(g.s + rx) * n1 + ka], y2 = g.facy[(g.s + ry) * n2 + kb];
-  const double2 d00 = cmul(x0, y0);
-  double2 d = cadd(cadd(cmul(x2, y0), cmul(x0, y2)), cscale(d00, g.k2));
-  return cscale(d, g.opscale);
-}
-
-// Engine kernels know the dimension at compile time (D1: 1D); the other
-// dimension's code is then not compiled into them.
-template <bool D1>
-__device__ __forceinline__ double2 specA_d(const Geo& g, int ph, int ka, int kb) {
-  if constexpr (D1) return g.spA[(int64_t)ph * g.N + (int64_t)ka * g.N2 + kb];
-  else return cscale(spec2d(g, ph, ka, kb), 1.0 / (double)g.N);
-}
-template <bool D1>
-__device__ __forceinline__ double2 specZ_d(const Geo& g, int ph, int ka, int kb) {
-  if constexpr (D1) return g.spZ[(int64_t)ph * g.N + (int64_t)ka * g.N2 + kb];
-  else return cscale(cconj(spec2d(g, ph, ka, kb)), g.w2[(int64_t)ka * g.N2 + kb]);
-}
-
-__device__ __forceinline__ double2 specA(const Geo& g, int ph, int ka, int kb) {
-  if (g.dim == 1) return g.spA[(int64_t)ph * g.N + (int64_t)ka * g.N2 + kb];
-  return cscale(spec2d(g, ph, ka, kb), 1.0 / (double)g.N);
-}
-
-__device__ __forceinline__ double2 specZ(const Geo& g, int ph, int ka, int kb) {
-  if (g.dim == 1) return g.spZ[(int64_t)ph * g.N + (int64_t)ka * g.N2 + kb];
-  return cscale(cconj(spec2d(g, ph, ka, kb)), g.w2[(int64_t)ka * g.N2 + kb]);
-}
 
 // Y[row, v0..v0+1] = alpha * val + beta * Yin[row, v0..v0+1] (Yin unread if beta == 0;
 // Yin may equal Y).
@@ -1246,8 +1180,9 @@ int ops_apply_A(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alph
     Yin = Y;
     ldyi = ldy;
   }
-  if (P.fused) {
-    AZ_TRY(fused_A(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st));
+  if (P.fused || P.generic) {
+    if (P.generic) AZ_TRY(gen_apply_A(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st));
+    else AZ_TRY(fused_A(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st));
     return boundary_rows(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st);
   }
   const int64_t npairs = (nvec + 1) / 2;
@@ -1278,6 +1213,7 @@ int ops_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alph
     Zin = Z;
     ldzi = ldz;
   }
+  if (P.generic) return gen_apply_Z(P, R, ldr, nvec, alpha, beta, Zin, ldzi, Z, ldz, st);
   if (P.fused) return fused_Z(P, R, ldr, nvec, alpha, beta, Zin, ldzi, Z, ldz, st);
   const int64_t npairs = (nvec + 1) / 2;
   const int64_t chunk = engine_chunk(P, npairs);
@@ -1298,6 +1234,13 @@ int ops_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alph
 
 static int fft_lines_fwd(Plan& P, const double2* in, double2* out, int n, int64_t lines, bool engine,
                          hipStream_t st) {
+  if ((n & (n - 1)) != 0) {   // mixed radix (the plan's other axis may be a power of two)
+    double2* tmp = nullptr;
+    AZ_TRY(P.alloc((void**)&tmp, lines * n * (int64_t)sizeof(double2)));
+    const int rc = gfft_lines_fwd(in, out, tmp, n, lines, st);
+    P.release_one_after(tmp, st);
+    return rc;
+  }
   if (!engine) { AZ_SWITCH_N(n, launch_fused_fwd, P.tw, in, out, lines, st) }
   ColArgs c{&P, 4, nullptr, 0, in, out, 0, 0, lines, 0, 0, nullptr, 0, nullptr, 0, st};
   AZ_TRY(run_col(c));
@@ -1322,7 +1265,7 @@ int ops_spectra(Plan& P, hipStream_t st) {
                   P.T, mimg, which, which == 0 ? red : nullptr);
     AZ_HIP(hipGetLastError());
   }
-  const bool engine = P.dim == 1 && !P.fused;
+  const bool engine = P.dim == 1 && !P.fused && !P.generic;
   AZ_TRY(fft_lines_fwd(P, samp, fac, n, (int64_t)nk * s, engine, st));
   double* D = nullptr;
   AZ_TRY(P.alloc((void**)&D, P.N * sizeof(double)));
@@ -1415,7 +1358,7 @@ int ops_apply_AZ(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alp
     Yin = Out;
     ldyi = ldo;
   }
-  if (P.fused) {
+  if (P.fused || P.generic) {
     AZ_TRY(ops_apply_Z(P, R, ldr, nvec, 1.0, 0.0, nullptr, 0, Zs, P.N, st));
     return ops_apply_A(P, Zs, P.N, nvec, alpha, beta, Yin, ldyi, Out, ldo, st);
   }

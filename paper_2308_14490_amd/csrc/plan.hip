@@ -427,13 +427,16 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
   if (q.nb < 0 || (q.nb > 0 && (!q.bpts || q.op != AZRBF_OP_BVP))) return AZRBF_EINVAL;
   if (!(q.tau > 0) || q.tauZ < 0 || q.refine < 0 || q.refine > 8 || q.k < 0) return AZRBF_EINVAL;
   if (q.eps <= 0 && !(q.tau0 > 0 && q.tau0 < 1)) return AZRBF_EINVAL;
-  if (!az::pow2(q.n) || q.n < 16) return AZRBF_EUNSUPPORTED;
+  // centre counts: powers of two (the register-resident engine) or other
+  // products of 2, 3, 5 and 7 (the mixed-radix path)
+  if (!az::gfft_supported(q.n) || q.n < 16) return AZRBF_EUNSUPPORTED;
   if ((q.dim == 1 && q.n > (1 << 20)) || (q.dim == 2 && q.n > 512)) return AZRBF_EUNSUPPORTED;
   if (q.ny < 0 || q.Ty < 0 || (q.dim == 1 && (q.ny > 0 || q.Ty > 0))) return AZRBF_EINVAL;
-  if (q.dim == 2 && q.ny > 0 && (!az::pow2(q.ny) || q.ny < 16 || q.ny > 512)) return AZRBF_EUNSUPPORTED;
+  if (q.dim == 2 && q.ny > 0 && (!az::gfft_supported(q.ny) || q.ny < 16 || q.ny > 512)) return AZRBF_EUNSUPPORTED;
+  const bool generic = !az::pow2(q.n) || (q.dim == 2 && q.ny > 0 && !az::pow2(q.ny));
   // a column pass puts the s phases of a column in one block of at most 256
   // threads, n1 / 16 per phase (1D: n1 = n / 512 once n > 2^18)
-  if (q.dim == 1 && q.n > (1 << 18) && q.s * (q.n >> 9) / 16 > 256) return AZRBF_EUNSUPPORTED;
+  if (!generic && q.dim == 1 && q.n > (1 << 18) && q.s * (q.n >> 9) / 16 > 256) return AZRBF_EUNSUPPORTED;
   if (q.s < 1 || q.s > 4) return AZRBF_EUNSUPPORTED;
   bool neumann = false;
   if (q.nb > 0 && q.btype) {
@@ -460,6 +463,7 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
   P.prob.bnormal = nullptr;
   if (hipGetDevice(&P.device) != hipSuccess) { delete h; return AZRBF_EHIP; }
   P.dim = q.dim;
+  P.generic = generic;
   P.n = q.n;
   P.s = q.s;
   P.ph = q.dim == 1 ? q.s : q.s * q.s;
@@ -513,8 +517,8 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
       if (!q.mask[i]) { delete h; return AZRBF_EUNSUPPORTED; }   // 1D domains are intervals
     g.i0 = i0;
     const char* force = getenv("AZRBF_ENGINE");
-    P.fused = P.N <= 8192 && !(force && force[0] == '1' && P.N >= 256);
-    if (P.fused) {
+    P.fused = !P.generic && P.N <= 8192 && !(force && force[0] == '1' && P.N >= 256);
+    if (P.fused || P.generic) {
       g.N1 = 1;
       g.N2 = (int)P.N;
     } else {
@@ -643,7 +647,7 @@ int azrbf_apply_AZstar(azrbf_plan_t h, const double* R, int64_t ldr, int64_t nve
   if (R == Y && ldr != ldy) return AZRBF_EINVAL;
   P.last_stream = (hipStream_t)stream;
   AZ_TRY(az::plan_on_stream(P, P.last_stream));
-  if ((P.fused || P.Mb > 0) && nvec > P.azs_cols) {
+  if ((P.fused || P.generic || P.Mb > 0) && nvec > P.azs_cols) {
     // the previous scratch may still be in use by queued work on this stream
     double* old = P.azs;
     AZ_TRY(P.alloc((void**)&P.azs, sizeof(double) * P.N * nvec));
@@ -817,7 +821,11 @@ int64_t azrbf_footprint_bytes(const azrbf_problem* pr, int64_t max_rhs) {
   const int64_t pairs = (std::max<int64_t>(k, max_rhs) + 1) / 2;
   // FFT workspace; a 1D solve with k <= 64 keeps a second set for its side stream
   const int64_t wsets = pr->dim == 1 && k <= 64 ? 2 : 1;
-  if (!(pr->dim == 1 && N <= 8192)) b += wsets * 2 * ph * N * 16 * std::min<int64_t>(chunk, pairs);
+  const bool generic = !az::pow2(n) || !az::pow2(ny);
+  if (generic)
+    b += wsets * az::gen_ws_bytes(N, pairs);
+  else if (!(pr->dim == 1 && N <= 8192))
+    b += wsets * 2 * ph * N * 16 * std::min<int64_t>(chunk, pairs);
   if (k > 64) {
     b += 8 * az::wide_factor_doubles(N, Mt, k);
     b += 8 * (max_rhs * (2 * N + 3 * Mt + 2 * k + 64) + az::gemm_split_doubles(k, max_rhs, Mt, 1) + 1);

@@ -36,7 +36,7 @@ std::string engine_key(const Plan& P) {
   return b;
 }
 
-bool uses_engine(const Plan& P) { return !P.fused; }
+bool uses_engine(const Plan& P) { return !P.fused && !P.generic; }
 
 // Best of `reps` timings of apply_A (X -> Y) then apply_Z* (Y -> Z), in ms.
 int time_ops(Plan& P, const double* X, double* Y, double* Z, int64_t nvec, hipStream_t st, int reps,

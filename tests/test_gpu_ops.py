@@ -28,14 +28,17 @@ def _az():
 
 
 def _grid(prob):
-    """Rounding of the grid itself.  With s a power of two every fine-grid
-    point and centre is a binary fraction and x_i - c_j is exact on both
-    sides.  With s = 3 the points -T + i 2T/(3n) are rounded: the oracle's
-    x_i - c_j carries an error up to about 2uT, and the library samples the
-    kernel at (i - 3j) h_L with h_L rounded, so entries of the two matrices
-    differ by up to |phi'| 4uT <= 0.86 eps 4uT.  Relative to the largest
-    product entry (order one) this adds 8 eps T u."""
-    return 0.0 if prob.s & (prob.s - 1) == 0 else 8.0 * prob.eps * prob.T * U
+    """Rounding of the grid itself.  With s n a power of two (per axis) every
+    fine-grid point and centre is a binary fraction and x_i - c_j is exact on
+    both sides.  Otherwise (s = 3, or n = 100) the points -T + i 2T/(s n) are
+    rounded: the oracle's x_i - c_j carries an error up to about 2uT, and the
+    library samples the kernel at (i - s j) h_L with h_L rounded, so entries
+    of the two matrices differ by up to |phi'| 4uT <= 0.86 eps 4uT.  Relative
+    to the largest product entry (order one) this adds 8 eps T u."""
+    axes = prob.axes()
+    if all(((prob.s * n) & (prob.s * n - 1)) == 0 for n, _ in axes):
+        return 0.0
+    return 8.0 * prob.eps * max(T for _, T in axes) * U
 
 
 def _tol_A(N, prob=None):
