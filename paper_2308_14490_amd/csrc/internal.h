@@ -131,10 +131,14 @@ int ops_rhs(const Plan& P, const double* f, int64_t ldf, const double* g, int64_
             int64_t ldb, hipStream_t st);
 // generic.hip: the operators for centre counts that are not powers of two
 // (n = 2^a 3^b 5^c 7^d), by mixed-radix FFTs in global memory.
+// (n = 2^a 3^b 5^c 7^d: mixed-radix passes; other n: Bluestein's chirp
+// convolution through power-of-two passes)
 bool gfft_supported(int64_t n);
-int64_t gen_ws_bytes(int64_t N, int64_t npairs);
-// Forward DFTs of `lines` contiguous n-point lines, in -> out (tmp: scratch of the same size).
-int gfft_lines_fwd(const double2* in, double2* out, double2* tmp, int n, int64_t lines, hipStream_t st);
+int64_t gen_ws_bytes(int64_t N1, int64_t N2, int64_t npairs);
+// Bluestein tables for the plan's axes that need them (before any transform).
+int gen_tables(Plan& P, hipStream_t st);
+// Forward DFTs of `lines` contiguous n-point lines, in -> out.
+int gfft_lines_fwd(Plan& P, const double2* in, double2* out, int n, int64_t lines, hipStream_t st);
 int gen_apply_A(Plan& P, const double* X, int64_t ldx, int64_t nvec, double alpha, double beta,
                 const double* Yin, int64_t ldyi, double* Y, int64_t ldy, hipStream_t st);
 int gen_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alpha, double beta, const double* Zin,
@@ -255,7 +259,17 @@ struct Plan {
   double2* wsB1 = nullptr;
   double2* wsB2 = nullptr;
   int64_t wsB_pairs = 0;
-  // workspace of the mixed-radix path (three N-point buffers per pair), and its second set
+  // Bluestein tables of an axis whose centre count has a prime factor above
+  // 7 (mixed-radix path): M-point DFTs of the chirp filters of the forward
+  // and inverse n-point transforms, M = the power of two >= 2n - 1
+  struct BlueAxis {
+    int n = 0, M = 0;
+    double2* hf = nullptr;
+    double2* hi = nullptr;
+  };
+  BlueAxis blue[2];
+  // workspace of the mixed-radix path (three N-point buffers per pair, and
+  // the Bluestein convolutions' buffers), and its second set
   double2* gws = nullptr;
   int64_t gws_pairs = 0;
   double2* gwsB = nullptr;

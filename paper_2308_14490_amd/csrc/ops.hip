@@ -1234,13 +1234,8 @@ int ops_apply_Z(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alph
 
 static int fft_lines_fwd(Plan& P, const double2* in, double2* out, int n, int64_t lines, bool engine,
                          hipStream_t st) {
-  if ((n & (n - 1)) != 0) {   // mixed radix (the plan's other axis may be a power of two)
-    double2* tmp = nullptr;
-    AZ_TRY(P.alloc((void**)&tmp, lines * n * (int64_t)sizeof(double2)));
-    const int rc = gfft_lines_fwd(in, out, tmp, n, lines, st);
-    P.release_one_after(tmp, st);
-    return rc;
-  }
+  // mixed radix or Bluestein (the plan's other axis may be a power of two)
+  if ((n & (n - 1)) != 0) return gfft_lines_fwd(P, in, out, n, lines, st);
   if (!engine) { AZ_SWITCH_N(n, launch_fused_fwd, P.tw, in, out, lines, st) }
   ColArgs c{&P, 4, nullptr, 0, in, out, 0, 0, lines, 0, 0, nullptr, 0, nullptr, 0, st};
   AZ_TRY(run_col(c));
@@ -1260,6 +1255,7 @@ int ops_spectra(Plan& P, hipStream_t st) {
   double* red = nullptr;   // [dmax, wmax, zeroed(int)]
   AZ_TRY(P.alloc((void**)&red, 4 * sizeof(double)));
   const int64_t ns = (int64_t)n * s;
+  if (P.generic) AZ_TRY(gen_tables(P, st));
   for (int which = 0; which < nk; ++which) {
     launch_kernel(k_sample_phases, (unsigned)((ns + 255) / 256), 256, 0, st, samp + which * ns, n, s, P.hL, P.eps,
                   P.T, mimg, which, which == 0 ? red : nullptr);

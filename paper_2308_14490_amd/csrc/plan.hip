@@ -427,12 +427,12 @@ int azrbf_plan(const azrbf_problem* pr, void* stream, azrbf_plan_t* out) {
   if (q.nb < 0 || (q.nb > 0 && (!q.bpts || q.op != AZRBF_OP_BVP))) return AZRBF_EINVAL;
   if (!(q.tau > 0) || q.tauZ < 0 || q.refine < 0 || q.refine > 8 || q.k < 0) return AZRBF_EINVAL;
   if (q.eps <= 0 && !(q.tau0 > 0 && q.tau0 < 1)) return AZRBF_EINVAL;
-  // centre counts: powers of two (the register-resident engine) or other
-  // products of 2, 3, 5 and 7 (the mixed-radix path)
-  if (!az::gfft_supported(q.n) || q.n < 16) return AZRBF_EUNSUPPORTED;
+  // centre counts: powers of two (the register-resident engine) or any
+  // other count (the mixed-radix path; Bluestein for prime factors above 7)
+  if (q.n < 16) return AZRBF_EUNSUPPORTED;
   if ((q.dim == 1 && q.n > (1 << 20)) || (q.dim == 2 && q.n > 512)) return AZRBF_EUNSUPPORTED;
   if (q.ny < 0 || q.Ty < 0 || (q.dim == 1 && (q.ny > 0 || q.Ty > 0))) return AZRBF_EINVAL;
-  if (q.dim == 2 && q.ny > 0 && (!az::gfft_supported(q.ny) || q.ny < 16 || q.ny > 512)) return AZRBF_EUNSUPPORTED;
+  if (q.dim == 2 && q.ny > 0 && (q.ny < 16 || q.ny > 512)) return AZRBF_EUNSUPPORTED;
   const bool generic = !az::pow2(q.n) || (q.dim == 2 && q.ny > 0 && !az::pow2(q.ny));
   // a column pass puts the s phases of a column in one block of at most 256
   // threads, n1 / 16 per phase (1D: n1 = n / 512 once n > 2^18)
@@ -823,7 +823,7 @@ int64_t azrbf_footprint_bytes(const azrbf_problem* pr, int64_t max_rhs) {
   const int64_t wsets = pr->dim == 1 && k <= 64 ? 2 : 1;
   const bool generic = !az::pow2(n) || !az::pow2(ny);
   if (generic)
-    b += wsets * az::gen_ws_bytes(N, pairs);
+    b += wsets * az::gen_ws_bytes(pr->dim == 1 ? 1 : n, pr->dim == 1 ? N : ny, pairs);
   else if (!(pr->dim == 1 && N <= 8192))
     b += wsets * 2 * ph * N * 16 * std::min<int64_t>(chunk, pairs);
   if (k > 64) {

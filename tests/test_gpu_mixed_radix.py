@@ -1,5 +1,6 @@
 """Centre counts that are not powers of two (the mixed-radix path: radices
-2, 3, 4, 5, 7 in global memory).  Operator parity against the oracle's dense
+2, 3, 4, 5, 7 in global memory; counts with a larger prime factor through
+Bluestein's chirp convolution).  Operator parity against the oracle's dense
 matrices with the same tolerances as the power-of-two engine (a mixed-radix
 transform of length N carries a rounding error of the same order, a few u per
 pass), and solves of the paper's own sizes: the ellipse of section 5.4 at
@@ -27,7 +28,8 @@ def _mods():
 
 
 @pytest.mark.parametrize("n,s,nvec", [(100, 2, 3), (96, 3, 2), (1000, 2, 3), (2187, 2, 2), (2401, 1, 1),
-                                      (3125, 3, 2), (6000, 2, 1)])
+                                      (3125, 3, 2), (6000, 2, 1), (101, 2, 3), (1031, 3, 2), (4099, 2, 1),
+                                      (2 * 11 * 13 * 3, 2, 2)])
 def test_apply_1d_mixed_radix(n, s, nvec):
     prob = W.config_c1a(n)
     prob.s = s
@@ -35,7 +37,8 @@ def test_apply_1d_mixed_radix(n, s, nvec):
     _case(prob, nvec, ld_pad=1 if nvec > 1 else 0, engine=False)
 
 
-@pytest.mark.parametrize("n,ny,nvec", [(20, 20, 2), (48, 48, 3), (60, 30, 2)])
+@pytest.mark.parametrize("n,ny,nvec", [(20, 20, 2), (48, 48, 3), (60, 30, 2), (22, 26, 2), (97, 64, 1),
+                                       (53, 51, 2)])
 def test_apply_2d_disk_mixed_radix(n, ny, nvec):
     prob = W.config_c3a(n)
     if ny != n:
@@ -98,7 +101,7 @@ def test_paper_E6_ellipse_at_the_paper_size():
     p.destroy()
 
 
-@pytest.mark.parametrize("n", [100, 300])
+@pytest.mark.parametrize("n", [100, 300, 101, 509])
 def test_periodic_1d_at_sizes_that_are_not_powers_of_two(n):
     """f = sin([N/5] pi x) on the periodic box, s = 3, tau0 = 1e-10 (section
     3.3's first experiment): maximum error below 1e-12, as printed."""

@@ -61,8 +61,8 @@ def test_plan_rejects_bad_arguments_before_touching_the_gpu():
     lib = azrbf._lib()
     mask = np.ones(64, dtype=np.uint8)
     h = ctypes.c_void_p()
-    # n = 22 = 2 x 11: a prime factor above 7 (the mixed-radix path takes 2, 3, 5, 7)
-    for field, val, code in [("n", 22, azrbf.EUNSUPPORTED), ("n", 26, azrbf.EUNSUPPORTED), ("s", 5, azrbf.EUNSUPPORTED),
+    # any count from 16 on is planned (powers of two, mixed radix, Bluestein); below 16 is not
+    for field, val, code in [("n", 8, azrbf.EUNSUPPORTED), ("n", 15, azrbf.EUNSUPPORTED), ("s", 5, azrbf.EUNSUPPORTED),
                              ("dim", 3, azrbf.EINVAL), ("tau", 0.0, azrbf.EINVAL),
                              ("n", 1 << 21, azrbf.EUNSUPPORTED)]:
         pr = azrbf._Problem()
