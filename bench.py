@@ -340,6 +340,66 @@ def million_1d(log_fn, n=1 << 20, nrhs=64):
     return out
 
 
+def transform_paths(log_fn, nvec=64):
+    """apply_A followed by apply_Z* on nvec vectors at about a million
+    centres through the three transform paths: the power-of-two engine
+    (N = 2^20), mixed radix (N = 10^6 = 2^6 5^6) and Bluestein (N = 999983,
+    a prime), ms per pair of applications (best of three)."""
+    import torch
+    import workloads as W
+    from paper_2308_14490_amd import azrbf, problems
+    out = {"workload": f"apply_A then apply_Zstar on {nvec} vectors, 1D family, s=2"}
+    for name, n in (("engine_2^20", 1 << 20), ("mixed_radix_10^6", 10 ** 6), ("bluestein_999983", 999983)):
+        p = problems.plan_for(W.family_1d(n, 1))
+        X = azrbf.gaussian(3, p.N, nvec)
+        Y = azrbf.apply_A(p, X)
+        Z = azrbf.apply_Zstar(p, Y)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(3):
+            t0 = time.perf_counter()
+            azrbf.apply_A(p, X, Y)
+            azrbf.apply_Zstar(p, Y, Z)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        out[name] = {"N": n, "ms": round(best * 1e3, 2)}
+        p.destroy()
+        del X, Y, Z
+    azrbf.release_cached_memory()
+    log_fn("transform paths: " + ", ".join(f"{k} {v['ms']} ms" for k, v in out.items() if isinstance(v, dict)))
+    return out
+
+
+def flower_paper_size(log_fn):
+    """Section 6.3's last experiment at the paper's size: Helmholtz on the
+    flower with a hole, 100 x 100 centres (mixed radix), 200 Neumann and 100
+    Dirichlet points, the paper's source and homogeneous data: plan + factor
+    + solve time (the paper's Matlab AZ took 87 s on a laptop)."""
+    import torch
+    import workloads as W
+    from paper_2308_14490_amd import azrbf, problems
+    prob = W.config_flower(100)
+    p = problems.plan_for(prob)
+    B = problems.rhs_for(p, prob)
+    torch.cuda.synchronize()
+    p.destroy()
+    t0 = time.perf_counter()
+    p = problems.plan_for(prob)
+    X, rel = azrbf.solve(p, B)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    inf = p.info()
+    out = {"workload": f"flower r=0.69+0.1cos5t minus a circle of radius 0.1, 100x100 centres, s=2, "
+                       f"M={inf['M']}, Mb={inf['Mb']} (200 Neumann, 100 Dirichlet), Helmholtz k^2=4",
+           "rows": inf["M"] + inf["Mb"], "cols": inf["N"], "k": inf["k"], "rank": inf["rank"],
+           "plan_factor_solve_s": round(dt, 3), "relres": float(rel.max()),
+           "coef_norm": float(X.norm())}
+    p.destroy()
+    azrbf.release_cached_memory()
+    log_fn(f"flower 100x100: {out['plan_factor_solve_s']} s, relres {out['relres']:.2e}")
+    return out
+
+
 def copies_1d(log_fn, copies=4096, plain=64):
     """The 256-centre 1D problem (eps*h = 0.5, f = e^x sin 7x + x^2) solved for
     `copies` right-hand sides at once on one plan (one launch sequence for all
@@ -577,9 +637,12 @@ def main():
     out["fft_passes_beyond_cache"] = beyond_cache(log)
     out["copies_1d_n256"] = copies_1d(log)
     out["million_1d"] = million_1d(log)
+    out["million_1d_exact"] = million_1d(log, n=10 ** 6)
+    out["transform_paths"] = transform_paths(log)
     if not args.no_2d:
         out["wide_2d"] = wide_2d(log)
         out["poisson_2d_n256"] = bvp_2d(log)
+        out["flower_paper_size"] = flower_paper_size(log)
     if not args.no_cpu_baseline:
         log(f"cpu baseline (oracle) at N={args.cpu_n}")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.nrhs)

@@ -13,7 +13,8 @@ eps*h = 1), c4_96 and c4_128 (Poisson star, weak Dirichlet rows),
 ellipse128x64 (the ellipse x^2 + 4 y^2 <= 1 on the anisotropic box
 [-1.4, 1.4] x [-0.7, 0.7], 128 x 64 centres), flower128 (the multiply
 connected flower of section 6.3 with a manufactured solution: Helmholtz
-k^2 = 4, Neumann data on the outer curve, Dirichlet data on the hole).  Each case
+k^2 = 4, Neumann data on the outer curve, Dirichlet data on the hole),
+flower100 (the same at the paper's 100 x 100 centres).  Each case
 is written as soon as it finishes, so a long run can be resumed by naming the
 remaining cases.  The test-set error uses the 200 x 200 cell-centred lattice
 restricted to the domain, as the full-size GPU tests do.
@@ -39,6 +40,7 @@ M2D = 200
 CASES = {
     "ellipse128x64": lambda: W.config_ellipse(128, 64),
     "flower128": lambda: W.config_flower(128, manufactured=True),
+    "flower100": lambda: W.config_flower(100, manufactured=True),
     "c3a128": lambda: W.config_c3a(128),
     "c3_128": lambda: W.config_c3(128),
     "c4_96": lambda: W.config_c4(96),

@@ -247,6 +247,44 @@ def test_fullsize_1d_solve_at_a_million():
     p.destroy()
 
 
+def test_fullsize_1d_solve_at_exactly_a_million():
+    """N = 10^6 = 2^6 5^6 (the size of the paper's claim in section 3.3),
+    through the mixed-radix path: residual <= 1e-10 over every row by the
+    local evaluator, equal to the library's, and the test-set error within
+    10x the dense oracle's at N = 4096."""
+    prob = W.family_1d(10 ** 6, 4)
+    announce("1D 10^6", prob.N)
+    p, B, X, rel = _solve(prob)
+    rc = _cpu_residual(prob, p, X, B)
+    ro, eo = _oracle_levels(W.family_1d(4096, 4))
+    eg = _cpu_maxerr(prob, X)
+    announce("rank", p.info()["rank"], "relres gpu", rel, "cpu", rc, "oracle@4096", ro, "maxerr", eg, eo)
+    assert np.all(rc <= 1e-10)
+    assert np.allclose(rc, rel, rtol=1e-2, atol=1e-16)
+    assert np.all(rc <= 10 * ro + 1e-15)
+    assert np.all(eg <= 10 * eo + 1e-15)
+    p.destroy()
+
+
+def test_fullsize_flower_at_the_paper_size():
+    """The flower of section 6.3 at the paper's 100 x 100 centres (mixed
+    radix) with 200 Neumann and 100 Dirichlet rows, manufactured data,
+    against the dense oracle at the same size."""
+    prob = W.config_flower(100, manufactured=True)
+    p, B, X, rel = _solve(prob)
+    rc = _cpu_residual(prob, p, X, B)
+    ro, eo, ref = _golden("flower100")
+    assert ref["M"] == p.M and ref["Mb"] == p.Mb
+    eg = _cpu_maxerr(prob, X)
+    announce("flower 100", "k", p.info()["k"], "rank", p.info()["rank"], "relres gpu", rel, "cpu", rc,
+             "oracle", ro, "maxerr", eg, "oracle", eo)
+    assert np.all(rc <= 1e-10)
+    assert np.allclose(rc, rel, rtol=1e-2, atol=1e-16)
+    assert np.all(rc <= 10 * ro)
+    assert np.all(eg <= 10 * eo)
+    p.destroy()
+
+
 def test_fullsize_2d_ellipse_anisotropic():
     """The ellipse x^2 + 4 y^2 <= 1 on the anisotropic box [-1.4, 1.4] x
     [-0.7, 0.7] with 128 x 64 centres (section 5.4's experiment at powers of
