@@ -500,7 +500,7 @@ def main():
         azrbf.tune_load_file(tune_file)
         p0.destroy()
         p0 = problems.plan_for(prob)
-        key = next(iter(azrbf.tune_table()), None)
+        key = next((kk for kk in azrbf.tune_table() if kk.startswith("e")), None)
         tuned = {"engine": True, "source": os.path.relpath(tune_file, ROOT), "key": key}
         if key:
             tuned.update(dict(zip(("C", "L", "chunk"), azrbf.tune_table()[key])))

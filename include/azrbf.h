@@ -274,14 +274,19 @@ int azrbf_dgemm_noalloc(int32_t transa, int32_t transb, int64_t m, int64_t n, in
  * shapes (columns per block of the column passes, rows per block of the row
  * passes, vector pairs per launch), keeps the fastest in the plan and in a
  * process-wide table from which later plans of the same engine shape start.
+ * Then the TSQR tile of the low-rank stage (section 3.2.3): the rows one
+ * block QR holds (256, 512, 1024 or 2048, as registers allow for the width),
+ * timed on the whole TSQR of an (M + Mb) x k Gaussian matrix (k the sketch
+ * width, or the 64-column panels of wider sketches), kept the same way.
  * Synchronises the stream.  report (len bytes, may be NULL) receives a JSON
- * object with the choice and every trial's time ({"engine": false} when the
- * plan uses the single-kernel path).  Errors: EINVAL (nvec <= 0, report too
- * small), ENOMEM, EHIP. */
+ * object with the choices and every trial's time ({"engine": false} when the
+ * plan uses the single-kernel path; "tsqr": the TSQR trials).  Errors:
+ * EINVAL (nvec <= 0, report too small), ENOMEM, EHIP. */
 int azrbf_autotune(azrbf_plan_t plan, int64_t nvec, void* stream, char* report, int64_t len);
 
-/* The process-wide tile-shape table as text, one engine shape per line:
- * "e<dim>_<N1>x<N2>_s<s> <C> <rows> <pairs>"; and loading such text (e.g. saved
+/* The process-wide tile-shape table as text, one shape per line: engine
+ * shapes "e<dim>_<N1>x<N2>_s<s> <C> <rows> <pairs>", TSQR tiles
+ * "t<k>_<rows of the matrix> <rows per block> 0 0"; and loading such text (e.g. saved
  * from an earlier process).  Loading validates every line (EINVAL on a
  * malformed or out-of-range entry) and affects plans created afterwards. */
 int azrbf_tune_table(char* buf, int64_t len);

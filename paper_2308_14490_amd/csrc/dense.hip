@@ -69,10 +69,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // ------------------------------------------------------------------ TSQR
 
-// TSQR blocks (the block QR kernel lives in tsqr.hip) hold RB = 16384 / k
-// rows; the Q formation below uses the same row blocking.
+// TSQR blocks (the block QR kernel lives in tsqr.hip) hold RB rows (a tile
+// shape: 16384 / k by default, or the autotuner's); the Q formation below
+// uses the same row blocking.
 constexpr int TSQR_THREADS = 256;
-__host__ __device__ constexpr int tsqr_rows(int k) { return 16384 / k; }
 
 // E_b = H_0 ... H_{k-1} [C_b; 0] = [C_b; 0] - V (T (V_top^T C_b)) for block b
 // (compact WY; V_top = the block's first k reflector rows, unit lower
@@ -83,7 +83,7 @@ __host__ __device__ constexpr int tsqr_rows(int k) { return 16384 / k; }
 template <int K>
 __global__ void __launch_bounds__(TSQR_THREADS)
 k_tsqr_formq(const double* __restrict__ V, int64_t ldv, const double* __restrict__ Tin, int64_t m,
-             const double* __restrict__ Cup, int64_t ldc, double* __restrict__ E, int64_t lde) {
+             const double* __restrict__ Cup, int64_t ldc, double* __restrict__ E, int64_t lde, int RB) {
   constexpr int LD = K + 1;
   constexpr int PER = K * K / TSQR_THREADS > 0 ? K * K / TSQR_THREADS : 1;   // outputs per thread
   __shared__ double Cb[K * LD];      // C_b[l][c] at c * LD + l
@@ -91,7 +91,6 @@ k_tsqr_formq(const double* __restrict__ V, int64_t ldv, const double* __restrict
   __shared__ double Tm[K * LD];      // T[i][l] at l * LD + i
   __shared__ double Xs[K * LD];      // X = V_top^T C_b, X[l][c] at c * LD + l
   double* Mr = Vt;                   // M = T X, row-major (M[l][c] at l * K + c), over V_top once used
-  const int RB = tsqr_rows(K);
   const int t = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * RB;
   const double* Tb = Tin + (int64_t)blockIdx.x * K * K;
@@ -189,10 +188,9 @@ struct TsqrLevel {
   double* R;     // stacked R factors (nb*k x k): the next level's input
 };
 
-static void tsqr_plan(int64_t m, int k, std::vector<TsqrLevel>& lv, int64_t* scratch_doubles,
+static void tsqr_plan(int64_t m, int k, int RB, std::vector<TsqrLevel>& lv, int64_t* scratch_doubles,
                       int64_t* e_doubles) {
   lv.clear();
-  const int RB = tsqr_rows(k);
   int64_t mm = m, tot = 0, emax = 0;
   while (true) {
     TsqrLevel L{};
@@ -208,10 +206,12 @@ static void tsqr_plan(int64_t m, int k, std::vector<TsqrLevel>& lv, int64_t* scr
   *e_doubles = emax;
 }
 
+// Scratch for every tile shape: the smallest blocks (256 rows) make the
+// most of them.
 static int64_t tsqr_scratch_doubles(int64_t m, int k) {
   std::vector<TsqrLevel> lv;
   int64_t s, e;
-  tsqr_plan(m, k, lv, &s, &e);
+  tsqr_plan(m, k, 256, lv, &s, &e);
   return s + 2 * e;
 }
 
@@ -222,11 +222,12 @@ __global__ void k_copy_doubles(const double* __restrict__ a, double* __restrict_
 
 // W (m x k, leading dimension ld) is destroyed (level-0 reflectors); Q (m x k,
 // ld) and R (k x k, ld k) out.
-static int tsqr(double* W, int64_t m, int64_t ld, int k, double* scratch, double* Q, double* R, hipStream_t st,
-                hipEvent_t r_ready = nullptr) {
+static int tsqr(double* W, int64_t m, int64_t ld, int k, int rb, double* scratch, double* Q, double* R,
+                hipStream_t st, hipEvent_t r_ready = nullptr) {
+  if (!tsqr_rows_ok(k, rb)) return AZRBF_EUNSUPPORTED;
   std::vector<TsqrLevel> lv;
   int64_t sd, ed;
-  tsqr_plan(m, k, lv, &sd, &ed);
+  tsqr_plan(m, k, rb, lv, &sd, &ed);
   double* p = scratch;
   for (size_t l = 0; l < lv.size(); ++l) {
     lv[l].tau = p;             // T factors, nb x (k x k)
@@ -240,7 +241,7 @@ static int tsqr(double* W, int64_t m, int64_t ld, int k, double* scratch, double
     const TsqrLevel& L = lv[l];
     Prof pr(l == 0 ? "tsqr_block" : "tsqr_block (tree)", 16.0 * L.m * k + 8.0 * L.nb * k * (k + 1), st);
     const int64_t lda = l == 0 ? ld : L.m;
-    AZ_TRY(tsqr_block_qr(L.A, lda, L.m, k, L.R, L.nb * k, L.A, lda, L.tau, st));
+    AZ_TRY(tsqr_block_qr(L.A, lda, L.m, k, rb, L.R, L.nb * k, L.A, lda, L.tau, st));
   }
   // (a kernel rather than a runtime copy: a launch does not block the host)
   launch_kernel(k_copy_doubles, (unsigned)((k * k + 255) / 256), 256, 0, st, lv.back().R, R, (int64_t)k * k);
@@ -254,7 +255,7 @@ static int tsqr(double* W, int64_t m, int64_t ld, int k, double* scratch, double
     const int64_t lda = l == 0 ? ld : L.m;
     Prof pr(l == 0 ? "tsqr_formq" : "tsqr_formq (tree)", 16.0 * L.m * k + 8.0 * L.nb * k * (k + 1), st);
     auto formq = k == 16 ? k_tsqr_formq<16> : k == 32 ? k_tsqr_formq<32> : k_tsqr_formq<64>;
-    launch_kernel(formq, (unsigned)L.nb, TSQR_THREADS, 0, st, L.A, lda, L.tau, L.m, up, ldup, E, lda);
+    launch_kernel(formq, (unsigned)L.nb, TSQR_THREADS, 0, st, L.A, lda, L.tau, L.m, up, ldup, E, lda, rb);
     AZ_HIP(hipGetLastError());
     up = E;
     ldup = L.m;
@@ -263,8 +264,14 @@ static int tsqr(double* W, int64_t m, int64_t ld, int k, double* scratch, double
 }
 
 int64_t tsqr_scratch(int64_t m, int k) { return tsqr_scratch_doubles(m, k); }
-int tsqr_panel(double* W, int64_t m, int k, double* scratch, double* Q, double* R, hipStream_t st) {
-  return tsqr(W, m, m, k, scratch, Q, R, st);
+int tsqr_panel(double* W, int64_t m, int k, int rb, double* scratch, double* Q, double* R, hipStream_t st) {
+  return tsqr(W, m, m, k, rb, scratch, Q, R, st);
+}
+
+int plan_tsqr_rows(const Plan& P, int k) {
+  const int slot = k == 16 ? 0 : k == 32 ? 1 : 2;
+  const int rb = P.tsqr_rb[slot];
+  return rb > 0 && tsqr_rows_ok(k, rb) ? rb : tsqr_block_rows(k);
 }
 
 // ------------------------------------------------------------------ Jacobi SVD
@@ -540,25 +547,34 @@ int launch_jacobi(const double* R, int k, double tau_k, const double* dmax, doub
 // ------------------------------------------------------------------ skinny GEMMs
 
 // Out = alpha * A B + beta * Cin; A is m x k (ld lda), B is k x ncol (ld ldb,
-// small), Out/Cin m x ncol.  Each thread owns one row and up to NC columns;
-// B is staged in LDS with the columns of one reduction index contiguous.
-// (NC = 16 is the default: more blocks in flight beat streaming A once with
-// 64 accumulators per thread, measured on the 65536 x 32 by 32 x 64 case.)
-// Out may alias Cin (each element is read and written by the same thread).
-template <int NC>
+// small), Out/Cin m x ncol.  A block of 256 threads takes 256 / G rows and
+// G groups of NC columns: thread t owns row t mod (256 / G) and the NC
+// columns of group t / (256 / G).  The G groups of one block read the same
+// rows of A, so A comes from HBM once (a group per block would re-read it
+// from a later block); B is staged in LDS with the columns of one reduction
+// index contiguous.  Out may alias Cin (each element is read and written by
+// the same thread).
+template <int NC, int G>
 __global__ void __launch_bounds__(256)
 k_gemm_nn(const double* __restrict__ A, int64_t lda, int64_t m, int k, const double* __restrict__ B, int64_t ldb,
           int64_t ncol, double alpha, const double* Cin, int64_t ldci, double beta, double* Out, int64_t ldo) {
-  __shared__ double bs[KMAX * NC];   // bs[c * NC + v] = B(c, v0 + v)
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t v0 = (int64_t)blockIdx.y * NC;
-  const int nv = (int)std::min<int64_t>(NC, ncol - v0);
-  for (int e = threadIdx.x; e < k * NC; e += blockDim.x) {
+  constexpr int RB = 256 / G;        // rows per block
+  constexpr int W = G * NC;          // columns per block
+  __shared__ double bs[KMAX * W];    // bs[c * W + v] = B(c, vb + v)
+  const int t = threadIdx.x;
+  const int64_t vb = (int64_t)blockIdx.y * W;
+  const int nvb = (int)std::min<int64_t>(W, ncol - vb);
+  for (int e = t; e < k * W; e += 256) {
     const int c = e % k, v = e / k;
-    bs[c * NC + v] = v < nv ? B[c + ldb * (v0 + v)] : 0.0;
+    bs[c * W + v] = v < nvb ? B[c + ldb * (vb + v)] : 0.0;
   }
   __syncthreads();
-  if (i >= m) return;
+  const int cg = t / RB;
+  const int64_t i = (int64_t)blockIdx.x * RB + (t % RB);
+  const int64_t v0 = vb + (int64_t)cg * NC;
+  const int nv = (int)std::min<int64_t>(NC, ncol - v0);
+  if (i >= m || nv <= 0) return;
+  const double* bg = bs + cg * NC;
   double acc[NC];
 #pragma unroll
   for (int v = 0; v < NC; ++v) acc[v] = 0.0;
@@ -569,7 +585,7 @@ k_gemm_nn(const double* __restrict__ A, int64_t lda, int64_t m, int k, const dou
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int v = 0; v < NC; ++v) acc[v] = fma(a[u], bs[(c + u) * NC + v], acc[v]);
+      for (int v = 0; v < NC; ++v) acc[v] = fma(a[u], bg[(c + u) * W + v], acc[v]);
   }
 #pragma unroll
   for (int v = 0; v < NC; ++v) {
@@ -692,17 +708,17 @@ static int gemm_nn(const double* A, int64_t lda, int64_t m, int k, const double*
                    double alpha, const double* Cin, int64_t ldci, double beta, double* Out, int64_t ldo,
                    hipStream_t st) {
   if (m <= 0 || ncol <= 0) return AZRBF_OK;
-#ifndef AZ_NN_NCMAX
-#define AZ_NN_NCMAX 16
-#endif
-  const int nc = ncol > 32 && AZ_NN_NCMAX >= 64 ? 64 : ncol > 16 && AZ_NN_NCMAX >= 32 ? 32 : 16;
-  const dim3 grid((unsigned)((m + 255) / 256), (unsigned)((ncol + nc - 1) / nc));
+  // column groups of 16 per block: up to four (64 columns), so that the
+  // groups sharing rows of A run in one block
+  const int G = ncol > 32 ? 4 : ncol > 16 ? 2 : 1;
+  const int W = 16 * G, RB = 256 / G;
+  const dim3 grid((unsigned)((m + RB - 1) / RB), (unsigned)((ncol + W - 1) / W));
   Prof pr("gemm_nn", 8.0 * m * (k + ncol * (beta != 0.0 ? 2.0 : 1.0)), st);
-  if (nc == 64) launch_kernel(k_gemm_nn<64>, grid, 256, 0, st, A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta,
-                              Out, ldo);
-  else if (nc == 32) launch_kernel(k_gemm_nn<32>, grid, 256, 0, st, A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci,
-                                   beta, Out, ldo);
-  else launch_kernel(k_gemm_nn<16>, grid, 256, 0, st, A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta, Out, ldo);
+  if (G == 4) launch_kernel(k_gemm_nn<16, 4>, grid, 256, 0, st, A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta,
+                           Out, ldo);
+  else if (G == 2) launch_kernel(k_gemm_nn<16, 2>, grid, 256, 0, st, A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci,
+                                 beta, Out, ldo);
+  else launch_kernel(k_gemm_nn<16, 1>, grid, 256, 0, st, A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta, Out, ldo);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
@@ -780,7 +796,7 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch, const
   } else {
     js = st;
   }
-  int rc = tsqr(W, Mt, Ld, k, tq, P.Q, P.Rf, st, js != st ? eR : nullptr);
+  int rc = tsqr(W, Mt, Ld, k, plan_tsqr_rows(P, k), tq, P.Q, P.Rf, st, js != st ? eR : nullptr);
   if (!rc && js != st && hipStreamWaitEvent(js, eR, 0) != hipSuccess) rc = AZRBF_EHIP;
   if (!rc) {
     Prof pj("jacobi", 8.0 * 3 * k * k, js);

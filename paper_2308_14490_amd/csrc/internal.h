@@ -152,8 +152,11 @@ int ops_apply_AZ(Plan& P, const double* R, int64_t ldr, int64_t nvec, double alp
 // 64}, RB = tsqr_block_rows(k)); R factors stacked at rows b*k of R, the
 // reflectors over A's rows into V (may equal A), compact-WY T factors at
 // T + b*k*k.
+// RB: rows per block, the tile shape (tsqr_block_rows(k) by default; the
+// autotuner picks among those tsqr_rows_ok accepts).
 int tsqr_block_rows(int k);
-int tsqr_block_qr(const double* A, int64_t lda, int64_t m, int k, double* R, int64_t ldr, double* V,
+bool tsqr_rows_ok(int k, int rb);
+int tsqr_block_qr(const double* A, int64_t lda, int64_t m, int k, int rb, double* R, int64_t ldr, double* V,
                   int64_t ldv, double* T, hipStream_t st);
 
 // gemm.hip: C = alpha op(A) op(B) + beta C on the FP64 matrix cores, batch
@@ -173,7 +176,13 @@ int gemm_mfma_c(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
 int dense_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* dst, int64_t ld, hipStream_t st);
 // Householder TSQR of W (m x k, ld m, destroyed): Q (m x k, ld m), R (k x k, ld k)
 int64_t tsqr_scratch(int64_t m, int k);
-int tsqr_panel(double* W, int64_t m, int k, double* scratch, double* Q, double* R, hipStream_t st);
+int tsqr_panel(double* W, int64_t m, int k, int rb, double* scratch, double* Q, double* R, hipStream_t st);
+// The plan's TSQR tile (rows per block) for width k: the tuned one for
+// (k, Mt), else the default.
+int plan_tsqr_rows(const Plan& P, int k);
+// Time the TSQR (block QR tree and Q formation) of an m x k matrix for every
+// tile shape and keep the fastest (tune.hip).
+int tune_tsqr(Plan& P, int k, hipStream_t st, std::string* report);
 // relres[c] = ||R(:, c)|| / ||B(:, c)|| over m rows; nrm holds 2 relres_chunks() x ncol
 int relres_chunks();
 int relres_norms(const double* R, int64_t ldr, const double* B, int64_t ldb, int64_t m, int64_t ncol,
@@ -251,6 +260,8 @@ struct Plan {
   // engine tile shapes (0: defaults): columns per block of the column
   // passes, rows per block of the row passes, vector pairs per chunk
   int tune_C = 0, tune_L = 0, tune_chunk = 0;
+  // TSQR tile shapes (rows per block) for widths 16, 32, 64 (0: default)
+  int tsqr_rb[3] = {0, 0, 0};
 
   // FFT-engine workspace, and a second set for work queued on a side stream
   double2* ws1 = nullptr;

@@ -875,9 +875,14 @@ int azrbf_autotune(azrbf_plan_t h, int64_t nvec, void* stream, char* report, int
   Plan& P = h->p;
   P.last_stream = (hipStream_t)stream;
   AZ_TRY(az::plan_on_stream(P, P.last_stream));
-  std::string rep;
-  const int rc = az::tune_plan(P, nvec, (hipStream_t)stream, &rep);
+  std::string rep, trep;
+  int rc = az::tune_plan(P, nvec, (hipStream_t)stream, &rep);
   if (rc) return rc;
+  // the TSQR tile of the low-rank stage: the plan's sketch width, or the
+  // 64-column panels of the wide stage
+  rc = az::tune_tsqr(P, P.k <= 64 ? P.k : 64, (hipStream_t)stream, &trep);
+  if (rc) return rc;
+  if (!trep.empty()) rep = rep.substr(0, rep.size() - 1) + ", \"tsqr\": " + trep + "}";
   if (report && len > 0) {
     if ((int64_t)rep.size() + 1 > len) return AZRBF_EINVAL;
     memcpy(report, rep.c_str(), rep.size() + 1);

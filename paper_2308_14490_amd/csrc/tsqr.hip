@@ -21,9 +21,11 @@ namespace az {
 
 namespace {
 
-template <int K>
+// RPT rows per thread (the block's tile shape, picked by the autotuner among
+// the shapes whose K RPT doubles fit the registers; 64 / K by default).
+template <int K, int RPT_>
 struct RegQR {
-  static constexpr int RPT = 64 / K;   // rows per thread
+  static constexpr int RPT = RPT_;     // rows per thread
   static constexpr int RB = 256 * RPT; // rows per block
 };
 
@@ -164,10 +166,9 @@ struct QrShared {
 };
 
 // Column J of the sweep (J static, so every register index is static).
-template <int K, int J>
-__device__ __forceinline__ void qr_column(double (&a)[RegQR<K>::RPT][K], const QrShared<K>& sh, int t,
+template <int K, int RPT, int J>
+__device__ __forceinline__ void qr_column(double (&a)[RPT][K], const QrShared<K>& sh, int t,
                                           int lane, int wave, int col, bool writer) {
-  constexpr int RPT = RegQR<K>::RPT;
   double p[K];
 #pragma unroll
   for (int c = 0; c < K; ++c) p[c] = 0.0;
@@ -227,11 +228,11 @@ __device__ __forceinline__ void qr_column(double (&a)[RegQR<K>::RPT][K], const Q
   }
 }
 
-template <int K, int... J>
-__device__ __forceinline__ void qr_columns(double (&a)[RegQR<K>::RPT][K], const QrShared<K>& sh, int t,
+template <int K, int RPT, int... J>
+__device__ __forceinline__ void qr_columns(double (&a)[RPT][K], const QrShared<K>& sh, int t,
                                            int lane, int wave, int col, bool writer,
                                            std::integer_sequence<int, J...>) {
-  (qr_column<K, J>(a, sh, t, lane, wave, col, writer), ...);
+  (qr_column<K, RPT, J>(a, sh, t, lane, wave, col, writer), ...);
 }
 
 // One block of RB rows: R (upper k x k) to rows b*k.. of Rout, the
@@ -239,11 +240,11 @@ __device__ __forceinline__ void qr_columns(double (&a)[RegQR<K>::RPT][K], const 
 // compact-WY T (k x k, column-major) to Tout + b*k*k, so that
 // H_0 ... H_{k-1} = I - V T V^T.  Rows >= m are read as zero and not
 // written.  A and V may be the same array.
-template <int K>
+template <int K, int RPT>
 __global__ void __launch_bounds__(256)
 k_tsqr_reg(const double* A, int64_t lda, int64_t m, double* __restrict__ Rout, int64_t ldr, double* V,
            int64_t ldv, double* __restrict__ Tout) {
-  using C = RegQR<K>;
+  using C = RegQR<K, RPT>;
   __shared__ double red[4][K];    // per-wave column sums
   __shared__ double rowj[K];      // the pivot row
   __shared__ double wv[K];        // tau_j v_j^T a_c, c > j
@@ -311,11 +312,12 @@ k_tsqr_reg(const double* A, int64_t lda, int64_t m, double* __restrict__ Rout, i
   }
 }
 
-template <int K>
+template <int K, int RPT>
 int launch_reg(const double* A, int64_t lda, int64_t m, double* R, int64_t ldr, double* V, int64_t ldv,
                double* T, hipStream_t st) {
-  const int64_t nb = (m + RegQR<K>::RB - 1) / RegQR<K>::RB;
-  launch_kernel(k_tsqr_reg<K>, (unsigned)nb, 256, 0, st, A, lda, m, R, ldr, V, ldv, T);
+  constexpr int RB = RegQR<K, RPT>::RB;
+  const int64_t nb = (m + RB - 1) / RB;
+  launch_kernel(k_tsqr_reg<K, RPT>, (unsigned)nb, 256, 0, st, A, lda, m, R, ldr, V, ldv, T);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
@@ -323,13 +325,29 @@ int launch_reg(const double* A, int64_t lda, int64_t m, double* R, int64_t ldr, 
 
 int tsqr_block_rows(int k) { return 16384 / k; }
 
-int tsqr_block_qr(const double* A, int64_t lda, int64_t m, int k, double* R, int64_t ldr, double* V,
+// Tile shapes: RB = 256 RPT rows per block, K RPT <= 128 doubles per thread
+// (k = 16: RPT 2, 4, 8; k = 32: 1, 2, 4; k = 64: 1, 2).
+bool tsqr_rows_ok(int k, int rb) {
+  if (rb < 256 || rb % 256) return false;
+  const int rpt = rb / 256;
+  if (rpt & (rpt - 1)) return false;
+  return (k == 16 && rpt >= 2 && rpt <= 8) || (k == 32 && rpt <= 4) || (k == 64 && rpt <= 2);
+}
+
+int tsqr_block_qr(const double* A, int64_t lda, int64_t m, int k, int rb, double* R, int64_t ldr, double* V,
                   int64_t ldv, double* T, hipStream_t st) {
   if (m <= 0) return AZRBF_OK;
-  switch (k) {
-    case 16: return launch_reg<16>(A, lda, m, R, ldr, V, ldv, T, st);
-    case 32: return launch_reg<32>(A, lda, m, R, ldr, V, ldv, T, st);
-    case 64: return launch_reg<64>(A, lda, m, R, ldr, V, ldv, T, st);
+  if (!tsqr_rows_ok(k, rb)) return AZRBF_EUNSUPPORTED;
+  const int rpt = rb / 256;
+  switch (k * 16 + rpt) {
+    case 16 * 16 + 2: return launch_reg<16, 2>(A, lda, m, R, ldr, V, ldv, T, st);
+    case 16 * 16 + 4: return launch_reg<16, 4>(A, lda, m, R, ldr, V, ldv, T, st);
+    case 16 * 16 + 8: return launch_reg<16, 8>(A, lda, m, R, ldr, V, ldv, T, st);
+    case 32 * 16 + 1: return launch_reg<32, 1>(A, lda, m, R, ldr, V, ldv, T, st);
+    case 32 * 16 + 2: return launch_reg<32, 2>(A, lda, m, R, ldr, V, ldv, T, st);
+    case 32 * 16 + 4: return launch_reg<32, 4>(A, lda, m, R, ldr, V, ldv, T, st);
+    case 64 * 16 + 1: return launch_reg<64, 1>(A, lda, m, R, ldr, V, ldv, T, st);
+    case 64 * 16 + 2: return launch_reg<64, 2>(A, lda, m, R, ldr, V, ldv, T, st);
     default: return AZRBF_EUNSUPPORTED;
   }
 }

@@ -10,6 +10,12 @@
 // operator for each candidate (coordinate search: C, then Lr, then the
 // chunk), keeps the fastest in the plan and in a process-wide table keyed by
 // the engine shape, from which later plans of the same shape start.
+//
+// The TSQR of the low-rank stage has one tile parameter, the rows a block
+// QR holds in registers (RB = 256 RPT): larger blocks mean fewer blocks and
+// tree levels but more work per column step.  The autotuner times the whole
+// TSQR (block QR tree and Q formation) of an Mt x k Gaussian matrix for each
+// admissible RB and keeps the fastest under the key t<k>_<Mt>.
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -66,9 +72,21 @@ int time_ops(Plan& P, const double* X, double* Y, double* Z, int64_t nvec, hipSt
 
 }  // namespace
 
+std::string tsqr_key(int k, int64_t m) {
+  char b[64];
+  snprintf(b, sizeof(b), "t%d_%lld", k, (long long)m);
+  return b;
+}
+
+int tsqr_slot(int k) { return k == 16 ? 0 : k == 32 ? 1 : 2; }
+
 void tune_apply(Plan& P) {
-  if (!uses_engine(P)) return;
   std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (int k : {16, 32, 64}) {
+    auto t = g_tune.find(tsqr_key(k, P.Mt));
+    if (t != g_tune.end() && tsqr_rows_ok(k, t->second.C)) P.tsqr_rb[tsqr_slot(k)] = t->second.C;
+  }
+  if (!uses_engine(P)) return;
   auto it = g_tune.find(engine_key(P));
   if (it == g_tune.end()) return;
   const Shape& s = it->second;
@@ -145,6 +163,64 @@ int tune_plan(Plan& P, int64_t nvec, hipStream_t st, std::string* report) {
   return AZRBF_OK;
 }
 
+int tune_tsqr(Plan& P, int k, hipStream_t st, std::string* report) {
+  *report = "";
+  if (k != 16 && k != 32 && k != 64) return AZRBF_OK;
+  const int64_t m = P.Mt;
+  double *W0 = nullptr, *W = nullptr, *Q = nullptr, *R = nullptr, *scr = nullptr;
+  AZ_TRY(P.alloc((void**)&W0, sizeof(double) * m * k));
+  AZ_TRY(P.alloc((void**)&W, sizeof(double) * m * k));
+  AZ_TRY(P.alloc((void**)&Q, sizeof(double) * m * k));
+  AZ_TRY(P.alloc((void**)&R, sizeof(double) * k * k));
+  AZ_TRY(P.alloc((void**)&scr, sizeof(double) * tsqr_scratch(m, k)));
+  int rc = dense_gaussian(0x75a1, m, k, W0, m, st);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (!rc && (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)) rc = AZRBF_EHIP;
+  int best_rb = 0;
+  float best = 1e30f;
+  std::string log = "[";
+  for (int rb = 256; rb <= 2048 && !rc; rb *= 2) {
+    if (!tsqr_rows_ok(k, rb)) continue;
+    float t_best = 1e30f;
+    for (int rep = 0; rep < 4 && !rc; ++rep) {   // the first run warms the kernels up
+      if (hipMemcpyAsync(W, W0, sizeof(double) * m * k, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+          hipEventRecord(a, st) != hipSuccess) {
+        rc = AZRBF_EHIP;
+        break;
+      }
+      rc = tsqr_panel(W, m, k, rb, scr, Q, R, st);
+      if (!rc && (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess)) rc = AZRBF_EHIP;
+      float ms = 0.f;
+      if (!rc && hipEventElapsedTime(&ms, a, b) != hipSuccess) rc = AZRBF_EHIP;
+      if (!rc && rep > 0 && ms < t_best) t_best = ms;
+    }
+    if (rc) break;
+    char e[96];
+    snprintf(e, sizeof(e), "%s{\"rows\": %d, \"ms\": %.4f}", log.size() > 1 ? ", " : "", rb, t_best);
+    log += e;
+    if (t_best < best) {
+      best = t_best;
+      best_rb = rb;
+    }
+  }
+  log += "]";
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipStreamSynchronize(st);
+  for (double* p : {W0, W, Q, R, scr}) P.release_one(p);
+  if (rc) return rc;
+  P.tsqr_rb[tsqr_slot(k)] = best_rb;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tsqr_key(k, m)] = Shape{best_rb, 0, 0};
+  }
+  char h[160];
+  snprintf(h, sizeof(h), "{\"key\": \"%s\", \"rows\": %d, \"ms\": %.4f, \"trials\": ", tsqr_key(k, m).c_str(),
+           best_rb, best);
+  *report = std::string(h) + log + "}";
+  return AZRBF_OK;
+}
+
 int tune_table(std::string* out) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   std::string s;
@@ -165,13 +241,22 @@ int tune_load(const char* text) {
     int C = 0, L = 0, ch = 0, n = 0;
     if (sscanf(p, "%95s %d %d %d%n", key, &C, &L, &ch, &n) != 4) return AZRBF_EINVAL;
     int dim = 0, N1 = 0, N2 = 0, s = 0;
-    // engine shapes: rows up to 512; columns up to 512, or up to 2048 beside
-    // 512-long rows (1D transforms of 2^19 and 2^20)
-    if (sscanf(key, "e%d_%dx%d_s%d", &dim, &N1, &N2, &s) != 4 || N1 < 16 || N2 < 16 || N2 > 512 ||
-        N1 > (dim == 1 && N2 == 512 ? 2048 : 512) || (N1 & (N1 - 1)) || (N2 & (N2 - 1)))
-      return AZRBF_EINVAL;
-    if (!engine_shape_ok(N1, N2, C, L, ch)) return AZRBF_EINVAL;
-    g_tune[key] = Shape{C, L, ch};
+    if (key[0] == 't') {   // TSQR tile: t<k>_<rows> <RB> 0 0
+      int k = 0;
+      long long m = 0;
+      char tail = 0;
+      if (sscanf(key, "t%d_%lld%c", &k, &m, &tail) != 2 || m < 1 || !tsqr_rows_ok(k, C) || L != 0 || ch != 0)
+        return AZRBF_EINVAL;
+      g_tune[key] = Shape{C, 0, 0};
+    } else {
+      // engine shapes: rows up to 512; columns up to 512, or up to 2048 beside
+      // 512-long rows (1D transforms of 2^19 and 2^20)
+      if (sscanf(key, "e%d_%dx%d_s%d", &dim, &N1, &N2, &s) != 4 || N1 < 16 || N2 < 16 || N2 > 512 ||
+          N1 > (dim == 1 && N2 == 512 ? 2048 : 512) || (N1 & (N1 - 1)) || (N2 & (N2 - 1)))
+        return AZRBF_EINVAL;
+      if (!engine_shape_ok(N1, N2, C, L, ch)) return AZRBF_EINVAL;
+      g_tune[key] = Shape{C, L, ch};
+    }
     p += n;
     while (*p == '\n' || *p == ' ' || *p == '\t' || *p == '\r') ++p;
   }

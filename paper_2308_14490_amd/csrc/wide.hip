@@ -423,7 +423,7 @@ int64_t wide_factor_doubles(int64_t N, int64_t Mt, int k) {
 // Q (MFMA GEMMs), a TSQR of the panel, one more projection of the panel's Q
 // and a second TSQR (see below).  The scratch is laid out for m <= its rows.
 static int wide_qr(double* Xq, int64_t m, int k, double* R, double* scr, const WideScratch& L, double* rproj,
-                   hipStream_t st) {
+                   int rb, hipStream_t st) {
   double* tq = scr + L.tsqr;
   double* qpan = scr + L.qpan;
   double* rpan = scr + L.rpan;
@@ -446,7 +446,7 @@ static int wide_qr(double* Xq, int64_t m, int k, double* R, double* scr, const W
       launch_kernel(k_axpy, grid1(done * PB), 256, 0, st, done, PB, rproj, done, Rcol, k);
       AZ_HIP(hipGetLastError());
     }
-    AZ_TRY(tsqr_panel(X, m, PB, tq, qpan, rpan, st));
+    AZ_TRY(tsqr_panel(X, m, PB, rb, tq, qpan, rpan, st));
     if (p == 0) {
       AZ_HIP(hipMemcpyAsync(X, qpan, sizeof(double) * m * PB, hipMemcpyDeviceToDevice, st));
       AZ_HIP(hipMemcpy2DAsync(Rcol, sizeof(double) * k, rpan, sizeof(double) * PB, sizeof(double) * PB, PB,
@@ -462,7 +462,7 @@ static int wide_qr(double* Xq, int64_t m, int k, double* R, double* scr, const W
                      st));
     AZ_TRY(gemm_mfma(false, false, m, PB, done, -1.0, Xq, m, 0, rproj, done, 0, 1.0, qpan, m, 0, 1, part,
                      npart, st));
-    AZ_TRY(tsqr_panel(qpan, m, PB, tq, X, r3, st));
+    AZ_TRY(tsqr_panel(qpan, m, PB, rb, tq, X, r3, st));
     AZ_TRY(gemm_mfma(false, false, done, PB, PB, 1.0, rproj, done, 0, rpan, PB, 0, 1.0, Rcol, k, 0, 1, nullptr, 0,
                      st));
     AZ_TRY(gemm_mfma(false, false, PB, PB, PB, 1.0, r3, PB, 0, rpan, PB, 0, 0.0, Rcol + done, k, 0, 1, nullptr,
@@ -500,7 +500,7 @@ int wide_factor(Plan& P, hipStream_t st) {
   AZ_TRY(ops_apply_AZ(P, P.Q, Mt, k, -1.0, 1.0, P.Q, Mt, P.Q, Mt, P.Om2, st));  // W = Y - A Z* Y
   // 2. W = Q R
   P.ldq = Mt;
-  AZ_TRY(wide_qr(P.Q, Mt, k, P.Rf, scr, Lx, rproj, st));
+  AZ_TRY(wide_qr(P.Q, Mt, k, P.Rf, scr, Lx, rproj, plan_tsqr_rows(P, PB), st));
   // 3. block one-sided Jacobi, preconditioned: R^T = Q2 R2 (the same QR),
   // then Jacobi on G = R2^T with the rotations accumulated onto V = Q2
   // (fewer sweeps: the QR concentrates the weight of R2's rows on its
@@ -510,7 +510,7 @@ int wide_factor(Plan& P, hipStream_t st) {
     dim3 tg((unsigned)((k + 31) / 32), (unsigned)((k + 31) / 32));
     launch_kernel(k_transpose, tg, 256, 0, st, k, P.Rf, P.Vj);
     AZ_HIP(hipGetLastError());
-    AZ_TRY(wide_qr(P.Vj, k, k, P.Pm, scr, Lx, rproj, st));    // Vj = Q2, Pm = R2 (scratch until step 4)
+    AZ_TRY(wide_qr(P.Vj, k, k, P.Pm, scr, Lx, rproj, plan_tsqr_rows(P, PB), st));    // Vj = Q2, Pm = R2 (scratch until step 4)
     launch_kernel(k_transpose, tg, 256, 0, st, k, P.Pm, P.Gj);
     AZ_HIP(hipGetLastError());
   }

@@ -244,3 +244,59 @@ def test_solve_2d_anisotropic_helmholtz():
     prob = W.Problem("ellipse-helm", 2, 32, 2, 1.4, 0.5, base.domain, [lambda x, y: 8.0 * u(x, y)],
                      op=W.HELMHOLTZ, k2=5.0, bnd=[u], nb=150, exact=[u], ny=32, Ty=0.7)
     _check(prob)
+
+
+# ---------------------------------------------------------------- TSQR tile shapes
+
+@pytest.mark.parametrize("k,rows", [(32, 256), (32, 512), (32, 1024), (16, 512), (16, 2048), (64, 256), (64, 512)])
+def test_tsqr_tile_shapes_solve_alike(k, rows):
+    """Every TSQR tile (rows per block QR; widths 16, 32, 64) factors
+    the oracle's sketch W = (A - A Z* A) Omega: Q^T Q = I, R upper
+    triangular, Q R = W (section 3.2.3), the same retained rank as the
+    default tile, and a residual <= 1e-10 (1D family, N = 4096, M = 4097: a
+    tree of two or three levels)."""
+    azrbf, problems = _az()
+    prob = W.family_1d(4096, 4)
+    prob.k = k
+    saved = azrbf.tune_table()
+    p = problems.plan_for(prob)
+    azrbf.factor(p)
+    rank0 = p.info()["rank"]
+    Mt = p.Mt
+    p.destroy()
+    try:
+        azrbf.tune_load({f"t{k}_{Mt}": (rows, 0, 0)})
+        p = problems.plan_for(prob)
+        B = problems.rhs_for(p, prob)
+        X, rel = azrbf.solve(p, B)
+        torch.cuda.synchronize()
+        A, idx, pts, bpts = dense.system_matrix(prob)
+        Z = periodic.zstar_normal(prob, idx)
+        Om = philox.gaussian_sketch(prob.N, p.k, prob.seed)
+        Wo = (A - A @ Z @ A) @ Om
+        Q = azrbf.get_factor(p, "Q").cpu().numpy().T
+        R = azrbf.get_factor(p, "R").cpu().numpy().T
+        rank = p.info()["rank"]
+        announce("tsqr tile", k, rows, "rank", rank, rank0, "relres", float(rel.max()))
+        assert np.max(np.abs(Q.T @ Q - np.eye(p.k))) < 1e-13
+        assert np.max(np.abs(np.tril(R, -1))) == 0.0
+        assert np.max(np.abs(Q @ R - Wo)) < 1e-10 * np.abs(Wo).max()
+        assert rank == rank0
+        assert float(rel.max()) <= 1e-10
+        p.destroy()
+    finally:   # back to the default tile (16384 / k rows) for later plans of this shape
+        azrbf.tune_load(dict(saved, **{f"t{k}_{Mt}": saved.get(f"t{k}_{Mt}", (16384 // k, 0, 0))}))
+
+
+def test_autotune_picks_a_tsqr_tile():
+    """azrbf_autotune also times the TSQR tiles on the plan's (M + Mb) x k
+    shape and keeps the fastest in the table."""
+    azrbf, problems = _az()
+    prob = W.family_1d(65536, 2)
+    p = problems.plan_for(prob)
+    rep = azrbf.autotune(p, 8)
+    t = rep["tsqr"]
+    announce("tsqr tiles", t)
+    assert t["rows"] in (256, 512, 1024) and len(t["trials"]) == 3
+    assert azrbf.tune_table()[t["key"]][0] == t["rows"]
+    p.destroy()

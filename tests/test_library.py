@@ -114,6 +114,14 @@ def test_tune_table_round_trip_and_validation():
     assert lib.azrbf_tune_load(b"e1_4096x512_s2 1 2 16\n") == azrbf.EINVAL     # N1 out of range
     assert lib.azrbf_tune_load(b"e1_2048x512_s2 2 2 8\n") == 0                  # a 2^20 transform
     assert lib.azrbf_tune_load(b"garbage\n") == azrbf.EINVAL
+    # TSQR tiles: rows per block 256 RPT with k RPT <= 128 (k = 16 from RPT 2)
+    assert lib.azrbf_tune_load(b"t32_65537 512 0 0\nt64_32937 256 0 0\nt16_4097 2048 0 0\n") == azrbf.OK
+    assert lib.azrbf_tune_load(b"t32_65537 2048 0 0\n") == azrbf.EINVAL     # 32 x 8 doubles per thread
+    assert lib.azrbf_tune_load(b"t16_4097 256 0 0\n") == azrbf.EINVAL       # not instantiated
+    assert lib.azrbf_tune_load(b"t48_4097 512 0 0\n") == azrbf.EINVAL       # width
+    assert lib.azrbf_tune_load(b"t32_4097 768 0 0\n") == azrbf.EINVAL       # RPT not a power of two
+    assert lib.azrbf_tune_load(b"t32_4097x 512 0 0\n") == azrbf.EINVAL      # key
+    assert lib.azrbf_tune_load(b"t32_4097 512 1 0\n") == azrbf.EINVAL
     assert lib.azrbf_tune_load(b"e2_128x128_s2 16 16 8\ne2_64x64_s2 4 8 2\n") == 0
     t = azrbf.tune_table()
     assert t["e2_128x128_s2"] == (16, 16, 8) and t["e2_64x64_s2"] == (4, 8, 2)
