@@ -124,11 +124,12 @@ def roofline_of(r, total_ms):
     return out
 
 
-def served_vs_plain(count, seed, sides, log_fn):
-    """Reduced mixed stream (70% 1D N = 2^10..2^16, 30% 2D approximation on
-    disks and stars): plain FIFO per-problem solves against the
+def served_vs_plain(count, seed, sides, log_fn, modes=("plain", "closed", "open"), rate=None):
+    """Mixed stream (70% 1D N = 2^10..2^16, 30% 2D approximation on disks
+    and stars of the given sides): plain FIFO per-problem solves against the
     continuous-batching server, both closed-loop (all requests queued at the
-    start), then the server open-loop at twice the plain request rate."""
+    start), then the server open-loop (Poisson arrivals at `rate`, by default
+    twice the plain request rate).  `modes` selects the parts to run."""
     import torch
     import workloads as W
     from paper_2308_14490_amd import serve
@@ -138,6 +139,13 @@ def served_vs_plain(count, seed, sides, log_fn):
     reqs = W.served_stream(count=count, seed=seed, rate=1e9, sides=sides)
     for r in reqs:
         r.arrival = 0.0
+    last = [time.perf_counter()]
+
+    def progress(done, tot):
+        now = time.perf_counter()
+        if done == tot or now - last[0] > 20.0:
+            last[0] = now
+            log_fn(f"  {done}/{tot} requests done")
     # warm the kernels of every size once
     warm = {}
     for r in reqs:
@@ -146,24 +154,32 @@ def served_vs_plain(count, seed, sides, log_fn):
             warm[key] = r
     serve.run_plain(be, list(warm.values()))
     torch.cuda.synchronize()
-    plain = serve.summarize(serve.run_plain(be, reqs))
-    log_fn(f"served stream: plain {plain['solves_per_s']:.1f} solves/s, p50 {plain['p50_ms']:.1f} ms")
-    srv = serve.Server(be, budget)
-    closed = serve.summarize(srv.run(reqs))
-    srv.close()
-    log_fn(f"served stream: served closed-loop {closed['solves_per_s']:.1f} solves/s")
-    rate = 2.0 * plain["requests"] / plain["makespan_s"]
-    open_reqs = W.served_stream(count=count, seed=seed, rate=rate, sides=sides)
-    srv = serve.Server(be, budget)
-    openl = serve.summarize(srv.run(open_reqs))
-    ticks = len(srv.ticks)
-    srv.close()
+    out = {"requests": count, "seed": seed, "sides_2d": list(sides), "exps_1d": [10, 16], "budget_bytes": budget}
+    if "plain" in modes:
+        plain = serve.summarize(serve.run_plain(be, reqs, progress=progress))
+        log_fn(f"served stream: plain {plain['solves_per_s']:.1f} solves/s, p50 {plain['p50_ms']:.1f} ms")
+        out["plain"] = plain
+    if "closed" in modes:
+        srv = serve.Server(be, budget)
+        closed = serve.summarize(srv.run(reqs, progress=progress))
+        srv.close()
+        log_fn(f"served stream: served closed-loop {closed['solves_per_s']:.1f} solves/s")
+        out["served_closed_loop"] = closed
+        if "plain" in out:
+            out["speedup_closed_loop"] = round(closed["solves_per_s"] / out["plain"]["solves_per_s"], 3)
+    if "open" in modes:
+        if rate is None:
+            rate = 2.0 * out["plain"]["requests"] / out["plain"]["makespan_s"]
+        open_reqs = W.served_stream(count=count, seed=seed, rate=rate, sides=sides)
+        srv = serve.Server(be, budget)
+        openl = serve.summarize(srv.run(open_reqs, progress=progress))
+        ticks = len(srv.ticks)
+        srv.close()
+        log_fn(f"served stream: open-loop at {rate:.1f} req/s: p50 {openl['p50_ms']:.1f} ms "
+               f"p99 {openl['p99_ms']:.1f} ms")
+        out["served_open_loop"] = dict(openl, rate_req_per_s=round(rate, 2), groups=ticks)
     be.close()
-    log_fn(f"served stream: open-loop at {rate:.1f} req/s: p50 {openl['p50_ms']:.1f} ms p99 {openl['p99_ms']:.1f} ms")
-    return {"requests": count, "seed": seed, "sides_2d": list(sides), "exps_1d": [10, 16],
-            "budget_bytes": budget, "plain": plain, "served_closed_loop": closed,
-            "served_open_loop": dict(openl, rate_req_per_s=round(rate, 2), groups=ticks),
-            "speedup_closed_loop": round(closed["solves_per_s"] / plain["solves_per_s"], 3)}
+    return out
 
 
 def wide_2d(log_fn, n=128):
@@ -459,6 +475,11 @@ def main():
                     help="after the steps, run an elementwise kernel of known size (1 GiB read, 1 GiB written) "
                          "for hardware-counter calibration")
     ap.add_argument("--serve-count", type=int, default=48)
+    ap.add_argument("--serve-sides", default="64", help="2D grid sides of the served stream, comma-separated")
+    ap.add_argument("--served-only", action="store_true",
+                    help="run only the served-stream comparison and print its JSON")
+    ap.add_argument("--serve-modes", default="plain,closed,open")
+    ap.add_argument("--serve-rate", type=float, default=None, help="open-loop arrival rate (req/s)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps only (for rocprofv3 runs)")
     ap.add_argument("--only-2d", action="store_true",
@@ -479,6 +500,12 @@ def main():
     dev = torch.device("cuda", 0)
     if args.only_2d:
         print(json.dumps(wide_2d(log)), flush=True)
+        return 0
+    sides = tuple(int(v) for v in args.serve_sides.split(","))
+    if args.served_only:
+        azrbf.tune_load_file(os.path.join(ROOT, "paper_2308_14490_amd", "tune_mi355x.json"))
+        print(json.dumps(served_vs_plain(args.serve_count, 2024, sides, log, tuple(args.serve_modes.split(",")),
+                                         args.serve_rate)), flush=True)
         return 0
     prob = W.config_c2(n=args.n, nrhs=args.nrhs)
     mask = azrbf.make_mask(1, prob.n, prob.s, prob.T, prob.domain.contains)
@@ -633,7 +660,7 @@ def main():
         "kernels": table,
     }
     if not args.no_served:
-        out["served_stream"] = served_vs_plain(args.serve_count, 2024, (64,), log)
+        out["served_stream"] = served_vs_plain(args.serve_count, 2024, sides, log)
     out["fft_passes_beyond_cache"] = beyond_cache(log)
     out["copies_1d_n256"] = copies_1d(log)
     out["million_1d"] = million_1d(log)

@@ -251,9 +251,10 @@ class Server:
             count += 1
         return groups
 
-    def run(self, requests, start=None):
+    def run(self, requests, start=None, progress=None):
         """Serves requests (objects with rid, arrival, problem) in real time.
-        Arrival times are seconds from the start of the run."""
+        Arrival times are seconds from the start of the run.  progress(done,
+        total), if given, is called as results come in."""
         be = self.be
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
         queue = []
@@ -277,6 +278,8 @@ class Server:
                                             np.asarray(rel), X, key)
                 self.ticks.append((fl.t_admit, t_done, len(fl.reqs), fl.new))
                 progressed = True
+                if progress:
+                    progress(len(results), len(requests))
             if queue:
                 t_admit = be.now() - t0
                 for key, (reqs, reserve) in self._admit(queue).items():
@@ -303,7 +306,7 @@ class Server:
         self.cache.clear()
 
 
-def run_plain(backend, requests, start=None):
+def run_plain(backend, requests, start=None, progress=None):
     """FIFO, one request at a time, no plan reuse: plan, factor, solve, free."""
     be = backend
     results = {}
@@ -320,6 +323,8 @@ def run_plain(backend, requests, start=None):
         td = be.now() - t0
         be.destroy(plan)
         results[r.rid] = Result(r.rid, len(r.problem.rhs), r.arrival, ta, td, np.asarray(rel), X)
+        if progress:
+            progress(len(results), len(requests))
     return results
 
 
