@@ -140,6 +140,18 @@ def served_vs_plain(count, seed, sides, log_fn, modes=("plain", "closed", "open"
     for r in reqs:
         r.arrival = 0.0
     last = [time.perf_counter()]
+    dims = {r.rid: r.problem.dim for r in reqs}
+
+    def by_dim(res):
+        """p50 / p99 latency of the 1D and of the 2D requests separately."""
+        import numpy as np
+        out_d = {}
+        for d in (1, 2):
+            lat = [(r.done - r.arrival) * 1e3 for r in res.values() if dims[r.rid] == d]
+            if lat:
+                out_d[f"{d}d"] = {"requests": len(lat), "p50_ms": float(np.percentile(lat, 50)),
+                                  "p99_ms": float(np.percentile(lat, 99))}
+        return out_d
 
     def progress(done, tot):
         now = time.perf_counter()
@@ -156,12 +168,14 @@ def served_vs_plain(count, seed, sides, log_fn, modes=("plain", "closed", "open"
     torch.cuda.synchronize()
     out = {"requests": count, "seed": seed, "sides_2d": list(sides), "exps_1d": [10, 16], "budget_bytes": budget}
     if "plain" in modes:
-        plain = serve.summarize(serve.run_plain(be, reqs, progress=progress))
+        res = serve.run_plain(be, reqs, progress=progress)
+        plain = dict(serve.summarize(res), by_dim=by_dim(res))
         log_fn(f"served stream: plain {plain['solves_per_s']:.1f} solves/s, p50 {plain['p50_ms']:.1f} ms")
         out["plain"] = plain
     if "closed" in modes:
         srv = serve.Server(be, budget)
-        closed = serve.summarize(srv.run(reqs, progress=progress))
+        res = srv.run(reqs, progress=progress)
+        closed = dict(serve.summarize(res), by_dim=by_dim(res))
         srv.close()
         log_fn(f"served stream: served closed-loop {closed['solves_per_s']:.1f} solves/s")
         out["served_closed_loop"] = closed
@@ -172,7 +186,8 @@ def served_vs_plain(count, seed, sides, log_fn, modes=("plain", "closed", "open"
             rate = 2.0 * out["plain"]["requests"] / out["plain"]["makespan_s"]
         open_reqs = W.served_stream(count=count, seed=seed, rate=rate, sides=sides)
         srv = serve.Server(be, budget)
-        openl = serve.summarize(srv.run(open_reqs, progress=progress))
+        res = srv.run(open_reqs, progress=progress)
+        openl = dict(serve.summarize(res), by_dim=by_dim(res))
         ticks = len(srv.ticks)
         srv.close()
         log_fn(f"served stream: open-loop at {rate:.1f} req/s: p50 {openl['p50_ms']:.1f} ms "
