@@ -547,34 +547,36 @@ int launch_jacobi(const double* R, int k, double tau_k, const double* dmax, doub
 // ------------------------------------------------------------------ skinny GEMMs
 
 // Out = alpha * A B + beta * Cin; A is m x k (ld lda), B is k x ncol (ld ldb,
-// small), Out/Cin m x ncol.  A block of 256 threads takes 256 / G rows and
-// G groups of NC columns: thread t owns row t mod (256 / G) and the NC
-// columns of group t / (256 / G).  The G groups of one block read the same
-// rows of A, so A comes from HBM once (a group per block would re-read it
-// from a later block); B is staged in LDS with the columns of one reduction
-// index contiguous.  Out may alias Cin (each element is read and written by
-// the same thread).
-template <int NC, int G>
+// small), Out/Cin m x ncol.  Each thread owns one row and up to NC columns;
+// B is staged in LDS with the columns of one reduction index contiguous.
+// (NC = 16: more blocks in flight beat streaming A once with 64 accumulators
+// per thread, measured on the 65536 x 32 by 32 x 64 case.)  The G column
+// groups of a row block read the same 256 rows of A; blocks are numbered so
+// that those G blocks are dispatched together and to the same XCD (block b
+// runs on XCD b mod 8), where they share A through that XCD's L2 instead of
+// each fetching it from HBM.  Out may alias Cin (each element is read and
+// written by the same thread).
+template <int NC>
 __global__ void __launch_bounds__(256)
 k_gemm_nn(const double* __restrict__ A, int64_t lda, int64_t m, int k, const double* __restrict__ B, int64_t ldb,
-          int64_t ncol, double alpha, const double* Cin, int64_t ldci, double beta, double* Out, int64_t ldo) {
-  constexpr int RB = 256 / G;        // rows per block
-  constexpr int W = G * NC;          // columns per block
-  __shared__ double bs[KMAX * W];    // bs[c * W + v] = B(c, vb + v)
-  const int t = threadIdx.x;
-  const int64_t vb = (int64_t)blockIdx.y * W;
-  const int nvb = (int)std::min<int64_t>(W, ncol - vb);
-  for (int e = t; e < k * W; e += 256) {
+          int64_t ncol, double alpha, const double* Cin, int64_t ldci, double beta, double* Out, int64_t ldo,
+          int64_t nrb, int G) {
+  __shared__ double bs[KMAX * NC];   // bs[c * NC + v] = B(c, v0 + v)
+  // linear block L = (rb / 8) (8 G) + cg 8 + rb mod 8
+  const int64_t L = blockIdx.x;
+  const int64_t q = L / (8 * G), rem = L % (8 * G);
+  const int cg = (int)(rem / 8);
+  const int64_t rb = q * 8 + rem % 8;
+  if (rb >= nrb) return;
+  const int64_t i = rb * 256 + threadIdx.x;
+  const int64_t v0 = (int64_t)cg * NC;
+  const int nv = (int)std::min<int64_t>(NC, ncol - v0);
+  for (int e = threadIdx.x; e < k * NC; e += blockDim.x) {
     const int c = e % k, v = e / k;
-    bs[c * W + v] = v < nvb ? B[c + ldb * (vb + v)] : 0.0;
+    bs[c * NC + v] = v < nv ? B[c + ldb * (v0 + v)] : 0.0;
   }
   __syncthreads();
-  const int cg = t / RB;
-  const int64_t i = (int64_t)blockIdx.x * RB + (t % RB);
-  const int64_t v0 = vb + (int64_t)cg * NC;
-  const int nv = (int)std::min<int64_t>(NC, ncol - v0);
-  if (i >= m || nv <= 0) return;
-  const double* bg = bs + cg * NC;
+  if (i >= m) return;
   double acc[NC];
 #pragma unroll
   for (int v = 0; v < NC; ++v) acc[v] = 0.0;
@@ -585,7 +587,7 @@ k_gemm_nn(const double* __restrict__ A, int64_t lda, int64_t m, int k, const dou
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int v = 0; v < NC; ++v) acc[v] = fma(a[u], bg[(c + u) * W + v], acc[v]);
+      for (int v = 0; v < NC; ++v) acc[v] = fma(a[u], bs[(c + u) * NC + v], acc[v]);
   }
 #pragma unroll
   for (int v = 0; v < NC; ++v) {
@@ -708,17 +710,12 @@ static int gemm_nn(const double* A, int64_t lda, int64_t m, int k, const double*
                    double alpha, const double* Cin, int64_t ldci, double beta, double* Out, int64_t ldo,
                    hipStream_t st) {
   if (m <= 0 || ncol <= 0) return AZRBF_OK;
-  // column groups of 16 per block: up to four (64 columns), so that the
-  // groups sharing rows of A run in one block
-  const int G = ncol > 32 ? 4 : ncol > 16 ? 2 : 1;
-  const int W = 16 * G, RB = 256 / G;
-  const dim3 grid((unsigned)((m + RB - 1) / RB), (unsigned)((ncol + W - 1) / W));
+  const int64_t nrb = (m + 255) / 256;                 // row blocks
+  const int G = (int)((ncol + 15) / 16);               // column groups of 16
+  const int64_t nblk = (nrb + 7) / 8 * 8 * G;          // whole groups of eight row blocks
   Prof pr("gemm_nn", 8.0 * m * (k + ncol * (beta != 0.0 ? 2.0 : 1.0)), st);
-  if (G == 4) launch_kernel(k_gemm_nn<16, 4>, grid, 256, 0, st, A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta,
-                           Out, ldo);
-  else if (G == 2) launch_kernel(k_gemm_nn<16, 2>, grid, 256, 0, st, A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci,
-                                 beta, Out, ldo);
-  else launch_kernel(k_gemm_nn<16, 1>, grid, 256, 0, st, A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta, Out, ldo);
+  launch_kernel(k_gemm_nn<16>, (unsigned)nblk, 256, 0, st, A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta, Out,
+                ldo, nrb, G);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
