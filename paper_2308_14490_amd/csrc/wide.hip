@@ -414,7 +414,7 @@ WideScratch wide_layout(int64_t Mt, int k) {
 }  // namespace
 
 int64_t wide_factor_doubles(int64_t N, int64_t Mt, int k) {
-  return 2 * N * k + Mt * k + 4 * (int64_t)k * k + 2 * k + wide_layout(Mt, k).total + (int64_t)k * PB + 8;
+  return 2 * N * k + Mt * k + 4 * (int64_t)k * k + 2 * k + wide_layout(Mt, k).total + 2 * (int64_t)k * PB + panel_part(k, Mt) + 8;
 }
 
 // Block classical Gram-Schmidt QR with reorthogonalisation (BCGS2) of the
@@ -422,35 +422,87 @@ int64_t wide_factor_doubles(int64_t N, int64_t Mt, int k) {
 // triangular factor.  64-column panels: two projections against the finished
 // Q (MFMA GEMMs), a TSQR of the panel, one more projection of the panel's Q
 // and a second TSQR (see below).  The scratch is laid out for m <= its rows.
+//
+// Look-ahead: a panel's projections are split into the panels finished
+// before its predecessor (the old group) and its predecessor (the new one),
+// each projected twice.  The old group's projections of panel p + 1 do not
+// wait for panel p, so they run on a side stream (ss, with its own partials
+// part2 and coefficients rproj2) while panel p's latency-bound TSQRs run on
+// st; panel p + 1 then only projects against panel p on st.  With ss == st
+// the same work runs in order.
 static int wide_qr(double* Xq, int64_t m, int k, double* R, double* scr, const WideScratch& L, double* rproj,
-                   int rb, hipStream_t st) {
+                   int rb, hipStream_t st, hipStream_t ss, double* part2, double* rproj2) {
   double* tq = scr + L.tsqr;
   double* qpan = scr + L.qpan;
   double* rpan = scr + L.rpan;
   double* r3 = scr + L.rpan2;
   double* part = scr + L.part;
   const int64_t npart = panel_part(k, m);
-  AZ_HIP(hipMemsetAsync(R, 0, sizeof(double) * k * k, st));
-  for (int p = 0; p < k / PB; ++p) {
+  const int np = k / PB;
+  hipEvent_t ev_final = nullptr, ev_old = nullptr;   // panels before p final (st); old group of p + 1 done (ss)
+  if (ss != st) {
+    AZ_HIP(hipEventCreateWithFlags(&ev_final, hipEventDisableTiming));
+    if (hipEventCreateWithFlags(&ev_old, hipEventDisableTiming) != hipSuccess) {
+      (void)hipEventDestroy(ev_final);
+      return AZRBF_EHIP;
+    }
+  }
+  int rc = AZRBF_OK;
+  // projections of panel X against the done_g finished columns Qg (offset off
+  // in its R column), twice: R[off..] = c1 + c2, X -= Qg (c1 + c2)
+  auto project = [&](const double* Qg, int64_t done_g, int64_t off, double* X, double* Rcol, double* tmp,
+                     double* prt, hipStream_t s) -> int {
+    AZ_TRY(gemm_mfma(true, false, done_g, PB, m, 1.0, Qg, m, 0, X, m, 0, 0.0, Rcol + off, k, 0, 1, prt, npart, s));
+    AZ_TRY(gemm_mfma(false, false, m, PB, done_g, -1.0, Qg, m, 0, Rcol + off, k, 0, 1.0, X, m, 0, 1, prt, npart, s));
+    AZ_TRY(gemm_mfma(true, false, done_g, PB, m, 1.0, Qg, m, 0, X, m, 0, 0.0, tmp, done_g, 0, 1, prt, npart, s));
+    AZ_TRY(gemm_mfma(false, false, m, PB, done_g, -1.0, Qg, m, 0, tmp, done_g, 0, 1.0, X, m, 0, 1, prt, npart, s));
+    launch_kernel(k_axpy, grid1(done_g * PB), 256, 0, s, done_g, PB, tmp, done_g, Rcol + off, k);
+    return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+  };
+  rc = hipMemsetAsync(R, 0, sizeof(double) * k * k, st) == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+  for (int p = 0; p < np && !rc; ++p) {
     double* X = Xq + (int64_t)p * PB * m;
     const int64_t done = (int64_t)p * PB;
     double* Rcol = R + (int64_t)p * PB * k;
     if (p > 0) {
-      AZ_TRY(gemm_mfma(true, false, done, PB, m, 1.0, Xq, m, 0, X, m, 0, 0.0, Rcol, k, 0, 1, part, npart, st));
-      AZ_TRY(gemm_mfma(false, false, m, PB, done, -1.0, Xq, m, 0, Rcol, k, 0, 1.0, X, m, 0, 1, part, npart,
-                       st));
-      AZ_TRY(gemm_mfma(true, false, done, PB, m, 1.0, Xq, m, 0, X, m, 0, 0.0, rproj, done, 0, 1, part, npart,
-                       st));
-      AZ_TRY(gemm_mfma(false, false, m, PB, done, -1.0, Xq, m, 0, rproj, done, 0, 1.0, X, m, 0, 1, part,
-                       npart, st));
-      launch_kernel(k_axpy, grid1(done * PB), 256, 0, st, done, PB, rproj, done, Rcol, k);
-      AZ_HIP(hipGetLastError());
+      // panels 0 .. p - 1 are final here: the old group of panel p + 1 may start
+      if (ss != st && p + 1 < np) {
+        if (hipEventRecord(ev_final, st) != hipSuccess || hipStreamWaitEvent(ss, ev_final, 0) != hipSuccess) {
+          rc = AZRBF_EHIP;
+          break;
+        }
+      }
+      // the old group of this panel (panels 0 .. p - 2): queued on ss during
+      // the previous panel, or here when there is no side stream
+      if (p >= 2) {
+        if (ss != st) {
+          if (hipStreamWaitEvent(st, ev_old, 0) != hipSuccess) {
+            rc = AZRBF_EHIP;
+            break;
+          }
+        } else if ((rc = project(Xq, done - PB, 0, X, Rcol, rproj, part, st)) != AZRBF_OK) {
+          break;
+        }
+      }
+      // the new group: the previous panel
+      if ((rc = project(Xq + (done - PB) * m, PB, done - PB, X, Rcol, rproj, part, st)) != AZRBF_OK) break;
     }
-    AZ_TRY(tsqr_panel(X, m, PB, rb, tq, qpan, rpan, st));
+    if ((rc = tsqr_panel(X, m, PB, rb, tq, qpan, rpan, st)) != AZRBF_OK) break;
+    // queue the old group of panel p + 1 (panels 0 .. p - 1) beside this panel's TSQRs
+    if (ss != st && p >= 1 && p + 1 < np) {
+      double* Xn = Xq + (int64_t)(p + 1) * PB * m;
+      double* Rn = R + (int64_t)(p + 1) * PB * k;
+      if ((rc = project(Xq, done, 0, Xn, Rn, rproj2, part2, ss)) != AZRBF_OK) break;
+      if (hipEventRecord(ev_old, ss) != hipSuccess) {
+        rc = AZRBF_EHIP;
+        break;
+      }
+    }
     if (p == 0) {
-      AZ_HIP(hipMemcpyAsync(X, qpan, sizeof(double) * m * PB, hipMemcpyDeviceToDevice, st));
-      AZ_HIP(hipMemcpy2DAsync(Rcol, sizeof(double) * k, rpan, sizeof(double) * PB, sizeof(double) * PB, PB,
-                              hipMemcpyDeviceToDevice, st));
+      if (hipMemcpyAsync(X, qpan, sizeof(double) * m * PB, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+          hipMemcpy2DAsync(Rcol, sizeof(double) * k, rpan, sizeof(double) * PB, sizeof(double) * PB, PB,
+                           hipMemcpyDeviceToDevice, st) != hipSuccess)
+        rc = AZRBF_EHIP;
       continue;
     }
     // Past the numerical rank the projected panel is rounding noise, and
@@ -458,17 +510,25 @@ static int wide_qr(double* Xq, int64_t m, int k, double* R, double* scr, const W
     // finished Q.  One more projection of the panel's Q and a second TSQR
     // restore orthogonality:  Qp = Q S3 + Q'' R3, so the panel's R column
     // gains S3 Rpp and its diagonal block becomes R3 Rpp.
-    AZ_TRY(gemm_mfma(true, false, done, PB, m, 1.0, Xq, m, 0, qpan, m, 0, 0.0, rproj, done, 0, 1, part, npart,
-                     st));
-    AZ_TRY(gemm_mfma(false, false, m, PB, done, -1.0, Xq, m, 0, rproj, done, 0, 1.0, qpan, m, 0, 1, part,
-                     npart, st));
-    AZ_TRY(tsqr_panel(qpan, m, PB, rb, tq, X, r3, st));
-    AZ_TRY(gemm_mfma(false, false, done, PB, PB, 1.0, rproj, done, 0, rpan, PB, 0, 1.0, Rcol, k, 0, 1, nullptr, 0,
-                     st));
-    AZ_TRY(gemm_mfma(false, false, PB, PB, PB, 1.0, r3, PB, 0, rpan, PB, 0, 0.0, Rcol + done, k, 0, 1, nullptr,
-                     0, st));
+    if ((rc = gemm_mfma(true, false, done, PB, m, 1.0, Xq, m, 0, qpan, m, 0, 0.0, rproj, done, 0, 1, part, npart,
+                        st)) != AZRBF_OK)
+      break;
+    if ((rc = gemm_mfma(false, false, m, PB, done, -1.0, Xq, m, 0, rproj, done, 0, 1.0, qpan, m, 0, 1, part, npart,
+                        st)) != AZRBF_OK)
+      break;
+    if ((rc = tsqr_panel(qpan, m, PB, rb, tq, X, r3, st)) != AZRBF_OK) break;
+    if ((rc = gemm_mfma(false, false, done, PB, PB, 1.0, rproj, done, 0, rpan, PB, 0, 1.0, Rcol, k, 0, 1, nullptr, 0,
+                        st)) != AZRBF_OK)
+      break;
+    rc = gemm_mfma(false, false, PB, PB, PB, 1.0, r3, PB, 0, rpan, PB, 0, 0.0, Rcol + done, k, 0, 1, nullptr, 0, st);
   }
-  return AZRBF_OK;
+  if (rc && ss != st) {   // nothing queued on ss may outlive the call
+    (void)hipStreamSynchronize(ss);
+    (void)hipStreamSynchronize(st);
+  }
+  if (ev_final) (void)hipEventDestroy(ev_final);
+  if (ev_old) (void)hipEventDestroy(ev_old);
+  return rc;
 }
 
 int wide_factor(Plan& P, hipStream_t st) {
@@ -486,21 +546,28 @@ int wide_factor(Plan& P, hipStream_t st) {
     AZ_TRY(P.alloc((void**)&P.Vj, sizeof(double) * k * k));
     AZ_TRY(P.alloc((void**)&P.Pm, sizeof(double) * k * k));
     AZ_TRY(P.alloc((void**)&P.sig, sizeof(double) * 2 * k));
-    // rpan must hold done x 64 coefficients of the second projection
-    const int64_t sd = L.total + (int64_t)k * PB + 8;
+    // second-projection coefficients (k x 64), then the side stream's split-K
+    // partials and coefficients
+    const int64_t sd = L.total + 2 * (int64_t)k * PB + panel_part(k, Mt) + 8;
     AZ_TRY(P.alloc((void**)&P.dscr, sizeof(double) * sd));
     P.dscr_bytes = sizeof(double) * sd;
   }
   double* scr = P.dscr;
   const WideScratch& Lx = L;
   double* rproj = scr + L.total;   // second-projection coefficients, k x 64
+  double* rproj2 = rproj + (int64_t)k * PB;
+  double* part2 = rproj2 + (int64_t)k * PB;
+  // the panels' look-ahead projections go to a side stream (not when kernels
+  // are being timed one by one)
+  hipStream_t ss = st;
+  if (!prof_enabled() && side_stream(P.device, &ss) != AZRBF_OK) ss = st;
   // 1. sketch
   AZ_TRY(dense_gaussian(P.prob.seed, N, k, P.Om, N, st));
   AZ_TRY(ops_apply_A(P, P.Om, N, k, 1.0, 0.0, nullptr, 0, P.Q, Mt, st));        // Y = A Omega
   AZ_TRY(ops_apply_AZ(P, P.Q, Mt, k, -1.0, 1.0, P.Q, Mt, P.Q, Mt, P.Om2, st));  // W = Y - A Z* Y
   // 2. W = Q R
   P.ldq = Mt;
-  AZ_TRY(wide_qr(P.Q, Mt, k, P.Rf, scr, Lx, rproj, plan_tsqr_rows(P, PB), st));
+  AZ_TRY(wide_qr(P.Q, Mt, k, P.Rf, scr, Lx, rproj, plan_tsqr_rows(P, PB), st, ss, part2, rproj2));
   // 3. block one-sided Jacobi, preconditioned: R^T = Q2 R2 (the same QR),
   // then Jacobi on G = R2^T with the rotations accumulated onto V = Q2
   // (fewer sweeps: the QR concentrates the weight of R2's rows on its
@@ -510,7 +577,7 @@ int wide_factor(Plan& P, hipStream_t st) {
     dim3 tg((unsigned)((k + 31) / 32), (unsigned)((k + 31) / 32));
     launch_kernel(k_transpose, tg, 256, 0, st, k, P.Rf, P.Vj);
     AZ_HIP(hipGetLastError());
-    AZ_TRY(wide_qr(P.Vj, k, k, P.Pm, scr, Lx, rproj, plan_tsqr_rows(P, PB), st));    // Vj = Q2, Pm = R2 (scratch until step 4)
+    AZ_TRY(wide_qr(P.Vj, k, k, P.Pm, scr, Lx, rproj, plan_tsqr_rows(P, PB), st, ss, part2, rproj2));    // Vj = Q2, Pm = R2 (scratch until step 4)
     launch_kernel(k_transpose, tg, 256, 0, st, k, P.Pm, P.Gj);
     AZ_HIP(hipGetLastError());
   }
