@@ -473,6 +473,79 @@ def copies_1d(log_fn, copies=4096, plain=64):
     return out
 
 
+def uneven_1d(log_fn, count=256, seed=77, reps=3):
+    """Many small 1D problems of uneven sizes with resident factors, the
+    per-request work of a serving loop: N = 2^10 .. 2^13, s = 2 or 3,
+    eps*h in [0.48, 0.52], seeded intervals inside [-0.7, 0.7], 1..16
+    random-trig right-hand sides each.  Solved one plan after another
+    (azrbf_solve), on four streams (azrbf_solve_many) and in one grouped call
+    (azrbf_solve_batched); every mode counts only right-hand sides with a
+    residual <= 1e-10."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2308_14490_amd import azrbf, problems
+    rng = np.random.default_rng(seed)
+    probs = []
+    for i in range(count):
+        n = int(2 ** rng.integers(10, 14))
+        s = int(rng.integers(2, 4))
+        eh = float(rng.uniform(0.48, 0.52))
+        c = float(rng.uniform(-0.2, 0.2))
+        w = float(rng.uniform(0.35, 0.5))
+        nr = int(rng.integers(1, 17))
+        probs.append(W.Problem(f"u{i}", 1, n, s, 1.0, eh, W.interval(c - w, c + w),
+                               [W.trig_sum_1d(10000 * seed + 32 * i + j) for j in range(nr)], k=32))
+    plans = [problems.plan_for(p) for p in probs]
+    Bs = [problems.rhs_for(pl, p) for pl, p in zip(plans, probs)]
+    for pl in plans:
+        azrbf.factor(pl)
+    nrhs = sum(B.shape[0] for B in Bs)
+    Xs = [torch.empty((B.shape[0], pl.N), dtype=torch.float64, device=B.device) for pl, B in zip(plans, Bs)]
+    rels = [torch.empty(B.shape[0], dtype=torch.float64, device=B.device) for B in Bs]
+
+    def good():
+        return sum(int((r <= 1e-10).sum()) for r in rels)
+
+    def plain():
+        for pl, B, X, r in zip(plans, Bs, Xs, rels):
+            azrbf.solve(pl, B, X, r)
+
+    def many():
+        azrbf.solve_many(plans, Bs, Xs)
+
+    def grouped():
+        azrbf.solve_batched(plans, Bs, Xs, rels)
+
+    out = {"workload": f"{count} 1D problems, N = 2^10..2^13, s = 2..3, eps*h 0.48..0.52, seeded intervals, "
+                       f"1..16 RHS each ({nrhs} in all), factors resident",
+           "problems": count, "rhs": nrhs}
+    for name, fn in (("plain", plain), ("solve_many", many), ("grouped", grouped)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ok = 0
+        for _ in range(reps):
+            fn()
+            torch.cuda.synchronize()
+            if name != "solve_many":
+                ok += good()
+        dt = time.perf_counter() - t0
+        if name == "solve_many":     # solve_many returns its own residual arrays: count them once more
+            _, rr = azrbf.solve_many(plans, Bs, Xs)
+            torch.cuda.synchronize()
+            ok = reps * sum(int((r <= 1e-10).sum()) for r in rr)
+        out[name] = {"solves_per_s": round(ok / dt, 1), "problems_per_s": round(reps * count / dt, 1),
+                     "ms_per_pass": round(dt / reps * 1e3, 3)}
+        log_fn(f"uneven 1D {name}: {out[name]}")
+    out["grouped_over_plain"] = round(out["grouped"]["solves_per_s"] / out["plain"]["solves_per_s"], 2)
+    out["grouped_over_solve_many"] = round(out["grouped"]["solves_per_s"] / out["solve_many"]["solves_per_s"], 2)
+    for pl in plans:
+        pl.destroy()
+    azrbf.release_cached_memory()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -497,6 +570,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=None, help="open-loop arrival rate (req/s)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps only (for rocprofv3 runs)")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="run only the uneven-problems comparison (plain, solve_many, grouped) and print its JSON")
     ap.add_argument("--only-2d", action="store_true",
                     help="run only the full-size 2D factorisation and solve, print its figures as JSON "
                          "(for rocprofv3 runs of the wide-sketch stage)")
@@ -515,6 +590,9 @@ def main():
     dev = torch.device("cuda", 0)
     if args.only_2d:
         print(json.dumps(wide_2d(log)), flush=True)
+        return 0
+    if args.uneven_only:
+        print(json.dumps(uneven_1d(log)), flush=True)
         return 0
     sides = tuple(int(v) for v in args.serve_sides.split(","))
     if args.served_only:
@@ -678,6 +756,7 @@ def main():
         out["served_stream"] = served_vs_plain(args.serve_count, 2024, sides, log)
     out["fft_passes_beyond_cache"] = beyond_cache(log)
     out["copies_1d_n256"] = copies_1d(log)
+    out["uneven_1d"] = uneven_1d(log)
     out["million_1d"] = million_1d(log)
     out["million_1d_exact"] = million_1d(log, n=10 ** 6)
     out["transform_paths"] = transform_paths(log)

@@ -223,6 +223,33 @@ int azrbf_solve_many(int32_t nprob, const azrbf_plan_t* plans,
                      double* const* X, const int64_t* ldx, double* const* relres,
                      void* stream);
 
+/* Grouped form of azrbf_solve (Algorithm 1 and its refinement passes, the
+ * solve phase of section 3.2.3) for many small problems of uneven sizes, on
+ * the caller's stream.  Entries whose plan is 1D on the single-kernel
+ * transform (n a power of two <= 8192, no boundary rows, sketch width <= 64)
+ * share every launch: one pass over all of them is seven launches (the
+ * transforms once per size class (n, s)), however many entries and sizes
+ * there are, instead of about twenty per plan.  Other entries are solved one
+ * after another as by azrbf_solve.  Plans that are not factored are factored
+ * first, on the stream (one after another).  Arrays have length nprob; entry
+ * i solves plans[i] for nrhs[i] right-hand sides B[i] ((M + Mb) x nrhs[i],
+ * ld ldb[i], device) into X[i] (N x nrhs[i], ld ldx[i], device), with
+ * relres[i] (device, nrhs[i] doubles) receiving ||B - A X|| / ||B|| per
+ * column when relres and relres[i] are not NULL.  A plan may appear in
+ * several entries (each has its own workspace; their X must not overlap).
+ * The grouped dense products sum in another order than azrbf_solve's, so the
+ * results agree with it to rounding, not bit for bit.  The library keeps
+ * staging buffers per device (descriptors in pinned host memory, workspace in
+ * device memory, reused once the previous call's work is done) and the call
+ * returns once the work is queued; a plan must not be destroyed or factored
+ * again while that work is queued.  Errors: EINVAL (bad sizes or pointers,
+ * plans of another device, more than 65535 entries), EHIP, else the first
+ * failing plan's code. */
+int azrbf_solve_batched(int32_t nprob, const azrbf_plan_t* plans,
+                        const double* const* B, const int64_t* ldb, const int64_t* nrhs,
+                        double* const* X, const int64_t* ldx, double* const* relres,
+                        void* stream);
+
 /* Device bytes a plan for prob needs (plan + factor + workspace for up to
  * max_rhs right-hand sides per call); used for admission by memory. */
 int64_t azrbf_footprint_bytes(const azrbf_problem* prob, int64_t max_rhs);

@@ -68,6 +68,9 @@ EXPORTS = {
     "azrbf_solve_many": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P),
                                         ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_P),
                                         ctypes.POINTER(_I64), ctypes.POINTER(_P), _P]),
+    "azrbf_solve_batched": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P),
+                                           ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_P),
+                                           ctypes.POINTER(_I64), ctypes.POINTER(_P), _P]),
     "azrbf_footprint_bytes": (ctypes.c_int64, [ctypes.POINTER(_Problem), _I64]),
     "azrbf_get_factor": (ctypes.c_int, [_P, ctypes.c_int32, _P, _I64, _P]),
     "azrbf_gaussian": (ctypes.c_int, [ctypes.c_uint64, _I64, _I64, _P, _I64, _P]),
@@ -319,6 +322,36 @@ def solve(p, B, X=None, relres=None, stream=None):
                               _stream(stream)), "azrbf_solve")
     p.k = p.dims()[4]       # a first solve factors, and the width may have grown
     return X, relres
+
+
+def _many_args(plans, Bs, Xs, rels):
+    n = len(plans)
+    hp = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    bp = (ctypes.c_void_p * n)()
+    xp = (ctypes.c_void_p * n)()
+    rp = (ctypes.c_void_p * n)()
+    ldb = (ctypes.c_int64 * n)()
+    ldx = (ctypes.c_int64 * n)()
+    nr = (ctypes.c_int64 * n)()
+    for i, (p, B, X, r) in enumerate(zip(plans, Bs, Xs, rels)):
+        B, nrhs, lb = _vecs(B, p.Mt, "B")
+        X, _, lx = _vecs(X, p.N, "X")
+        bp[i], xp[i], rp[i] = B.data_ptr(), X.data_ptr(), r.data_ptr()
+        ldb[i], ldx[i], nr[i] = lb, lx, nrhs
+    return hp, bp, ldb, nr, xp, ldx, rp
+
+
+def solve_batched(plans, Bs, Xs=None, rels=None, stream=None):
+    """Grouped solve of many (possibly repeated) plans in one call, each with
+    its own right-hand sides; returns (Xs, relres list)."""
+    n = len(plans)
+    Xs = Xs or [torch.empty((B.shape[0], p.N), dtype=torch.float64, device=B.device) for p, B in zip(plans, Bs)]
+    rels = rels or [torch.empty(B.shape[0], dtype=torch.float64, device=B.device) for B in Bs]
+    args = _many_args(plans, Bs, Xs, rels)
+    _check(_lib().azrbf_solve_batched(n, *args, _stream(stream)), "azrbf_solve_batched")
+    for p in plans:
+        p.k = p.dims()[4]
+    return Xs, rels
 
 
 def solve_many(plans, Bs, Xs=None, stream=None):

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libazrbf.so")
-SOURCES = ["ops.hip", "generic.hip", "dense.hip", "tsqr.hip", "gemm.hip", "wide.hip", "tune.hip", "plan.hip"]
+SOURCES = ["ops.hip", "generic.hip", "dense.hip", "tsqr.hip", "gemm.hip", "wide.hip", "batched.hip", "tune.hip", "plan.hip"]
 ARCH = os.environ.get("AZRBF_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -55,6 +55,22 @@ struct Geo {
   double k2, opscale;        // BVP: spectrum = opscale*(d2 d0 + d0 d2 + k2 d0 d0)
 };
 
+// One operand block of a grouped operator launch (1D plans on the
+// single-kernel transform): out = alpha * op(in) + beta * yin, column-major
+// blocks of nvec vectors, op = A (in: coefficients, out: collocation rows) or
+// Z* (the reverse).  nvec = 0 leaves the entry out of the launch.
+struct BatOp {
+  Geo g;
+  const double2* tw;
+  const double* in;
+  int64_t ldin, nvec;
+  double alpha, beta;
+  const double* yin;
+  int64_t ldyi;
+  double* out;
+  int64_t ldo;
+};
+
 struct Plan;
 
 // Per-launch timing (plan.hip).  When enabled, a Prof object brackets the
@@ -117,6 +133,10 @@ int ops_norms(Plan& P, hipStream_t st);
 // Work on a stream other than the plan's own first waits for its set-up
 // (and for a factor queued on another stream).
 int plan_on_stream(Plan& P, hipStream_t st);
+// One launch of op (0: A, 1: Z*) over count device-resident operand blocks of
+// the size class (n, s); maxvec bounds their nvec.  bytes: the launch's
+// algorithmic traffic (for per-launch timing).
+int ops_batched(int which, int n, int s, const BatOp* ops, int count, int64_t maxvec, double bytes, hipStream_t st);
 // Marks the end of set-up or factor work queued on st.
 int plan_mark_ready(Plan& P, hipStream_t st);
 // Reads back rank and sweeps of a factor queued without waiting.
@@ -217,6 +237,19 @@ int dense_first_qtc(Plan& P, int64_t nrhs, hipStream_t st);
 // qtc_done: so is its Q^T c
 int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
                 double* relres, hipStream_t st, bool first_done = false, bool qtc_done = false);
+
+// batched.hip: the grouped solve of many factored 1D plans (one entry per
+// block of right-hand sides; a plan may appear in several entries).
+struct BatchItem {
+  Plan* P;
+  const double* B;
+  int64_t ldb, nrhs;
+  double* X;
+  int64_t ldx;
+  double* relres;
+};
+bool batched_eligible(const Plan& P);
+int batched_solve(const std::vector<BatchItem>& items, hipStream_t st);
 
 struct Plan {
   azrbf_problem prob{};

@@ -93,14 +93,15 @@ struct Fused {
 // (rows s*e + r): they are computed into registers first and written
 // together, so each store instruction covers contiguous rows.
 template <int N, int S>
-__global__ void __launch_bounds__(Fused<N>::BLOCK)
-k_fused_A(Geo g, const double2* __restrict__ tw, const double* __restrict__ X, int64_t ldx,
-          int64_t nvec, double alpha, double beta, const double* Yin, int64_t ldyi, double* Y, int64_t ldy) {
+__device__ __forceinline__ void fused_A_block(const Geo& g, const double2* __restrict__ tw,
+                                              const double* __restrict__ X, int64_t ldx, int64_t nvec, double alpha,
+                                              double beta, const double* Yin, int64_t ldyi, double* Y, int64_t ldy,
+                                              int64_t blk) {
   using F = Fused<N>;
   extern __shared__ double2 smem[];
   const RowLds lds{smem, RowLds::stride(N)};
   const int t = threadIdx.x % F::T, line = threadIdx.x / F::T;
-  const int64_t v0 = 2 * ((int64_t)blockIdx.x * F::LINES + line);
+  const int64_t v0 = 2 * (blk * F::LINES + line);
   double2 a[RADIX];
 #pragma unroll
   for (int m = 0; m < RADIX; ++m) a[m] = load_pair(X, ldx, t + m * F::T, v0, nvec);
@@ -126,13 +127,21 @@ k_fused_A(Geo g, const double2* __restrict__ tw, const double* __restrict__ X, i
 
 template <int N, int S>
 __global__ void __launch_bounds__(Fused<N>::BLOCK)
-k_fused_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R, int64_t ldr,
-          int64_t nvec, double alpha, double beta, const double* Zin, int64_t ldzi, double* Z, int64_t ldz) {
+k_fused_A(Geo g, const double2* __restrict__ tw, const double* __restrict__ X, int64_t ldx,
+          int64_t nvec, double alpha, double beta, const double* Yin, int64_t ldyi, double* Y, int64_t ldy) {
+  fused_A_block<N, S>(g, tw, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, blockIdx.x);
+}
+
+template <int N, int S>
+__device__ __forceinline__ void fused_Z_block(const Geo& g, const double2* __restrict__ tw,
+                                              const double* __restrict__ R, int64_t ldr, int64_t nvec, double alpha,
+                                              double beta, const double* Zin, int64_t ldzi, double* Z, int64_t ldz,
+                                              int64_t blk) {
   using F = Fused<N>;
   extern __shared__ double2 smem[];
   const RowLds lds{smem, RowLds::stride(N)};
   const int t = threadIdx.x % F::T, line = threadIdx.x / F::T;
-  const int64_t v0 = 2 * ((int64_t)blockIdx.x * F::LINES + line);
+  const int64_t v0 = 2 * (blk * F::LINES + line);
   double2 in[S][RADIX];
 #pragma unroll
   for (int m = 0; m < RADIX; ++m) {
@@ -157,6 +166,30 @@ k_fused_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R, i
 #pragma unroll
     for (int m = 0; m < RADIX; ++m) store_pair(Z, ldz, Zin, ldzi, t + m * F::T, v0, nvec, acc[m], alpha, beta);
   }
+}
+
+template <int N, int S>
+__global__ void __launch_bounds__(Fused<N>::BLOCK)
+k_fused_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R, int64_t ldr,
+          int64_t nvec, double alpha, double beta, const double* Zin, int64_t ldzi, double* Z, int64_t ldz) {
+  fused_Z_block<N, S>(g, tw, R, ldr, nvec, alpha, beta, Zin, ldzi, Z, ldz, blockIdx.x);
+}
+
+// Grouped launches over many plans of one size class (N, S): entry blockIdx.y
+// of the operand list, its line block blockIdx.x.  Blocks past an entry's
+// vectors leave at once (the whole block: the transform synchronises it).
+template <int N, int S>
+__global__ void __launch_bounds__(Fused<N>::BLOCK) k_bat_A(const BatOp* __restrict__ ops) {
+  const BatOp o = ops[blockIdx.y];
+  if (2 * (int64_t)blockIdx.x * Fused<N>::LINES >= o.nvec) return;
+  fused_A_block<N, S>(o.g, o.tw, o.in, o.ldin, o.nvec, o.alpha, o.beta, o.yin, o.ldyi, o.out, o.ldo, blockIdx.x);
+}
+
+template <int N, int S>
+__global__ void __launch_bounds__(Fused<N>::BLOCK) k_bat_Z(const BatOp* __restrict__ ops) {
+  const BatOp o = ops[blockIdx.y];
+  if (2 * (int64_t)blockIdx.x * Fused<N>::LINES >= o.nvec) return;
+  fused_Z_block<N, S>(o.g, o.tw, o.in, o.ldin, o.nvec, o.alpha, o.beta, o.yin, o.ldyi, o.out, o.ldo, blockIdx.x);
 }
 
 // Forward FFT of complex lines (spectra set-up), natural order, length N <= 8192.
@@ -870,6 +903,42 @@ static int launch_fused_A(const Plan& P, const double* X, int64_t ldx, int64_t n
     case 3: return launch_fused_A_s<N, 3>(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st);
     default: return launch_fused_A_s<N, 4>(P, X, ldx, nvec, alpha, beta, Yin, ldyi, Y, ldy, st);
   }
+}
+
+template <int N, int S>
+static int launch_bat_s(int which, const BatOp* ops, int count, int64_t maxvec, double bytes, hipStream_t st) {
+  using F = Fused<N>;
+  const int64_t blocks = ((maxvec + 1) / 2 + F::LINES - 1) / F::LINES;
+  const dim3 grid((unsigned)blocks, (unsigned)count);
+  if (which == 0) {
+    AZ_TRY(set_lds(k_bat_A<N, S>, F::LDS));
+    static const std::string name = "bat_A n=" + std::to_string(N);
+    Prof pr(name.c_str(), bytes, st);
+    launch_kernel(k_bat_A<N, S>, grid, dim3(F::BLOCK), F::LDS, st, ops);
+  } else {
+    AZ_TRY(set_lds(k_bat_Z<N, S>, F::LDS));
+    static const std::string name = "bat_Z n=" + std::to_string(N);
+    Prof pr(name.c_str(), bytes, st);
+    launch_kernel(k_bat_Z<N, S>, grid, dim3(F::BLOCK), F::LDS, st, ops);
+  }
+  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+}
+
+template <int N>
+static int launch_bat(int which, int s, const BatOp* ops, int count, int64_t maxvec, double bytes, hipStream_t st) {
+  switch (s) {
+    case 1: return launch_bat_s<N, 1>(which, ops, count, maxvec, bytes, st);
+    case 2: return launch_bat_s<N, 2>(which, ops, count, maxvec, bytes, st);
+    case 3: return launch_bat_s<N, 3>(which, ops, count, maxvec, bytes, st);
+    case 4: return launch_bat_s<N, 4>(which, ops, count, maxvec, bytes, st);
+    default: return AZRBF_EUNSUPPORTED;
+  }
+}
+
+int ops_batched(int which, int n, int s, const BatOp* ops, int count, int64_t maxvec, double bytes, hipStream_t st) {
+  if (count <= 0 || maxvec <= 0) return AZRBF_OK;
+  if (count > 65535 || (which != 0 && which != 1)) return AZRBF_EINVAL;
+  AZ_SWITCH_N(n, launch_bat, which, s, ops, count, maxvec, bytes, st)
 }
 
 template <int N, int S>

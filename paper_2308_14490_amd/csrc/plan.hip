@@ -797,6 +797,48 @@ int azrbf_solve_many(int32_t nprob, const azrbf_plan_t* plans, const double* con
   return rc;
 }
 
+int azrbf_solve_batched(int32_t nprob, const azrbf_plan_t* plans, const double* const* B, const int64_t* ldb,
+                        const int64_t* nrhs, double* const* X, const int64_t* ldx, double* const* relres,
+                        void* stream) {
+  if (nprob < 0 || nprob > 65535 || (nprob > 0 && (!plans || !B || !ldb || !nrhs || !X || !ldx))) return AZRBF_EINVAL;
+  if (nprob == 0) return AZRBF_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return AZRBF_EHIP;
+  for (int32_t i = 0; i < nprob; ++i) {
+    if (!plans[i] || nrhs[i] < 0) return AZRBF_EINVAL;
+    const Plan& P = plans[i]->p;
+    if (P.device != dev) return AZRBF_EINVAL;
+    if (nrhs[i] > 0 && (!B[i] || !X[i] || ldb[i] < P.Mt || ldx[i] < P.N)) return AZRBF_EINVAL;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  // set-up and factors first (each plan once), then the other entries one by
+  // one, then the grouped entries together
+  std::vector<az::BatchItem> items;
+  for (int32_t i = 0; i < nprob; ++i) {
+    if (nrhs[i] == 0) continue;
+    Plan& P = plans[i]->p;
+    P.last_stream = st;
+    AZ_TRY(az::plan_on_stream(P, st));
+    if (!P.factored) {
+      const int rc = az::factor_plan(P, st);
+      if (rc != AZRBF_OK && rc != AZRBF_ERANK) return rc;
+    }
+  }
+  for (int32_t i = 0; i < nprob; ++i) {
+    if (nrhs[i] == 0) continue;
+    Plan& P = plans[i]->p;
+    double* rr = relres ? relres[i] : nullptr;
+    if (az::batched_eligible(P)) {
+      items.push_back(az::BatchItem{&P, B[i], ldb[i], nrhs[i], X[i], ldx[i], rr});
+    } else if (P.k > 64) {
+      AZ_TRY(az::wide_solve(P, B[i], ldb[i], nrhs[i], X[i], ldx[i], rr, st));
+    } else {
+      AZ_TRY(az::dense_solve(P, B[i], ldb[i], nrhs[i], X[i], ldx[i], rr, st));
+    }
+  }
+  return az::batched_solve(items, st);
+}
+
 int64_t azrbf_footprint_bytes(const azrbf_problem* pr, int64_t max_rhs) {
   if (!pr || pr->n <= 0 || pr->s <= 0 || (pr->dim != 1 && pr->dim != 2) || max_rhs < 0) return -1;
   const int64_t n = pr->n, s = pr->s;

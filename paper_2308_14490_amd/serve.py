@@ -21,6 +21,10 @@ Scheduling is continuous: the run loop never waits for the GPU as a whole.
     group is handed to the backend at once and runs on its own stream, beside
     the groups already in flight (a 1D solve does not wait for a 2D
     factorisation that started before it).
+  * Groups of one admission pass whose plans are resident small 1D plans
+    (single-kernel transform, no boundary rows) go to the GPU together in one
+    grouped solve (azrbf_solve_batched): seven launches per refinement pass
+    for all of them instead of about twenty per group.
   * Completion is polled through per-group events; a finished group's
     results are recorded and its plan becomes idle and resident.
 
@@ -100,6 +104,50 @@ class _GpuGroup:
         return plan, parts
 
 
+class _Member:
+    """One group of a grouped solve: shares the grouped call's handle."""
+
+    def __init__(self, shared, i):
+        self.shared, self.i = shared, i
+
+    def done(self):
+        return self.shared.done()
+
+    def result(self):
+        return self.shared.result()[self.i]
+
+
+class _GpuBatch:
+    """Several groups solved in one grouped call: the worker's future, then
+    the completion event."""
+
+    def __init__(self, future, keep_x):
+        self.future = future
+        self.keep_x = keep_x
+        self._res = None
+
+    def done(self):
+        if not self.future.done():
+            return False
+        if self.future.exception() is not None:
+            return True
+        return self.future.result()[1].query()
+
+    def result(self):
+        if self._res is None:
+            items, ev = self.future.result()
+            ev.synchronize()
+            self._res = []
+            for plan, X, rel, sizes in items:
+                rr = rel.cpu().numpy()
+                parts, o = [], 0
+                for n in sizes:
+                    parts.append((X[o:o + n] if self.keep_x else None, rr[o:o + n]))
+                    o += n
+                self._res.append((plan, parts))
+        return self._res
+
+
 class GpuBackend:
     """Plans, right-hand sides and solves on the current HIP device.  Each
     group is queued by a worker thread on that thread's own stream (default
@@ -161,6 +209,34 @@ class GpuBackend:
         plan None: make it first).  Returns a handle with done()/result()."""
         return _GpuGroup(self._pool.submit(self._work, plan, probs), self.keep_x)
 
+    def batchable(self, plan):
+        """Whether a resident plan's groups share the grouped solve's
+        launches (1D on the single-kernel transform, no boundary rows, sketch
+        width <= 64)."""
+        return (plan.dim == 1 and plan.N <= 8192 and (plan.N & (plan.N - 1)) == 0 and plan.Mb == 0
+                and plan.k <= 64)
+
+    def _work_batch(self, items):
+        torch = self.torch
+        st = self._stream()
+        with torch.cuda.stream(st):
+            plans, Bs, sizes = [], [], []
+            for plan, probs in items:
+                bl = [self.problems.rhs_for(plan, p, device=self.dev) for p in probs]
+                plans.append(plan)
+                Bs.append(torch.cat(bl, 0).contiguous() if len(bl) > 1 else bl[0])
+                sizes.append([b.shape[0] for b in bl])
+            Xs, rels = self.azrbf.solve_batched(plans, Bs, stream=st)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return [(pl, X, r, sz) for pl, X, r, sz in zip(plans, Xs, rels, sizes)], ev
+
+    def launch_batch(self, items):
+        """Queues one grouped solve of several groups [(resident plan,
+        problems)]; returns one handle per group."""
+        shared = _GpuBatch(self._pool.submit(self._work_batch, items), self.keep_x)
+        return [_Member(shared, i) for i in range(len(items))]
+
     def destroy(self, plan):
         plan.destroy()
 
@@ -200,6 +276,7 @@ class Server:
         self.ticks = []                          # per launched group: (t_admit, t_done, n_requests, new plan)
         self.evictions = 0
         self.created = 0
+        self.batched_calls = 0                   # grouped solves launched
         self.peak_committed = 0
 
     def resident_bytes(self):
@@ -282,6 +359,7 @@ class Server:
                     progress(len(results), len(requests))
             if queue:
                 t_admit = be.now() - t0
+                batch = []        # resident groups that share one grouped solve
                 for key, (reqs, reserve) in self._admit(queue).items():
                     new = key not in self.cache
                     if new:
@@ -289,8 +367,22 @@ class Server:
                     else:
                         self.cache.move_to_end(key)
                     plan = None if new else self.cache[key][0]
+                    if plan is not None and hasattr(be, "launch_batch") and be.batchable(plan):
+                        batch.append((key, reqs, reserve, plan))
+                        continue
                     handle = be.launch(plan, [r.problem for r in reqs])
                     self.flights[key] = _Flight(key, reqs, handle, t_admit, new, reserve)
+                    progressed = True
+                if len(batch) == 1:
+                    key, reqs, reserve, plan = batch[0]
+                    self.flights[key] = _Flight(key, reqs, be.launch(plan, [r.problem for r in reqs]), t_admit,
+                                                False, reserve)
+                    progressed = True
+                elif batch:
+                    handles = be.launch_batch([(plan, [r.problem for r in reqs]) for _, reqs, _, plan in batch])
+                    for (key, reqs, reserve, _), h in zip(batch, handles):
+                        self.flights[key] = _Flight(key, reqs, h, t_admit, False, reserve)
+                    self.batched_calls += 1
                     progressed = True
                 self.peak_committed = max(self.peak_committed, self.committed_bytes())
             if progressed:

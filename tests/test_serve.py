@@ -219,3 +219,50 @@ def test_operator_key_ignores_the_seed_but_not_the_domain():
     assert serve.operator_key(a, m) != serve.operator_key(a, m2)
     c = W.family_1d(512, 2)
     assert serve.operator_key(a, m) != serve.operator_key(c, m)
+
+
+class BatchingBackend(FakeBackend):
+    """A fake backend with a grouped solve: resident plans whose key starts
+    with "s" (small) are batchable; a grouped call costs one solve."""
+
+    def __init__(self, budget=1e18):
+        super().__init__(budget)
+        self.batches = []
+
+    def batchable(self, plan):
+        return plan.key.startswith("s")
+
+    def launch_batch(self, items):
+        self.batches.append(sorted(plan.key for plan, _ in items))
+        finish = self.t + 0.1
+        hs = []
+        for plan, probs in items:
+            assert plan.alive and self.batchable(plan)
+            self.launches.append((plan.key, sum(len(p.rhs) for p in probs), self.t))
+            h = FakeHandle(self, plan, probs, finish)
+            self.live_handles.append(h)
+            hs.append(h)
+        return hs
+
+
+def test_resident_small_groups_of_one_pass_share_a_grouped_solve():
+    """First pass: three new operators, each factored on its own.  Second
+    pass (all resident): the two small operators' groups go in one grouped
+    call, the large one alone; every request gets its results."""
+    be = BatchingBackend()
+    srv = serve.Server(be, 1e9)
+    reqs = [FakeRequest(0, 0.0, FakeProblem("s1", 10, [1.0])),
+            FakeRequest(1, 0.0, FakeProblem("s2", 10, [1.0, 2.0])),
+            FakeRequest(2, 0.0, FakeProblem("L", 10, [1.0])),
+            FakeRequest(3, 5.0, FakeProblem("s1", 10, [1.0, 2.0, 3.0])),
+            FakeRequest(4, 5.0, FakeProblem("s2", 10, [1.0])),
+            FakeRequest(5, 5.0, FakeProblem("L", 10, [1.0])),
+            FakeRequest(6, 5.0, FakeProblem("s2", 10, [1.0]))]
+    res = srv.run(reqs)
+    assert sorted(res) == list(range(7))
+    assert be.created == ["s1", "s2", "L"]
+    assert be.batches == [["s1", "s2"]]
+    assert srv.batched_calls == 1
+    assert all(len(r.relres) == r.nrhs for r in res.values())
+    assert res[3].nrhs == 3 and res[4].done == res[3].done
+    assert res[6].admitted == res[4].admitted            # same operator, same group
