@@ -89,9 +89,14 @@ struct Fused {
 
 // ------------------------------------------------------------------ fused 1D
 
-// The s phase results of a coefficient index are adjacent on the fine grid
-// (rows s*e + r): they are computed into registers first and written
-// together, so each store instruction covers contiguous rows.
+// The s phases are transformed one at a time, each written (A) or
+// accumulated (Z*) at once, with the thread's indices opaque in each, so that
+// no address is computed ahead and held across the transforms.  Holding all
+// phases in registers to store the s rows of a coefficient index together
+// (contiguous rows per store) needed up to 512 registers per lane (occupancy
+// 1, scratch spills for s = 4 and for N = 8192, whose 512-thread blocks cap a
+// wave at 256) and was slower: the phases' rows meet again in L2 before they
+// go to HBM.
 template <int N, int S>
 __device__ __forceinline__ void fused_A_block(const Geo& g, const double2* __restrict__ tw,
                                               const double* __restrict__ X, int64_t ldx, int64_t nvec, double alpha,
@@ -106,20 +111,18 @@ __device__ __forceinline__ void fused_A_block(const Geo& g, const double2* __res
 #pragma unroll
   for (int m = 0; m < RADIX; ++m) a[m] = load_pair(X, ldx, t + m * F::T, v0, nvec);
   fft_line<N, false>(a, lds, line, t, tw);
-  double2 res[S][RADIX];
-#pragma unroll
+#pragma unroll 1
   for (int r = 0; r < S; ++r) {
+    const int tt = opaque(t), ll = opaque(line);
+    double2 res[RADIX];
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) res[r][m] = cmul(a[m], g.spA[(int64_t)r * N + t + m * F::T]);
-    fft_line<N, true>(res[r], lds, line, t, tw);
-  }
-  if (v0 < nvec) {
+    for (int m = 0; m < RADIX; ++m) res[m] = cmul(a[m], g.spA[(int64_t)r * N + tt + m * F::T]);
+    fft_line<N, true>(res, lds, ll, tt, tw);
+    if (v0 < nvec) {
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m) {
-#pragma unroll
-      for (int r = 0; r < S; ++r) {
-        const int64_t row = (int64_t)S * (t + m * F::T) + r - g.i0;
-        if (row >= 0 && row < g.M) store_pair(Y, ldy, Yin, ldyi, row, v0, nvec, res[r][m], alpha, beta);
+      for (int m = 0; m < RADIX; ++m) {
+        const int64_t row = (int64_t)S * (tt + m * F::T) + r - g.i0;
+        if (row >= 0 && row < g.M) store_pair(Y, ldy, Yin, ldyi, row, v0, nvec, res[m], alpha, beta);
       }
     }
   }
@@ -142,24 +145,21 @@ __device__ __forceinline__ void fused_Z_block(const Geo& g, const double2* __res
   const RowLds lds{smem, RowLds::stride(N)};
   const int t = threadIdx.x % F::T, line = threadIdx.x / F::T;
   const int64_t v0 = 2 * (blk * F::LINES + line);
-  double2 in[S][RADIX];
-#pragma unroll
-  for (int m = 0; m < RADIX; ++m) {
-#pragma unroll
-    for (int q = 0; q < S; ++q) {
-      const int64_t row = (int64_t)S * (t + m * F::T) + q - g.i0;
-      in[q][m] = (row >= 0 && row < g.M) ? load_pair(R, ldr, row, v0, nvec) : make_double2(0.0, 0.0);
-    }
-  }
   double2 acc[RADIX];
 #pragma unroll
   for (int m = 0; m < RADIX; ++m) acc[m] = make_double2(0.0, 0.0);
-#pragma unroll
+#pragma unroll 1
   for (int q = 0; q < S; ++q) {
-    fft_line<N, false>(in[q], lds, line, t, tw);
+    const int tt = opaque(t), ll = opaque(line);
+    double2 in[RADIX];
 #pragma unroll
-    for (int m = 0; m < RADIX; ++m)
-      acc[m] = cadd(acc[m], cmul(in[q][m], g.spZ[(int64_t)q * N + t + m * F::T]));
+    for (int m = 0; m < RADIX; ++m) {
+      const int64_t row = (int64_t)S * (tt + m * F::T) + q - g.i0;
+      in[m] = (row >= 0 && row < g.M) ? load_pair(R, ldr, row, v0, nvec) : make_double2(0.0, 0.0);
+    }
+    fft_line<N, false>(in, lds, ll, tt, tw);
+#pragma unroll
+    for (int m = 0; m < RADIX; ++m) acc[m] = cadd(acc[m], cmul(in[m], g.spZ[(int64_t)q * N + tt + m * F::T]));
   }
   fft_line<N, true>(acc, lds, line, t, tw);
   if (v0 < nvec) {
