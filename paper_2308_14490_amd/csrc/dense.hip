@@ -599,76 +599,6 @@ k_gemm_nn(const double* __restrict__ A, int64_t lda, int64_t m, int k, const dou
   }
 }
 
-constexpr int TN_ROWS = 256;   // rows per partial-sum block
-constexpr int TN_COLS = 64;    // right-hand sides per block
-
-// part[blk][v][c] = sum over the block's rows of Q[i, c] * C[i, v]
-// (k * TN_COLS outputs per block, up to 16 per thread).
-__global__ void __launch_bounds__(256)
-k_gemm_tn_part(const double* __restrict__ Q, int64_t ldq, int64_t m, int k, const double* __restrict__ C,
-               int64_t ldc, int64_t ncol, double* __restrict__ part) {
-  __shared__ double qs[32 * (KMAX + 1)];
-  __shared__ double cs[32 * (TN_COLS + 1)];
-  const int64_t r0 = (int64_t)blockIdx.x * TN_ROWS;
-  const int64_t v0 = (int64_t)blockIdx.y * TN_COLS;
-  const int nv = (int)std::min<int64_t>(TN_COLS, ncol - v0);
-  const int t = threadIdx.x;
-  const int nout = k * nv;
-  double acc[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-  const int64_t rend = std::min<int64_t>(m, r0 + TN_ROWS);
-  for (int64_t rb = r0; rb < rend; rb += 32) {
-    const int nr = (int)std::min<int64_t>(32, rend - rb);
-    for (int e = t; e < 32 * k; e += 256) {
-      const int r = e % 32, c = e / 32;
-      qs[r * (KMAX + 1) + c] = r < nr ? Q[rb + r + ldq * c] : 0.0;
-    }
-    for (int e = t; e < 32 * nv; e += 256) {
-      const int r = e % 32, v = e / 32;
-      cs[r * (TN_COLS + 1) + v] = r < nr ? C[rb + r + ldc * (v0 + v)] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = t + 256 * u;
-      if (e < nout) {
-        const int c = e % k, v = e / k;
-        double a = acc[u];
-#pragma unroll 8
-        for (int r = 0; r < 32; ++r) a = fma(qs[r * (KMAX + 1) + c], cs[r * (TN_COLS + 1) + v], a);
-        acc[u] = a;
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int e = t + 256 * u;
-    if (e < nout) {
-      const int c = e % k, v = e / k;
-      part[((int64_t)blockIdx.x * ncol + v0 + v) * k + c] = acc[u];
-    }
-  }
-}
-
-// T[c + k v] = sum_blk part[blk][v][c], blocks summed in order.
-__global__ void k_reduce_part(const double* __restrict__ part, int64_t nblk, int k, int64_t ncol,
-                              double* __restrict__ T) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)k * ncol) return;
-  // eight independent partial sums keep eight loads in flight
-  const int64_t st = ncol * k;
-  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  int64_t b = 0;
-  for (; b + 8 <= nblk; b += 8) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] += part[(b + u) * st + e];
-  }
-  for (; b < nblk; ++b) s[0] += part[b * st + e];
-  T[e] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-}
-
 constexpr int NORM_CHUNKS = 32;
 int relres_chunks() { return NORM_CHUNKS; }
 
@@ -716,22 +646,6 @@ static int gemm_nn(const double* A, int64_t lda, int64_t m, int k, const double*
   Prof pr("gemm_nn", 8.0 * m * (k + ncol * (beta != 0.0 ? 2.0 : 1.0)), st);
   launch_kernel(k_gemm_nn<16>, (unsigned)nblk, 256, 0, st, A, lda, m, k, B, ldb, ncol, alpha, Cin, ldci, beta, Out,
                 ldo, nrb, G);
-  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
-}
-
-static int64_t tn_blocks(int64_t m) { return (m + TN_ROWS - 1) / TN_ROWS; }
-
-static int gemm_tn(const double* Q, int64_t ldq, int64_t m, int k, const double* C, int64_t ldc, int64_t ncol,
-                   double* part, double* T, hipStream_t st) {
-  const int64_t nb = tn_blocks(m);
-  {
-    Prof pr("gemm_tn", 8.0 * m * (k + ncol), st);
-    launch_kernel(k_gemm_tn_part, dim3((unsigned)nb, (unsigned)((ncol + TN_COLS - 1) / TN_COLS)), 256, 0, st, Q, ldq,
-                  m, k, C, ldc, ncol, part);
-  }
-  AZ_HIP(hipGetLastError());
-  const int64_t ne = (int64_t)k * ncol;
-  launch_kernel(k_reduce_part, (unsigned)((ne + 255) / 256), 256, 0, st, part, nb, k, ncol, T);
   return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
