@@ -136,3 +136,40 @@ def test_1d_request_overtakes_a_2d_factorisation():
     alone.destroy()
     srv.close()
     be.close()
+
+
+def test_resident_small_1d_groups_share_a_grouped_solve():
+    """Three small 1D operators are factored by a first wave of requests; a
+    second wave for all three, arriving together once they are resident,
+    goes to the GPU in one grouped solve (azrbf_solve_batched), and each
+    result matches the request solved alone."""
+    azrbf, problems, serve = _mods()
+    ops = [W.family_1d(1024, 2, seed0=1000, name="g0"), W.family_1d(4096, 3, seed0=2000, name="g1"),
+           W.family_1d(8192, 1, seed0=3000, name="g2")]
+    reqs = [W.Request(i, 0.0, p) for i, p in enumerate(ops)]
+    second = []
+    for i, p in enumerate(ops):
+        q = W.family_1d(p.n, 2 + i, seed0=5000 + 100 * i, name=p.name + "b")
+        second.append(W.Request(10 + i, 1.0, q))
+    be = serve.GpuBackend(keep_x=True)
+    srv = serve.Server(be, budget_bytes=8 << 30)
+    res = srv.run(reqs + second)
+    announce("grouped serving", "created", srv.created, "grouped calls", srv.batched_calls)
+    assert srv.created == 3
+    assert srv.batched_calls == 1
+    for r in second:
+        p = r.problem
+        alone = problems.plan_for(p)
+        B = problems.rhs_for(alone, p)
+        Xa, ra = azrbf.solve(alone, B)
+        Ya = azrbf.apply_A(alone, Xa)
+        Ys = azrbf.apply_A(alone, res[r.rid].X)
+        torch.cuda.synchronize()
+        rs = torch.from_numpy(res[r.rid].relres)
+        diff = (torch.linalg.norm(Ya - Ys, dim=1) / torch.linalg.norm(B, dim=1)).cpu()
+        announce(p.name, "relres alone", ra.cpu().numpy(), "served", rs.numpy())
+        assert torch.all(rs <= 1e-10) and torch.all(ra.cpu() <= 1e-10)
+        assert torch.all(diff <= 10 * (ra.cpu() + rs) + 1e-13)
+        alone.destroy()
+    srv.close()
+    be.close()
