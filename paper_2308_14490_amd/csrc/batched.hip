@@ -59,48 +59,76 @@ __device__ __forceinline__ double wsum(double v) {
 }
 
 // Partial products of t = Q^T c over BQ_ROWS rows of one column block:
-// grid (row block, column block, entry).
+// grid (row block, column block, entry).  Thread (i, ph) = (t mod k, t / k)
+// sums column i of Q against the 16 right-hand sides over its share of each
+// 64-row slice; the next slice's loads are issued before the current one is
+// used (one slice in LDS, one in flight in registers).
 __global__ void __launch_bounds__(256) k_bat_qtc_part(const BatEntry* __restrict__ es, int it) {
   const BatEntry e = es[blockIdx.z];
   const int64_t r0 = (int64_t)blockIdx.x * BQ_ROWS, c0 = (int64_t)blockIdx.y * BCOLS;
   if (it > e.refine || r0 >= e.M || c0 >= e.nrhs) return;
   __shared__ double qs[KMAXB][BQ_SUB + 1];
   __shared__ double cs[BCOLS][BQ_SUB + 1];
-  const int tid = threadIdx.x, i = tid & 63, ph = tid >> 6;
-  const int k = e.k;
+  const int tid = threadIdx.x;
+  const int k = e.k;                       // 16, 32 or 64
+  const int i = tid % k, ph = tid / k;
+  const int nph = 256 / k, rpp = BQ_SUB / nph;
+  const int nq = k * BQ_SUB / 256;         // Q elements a thread stages per slice (4, 8 or 16)
   const int64_t r1 = r0 + BQ_ROWS < e.M ? r0 + BQ_ROWS : e.M;
+  double qn[KMAXB * BQ_SUB / 256], cn[BCOLS * BQ_SUB / 256];
+  auto fetch = [&](int64_t rs) {
+#pragma unroll
+    for (int u = 0; u < KMAXB * BQ_SUB / 256; ++u) {
+      if (u < nq) {
+        const int idx = u * 256 + tid, col = idx / BQ_SUB, r = idx % BQ_SUB;
+        qn[u] = rs + r < r1 ? e.Q[rs + r + (int64_t)col * e.Ld] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < BCOLS * BQ_SUB / 256; ++u) {
+      const int idx = u * 256 + tid, j = idx / BQ_SUB, r = idx % BQ_SUB;
+      cn[u] = c0 + j < e.nrhs && rs + r < r1 ? e.C[rs + r + (c0 + j) * e.Ld] : 0.0;
+    }
+  };
   double acc[BCOLS];
 #pragma unroll
   for (int j = 0; j < BCOLS; ++j) acc[j] = 0.0;
+  fetch(r0);
   for (int64_t rs = r0; rs < r1; rs += BQ_SUB) {
-    for (int idx = tid; idx < KMAXB * BQ_SUB; idx += 256) {
-      const int col = idx / BQ_SUB, r = idx % BQ_SUB;
-      qs[col][r] = col < k && rs + r < r1 ? e.Q[rs + r + (int64_t)col * e.Ld] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < KMAXB * BQ_SUB / 256; ++u) {
+      if (u < nq) {
+        const int idx = u * 256 + tid;
+        qs[idx / BQ_SUB][idx % BQ_SUB] = qn[u];
+      }
     }
-    for (int idx = tid; idx < BCOLS * BQ_SUB; idx += 256) {
-      const int j = idx / BQ_SUB, r = idx % BQ_SUB;
-      cs[j][r] = c0 + j < e.nrhs && rs + r < r1 ? e.C[rs + r + (c0 + j) * e.Ld] : 0.0;
+#pragma unroll
+    for (int u = 0; u < BCOLS * BQ_SUB / 256; ++u) {
+      const int idx = u * 256 + tid;
+      cs[idx / BQ_SUB][idx % BQ_SUB] = cn[u];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int rr = ph * (BQ_SUB / 4); rr < (ph + 1) * (BQ_SUB / 4); ++rr) {
+    if (rs + BQ_SUB < r1) fetch(rs + BQ_SUB);
+    for (int rr = ph * rpp; rr < (ph + 1) * rpp; ++rr) {
       const double q = qs[i][rr];
 #pragma unroll
       for (int j = 0; j < BCOLS; ++j) acc[j] = fma(q, cs[j][rr], acc[j]);
     }
-    __syncthreads();
   }
-  // the four row phases, summed in a fixed order
-  double* red = &qs[0][0];   // 4 x 64 x BCOLS <= 64 x (BQ_SUB + 1)
+  __syncthreads();
+  // the row phases, summed in a fixed order
+  double* red = &qs[0][0];   // nph x k x BCOLS = 256 x BCOLS <= KMAXB x (BQ_SUB + 1)
 #pragma unroll
-  for (int j = 0; j < BCOLS; ++j) red[(ph * 64 + i) * BCOLS + j] = acc[j];
+  for (int j = 0; j < BCOLS; ++j) red[(ph * k + i) * BCOLS + j] = acc[j];
   __syncthreads();
   const int64_t ncb = (e.nrhs + BCOLS - 1) / BCOLS;
   double* out = e.part + ((int64_t)blockIdx.x * ncb + blockIdx.y) * k * BCOLS;
   for (int o = tid; o < k * BCOLS; o += 256) {
     const int ii = o / BCOLS, j = o % BCOLS;
-    out[o] = (red[ii * BCOLS + j] + red[(64 + ii) * BCOLS + j]) +
-             (red[(128 + ii) * BCOLS + j] + red[(192 + ii) * BCOLS + j]);
+    double sum = 0.0;
+    for (int p = 0; p < nph; ++p) sum += red[(p * k + ii) * BCOLS + j];
+    out[o] = sum;
   }
 }
 
@@ -143,6 +171,8 @@ __global__ void __launch_bounds__(256) k_bat_xr(const BatEntry* __restrict__ es,
   double acc[BCOLS];
 #pragma unroll
   for (int j = 0; j < BCOLS; ++j) acc[j] = 0.0;
+  // (k is 16, 32 or 64: eight loads issued at a time)
+#pragma unroll 8
   for (int i = 0; i < k; ++i) {
     const double a = A[row + (int64_t)i * lda];
 #pragma unroll
