@@ -222,8 +222,10 @@ __global__ void k_copy_doubles(const double* __restrict__ a, double* __restrict_
 
 // W (m x k, leading dimension ld) is destroyed (level-0 reflectors); Q (m x k,
 // ld) and R (k x k, ld k) out.
+// after_first, if given, runs once the first level (the leaf blocks, the only
+// level that spreads over the whole GPU) has been queued.
 static int tsqr(double* W, int64_t m, int64_t ld, int k, int rb, double* scratch, double* Q, double* R,
-                hipStream_t st, hipEvent_t r_ready = nullptr) {
+                hipStream_t st, hipEvent_t r_ready = nullptr, const std::function<int()>* after_first = nullptr) {
   if (!tsqr_rows_ok(k, rb)) return AZRBF_EUNSUPPORTED;
   std::vector<TsqrLevel> lv;
   int64_t sd, ed;
@@ -242,6 +244,7 @@ static int tsqr(double* W, int64_t m, int64_t ld, int k, int rb, double* scratch
     Prof pr(l == 0 ? "tsqr_block" : "tsqr_block (tree)", 16.0 * L.m * k + 8.0 * L.nb * k * (k + 1), st);
     const int64_t lda = l == 0 ? ld : L.m;
     AZ_TRY(tsqr_block_qr(L.A, lda, L.m, k, rb, L.R, L.nb * k, L.A, lda, L.tau, st));
+    if (l == 0 && after_first) AZ_TRY((*after_first)());
   }
   // (a kernel rather than a runtime copy: a launch does not block the host)
   launch_kernel(k_copy_doubles, (unsigned)((k * k + 255) / 256), 256, 0, st, lv.back().R, R, (int64_t)k * k);
@@ -692,9 +695,15 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch, const
   AZ_TRY(dense_gaussian(P.prob.seed, N, k, P.Om, N, st));
   AZ_TRY(ops_apply_A(P, P.Om, N, k, 1.0, 0.0, nullptr, 0, P.Yf, Ld, st));     // Y = A Omega
   AZ_TRY(ops_apply_AZ(P, P.Yf, Ld, k, -1.0, 1.0, P.Yf, Ld, W, Ld, Zy, st));  // W = Y - A Z* Y
-  // what follows is latency-bound: work on other streams may start here
-  if (after_sketch) AZ_HIP(hipEventRecord(after_sketch, st));
-  if (on_sketch) AZ_TRY(on_sketch());
+  // What follows the leaf level of the TSQR is latency-bound (a few blocks
+  // per level, then one workgroup for the Jacobi SVD): work on other streams
+  // starts there.  (Started before the leaf level, it competed with the leaf
+  // blocks for the CUs and stretched that level from 48 to 79 us.)
+  const std::function<int()> after_first = [&]() -> int {
+    if (after_sketch) AZ_HIP(hipEventRecord(after_sketch, st));
+    if (on_sketch) AZ_TRY(on_sketch());
+    return AZRBF_OK;
+  };
   // TSQR destroys W; the QR is of the sketch, W is then free scratch.  The
   // Jacobi SVD needs only R: it runs on a second stream while this one forms
   // the explicit Q, and the products below (which overwrite W) wait for both.
@@ -707,7 +716,7 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch, const
   } else {
     js = st;
   }
-  int rc = tsqr(W, Mt, Ld, k, plan_tsqr_rows(P, k), tq, P.Q, P.Rf, st, js != st ? eR : nullptr);
+  int rc = tsqr(W, Mt, Ld, k, plan_tsqr_rows(P, k), tq, P.Q, P.Rf, st, js != st ? eR : nullptr, &after_first);
   if (!rc && js != st && hipStreamWaitEvent(js, eR, 0) != hipSuccess) rc = AZRBF_EHIP;
   if (!rc) {
     Prof pj("jacobi", 8.0 * 3 * k * k, js);
