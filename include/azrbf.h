@@ -337,7 +337,9 @@ int azrbf_profile_report(char* buf, int64_t len);
  * after it). */
 void azrbf_destroy(azrbf_plan_t plan);
 
-/* Frees the pool's cached device blocks (blocks owned by live plans stay). */
+/* Frees the pool's cached device blocks (blocks owned by live plans stay)
+ * and the grouped solve's staging buffers (after waiting for the calls that
+ * use them). */
 int azrbf_release_cached_memory(void);
 const char* azrbf_strerror(int code);
 

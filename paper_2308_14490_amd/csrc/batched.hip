@@ -241,6 +241,30 @@ int64_t up16(int64_t x) { return (x + 15) / 16 * 16; }
 
 }  // namespace
 
+int batched_release() {
+  std::lock_guard<std::mutex> lk(g_bat_mu);
+  int prev = 0;
+  AZ_HIP(hipGetDevice(&prev));
+  int rc = AZRBF_OK;
+  for (auto& kv : g_bat) {
+    if (hipSetDevice(kv.first) != hipSuccess) {
+      rc = AZRBF_EHIP;
+      continue;
+    }
+    for (BatSlot& sl : kv.second.slot) {
+      if (sl.used && hipEventSynchronize(sl.done) != hipSuccess) rc = AZRBF_EHIP;
+      if (sl.dev && hipFree(sl.dev) != hipSuccess) rc = AZRBF_EHIP;
+      if (sl.host && hipHostFree(sl.host) != hipSuccess) rc = AZRBF_EHIP;
+      sl.dev = nullptr;
+      sl.host = nullptr;
+      sl.dcap = sl.hcap = 0;
+      sl.used = false;
+    }
+  }
+  if (hipSetDevice(prev) != hipSuccess) rc = AZRBF_EHIP;
+  return rc;
+}
+
 bool batched_eligible(const Plan& P) {
   return P.dim == 1 && P.fused && !P.generic && P.Mb == 0 && P.k <= KMAXB && P.factored && P.Om && P.Yf && P.Q;
 }

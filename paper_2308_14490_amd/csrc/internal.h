@@ -250,6 +250,8 @@ struct BatchItem {
 };
 bool batched_eligible(const Plan& P);
 int batched_solve(const std::vector<BatchItem>& items, hipStream_t st);
+// Frees the grouped solve's staging buffers once their last calls are done.
+int batched_release();
 
 struct Plan {
   azrbf_problem prob{};

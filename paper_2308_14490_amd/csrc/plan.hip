@@ -1013,6 +1013,10 @@ void azrbf_destroy(azrbf_plan_t h) {
   delete h;
 }
 
-int azrbf_release_cached_memory(void) { return az::pool_trim(); }
+int azrbf_release_cached_memory(void) {
+  const int a = az::pool_trim();
+  const int b = az::batched_release();
+  return a != AZRBF_OK ? a : b;
+}
 
 }  // extern "C"

@@ -118,7 +118,8 @@ def test_grouped_solve_matches_per_plan_solves_and_oracle():
 def test_grouped_solve_second_call_reuses_staging():
     """Two more calls on the factored plans, the second with fewer entries
     and fewer right-hand sides: each equals a fresh grouped call's result on
-    the same inputs bit for bit (the staging buffers carry nothing over)."""
+    the same inputs bit for bit (the staging buffers carry nothing over), also
+    after the staging buffers have been released."""
     azrbf, problems, probs, plans_a, plans_b, Bs = _build(seed0=900)
     Xs1, r1 = azrbf.solve_batched(plans_b, Bs)
     sub = [0, 2, 4]
@@ -132,6 +133,12 @@ def test_grouped_solve_second_call_reuses_staging():
         assert torch.equal(a, b)
     for r in r1 + r2:
         assert float(r.max()) <= 1e-10
+    # the staging buffers freed in between: the next call allocates them again
+    azrbf.release_cached_memory()
+    Xs4, r4 = azrbf.solve_batched([plans_b[i] for i in sub], Bsub)
+    torch.cuda.synchronize()
+    for a, b in zip(Xs2, Xs4):
+        assert torch.equal(a, b)
     for pl in plans_a + plans_b:
         pl.destroy()
 
