@@ -480,7 +480,8 @@ def uneven_1d(log_fn, count=256, seed=77, reps=3):
     random-trig right-hand sides each.  Solved one plan after another
     (azrbf_solve), on four streams (azrbf_solve_many) and in one grouped call
     (azrbf_solve_batched); every mode counts only right-hand sides with a
-    residual <= 1e-10."""
+    residual <= 1e-10.  The cold passes make new plans each time (plan +
+    factor + solve; the grouped call factors them together)."""
     import numpy as np
     import torch
     import workloads as W
@@ -541,6 +542,31 @@ def uneven_1d(log_fn, count=256, seed=77, reps=3):
         out[name] = {"solves_per_s": round(ok / dt, 1), "problems_per_s": round(reps * count / dt, 1),
                      "ms_per_pass": round(dt / reps * 1e3, 3)}
         log_fn(f"uneven 1D {name}: {out[name]}")
+    # cold: new plans every pass (plan + factor + solve); grouped factors them together
+    def cold(mode):
+        ps = [problems.plan_for(p) for p in probs]
+        if mode == "plain":
+            for pl, B, X, r in zip(ps, Bs, Xs, rels):
+                azrbf.solve(pl, B, X, r)
+        elif mode == "solve_many":
+            azrbf.solve_many(ps, Bs, Xs)
+        else:
+            azrbf.solve_batched(ps, Bs, Xs, rels)
+        return ps
+    for name in ("plain", "solve_many", "grouped"):
+        for pl in cold(name):
+            pl.destroy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ps = cold(name)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = sum(int((r <= 1e-10).sum()) for r in rels) if name != "solve_many" else None
+        for pl in ps:
+            pl.destroy()
+        out["cold_" + name] = {"ms_per_pass": round(dt * 1e3, 2), "problems_per_s": round(count / dt, 1),
+                               "rhs_good": ok}
+        log_fn(f"uneven 1D cold {name}: {out['cold_' + name]}")
     out["grouped_over_plain"] = round(out["grouped"]["solves_per_s"] / out["plain"]["solves_per_s"], 2)
     out["grouped_over_solve_many"] = round(out["grouped"]["solves_per_s"] / out["solve_many"]["solves_per_s"], 2)
     for pl in plans:

@@ -231,7 +231,10 @@ int azrbf_solve_many(int32_t nprob, const azrbf_plan_t* plans,
  * transforms once per size class (n, s)), however many entries and sizes
  * there are, instead of about twenty per plan.  Other entries are solved one
  * after another as by azrbf_solve.  Plans that are not factored are factored
- * first, on the stream (one after another).  Arrays have length nprob; entry
+ * first: those that qualify together, with one launch per step for all of
+ * them (the same kernels in the same order per plan as azrbf_factor, so the
+ * same factor bit for bit; the call then waits for the factors to read their
+ * ranks), the others one after another.  Arrays have length nprob; entry
  * i solves plans[i] for nrhs[i] right-hand sides B[i] ((M + Mb) x nrhs[i],
  * ld ldb[i], device) into X[i] (N x nrhs[i], ld ldx[i], device), with
  * relres[i] (device, nrhs[i] doubles) receiving ||B - A X|| / ||B|| per

@@ -7,6 +7,7 @@
 // Sketch widths k <= 64: every TSQR block holds RB x k values in registers
 // (tsqr.hip), the Jacobi SVD of the k x k factor runs in one workgroup.
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstring>
 
@@ -33,9 +34,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
   return c;
 }
 
-__global__ void k_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* __restrict__ dst, int64_t ld) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t c = blockIdx.y;
+__device__ __forceinline__ void gaussian_quad(uint64_t seed, int64_t rows, int64_t cols, double* __restrict__ dst,
+                                              int64_t ld, int64_t q, int64_t c) {
   if (4 * q >= rows || c >= cols) return;
   const uint4 w = philox4x32_10(make_uint4((uint32_t)q, (uint32_t)c, 0u, 0u),
                                 make_uint2((uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)));
@@ -49,6 +49,10 @@ __global__ void k_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* __
   double* out = dst + c * ld;
   for (int i = 0; i < 4; ++i)
     if (4 * q + i < rows) out[4 * q + i] = z[i];
+}
+
+__global__ void k_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* __restrict__ dst, int64_t ld) {
+  gaussian_quad(seed, rows, cols, dst, ld, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
 }
 
 int dense_gaussian(uint64_t seed, int64_t rows, int64_t cols, double* dst, int64_t ld, hipStream_t st) {
@@ -81,9 +85,9 @@ constexpr int TSQR_THREADS = 256;
 // several independent outputs, and each row's k outputs accumulate side by
 // side, so no long chain of dependent FMAs forms.
 template <int K>
-__global__ void __launch_bounds__(TSQR_THREADS)
-k_tsqr_formq(const double* __restrict__ V, int64_t ldv, const double* __restrict__ Tin, int64_t m,
-             const double* __restrict__ Cup, int64_t ldc, double* __restrict__ E, int64_t lde, int RB) {
+__device__ __forceinline__ void formq_block(const double* __restrict__ V, int64_t ldv, const double* __restrict__ Tin,
+                                            int64_t m, const double* __restrict__ Cup, int64_t ldc,
+                                            double* __restrict__ E, int64_t lde, int RB, int64_t blk) {
   constexpr int LD = K + 1;
   constexpr int PER = K * K / TSQR_THREADS > 0 ? K * K / TSQR_THREADS : 1;   // outputs per thread
   __shared__ double Cb[K * LD];      // C_b[l][c] at c * LD + l
@@ -92,11 +96,11 @@ k_tsqr_formq(const double* __restrict__ V, int64_t ldv, const double* __restrict
   __shared__ double Xs[K * LD];      // X = V_top^T C_b, X[l][c] at c * LD + l
   double* Mr = Vt;                   // M = T X, row-major (M[l][c] at l * K + c), over V_top once used
   const int t = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * RB;
-  const double* Tb = Tin + (int64_t)blockIdx.x * K * K;
+  const int64_t r0 = blk * RB;
+  const double* Tb = Tin + blk * K * K;
   for (int e = t; e < K * K; e += TSQR_THREADS) {
     const int r = e % K, c = e / K;
-    Cb[c * LD + r] = Cup ? Cup[(int64_t)blockIdx.x * K + r + ldc * c] : (r == c ? 1.0 : 0.0);
+    Cb[c * LD + r] = Cup ? Cup[blk * K + r + ldc * c] : (r == c ? 1.0 : 0.0);
     Vt[c * LD + r] = r0 + r < m ? V[r0 + r + ldv * c] : 0.0;   // unit lower, zeros above
     Tm[c * LD + r] = Tb[e];                                     // T, upper triangular
   }
@@ -179,6 +183,13 @@ k_tsqr_formq(const double* __restrict__ V, int64_t ldv, const double* __restrict
       for (int c = 0; c < CH; ++c) E[gi + lde * (c0p + c)] = acc[c];
     }
   }
+}
+
+template <int K>
+__global__ void __launch_bounds__(TSQR_THREADS)
+k_tsqr_formq(const double* __restrict__ V, int64_t ldv, const double* __restrict__ Tin, int64_t m,
+             const double* __restrict__ Cup, int64_t ldc, double* __restrict__ E, int64_t lde, int RB) {
+  formq_block<K>(V, ldv, Tin, m, Cup, ldc, E, lde, RB, blockIdx.x);
 }
 
 struct TsqrLevel {
@@ -360,9 +371,10 @@ __device__ __forceinline__ void sum16x3(double& a, double& b, double& c) {
 // On exit: sig (descending), info = {rank, sweeps} with rank = #{sigma > thr},
 // thr = tau_k sqrt(max D) read from the device, Pm = sum_{i < rank} (Q2 W)_i u_i^T / sigma_i.
 template <int K>
-__global__ void __launch_bounds__(8 * K)
-k_jacobi(const double* __restrict__ R, double tau_k, const double* __restrict__ dmax, double tol, int max_sweeps,
-         double* __restrict__ sig, double* __restrict__ Pm, int* __restrict__ info) {
+__device__ __forceinline__ void jacobi_block(const double* __restrict__ R, double tau_k,
+                                             const double* __restrict__ dmax, double tol, int max_sweeps,
+                                             double* __restrict__ sig, double* __restrict__ Pm,
+                                             int* __restrict__ info) {
   constexpr int LD = K + 1;       // column stride (doubles) of the LDS matrices
   constexpr int NT = 8 * K;       // threads
   constexpr int RPL = K / 16;     // rows per lane in a rotation
@@ -538,6 +550,13 @@ k_jacobi(const double* __restrict__ R, double tau_k, const double* __restrict__ 
   }
 }
 
+template <int K>
+__global__ void __launch_bounds__(8 * K)
+k_jacobi(const double* __restrict__ R, double tau_k, const double* __restrict__ dmax, double tol, int max_sweeps,
+         double* __restrict__ sig, double* __restrict__ Pm, int* __restrict__ info) {
+  jacobi_block<K>(R, tau_k, dmax, tol, max_sweeps, sig, Pm, info);
+}
+
 int launch_jacobi(const double* R, int k, double tau_k, const double* dmax, double tol, int max_sweeps, double* sig,
                   double* Pm, int* info, hipStream_t st) {
   if (k == 16) launch_kernel(k_jacobi<16>, 1, 128, 0, st, R, tau_k, dmax, tol, max_sweeps, sig, Pm, info);
@@ -667,13 +686,10 @@ int relres_norms(const double* R, int64_t ldr, const double* B, int64_t ldb, int
 
 // ------------------------------------------------------------------ factor
 
-int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch, const std::function<int()>& on_sketch,
-                         const std::function<int()>& before_products) {
+// The factor's buffers (kept across factorisations of the plan).
+static int dense_factor_alloc(Plan& P) {
   const int k = P.k;
-  // the Jacobi kernel pairs k/2 columns over 256 threads: 512 / k must be a shuffle width
-  if (k != 16 && k != 32 && k != 64) return AZRBF_EUNSUPPORTED;
-  const int64_t N = P.N, Mt = P.Mt;
-  const int64_t Ld = P.Mtp;   // leading dimension of the row-space matrices (whole 128-byte lines)
+  const int64_t N = P.N, Mt = P.Mt, Ld = P.Mtp;
   if (!P.Om) {
     AZ_TRY(P.alloc((void**)&P.Om, sizeof(double) * N * k));
     AZ_TRY(P.alloc((void**)&P.Om2, sizeof(double) * N * k));
@@ -687,6 +703,17 @@ int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch, const
     AZ_TRY(P.alloc((void**)&P.dscr, sizeof(double) * sd));
     P.dscr_bytes = sizeof(double) * sd;
   }
+  return AZRBF_OK;
+}
+
+int dense_factor_enqueue(Plan& P, hipStream_t st, hipEvent_t after_sketch, const std::function<int()>& on_sketch,
+                         const std::function<int()>& before_products) {
+  const int k = P.k;
+  // the Jacobi kernel pairs k/2 columns over 256 threads: 512 / k must be a shuffle width
+  if (k != 16 && k != 32 && k != 64) return AZRBF_EUNSUPPORTED;
+  const int64_t N = P.N, Mt = P.Mt;
+  const int64_t Ld = P.Mtp;   // leading dimension of the row-space matrices (whole 128-byte lines)
+  AZ_TRY(dense_factor_alloc(P));
   double* Zy = P.Om2;                  // N x k scratch, later Omega P
   double* W = P.Yf2;                   // Mt x k sketch (ld Ld), later (A Omega) P
   P.ldq = Ld;
@@ -764,6 +791,341 @@ int plan_fetch_rank(Plan& P) {
 int dense_factor(Plan& P, hipStream_t st) {
   AZ_TRY(dense_factor_enqueue(P, st, nullptr));
   return dense_factor_finish(P, st);
+}
+
+// ------------------------------------------------------------------ grouped factor
+
+// The factorisation of many 1D plans on the single-kernel transform as one
+// launch sequence: the same kernels in the same order per plan as
+// dense_factor (so the same factor bit for bit), each step one launch for all
+// plans (per size class for the transforms, per sketch width and row blocking
+// for the TSQR levels).  The per-plan path overlaps the Jacobi SVD with the Q
+// formation on a second stream; here they follow each other.
+
+namespace {
+
+struct GaussOp {
+  uint64_t seed;
+  int64_t rows, cols;
+  double* dst;
+  int64_t ld;
+};
+struct FormqOp {
+  const double* V;
+  int64_t ldv;
+  const double* T;
+  int64_t m;
+  const double* Cup;
+  int64_t ldc;
+  double* E;
+  int64_t lde;
+  int64_t nb;
+  int rb;
+};
+struct JacOp {
+  const double* R;
+  double tau_k;
+  const double* dmax;
+  double* sig;
+  double* Pm;
+  int* info;
+};
+struct ProdOp {     // Out = A B, A m x k (ld lda), B k x k (ld k), Out ld ldo
+  const double* A;
+  int64_t lda, m;
+  const double* B;
+  double* Out;
+  int64_t ldo;
+  int k;
+};
+struct CopyOp {
+  const double* src;
+  double* dst;
+  int64_t n;
+};
+
+__global__ void __launch_bounds__(256) k_bat_gaussian(const GaussOp* __restrict__ ops) {
+  const GaussOp o = ops[blockIdx.z];
+  gaussian_quad(o.seed, o.rows, o.cols, o.dst, o.ld, (int64_t)blockIdx.x * 256 + threadIdx.x, blockIdx.y);
+}
+
+template <int K>
+__global__ void __launch_bounds__(TSQR_THREADS) k_bat_formq(const FormqOp* __restrict__ ops) {
+  const FormqOp o = ops[blockIdx.y];
+  if ((int64_t)blockIdx.x >= o.nb) return;
+  formq_block<K>(o.V, o.ldv, o.T, o.m, o.Cup, o.ldc, o.E, o.lde, o.rb, blockIdx.x);
+}
+
+template <int K>
+__global__ void __launch_bounds__(8 * K) k_bat_jacobi(const JacOp* __restrict__ ops, double tol, int max_sweeps) {
+  const JacOp o = ops[blockIdx.x];
+  jacobi_block<K>(o.R, o.tau_k, o.dmax, tol, max_sweeps, o.sig, o.Pm, o.info);
+}
+
+// as k_gemm_nn<16> with alpha = 1, beta = 0 (the same sums in the same order)
+__global__ void __launch_bounds__(256) k_bat_prod(const ProdOp* __restrict__ ops) {
+  const ProdOp o = ops[blockIdx.z];
+  const int v0 = blockIdx.y * 16;
+  if ((int64_t)blockIdx.x * 256 >= o.m || v0 >= o.k) return;
+  __shared__ double bs[KMAX * 16];
+  const int k = o.k;
+  for (int e = threadIdx.x; e < k * 16; e += 256) {
+    const int c = e % k, v = e / k;
+    bs[c * 16 + v] = o.B[c + (int64_t)k * (v0 + v)];
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= o.m) return;
+  double acc[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0;
+  for (int c = 0; c < k; c += 4) {
+    double a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = o.A[i + o.lda * (c + u)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = fma(a[u], bs[(c + u) * 16 + v], acc[v]);
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) o.Out[i + o.ldo * (v0 + v)] = 1.0 * acc[v];
+}
+
+__global__ void __launch_bounds__(256) k_bat_copy(const CopyOp* __restrict__ ops) {
+  const CopyOp o = ops[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < o.n) o.dst[i] = o.src[i];
+}
+
+}  // namespace
+
+bool dense_factor_batchable(const Plan& P) {
+  return P.dim == 1 && P.fused && !P.generic && P.Mb == 0 && (P.k == 16 || P.k == 32 || P.k == 64);
+}
+
+int dense_factor_batched(const std::vector<Plan*>& plans, std::vector<int>& rcs, hipStream_t st) {
+  const int E = (int)plans.size();
+  rcs.assign(E, AZRBF_OK);
+  if (E == 0) return AZRBF_OK;
+  if (E > 65535) return AZRBF_EINVAL;
+  for (Plan* P : plans)
+    if (!dense_factor_batchable(*P)) return AZRBF_EUNSUPPORTED;
+  // entries in size-class order (the transforms take one launch per (n, s))
+  std::vector<int> ord(E);
+  for (int i = 0; i < E; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    return plans[a]->n != plans[b]->n ? plans[a]->n < plans[b]->n : plans[a]->s < plans[b]->s;
+  });
+  struct Lay {
+    std::vector<TsqrLevel> lv;
+    double* Eb[2];
+    int rb;
+    int* info;
+  };
+  std::vector<Lay> lay(E);
+  int maxL = 0;
+  for (int q = 0; q < E; ++q) {
+    Plan& P = *plans[ord[q]];
+    AZ_TRY(dense_factor_alloc(P));
+    P.ldq = P.Mtp;
+    Lay& L = lay[q];
+    L.rb = plan_tsqr_rows(P, P.k);
+    if (!tsqr_rows_ok(P.k, L.rb)) return AZRBF_EUNSUPPORTED;
+    int64_t sd = 0, ed = 0;
+    tsqr_plan(P.Mt, P.k, L.rb, L.lv, &sd, &ed);
+    double* p = P.dscr;          // the same layout as tsqr()
+    for (size_t l = 0; l < L.lv.size(); ++l) {
+      L.lv[l].tau = p;
+      p += L.lv[l].nb * P.k * P.k;
+      L.lv[l].R = p;
+      p += L.lv[l].nb * P.k * P.k;
+      L.lv[l].A = l == 0 ? P.Yf2 : L.lv[l - 1].R;
+    }
+    L.Eb[0] = p;
+    L.Eb[1] = p + ed;
+    L.info = (int*)(P.dscr + tsqr_scratch_doubles(P.Mt, P.k));
+    maxL = std::max(maxL, (int)L.lv.size());
+  }
+  // host descriptors
+  std::vector<GaussOp> gauss(E);
+  std::vector<BatOp> bop(3 * (size_t)E);
+  std::vector<CopyOp> cop(E);
+  std::vector<ProdOp> pop(2 * (size_t)E);
+  int64_t maxq = 0, maxk = 0, maxrows = 0;
+  for (int q = 0; q < E; ++q) {
+    Plan& P = *plans[ord[q]];
+    const int k = P.k;
+    const int64_t N = P.N, Ld = P.Mtp;
+    gauss[q] = GaussOp{P.prob.seed, N, k, P.Om, N};
+    bop[q] = BatOp{P.geo, P.tw, P.Om, N, k, 1.0, 0.0, P.Yf, Ld, P.Yf, Ld};                 // Y = A Omega
+    bop[E + q] = BatOp{P.geo, P.tw, P.Yf, Ld, k, 1.0, 0.0, P.Om2, N, P.Om2, N};           // Zy = Z* Y
+    bop[2 * E + q] = BatOp{P.geo, P.tw, P.Om2, N, k, -1.0, 1.0, P.Yf, Ld, P.Yf2, Ld};     // W = Y - A Zy
+    cop[q] = CopyOp{lay[q].lv.back().R, P.Rf, (int64_t)k * k};
+    pop[q] = ProdOp{P.Om, N, N, P.Pm, P.Om2, N, k};                                         // Omega P
+    pop[E + q] = ProdOp{P.Yf, Ld, P.Mt, P.Pm, P.Yf2, Ld, k};                                // (A Omega) P
+    maxq = std::max(maxq, (N + 3) / 4);
+    maxk = std::max<int64_t>(maxk, k);
+    maxrows = std::max(maxrows, std::max(N, P.Mt));
+  }
+  struct Cls {
+    int n, s, first, count;
+    int64_t maxvec;
+  };
+  std::vector<Cls> cls;
+  for (int q = 0; q < E; ++q) {
+    const Plan& P = *plans[ord[q]];
+    if (cls.empty() || cls.back().n != P.n || cls.back().s != P.s) cls.push_back(Cls{P.n, P.s, q, 0, 0});
+    ++cls.back().count;
+    cls.back().maxvec = std::max<int64_t>(cls.back().maxvec, P.k);
+  }
+  // TSQR levels (ascending) and Q formation (descending): per level, the
+  // entries that have it, grouped by (k, rb) and by k
+  struct Grp {
+    int level, k, rb, first, count;
+    int64_t maxnb;
+  };
+  std::vector<TsqrOp> top;
+  std::vector<Grp> tg;
+  std::vector<FormqOp> fop;
+  std::vector<Grp> fg;
+  for (int l = 0; l < maxL; ++l) {
+    std::map<std::pair<int, int>, std::vector<int>> by;
+    for (int q = 0; q < E; ++q)
+      if ((int)lay[q].lv.size() > l) by[{plans[ord[q]]->k, lay[q].rb}].push_back(q);
+    for (auto& kv : by) {
+      Grp g{l, kv.first.first, kv.first.second, (int)top.size(), (int)kv.second.size(), 0};
+      for (int q : kv.second) {
+        Plan& P = *plans[ord[q]];
+        const TsqrLevel& L = lay[q].lv[l];
+        const int64_t lda = l == 0 ? P.Mtp : L.m;
+        top.push_back(TsqrOp{L.A, lda, L.m, L.R, L.nb * P.k, L.A, lda, L.tau});
+        g.maxnb = std::max(g.maxnb, L.nb);
+      }
+      tg.push_back(g);
+    }
+  }
+  for (int l = maxL - 1; l >= 0; --l) {
+    std::map<int, std::vector<int>> by;
+    for (int q = 0; q < E; ++q)
+      if ((int)lay[q].lv.size() > l) by[plans[ord[q]]->k].push_back(q);
+    for (auto& kv : by) {
+      Grp g{l, kv.first, 0, (int)fop.size(), (int)kv.second.size(), 0};
+      for (int q : kv.second) {
+        Plan& P = *plans[ord[q]];
+        const Lay& Y = lay[q];
+        const TsqrLevel& L = Y.lv[l];
+        const int64_t lda = l == 0 ? P.Mtp : L.m;
+        const bool top_level = l + 1 == (int)Y.lv.size();
+        const double* up = top_level ? nullptr : (l + 1 == 0 ? P.Q : Y.Eb[(l + 1) & 1]);
+        const int64_t ldup = top_level ? 0 : Y.lv[l + 1].m;
+        double* Eo = l == 0 ? P.Q : Y.Eb[l & 1];
+        fop.push_back(FormqOp{L.A, lda, L.tau, L.m, up, ldup, Eo, lda, L.nb, Y.rb});
+        g.maxnb = std::max(g.maxnb, L.nb);
+      }
+      fg.push_back(g);
+    }
+  }
+  std::vector<JacOp> jop;
+  std::vector<Grp> jg;
+  {
+    std::map<int, std::vector<int>> by;
+    for (int q = 0; q < E; ++q) by[plans[ord[q]]->k].push_back(q);
+    for (auto& kv : by) {
+      jg.push_back(Grp{0, kv.first, 0, (int)jop.size(), (int)kv.second.size(), 0});
+      for (int q : kv.second) {
+        Plan& P = *plans[ord[q]];
+        jop.push_back(JacOp{P.Rf, P.tau * sqrt((double)P.k), P.dred, P.sig, P.Pm, lay[q].info});
+      }
+    }
+  }
+  // one upload of every descriptor
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t o_g = 0, o_b = al(o_g + sizeof(GaussOp) * gauss.size()), o_c = al(o_b + sizeof(BatOp) * bop.size()),
+               o_p = al(o_c + sizeof(CopyOp) * cop.size()), o_t = al(o_p + sizeof(ProdOp) * pop.size()),
+               o_f = al(o_t + sizeof(TsqrOp) * top.size()), o_j = al(o_f + sizeof(FormqOp) * fop.size()),
+               total = al(o_j + sizeof(JacOp) * jop.size());
+  char* host = nullptr;
+  char* dev = nullptr;
+  AZ_HIP(hipHostMalloc((void**)&host, total, hipHostMallocDefault));
+  if (hipMalloc((void**)&dev, total) != hipSuccess) {
+    (void)hipHostFree(host);
+    return AZRBF_EHIP;
+  }
+  std::memcpy(host + o_g, gauss.data(), sizeof(GaussOp) * gauss.size());
+  std::memcpy(host + o_b, bop.data(), sizeof(BatOp) * bop.size());
+  std::memcpy(host + o_c, cop.data(), sizeof(CopyOp) * cop.size());
+  std::memcpy(host + o_p, pop.data(), sizeof(ProdOp) * pop.size());
+  std::memcpy(host + o_t, top.data(), sizeof(TsqrOp) * top.size());
+  std::memcpy(host + o_f, fop.data(), sizeof(FormqOp) * fop.size());
+  std::memcpy(host + o_j, jop.data(), sizeof(JacOp) * jop.size());
+  int rc = hipMemcpyAsync(dev, host, total, hipMemcpyHostToDevice, st) == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+  const BatOp* dbop = (const BatOp*)(dev + o_b);
+  auto grouped = [&](int which, int step) -> int {
+    for (const Cls& c : cls)
+      AZ_TRY(ops_batched(which, c.n, c.s, dbop + (int64_t)step * E + c.first, c.count, c.maxvec, 0.0, st));
+    return AZRBF_OK;
+  };
+  if (!rc) {
+    launch_kernel(k_bat_gaussian, dim3((unsigned)((maxq + 255) / 256), (unsigned)maxk, (unsigned)E), 256, 0, st,
+                  (const GaussOp*)(dev + o_g));
+    rc = hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+  }
+  if (!rc) rc = grouped(0, 0);
+  if (!rc) rc = grouped(1, 1);
+  if (!rc) rc = grouped(0, 2);
+  for (size_t i = 0; i < tg.size() && !rc; ++i)
+    rc = tsqr_block_qr_batched(tg[i].k, tg[i].rb, (const TsqrOp*)(dev + o_t) + tg[i].first, tg[i].count,
+                               tg[i].maxnb, st);
+  if (!rc) {
+    int64_t kk = maxk * maxk;
+    launch_kernel(k_bat_copy, dim3((unsigned)((kk + 255) / 256), (unsigned)E), 256, 0, st, (const CopyOp*)(dev + o_c));
+    rc = hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+  }
+  for (size_t i = 0; i < fg.size() && !rc; ++i) {
+    const FormqOp* f = (const FormqOp*)(dev + o_f) + fg[i].first;
+    const dim3 grid((unsigned)fg[i].maxnb, (unsigned)fg[i].count);
+    if (fg[i].k == 16) launch_kernel(k_bat_formq<16>, grid, TSQR_THREADS, 0, st, f);
+    else if (fg[i].k == 32) launch_kernel(k_bat_formq<32>, grid, TSQR_THREADS, 0, st, f);
+    else launch_kernel(k_bat_formq<64>, grid, TSQR_THREADS, 0, st, f);
+    rc = hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+  }
+  for (size_t i = 0; i < jg.size() && !rc; ++i) {
+    const JacOp* j = (const JacOp*)(dev + o_j) + jg[i].first;
+    const int k = jg[i].k;
+    const double tol = 4.0 * k * 1.1102230246251565e-16;
+    if (k == 16) launch_kernel(k_bat_jacobi<16>, jg[i].count, 128, 0, st, j, tol, 40);
+    else if (k == 32) launch_kernel(k_bat_jacobi<32>, jg[i].count, 256, 0, st, j, tol, 40);
+    else launch_kernel(k_bat_jacobi<64>, jg[i].count, 512, 0, st, j, tol, 40);
+    rc = hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+  }
+  if (!rc) {
+    launch_kernel(k_bat_prod, dim3((unsigned)((maxrows + 255) / 256), (unsigned)(maxk / 16), (unsigned)(2 * E)), 256,
+                  0, st, (const ProdOp*)(dev + o_p));
+    rc = hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+  }
+  for (int q = 0; q < E && !rc; ++q) {
+    Plan& P = *plans[ord[q]];
+    if (hipMemcpyAsync(P.hinfo, lay[q].info, sizeof(P.hinfo), hipMemcpyDeviceToHost, st) != hipSuccess)
+      rc = AZRBF_EHIP;
+  }
+  const int rs = hipStreamSynchronize(st) == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
+  (void)hipFree(dev);
+  (void)hipHostFree(host);
+  if (rc) return rc;
+  if (rs) return rs;
+  for (int q = 0; q < E; ++q) {
+    Plan& P = *plans[ord[q]];
+    std::swap(P.Om, P.Om2);
+    std::swap(P.Yf, P.Yf2);
+    P.dinfo = lay[q].info;
+    P.rank = P.hinfo[0];
+    P.sweeps = P.hinfo[1];
+    P.rank_pending = false;
+    P.factored = true;
+    rcs[ord[q]] = 10 * (int64_t)P.rank > 9 * (int64_t)P.k ? AZRBF_ERANK : AZRBF_OK;
+  }
+  return AZRBF_OK;
 }
 
 // ------------------------------------------------------------------ solve

@@ -238,6 +238,27 @@ int dense_first_qtc(Plan& P, int64_t nrhs, hipStream_t st);
 int dense_solve(Plan& P, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
                 double* relres, hipStream_t st, bool first_done = false, bool qtc_done = false);
 
+// One block-QR level of one plan in a grouped launch (the arguments of
+// tsqr_block_qr): rows m of A (ld lda) in blocks of rb, R (ld ldr), the
+// reflectors over V (ld ldv), the compact-WY factors at T.
+struct TsqrOp {
+  const double* A;
+  int64_t lda, m;
+  double* R;
+  int64_t ldr;
+  double* V;
+  int64_t ldv;
+  double* T;
+};
+// One launch over count device-resident levels of plans with the same k and
+// row blocking rb; maxnb bounds their block counts (tsqr.hip).
+int tsqr_block_qr_batched(int k, int rb, const TsqrOp* ops, int count, int64_t maxnb, hipStream_t st);
+// Grouped factorisation of unfactored 1D plans on the single-kernel
+// transform (batched_eligible once factored); rcs[i]: the plan's code (OK or
+// ERANK: retained rank above 90 % of the width).  Synchronises st.
+int dense_factor_batched(const std::vector<Plan*>& plans, std::vector<int>& rcs, hipStream_t st);
+bool dense_factor_batchable(const Plan& P);
+
 // batched.hip: the grouped solve of many factored 1D plans (one entry per
 // block of right-hand sides; a plan may appear in several entries).
 struct BatchItem {

@@ -811,17 +811,34 @@ int azrbf_solve_batched(int32_t nprob, const azrbf_plan_t* plans, const double* 
     if (nrhs[i] > 0 && (!B[i] || !X[i] || ldb[i] < P.Mt || ldx[i] < P.N)) return AZRBF_EINVAL;
   }
   hipStream_t st = (hipStream_t)stream;
-  // set-up and factors first (each plan once), then the other entries one by
-  // one, then the grouped entries together
+  // set-up and factors first (each plan once: the single-kernel 1D plans in
+  // one grouped factorisation, the others one by one), then the other entries
+  // one by one, then the grouped entries together
   std::vector<az::BatchItem> items;
+  std::vector<Plan*> grouped_factor;
   for (int32_t i = 0; i < nprob; ++i) {
     if (nrhs[i] == 0) continue;
     Plan& P = plans[i]->p;
     P.last_stream = st;
     AZ_TRY(az::plan_on_stream(P, st));
-    if (!P.factored) {
+    if (P.factored) continue;
+    if (az::dense_factor_batchable(P)) {
+      if (std::find(grouped_factor.begin(), grouped_factor.end(), &P) == grouped_factor.end())
+        grouped_factor.push_back(&P);
+    } else {
       const int rc = az::factor_plan(P, st);
       if (rc != AZRBF_OK && rc != AZRBF_ERANK) return rc;
+    }
+  }
+  {
+    std::vector<int> rcs;
+    AZ_TRY(az::dense_factor_batched(grouped_factor, rcs, st));
+    for (size_t i = 0; i < grouped_factor.size(); ++i) {
+      // too narrow with the width left open: factored again on its own, widened
+      if (rcs[i] == AZRBF_ERANK && grouped_factor[i]->prob.k == 0) {
+        const int rc = az::factor_plan(*grouped_factor[i], st);
+        if (rc != AZRBF_OK && rc != AZRBF_ERANK) return rc;
+      }
     }
   }
   for (int32_t i = 0; i < nprob; ++i) {

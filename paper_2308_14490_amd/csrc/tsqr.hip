@@ -241,9 +241,9 @@ __device__ __forceinline__ void qr_columns(double (&a)[RPT][K], const QrShared<K
 // H_0 ... H_{k-1} = I - V T V^T.  Rows >= m are read as zero and not
 // written.  A and V may be the same array.
 template <int K, int RPT>
-__global__ void __launch_bounds__(256)
-k_tsqr_reg(const double* A, int64_t lda, int64_t m, double* __restrict__ Rout, int64_t ldr, double* V,
-           int64_t ldv, double* __restrict__ Tout) {
+__device__ __forceinline__ void tsqr_reg_block(const double* A, int64_t lda, int64_t m, double* __restrict__ Rout,
+                                               int64_t ldr, double* V, int64_t ldv, double* __restrict__ Tout,
+                                               int64_t blk) {
   using C = RegQR<K, RPT>;
   __shared__ double red[4][K];    // per-wave column sums
   __shared__ double rowj[K];      // the pivot row
@@ -253,7 +253,7 @@ k_tsqr_reg(const double* A, int64_t lda, int64_t m, double* __restrict__ Rout, i
   __shared__ double scal[4];      // beta, tau, scale
   __shared__ double Tm[K * K];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int64_t r0 = (int64_t)blockIdx.x * C::RB;
+  const int64_t r0 = blk * C::RB;
   double a[C::RPT][K];
 #pragma unroll
   for (int i = 0; i < C::RPT; ++i) {
@@ -295,11 +295,11 @@ k_tsqr_reg(const double* A, int64_t lda, int64_t m, double* __restrict__ Rout, i
   }
   for (int e = t; e < K * K; e += 256) {
     const int r = e % K, c = e / K;
-    Tout[(int64_t)blockIdx.x * K * K + e] = r <= c ? Tm[c * K + r] : 0.0;
+    Tout[blk * K * K + e] = r <= c ? Tm[c * K + r] : 0.0;
   }
   if (t < K) {
 #pragma unroll
-    for (int c = 0; c < K; ++c) Rout[(int64_t)blockIdx.x * K + t + ldr * c] = c >= t ? a[0][c] : 0.0;
+    for (int c = 0; c < K; ++c) Rout[blk * K + t + ldr * c] = c >= t ? a[0][c] : 0.0;
   }
 #pragma unroll
   for (int i = 0; i < C::RPT; ++i) {
@@ -310,6 +310,28 @@ k_tsqr_reg(const double* A, int64_t lda, int64_t m, double* __restrict__ Rout, i
       for (int c = 0; c < K; ++c) V[gr + ldv * c] = row > c ? a[i][c] : (row == c ? 1.0 : 0.0);
     }
   }
+}
+
+template <int K, int RPT>
+__global__ void __launch_bounds__(256)
+k_tsqr_reg(const double* A, int64_t lda, int64_t m, double* __restrict__ Rout, int64_t ldr, double* V,
+           int64_t ldv, double* __restrict__ Tout) {
+  tsqr_reg_block<K, RPT>(A, lda, m, Rout, ldr, V, ldv, Tout, blockIdx.x);
+}
+
+// Grouped: level blockIdx.y of the list, its block blockIdx.x (blocks past
+// the level's rows leave at once, the whole block).
+template <int K, int RPT>
+__global__ void __launch_bounds__(256) k_bat_tsqr_reg(const TsqrOp* __restrict__ ops) {
+  const TsqrOp o = ops[blockIdx.y];
+  if ((int64_t)blockIdx.x * RegQR<K, RPT>::RB >= o.m) return;
+  tsqr_reg_block<K, RPT>(o.A, o.lda, o.m, o.R, o.ldr, o.V, o.ldv, o.T, blockIdx.x);
+}
+
+template <int K, int RPT>
+int launch_bat_reg(const TsqrOp* ops, int count, int64_t maxnb, hipStream_t st) {
+  launch_kernel(k_bat_tsqr_reg<K, RPT>, dim3((unsigned)maxnb, (unsigned)count), 256, 0, st, ops);
+  return hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
 }
 
 template <int K, int RPT>
@@ -348,6 +370,24 @@ int tsqr_block_qr(const double* A, int64_t lda, int64_t m, int k, int rb, double
     case 32 * 16 + 4: return launch_reg<32, 4>(A, lda, m, R, ldr, V, ldv, T, st);
     case 64 * 16 + 1: return launch_reg<64, 1>(A, lda, m, R, ldr, V, ldv, T, st);
     case 64 * 16 + 2: return launch_reg<64, 2>(A, lda, m, R, ldr, V, ldv, T, st);
+    default: return AZRBF_EUNSUPPORTED;
+  }
+}
+
+int tsqr_block_qr_batched(int k, int rb, const TsqrOp* ops, int count, int64_t maxnb, hipStream_t st) {
+  if (count <= 0 || maxnb <= 0) return AZRBF_OK;
+  if (!tsqr_rows_ok(k, rb) || count > 65535) return AZRBF_EUNSUPPORTED;
+  const int rpt = rb / 256;
+  Prof pr("bat_tsqr_block", 0.0, st);
+  switch (k * 16 + rpt) {
+    case 16 * 16 + 2: return launch_bat_reg<16, 2>(ops, count, maxnb, st);
+    case 16 * 16 + 4: return launch_bat_reg<16, 4>(ops, count, maxnb, st);
+    case 16 * 16 + 8: return launch_bat_reg<16, 8>(ops, count, maxnb, st);
+    case 32 * 16 + 1: return launch_bat_reg<32, 1>(ops, count, maxnb, st);
+    case 32 * 16 + 2: return launch_bat_reg<32, 2>(ops, count, maxnb, st);
+    case 32 * 16 + 4: return launch_bat_reg<32, 4>(ops, count, maxnb, st);
+    case 64 * 16 + 1: return launch_bat_reg<64, 1>(ops, count, maxnb, st);
+    case 64 * 16 + 2: return launch_bat_reg<64, 2>(ops, count, maxnb, st);
     default: return AZRBF_EUNSUPPORTED;
   }
 }

@@ -161,3 +161,25 @@ def test_grouped_solve_with_entries_on_the_per_plan_path():
     assert float(rels[2].max()) <= 1e-10
     for pl in pa + pb:
         pl.destroy()
+
+
+def test_grouped_factor_equals_per_plan_factor():
+    """Unfactored plans of a grouped call are factored together (one launch
+    per step for all of them) with the per-plan kernels in the same order per
+    plan: Q, R, the singular values and the retained rank equal those of
+    azrbf_factor bit for bit, and so do the solutions on either factor."""
+    azrbf, problems, probs, plans_a, plans_b, Bs = _build(seed0=1300)
+    for pl in plans_a:
+        azrbf.factor(pl)
+    azrbf.solve_batched(plans_b, [B[:1].contiguous() for B in Bs])    # factors plans_b in one grouped call
+    torch.cuda.synchronize()
+    for (p, _), pa, pb, B in zip(probs, plans_a, plans_b, Bs):
+        for which in ("Q", "R", "sigma"):
+            assert torch.equal(azrbf.get_factor(pa, which), azrbf.get_factor(pb, which)), (p.name, which)
+        assert pa.info()["rank"] == pb.info()["rank"], p.name
+        Xa, ra = azrbf.solve(pa, B)
+        Xb, rb = azrbf.solve(pb, B)
+        torch.cuda.synchronize()
+        assert torch.equal(Xa, Xb) and torch.equal(ra, rb), p.name
+    for pl in plans_a + plans_b:
+        pl.destroy()
