@@ -1099,9 +1099,9 @@ int dense_factor_batched(const std::vector<Plan*>& plans, std::vector<int>& rcs,
     else launch_kernel(k_bat_jacobi<64>, jg[i].count, 512, 0, st, j, tol, 40);
     rc = hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
   }
-  if (!rc) {
-    launch_kernel(k_bat_prod, dim3((unsigned)((maxrows + 255) / 256), (unsigned)(maxk / 16), (unsigned)(2 * E)), 256,
-                  0, st, (const ProdOp*)(dev + o_p));
+  for (int h = 0; h < 2 && !rc; ++h) {   // Omega P, then (A Omega) P: E entries per launch (grid z <= 65535)
+    launch_kernel(k_bat_prod, dim3((unsigned)((maxrows + 255) / 256), (unsigned)(maxk / 16), (unsigned)E), 256, 0,
+                  st, (const ProdOp*)(dev + o_p) + (int64_t)h * E);
     rc = hipGetLastError() == hipSuccess ? AZRBF_OK : AZRBF_EHIP;
   }
   for (int q = 0; q < E && !rc; ++q) {
