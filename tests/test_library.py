@@ -27,7 +27,8 @@ def _lib_path():
 def test_header_declares_the_boundary():
     names = _declared()
     for must in ["azrbf_plan", "azrbf_apply_A", "azrbf_apply_Zstar", "azrbf_apply_AZstar", "azrbf_plan_dims", "azrbf_solve", "azrbf_factor",
-                 "azrbf_destroy", "azrbf_strerror", "azrbf_footprint_bytes", "azrbf_solve_many"]:
+                 "azrbf_destroy", "azrbf_strerror", "azrbf_footprint_bytes", "azrbf_solve_many",
+                 "azrbf_solve_batched"]:
         assert must in names
 
 
@@ -125,3 +126,17 @@ def test_tune_table_round_trip_and_validation():
     assert lib.azrbf_tune_load(b"e2_128x128_s2 16 16 8\ne2_64x64_s2 4 8 2\n") == 0
     t = azrbf.tune_table()
     assert t["e2_128x128_s2"] == (16, 16, 8) and t["e2_64x64_s2"] == (4, 8, 2)
+
+
+def test_grouped_and_multi_plan_solves_check_arguments_before_touching_the_gpu():
+    """The argument checks that need no device: a negative count or one past
+    the grid's entry axis is EINVAL, an empty call is OK, missing arrays are
+    EINVAL."""
+    from paper_2308_14490_amd import azrbf
+    lib = azrbf._lib()
+    null = ctypes.c_void_p()
+    for f in (lib.azrbf_solve_batched, lib.azrbf_solve_many):
+        assert f(-1, None, None, None, None, None, None, None, null) == azrbf.EINVAL
+        assert f(0, None, None, None, None, None, None, None, null) == azrbf.OK
+        assert f(3, None, None, None, None, None, None, None, null) == azrbf.EINVAL
+    assert lib.azrbf_solve_batched(65536, None, None, None, None, None, None, None, null) == azrbf.EINVAL
