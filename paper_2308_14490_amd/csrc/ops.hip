@@ -97,11 +97,12 @@ struct Fused {
 // 1, scratch spills for s = 4 and for N = 8192, whose 512-thread blocks cap a
 // wave at 256) and was slower: the phases' rows meet again in L2 before they
 // go to HBM.
+// Phases r0 .. r1 - 1 of the block's vector pair (all of them: 0 .. S).
 template <int N, int S>
 __device__ __forceinline__ void fused_A_block(const Geo& g, const double2* __restrict__ tw,
                                               const double* __restrict__ X, int64_t ldx, int64_t nvec, double alpha,
                                               double beta, const double* Yin, int64_t ldyi, double* Y, int64_t ldy,
-                                              int64_t blk) {
+                                              int64_t blk, int r0 = 0, int r1 = S) {
   using F = Fused<N>;
   extern __shared__ double2 smem[];
   const RowLds lds{smem, RowLds::stride(N)};
@@ -112,7 +113,7 @@ __device__ __forceinline__ void fused_A_block(const Geo& g, const double2* __res
   for (int m = 0; m < RADIX; ++m) a[m] = load_pair(X, ldx, t + m * F::T, v0, nvec);
   fft_line<N, false>(a, lds, line, t, tw);
 #pragma unroll 1
-  for (int r = 0; r < S; ++r) {
+  for (int r = r0; r < r1; ++r) {
     const int tt = opaque(t), ll = opaque(line);
     double2 res[RADIX];
 #pragma unroll
@@ -178,11 +179,15 @@ k_fused_Z(Geo g, const double2* __restrict__ tw, const double* __restrict__ R, i
 // Grouped launches over many plans of one size class (N, S): entry blockIdx.y
 // of the operand list, its line block blockIdx.x.  Blocks past an entry's
 // vectors leave at once (the whole block: the transform synchronises it).
+// One phase per block (blockIdx.z): a grouped launch has few blocks per
+// entry, so the s phases run side by side, each block transforming the
+// vector pair forward itself (the same values in every block).
 template <int N, int S>
 __global__ void __launch_bounds__(Fused<N>::BLOCK) k_bat_A(const BatOp* __restrict__ ops) {
   const BatOp o = ops[blockIdx.y];
   if (2 * (int64_t)blockIdx.x * Fused<N>::LINES >= o.nvec) return;
-  fused_A_block<N, S>(o.g, o.tw, o.in, o.ldin, o.nvec, o.alpha, o.beta, o.yin, o.ldyi, o.out, o.ldo, blockIdx.x);
+  fused_A_block<N, S>(o.g, o.tw, o.in, o.ldin, o.nvec, o.alpha, o.beta, o.yin, o.ldyi, o.out, o.ldo, blockIdx.x,
+                      (int)blockIdx.z, (int)blockIdx.z + 1);
 }
 
 template <int N, int S>
@@ -909,7 +914,7 @@ template <int N, int S>
 static int launch_bat_s(int which, const BatOp* ops, int count, int64_t maxvec, double bytes, hipStream_t st) {
   using F = Fused<N>;
   const int64_t blocks = ((maxvec + 1) / 2 + F::LINES - 1) / F::LINES;
-  const dim3 grid((unsigned)blocks, (unsigned)count);
+  const dim3 grid((unsigned)blocks, (unsigned)count, which == 0 ? (unsigned)S : 1u);
   if (which == 0) {
     AZ_TRY(set_lds(k_bat_A<N, S>, F::LDS));
     static const std::string name = "bat_A n=" + std::to_string(N);
