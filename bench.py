@@ -548,20 +548,20 @@ def uneven_1d(log_fn, count=256, seed=77, reps=3):
         if mode == "plain":
             for pl, B, X, r in zip(ps, Bs, Xs, rels):
                 azrbf.solve(pl, B, X, r)
-        elif mode == "solve_many":
-            azrbf.solve_many(ps, Bs, Xs)
-        else:
-            azrbf.solve_batched(ps, Bs, Xs, rels)
-        return ps
+            return ps, rels
+        if mode == "solve_many":
+            return ps, azrbf.solve_many(ps, Bs, Xs)[1]
+        azrbf.solve_batched(ps, Bs, Xs, rels)
+        return ps, rels
     for name in ("plain", "solve_many", "grouped"):
-        for pl in cold(name):
+        for pl in cold(name)[0]:
             pl.destroy()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ps = cold(name)
+        ps, rr = cold(name)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        ok = sum(int((r <= 1e-10).sum()) for r in rels) if name != "solve_many" else None
+        ok = sum(int((r <= 1e-10).sum()) for r in rr)
         for pl in ps:
             pl.destroy()
         out["cold_" + name] = {"ms_per_pass": round(dt * 1e3, 2), "problems_per_s": round(count / dt, 1),
