@@ -183,3 +183,27 @@ def test_grouped_factor_equals_per_plan_factor():
         assert torch.equal(Xa, Xb) and torch.equal(ra, rb), p.name
     for pl in plans_a + plans_b:
         pl.destroy()
+
+
+def test_grouped_call_edge_cases():
+    """No qualifying entry (a four-step plan only), only empty entries, and a
+    single entry: each as by azrbf_solve."""
+    azrbf, problems = _mods()
+    big = W.family_1d(16384, 2, seed0=61, name="big-only")
+    small = W.family_1d(512, 3, seed0=71, name="small-only")
+    pa, pb = problems.plan_for(big), problems.plan_for(big)
+    qa, qb = problems.plan_for(small), problems.plan_for(small)
+    Bb, Bs = problems.rhs_for(pa, big), problems.rhs_for(qa, small)
+    Xa, ra = azrbf.solve(pa, Bb)
+    Xb, rb = azrbf.solve_batched([pb], [Bb])
+    Ya, sa = azrbf.solve(qa, Bs)
+    Yb, sb = azrbf.solve_batched([qb], [Bs])
+    Xe, re_ = azrbf.solve_batched([pb, qb], [Bb[:0], Bs[:0]])
+    torch.cuda.synchronize()
+    assert torch.equal(Xa, Xb[0]) and torch.equal(ra, rb[0])
+    # the single small entry goes through the grouped kernels: same residual level
+    assert float(sb[0].max()) <= 1e-10 and float(sa.max()) <= 1e-10
+    assert torch.all(sb[0].cpu() <= 10 * sa.cpu() + 1e-15)
+    assert Xe[0].shape[0] == 0 and Xe[1].shape[0] == 0
+    for p in (pa, pb, qa, qb):
+        p.destroy()
